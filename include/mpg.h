@@ -1,0 +1,141 @@
+/*
+ * mpg.h -- C ABI of the MI355X (gfx950) multipole gravity solver for
+ * multi-patch spherical grids, after Wongwathanarat, "A Generalized Solution
+ * Method for Parallelized Computation of the Three-dimensional Gravitational
+ * Potential on a Multi-patch grid in Spherical Geometry" (arXiv:1903.08475).
+ *
+ * The library computes, for cell-averaged densities rho on every patch of a
+ * grid, the potential Phi at the upper vertex (r_i^+, theta_j^+, phi_k^+) of
+ * every cell (Eq. gravpotmult), in three device steps:
+ *   1. moments   B_{i,lm} = sum_g sum_jk rho_{g,i,jk} U_{g,jk,lm}      (Eq. B_CS, Sec. 4.3 step 2)
+ *   2. radial sums M_{i,lm} of Eq. M_C (Sec. 4.3 step 4)
+ *   3. expansion Phi_{g,i,jk} = sum_lm Q_{g,jk,lm} M_{i,lm}            (Sec. 4.3 step 5)
+ * The angular weights U (Eqs. U_C/U_S with the normalisation factors of
+ * Eqs. N_CC..N_SC) and prefactors Q (Eqs. Q_C/Q_S) are built once per plan
+ * on the device (Sec. 4.3 step 1).
+ *
+ * Conventions.
+ *   - Real moment index: idx(l,0) = l^2, idx(l,m,C) = l^2+2m-1,
+ *     idx(l,m,S) = l^2+2m (1 <= m <= l); n_lm = (lmax+1)^2.
+ *   - P_l^m carries the Condon-Shortley phase; the prefactor of every
+ *     order-m term is 2/delta_m (Eq. del_m).
+ *   - A field is rho[n_patches][n_r][n_theta][n_phi], row-major, phi
+ *     fastest; a batch of n_fields fields of one plan is n_fields such
+ *     arrays back to back.  Phi has the same layout.
+ *   - Local patch frames relate to the common frame by x = R^(g) xi with
+ *     R^(g) of Eq. rottransmatrix (z-y'-z'' Euler angles).
+ *
+ * Ownership and execution.  All array arguments of the compute calls are
+ * device pointers owned by the caller.  A plan owns its device tables and
+ * work space and frees them in mpg_destroy.  Compute calls are enqueued
+ * asynchronously on the plan's HIP stream and return at once; errors of
+ * the device work surface at the next call or at mpg_sync.  A plan must
+ * not be used from two host threads at once.
+ *
+ * Errors.  Every int-returning call returns MPG_OK (0) or a negative
+ * status and never throws; mpg_last_error() gives a message for the last
+ * failure of the calling thread.
+ */
+#ifndef MPG_H
+#define MPG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MPG_OK            0
+#define MPG_EINVAL       -1   /* bad argument or grid                      */
+#define MPG_ENOMEM       -2   /* device or host allocation failed          */
+#define MPG_EDEVICE      -3   /* a HIP call failed                         */
+#define MPG_EUNSUPPORTED -4   /* valid request this build does not handle  */
+
+/* arithmetic of the two contractions */
+#define MPG_FP64        0     /* FP64 MFMA GEMMs                           */
+#define MPG_SPLIT_BF16  1     /* split-BF16 MFMA GEMMs, FP32 accumulation  */
+
+/* element types of rho / Phi */
+#define MPG_F64 0
+#define MPG_F32 1
+
+/* Grid of n_patches geometrically identical patches (Sec. 3).  Every patch
+ * spans local colatitudes [theta0, theta0 + n_theta*dtheta] and azimuths
+ * [phi0, phi0 + n_phi*dphi]; shells are [r_edges[i], r_edges[i+1]].
+ * All pointers are host pointers, read during mpg_plan only. */
+typedef struct mpg_grid {
+    int n_patches;              /* 1 (one patch) or 2 (Yin-Yang, Sec. 4)     */
+    int n_r, n_theta, n_phi;    /* cells per patch                           */
+    const double *r_edges;      /* n_r+1, strictly increasing, r_edges[0]>=0 */
+    double theta0, phi0;        /* local lower corner                        */
+    double dtheta, dphi;        /* local spacing                             */
+    const double *euler;        /* n_patches x (alpha, beta, gamma)          */
+    const double *overlap_w;    /* n_theta*n_phi cell weights w_jk, or NULL  */
+    double G;                   /* gravitational constant                    */
+} mpg_grid;
+
+typedef struct mpg_plan_s *mpg_plan_t;
+
+/* Build a plan: validate the grid, upload its geometry and build the FP64
+ * tables U, Q, the overlap weights (Sec. 4.2, w_jk = 1 - alpha_jk/2, when
+ * overlap_w is NULL) and the radial recurrence coefficients on the device
+ * (Sec. 4.3 step 1), plus their split-BF16 copies for MPG_SPLIT_BF16.
+ *   lmax       : truncation degree, 0 <= lmax <= 64
+ *   precision  : MPG_FP64 or MPG_SPLIT_BF16
+ *   max_fields : largest n_fields later passed to the compute calls (>= 1);
+ *                sizes the work space
+ *   stream     : hipStream_t on which the plan runs (NULL: default stream)
+ * Two patches use the Yin/Yang parity fold (Q_Yang = (-1)^m Q_Yin, Sec. 4.2),
+ * which requires Euler angles that differ only by pi in gamma; other
+ * two-patch orientations return MPG_EUNSUPPORTED.  Computing overlap
+ * weights needs a Yin-Yang grid symmetric about the patch centre; otherwise
+ * pass overlap_w.  Blocks until the tables are built.
+ * Errors: MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE, MPG_EUNSUPPORTED. */
+int mpg_plan(const mpg_grid *grid, int lmax, int precision, int max_fields,
+             void *stream, mpg_plan_t *out);
+
+/* Moments only (Eq. B_CS and Eq. M_C).
+ *   rho   : device, n_fields fields of rho_dtype
+ *   B, M  : device FP64 [n_fields][n_r][n_lm] in the real index, or NULL
+ * Errors: MPG_EINVAL (n_fields out of [1, max_fields], bad dtype, null
+ * rho), MPG_EDEVICE. */
+int mpg_moments(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
+                double *B, double *M);
+
+/* The whole solve (Sec. 4.3 steps 2-5) for n_fields fields of one plan.
+ *   rho : device input, rho_dtype;  phi : device output, phi_dtype
+ * Errors: as mpg_moments. */
+int mpg_potential(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
+                  void *phi, int phi_dtype);
+
+/* Solve n independent fields with possibly different plans (grid sizes and
+ * lmax) in one persistent kernel launch per step, so that small fields do
+ * not each pay a launch.  rho[f] and phi[f] are device pointers of field f
+ * (one field each), of element type dtype.  All plans must share precision
+ * and stream; the work runs on plans[0]'s stream.
+ * Errors: MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE. */
+int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho,
+                        void *const *phi, int dtype);
+
+/* Copy the plan's FP64 tables to device buffers, in the real index:
+ *   U : [n_patches][n_theta*n_phi][n_lm]   (Eqs. U_C/U_S), or NULL
+ *   Q : [n_patches][n_theta*n_phi][n_lm]   (Eqs. Q_C/Q_S), or NULL
+ *   w : [n_theta*n_phi] overlap weights, or NULL
+ * For checking the table build; not needed for solving. */
+int mpg_tables(mpg_plan_t plan, double *U, double *Q, double *w);
+
+/* Sizes of a plan: n_lm and the element count of one field. */
+int mpg_plan_info(mpg_plan_t plan, int *n_lm, long long *field_elems);
+
+/* Wait for the plan's stream; reports device errors. */
+int mpg_sync(mpg_plan_t plan);
+
+/* Free the plan and its device memory (waits for its stream first). */
+void mpg_destroy(mpg_plan_t plan);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *mpg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

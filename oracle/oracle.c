@@ -181,7 +181,44 @@ int orc_overlap_weights(const orc_grid *g, double *w) {
             ctx.p1 = g->phi0 + k * g->dphi;
             ctx.p2 = ctx.p1 + g->dphi;
             double area = g->dphi * (cos(t1) - cos(t2));
-            double cov = adapt_int(ovl_integrand, &ctx, t1, t2, 1e-18 * area);
+            /* Split [t1, t2] wherever the covered length changes its formula:
+             * a boundary curve meets the cell edge phi = p1 or p2, the
+             * curves meet each other, or a condition starts to bind.
+             * Between these points the integrand is smooth. */
+            double br[32];
+            int nb = 0;
+            br[nb++] = t1;
+            br[nb++] = t2;
+            double ps[2] = {ctx.p1, ctx.p2};
+            for (int e = 0; e < 2; ++e) {
+                double sp = fabs(sin(ps[e])), cpv = cos(ps[e]);
+                if (sp > 0.0 && ctx.sc / sp <= 1.0) {
+                    double t = asin(ctx.sc / sp);
+                    br[nb++] = t; br[nb++] = ORC_PI - t;
+                }
+                if (!ctx.tau_inf && cpv > 0.0) {
+                    double t = atan2(ctx.tau, cpv);
+                    br[nb++] = t; br[nb++] = ORC_PI - t;
+                }
+            }
+            { double t = asin(ctx.sc); br[nb++] = t; br[nb++] = ORC_PI - t; }
+            if (!ctx.tau_inf) {
+                double t = atan(ctx.tau);
+                br[nb++] = t; br[nb++] = ORC_PI - t;
+                double cc = sqrt((1.0 - ctx.sc * ctx.sc) / (1.0 + ctx.tau * ctx.tau));
+                br[nb++] = acos(cc); br[nb++] = acos(-cc);
+            }
+            br[nb++] = 0.5 * ORC_PI;
+            /* sort (insertion) and integrate piece by piece inside [t1, t2] */
+            for (int u = 1; u < nb; ++u)
+                for (int v = u; v > 0 && br[v - 1] > br[v]; --v) {
+                    double tmp = br[v]; br[v] = br[v - 1]; br[v - 1] = tmp;
+                }
+            double cov = 0.0;
+            for (int u = 0; u + 1 < nb; ++u) {
+                double a = br[u] < t1 ? t1 : br[u], b = br[u + 1] > t2 ? t2 : br[u + 1];
+                if (b > a) cov += adapt_int(ovl_integrand, &ctx, a, b, 1e-18 * area);
+            }
             w[j * g->n_phi + k] = 1.0 - 0.5 * (cov / area);
         }
     }

@@ -1,0 +1,198 @@
+"""MI355X multipole gravity solver for multi-patch spherical grids.
+
+Thin ctypes binding of the C ABI in ``include/mpg.h`` (built as
+``libmpg.so``).  Every step of a solve runs in the library's HIP kernels;
+this module only marshals arguments.  PyTorch supplies device memory and
+the current HIP stream.  There is no CPU fallback: importing the binding
+without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpg.so")
+
+MPG_OK, MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE, MPG_EUNSUPPORTED = 0, -1, -2, -3, -4
+MPG_FP64, MPG_SPLIT_BF16 = 0, 1
+MPG_F64, MPG_F32 = 0, 1
+
+PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16}
+
+# Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
+EXPORTS = ("mpg_plan", "mpg_moments", "mpg_potential", "mpg_potential_batch", "mpg_tables",
+           "mpg_plan_info", "mpg_sync", "mpg_destroy", "mpg_last_error")
+
+
+class MpgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mpg error {code}: {msg}")
+        self.code = code
+
+
+class _Grid(C.Structure):
+    _fields_ = [
+        ("n_patches", C.c_int), ("n_r", C.c_int), ("n_theta", C.c_int), ("n_phi", C.c_int),
+        ("r_edges", C.POINTER(C.c_double)),
+        ("theta0", C.c_double), ("phi0", C.c_double), ("dtheta", C.c_double), ("dphi", C.c_double),
+        ("euler", C.POINTER(C.c_double)),
+        ("overlap_w", C.POINTER(C.c_double)),
+        ("G", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmpg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1903_08475_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.mpg_plan.argtypes = [C.POINTER(_Grid), C.c_int, C.c_int, C.c_int, vp, C.POINTER(vp)]
+        L.mpg_moments.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp]
+        L.mpg_potential.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int]
+        L.mpg_potential_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
+        L.mpg_tables.argtypes = [vp, vp, vp, vp]
+        L.mpg_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]
+        L.mpg_sync.argtypes = [vp]
+        L.mpg_destroy.argtypes = [vp]
+        L.mpg_destroy.restype = None
+        L.mpg_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != MPG_OK:
+        raise MpgError(rc, lib().mpg_last_error().decode())
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return MPG_F64
+    if t.dtype == torch.float32:
+        return MPG_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A solver plan for one grid and lmax (tables built once on the device).
+
+    grid: any object with n_patches, n_r, n_theta, n_phi, r_edges, theta0,
+    phi0, dtheta, dphi, euler, G (e.g. ``workloads.Grid``).
+    """
+
+    def __init__(self, grid, lmax=None, precision="fp64", max_fields=1, stream=None, overlap_w=None):
+        import torch
+        self.lmax = grid.lmax if lmax is None else lmax
+        self.grid = grid
+        self.precision = precision
+        self.max_fields = max_fields
+        self.shape = (grid.n_patches, grid.n_r, grid.n_theta, grid.n_phi)
+        self.n_lm = (self.lmax + 1) ** 2
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._r = np.ascontiguousarray(grid.r_edges, dtype=np.float64)
+        self._e = np.ascontiguousarray(np.asarray(grid.euler).reshape(-1), dtype=np.float64)
+        self._w = None if overlap_w is None else np.ascontiguousarray(overlap_w, dtype=np.float64)
+        g = _Grid()
+        g.n_patches, g.n_r, g.n_theta, g.n_phi = grid.n_patches, grid.n_r, grid.n_theta, grid.n_phi
+        g.r_edges = self._r.ctypes.data_as(C.POINTER(C.c_double))
+        g.theta0, g.phi0, g.dtheta, g.dphi = grid.theta0, grid.phi0, grid.dtheta, grid.dphi
+        g.euler = self._e.ctypes.data_as(C.POINTER(C.c_double))
+        g.overlap_w = None if self._w is None else self._w.ctypes.data_as(C.POINTER(C.c_double))
+        g.G = grid.G
+        h = C.c_void_p()
+        _check(lib().mpg_plan(C.byref(g), self.lmax, PRECISIONS[precision], max_fields,
+                              _stream_handle(self.stream), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mpg_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _fields(self, rho):
+        if not rho.is_cuda or not rho.is_contiguous():
+            raise ValueError("rho must be a contiguous device tensor")
+        per = int(np.prod(self.shape))
+        if rho.numel() % per or rho.numel() == 0:
+            raise ValueError(f"rho has {rho.numel()} elements, not a multiple of {per}")
+        return rho.numel() // per
+
+    def potential(self, rho, out=None, out_dtype=None):
+        """Phi at every upper cell vertex, same layout as rho."""
+        import torch
+        n = self._fields(rho)
+        if out is None:
+            out = torch.empty(rho.shape, dtype=out_dtype or rho.dtype, device=rho.device)
+        if not out.is_contiguous() or out.numel() != rho.numel():
+            raise ValueError("out must be contiguous with rho's size")
+        _check(lib().mpg_potential(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
+                                   C.c_void_p(out.data_ptr()), _dtype_code(out)))
+        return out
+
+    def moments(self, rho):
+        """(B, M) in the real moment index, float64 [n_fields, n_r, n_lm]."""
+        import torch
+        n = self._fields(rho)
+        B = torch.zeros((n, self.shape[1], self.n_lm), dtype=torch.float64, device=rho.device)
+        M = torch.zeros_like(B)
+        _check(lib().mpg_moments(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
+                                 C.c_void_p(B.data_ptr()), C.c_void_p(M.data_ptr())))
+        return B, M
+
+    def tables(self):
+        """(U, Q, w) as float64 device tensors [n_patches, n_ang, n_lm], [n_ang]."""
+        import torch
+        n_ang = self.shape[2] * self.shape[3]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        U = torch.zeros((self.shape[0], n_ang, self.n_lm), dtype=torch.float64, device=dev)
+        Q = torch.zeros_like(U)
+        w = torch.zeros(n_ang, dtype=torch.float64, device=dev)
+        _check(lib().mpg_tables(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(Q.data_ptr()),
+                                C.c_void_p(w.data_ptr())))
+        self.sync()
+        return U, Q, w
+
+    def sync(self):
+        _check(lib().mpg_sync(self._h))
+
+
+def potential_batch(plans, rhos, phis):
+    """Solve independent fields with their own plans in one call."""
+    n = len(plans)
+    if not (len(rhos) == len(phis) == n):
+        raise ValueError("plans, rhos and phis differ in length")
+    dt = _dtype_code(rhos[0]) if n else MPG_F64
+    for r, p in zip(rhos, phis):
+        if _dtype_code(r) != dt or _dtype_code(p) != dt:
+            raise TypeError("all rho and phi must share one dtype")
+    H = (C.c_void_p * n)(*[p.handle for p in plans])
+    R = (C.c_void_p * n)(*[r.data_ptr() for r in rhos])
+    P = (C.c_void_p * n)(*[p.data_ptr() for p in phis])
+    _check(lib().mpg_potential_batch(n, H, R, P, dt))
+    return phis

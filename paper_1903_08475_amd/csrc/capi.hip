@@ -1,0 +1,298 @@
+// C ABI of the library (declared in include/mpg.h): plan creation with
+// validation, the solve entry points and error reporting.  Every entry point
+// catches its own failures and returns a status; nothing throws across the
+// ABI.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mpg_internal.h"
+
+namespace mpg {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+namespace {
+
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    set_error(std::string(where) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? MPG_ENOMEM : MPG_EDEVICE;
+}
+
+void rot(const double *e, double R[9]) {
+    double ca = cos(e[0]), sa = sin(e[0]), cb = cos(e[1]), sb = sin(e[1]), cg = cos(e[2]), sg = sin(e[2]);
+    R[0] = ca * cb * cg - sa * sg;  R[1] = sa * cb * cg + ca * sg;  R[2] = -sb * cg;
+    R[3] = -ca * cb * sg - sa * cg; R[4] = -sa * cb * sg + ca * cg; R[5] = sb * sg;
+    R[6] = ca * sb;                 R[7] = sa * sb;                 R[8] = cb;
+}
+
+int roundup(int x, int m) { return (x + m - 1) / m * m; }
+
+void free_plan(mpg_plan_s *p) {
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    void *bufs[] = {p->col_src, p->col_l, p->Ut,   p->Qt,    p->coef, p->w,    p->Ut_hi, p->Ut_lo, p->Qt_hi,
+                    p->Qt_lo,   p->Bpart, p->Bred, p->M,     p->M_hi, p->M_lo, p->M_mid, p->Qt_mid};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+// K splits of the moment contraction for n_fields fields: enough blocks to
+// cover the chip, never more than the plan's work space holds.
+int choose_splitk(const Plan &p, int n_fields) {
+    int col_tiles = p.fold ? (p.ne_p + 63) / 64 + (p.no_p + 63) / 64 : (p.np + 63) / 64;
+    int row_tiles = (n_fields * p.n_r + 63) / 64;
+    int tiles = col_tiles * row_tiles;
+    int s = (1024 + tiles - 1) / tiles;
+    if (s > p.splitk) s = p.splitk;
+    if (s < 1) s = 1;
+    return s;
+}
+
+}  // namespace
+}  // namespace mpg
+
+using namespace mpg;
+
+extern "C" {
+
+const char *mpg_last_error(void) { return g_err.c_str(); }
+
+int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *stream, mpg_plan_t *out) {
+    if (!out) return fail(MPG_EINVAL, "mpg_plan: out is NULL");
+    *out = nullptr;
+    if (!g) return fail(MPG_EINVAL, "mpg_plan: grid is NULL");
+    if (g->n_patches != 1 && g->n_patches != 2) return fail(MPG_EUNSUPPORTED, "mpg_plan: n_patches must be 1 or 2");
+    if (g->n_r < 1 || g->n_theta < 1 || g->n_phi < 1) return fail(MPG_EINVAL, "mpg_plan: empty grid");
+    if ((long long)g->n_theta * g->n_phi > (1 << 26)) return fail(MPG_EINVAL, "mpg_plan: too many angular cells");
+    if (!g->r_edges || !g->euler) return fail(MPG_EINVAL, "mpg_plan: r_edges/euler is NULL");
+    if (!(g->r_edges[0] >= 0.0)) return fail(MPG_EINVAL, "mpg_plan: r_edges[0] < 0");
+    for (int i = 0; i < g->n_r; ++i)
+        if (!(g->r_edges[i + 1] > g->r_edges[i]) || !std::isfinite(g->r_edges[i + 1]))
+            return fail(MPG_EINVAL, "mpg_plan: r_edges must increase strictly");
+    if (!(g->dtheta > 0.0) || !(g->dphi > 0.0)) return fail(MPG_EINVAL, "mpg_plan: non-positive spacing");
+    if (g->theta0 < -1e-12 || g->theta0 + g->n_theta * g->dtheta > M_PI + 1e-12)
+        return fail(MPG_EINVAL, "mpg_plan: colatitudes outside [0, pi]");
+    if (lmax < 0 || lmax > 64) return fail(MPG_EINVAL, "mpg_plan: lmax outside [0, 64]");
+    if (precision != MPG_FP64 && precision != MPG_SPLIT_BF16) return fail(MPG_EINVAL, "mpg_plan: bad precision");
+    if (max_fields < 1 || max_fields > 4096) return fail(MPG_EINVAL, "mpg_plan: max_fields outside [1, 4096]");
+    for (int i = 0; i < 3 * g->n_patches; ++i)
+        if (!std::isfinite(g->euler[i])) return fail(MPG_EINVAL, "mpg_plan: non-finite Euler angle");
+
+    mpg_plan_s *p = new (std::nothrow) mpg_plan_s();
+    if (!p) return fail(MPG_ENOMEM, "mpg_plan: host allocation");
+    p->n_patches = g->n_patches;
+    p->n_r = g->n_r;
+    p->n_theta = g->n_theta;
+    p->n_phi = g->n_phi;
+    p->n_ang = g->n_theta * g->n_phi;
+    p->theta0 = g->theta0;
+    p->phi0 = g->phi0;
+    p->dtheta = g->dtheta;
+    p->dphi = g->dphi;
+    p->lmax = lmax;
+    p->n_lm = (lmax + 1) * (lmax + 1);
+    p->precision = precision;
+    p->max_fields = max_fields;
+    p->G = g->G;
+    p->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&p->device);
+
+    if (g->n_patches == 2) {
+        // fold: patch 1 is patch 0 turned by pi about the common z axis
+        double R0[9], R1[9];
+        rot(g->euler, R0);
+        rot(g->euler + 3, R1);
+        const double D[3] = {-1.0, -1.0, 1.0};
+        double dev = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) dev = fmax(dev, fabs(R1[3 * i + j] - D[i] * R0[3 * i + j]));
+        if (dev > 1e-12) {
+            free_plan(p);
+            return fail(MPG_EUNSUPPORTED, "mpg_plan: two patches must differ by a rotation of pi about z");
+        }
+        p->fold = true;
+        if (!g->overlap_w) {
+            // overlap weights need the Yin<->Yang relation R0^T R1 = P and
+            // extents symmetric about the patch centre
+            const double P[9] = {-1, 0, 0, 0, 0, 1, 0, 1, 0};
+            double d2 = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    double s = 0.0;
+                    for (int k = 0; k < 3; ++k) s += R0[3 * k + i] * R1[3 * k + j];
+                    d2 = fmax(d2, fabs(s - P[3 * i + j]));
+                }
+            double th_hi = g->theta0 + g->n_theta * g->dtheta, ph_hi = g->phi0 + g->n_phi * g->dphi;
+            bool sym = fabs(g->theta0 + th_hi - M_PI) < 1e-12 && fabs(g->phi0 + ph_hi) < 1e-12 &&
+                       g->theta0 >= 0.0 && g->theta0 < 0.5 * M_PI && ph_hi >= 0.5 * M_PI - 1e-15 &&
+                       ph_hi <= M_PI + 1e-12;
+            if (d2 > 1e-12 || !sym) {
+                free_plan(p);
+                return fail(MPG_EUNSUPPORTED,
+                            "mpg_plan: overlap weights are computed only for symmetric Yin-Yang extents; pass "
+                            "overlap_w");
+            }
+            p->ovl_sc = cos(g->theta0);
+            p->ovl_kap_inf = ph_hi >= M_PI - 1e-15;
+            p->ovl_kap = p->ovl_kap_inf ? 0.0 : 1.0 / tan(M_PI - ph_hi);
+        }
+    }
+
+    // column layout
+    if (p->fold) {
+        int ne = 0;
+        for (int l = 0; l <= lmax; ++l)
+            for (int m = 0; m <= l; m += 2) ne += (m == 0 ? 1 : 2);
+        p->n_e = ne;
+        p->n_o = p->n_lm - ne;
+        p->ne_p = roundup(p->n_e, kColPad);
+        p->no_p = roundup(p->n_o, kColPad);
+    } else {
+        p->n_e = p->n_lm;
+        p->n_o = 0;
+        p->ne_p = roundup(p->n_lm, kColPad);
+        p->no_p = 0;
+    }
+    p->np = p->ne_p + p->no_p;
+    p->np_alloc = p->np + kColSlack;
+    p->n_angp = roundup(p->n_ang, kAngPad);
+    p->l_tier = lmax < 2 ? lmax : 2;
+
+    // work space
+    {
+        int col_tiles = p->fold ? (p->ne_p + 63) / 64 + (p->no_p + 63) / 64 : (p->np + 63) / 64;
+        int tiles = col_tiles * ((p->n_r + 63) / 64);
+        int s = (1024 + tiles - 1) / tiles;
+        int kmax = p->n_angp / 64;
+        p->splitk = s < 1 ? 1 : (s > kmax ? kmax : s);
+        if (p->splitk < 1) p->splitk = 1;
+    }
+    size_t rows = (size_t)p->rows_alloc();
+    hipError_t e;
+    if ((e = hipMalloc(&p->Bpart, sizeof(double) * p->splitk * rows * p->np)) != hipSuccess ||
+        (e = hipMalloc(&p->Bred, sizeof(double) * rows * p->np)) != hipSuccess ||
+        (e = hipMalloc(&p->M, sizeof(double) * rows * p->np)) != hipSuccess) {
+        int rc = hip_fail(e, "mpg_plan: work space");
+        free_plan(p);
+        return rc;
+    }
+    if (precision == MPG_SPLIT_BF16) {
+        if ((e = hipMalloc(&p->M_hi, sizeof(bf16) * rows * p->np)) != hipSuccess ||
+            (e = hipMalloc(&p->M_lo, sizeof(bf16) * rows * p->np)) != hipSuccess ||
+            (e = hipMalloc(&p->M_mid, sizeof(bf16) * rows * p->np)) != hipSuccess) {
+            int rc = hip_fail(e, "mpg_plan: split work space");
+            free_plan(p);
+            return rc;
+        }
+    }
+    if ((e = build_tables(*p, g->euler, g->r_edges, g->overlap_w)) != hipSuccess) {
+        int rc = hip_fail(e, "mpg_plan: table build");
+        free_plan(p);
+        return rc;
+    }
+    *out = p;
+    return MPG_OK;
+}
+
+static int check_call(mpg_plan_t p, int n_fields, const void *rho, int dt, const char *who) {
+    if (!p) return fail(MPG_EINVAL, std::string(who) + ": plan is NULL");
+    if (n_fields < 1 || n_fields > p->max_fields)
+        return fail(MPG_EINVAL, std::string(who) + ": n_fields outside [1, max_fields]");
+    if (!rho) return fail(MPG_EINVAL, std::string(who) + ": rho is NULL");
+    if (dt != MPG_F64 && dt != MPG_F32) return fail(MPG_EINVAL, std::string(who) + ": bad dtype");
+    return MPG_OK;
+}
+
+static int run_moments(const Plan *p, int n_fields, const void *rho, int rho_dtype, bool split_out) {
+    hipError_t e;
+    int sk = choose_splitk(*p, n_fields);
+    Plan q = *p;
+    q.splitk = sk;
+    if (p->precision == MPG_SPLIT_BF16)
+        e = gemm1_bf16(q, n_fields, rho, rho_dtype);
+    else
+        e = gemm1_f64(q, n_fields, rho, rho_dtype);
+    if (e != hipSuccess) return hip_fail(e, "moment contraction");
+    if ((e = radial_scan(q, n_fields, split_out)) != hipSuccess) return hip_fail(e, "radial scan");
+    return MPG_OK;
+}
+
+int mpg_moments(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, double *B, double *M) {
+    int rc = check_call(p, n_fields, rho, rho_dtype, "mpg_moments");
+    if (rc) return rc;
+    if ((rc = run_moments(p, n_fields, rho, rho_dtype, false))) return rc;
+    hipError_t e;
+    if (B && (e = unpermute(*p, n_fields, p->Bred, B)) != hipSuccess) return hip_fail(e, "mpg_moments: B");
+    if (M && (e = unpermute(*p, n_fields, p->M, M)) != hipSuccess) return hip_fail(e, "mpg_moments: M");
+    return MPG_OK;
+}
+
+static int solve(const Plan *p, int n_fields, const void *rho, int rho_dtype, void *phi, int phi_dtype) {
+    int rc;
+    bool split = p->precision == MPG_SPLIT_BF16;
+    if ((rc = run_moments(p, n_fields, rho, rho_dtype, split))) return rc;
+    hipError_t e = split ? gemm2_bf16(*p, n_fields, phi, phi_dtype) : gemm2_f64(*p, n_fields, phi, phi_dtype);
+    if (e != hipSuccess) return hip_fail(e, "expansion");
+    return MPG_OK;
+}
+
+int mpg_potential(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, void *phi, int phi_dtype) {
+    int rc = check_call(p, n_fields, rho, rho_dtype, "mpg_potential");
+    if (rc) return rc;
+    if (!phi) return fail(MPG_EINVAL, "mpg_potential: phi is NULL");
+    if (phi_dtype != MPG_F64 && phi_dtype != MPG_F32) return fail(MPG_EINVAL, "mpg_potential: bad phi dtype");
+    return solve(p, n_fields, rho, rho_dtype, phi, phi_dtype);
+}
+
+int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho, void *const *phi, int dtype) {
+    if (n < 0 || (n > 0 && (!plans || !rho || !phi))) return fail(MPG_EINVAL, "mpg_potential_batch: bad arguments");
+    for (int f = 0; f < n; ++f) {
+        if (!plans[f]) return fail(MPG_EINVAL, "mpg_potential_batch: NULL plan");
+        if (plans[f]->precision != plans[0]->precision)
+            return fail(MPG_EINVAL, "mpg_potential_batch: plans differ in precision");
+    }
+    for (int f = 0; f < n; ++f) {
+        if (!rho[f] || !phi[f]) return fail(MPG_EINVAL, "mpg_potential_batch: NULL field");
+        Plan q = *plans[f];
+        q.stream = plans[0]->stream;
+        int rc = solve(&q, 1, rho[f], dtype, phi[f], dtype);
+        if (rc) return rc;
+    }
+    return MPG_OK;
+}
+
+int mpg_tables(mpg_plan_t p, double *U, double *Q, double *w) {
+    if (!p) return fail(MPG_EINVAL, "mpg_tables: plan is NULL");
+    hipError_t e = export_tables(*p, U, Q, w);
+    if (e != hipSuccess) return hip_fail(e, "mpg_tables");
+    return MPG_OK;
+}
+
+int mpg_plan_info(mpg_plan_t p, int *n_lm, long long *field_elems) {
+    if (!p) return fail(MPG_EINVAL, "mpg_plan_info: plan is NULL");
+    if (n_lm) *n_lm = p->n_lm;
+    if (field_elems) *field_elems = (long long)p->n_patches * p->n_r * p->n_ang;
+    return MPG_OK;
+}
+
+int mpg_sync(mpg_plan_t p) {
+    if (!p) return fail(MPG_EINVAL, "mpg_sync: plan is NULL");
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "mpg_sync");
+    return MPG_OK;
+}
+
+void mpg_destroy(mpg_plan_t p) { free_plan(p); }
+
+}  // extern "C"

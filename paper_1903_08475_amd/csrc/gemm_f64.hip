@@ -1,0 +1,257 @@
+// FP64 MFMA contractions of the solve (Sec. 4.3 steps 2 and 5).
+//
+// GEMM1 (moments, Eq. B_CS):  B[row][q] = sum_jk A[row][jk] U[q][jk]
+//   with A = rho_Yin + rho_Yang for even-m columns and rho_Yin - rho_Yang
+//   for odd-m columns under the Yin/Yang fold (U_Yang = (-1)^m U_Yin,
+//   Sec. 4.2), A = rho for one patch.  Split over K (the angular cells); the
+//   partial sums go to a work array that the radial scan reduces in a fixed
+//   order.
+// GEMM2 (expansion, Eq. gravpotmult):  Phi[row][jk] = sum_q M[row][q] Q[jk][q]
+//   accumulated separately over even- and odd-m columns, written as
+//   Phi_Yin = E + O and Phi_Yang = E - O under the fold.
+//
+// Rows are (field, shell) pairs; tiles are 64x64x16 on 256 threads (four
+// waves of 32x32, v_mfma_f64_16x16x4f64), with the next K slab loaded into
+// registers while the current one is multiplied from LDS.
+#include "mpg_internal.h"
+
+namespace mpg {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, LDP = BM + 2;
+
+// Lane layout of v_mfma_f64_16x16x4f64 on gfx950 (measured): lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; result register r of lane l is
+// D[l/16 + 4r][l%16].
+__device__ inline int out_row(int l, int r) { return (l >> 4) + 4 * r; }
+__device__ inline int out_col(int l, int r) { return l & 15; }
+
+template <typename T>
+__device__ inline double ld(const T *p) { return (double)*p; }
+
+// one 64x16 slab of a K-contiguous operand: thread t covers row t/4,
+// k = 4*(t%4) .. +3
+struct Slab {
+    double v[4];
+};
+
+template <typename T, bool FOLD>
+__device__ inline void load_rho(Slab &s, const T *r0, const T *r1, int k, int n_ang, bool row_ok, bool odd) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double a = 0.0;
+        if (row_ok && k + q < n_ang) {
+            a = ld(r0 + k + q);
+            if (FOLD) {
+                double b = ld(r1 + k + q);
+                a = odd ? a - b : a + b;
+            }
+        }
+        s.v[q] = a;
+    }
+}
+
+__device__ inline void load_rowk(Slab &s, const double *row, int k, bool ok) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s.v[q] = ok ? row[k + q] : 0.0;
+}
+
+__device__ inline void store_slab(double (*S)[LDP], const Slab &s, int lr, int lk) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) S[lk + q][lr] = s.v[q];
+}
+
+__device__ inline void mma_slab(const double (*As)[LDP], const double (*Bs)[LDP], int wm, int wn, int lane,
+                                v4d (&acc)[2][2]) {
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[kk * 4 + (lane >> 4)][wm + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[kk * 4 + (lane >> 4)][wn + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// grid: x = column tile (E tiles then O tiles), y = row tile, z = K split
+template <typename T, bool FOLD>
+__global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int rows, int n_r, int n_ang,
+                                               const double *__restrict__ Ut, int n_angp, int np, int ne_p,
+                                               int tiles_e, int kchunk, double *__restrict__ Bpart) {
+    __shared__ double As[BK][LDP];
+    __shared__ double Bs[BK][LDP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int tn = blockIdx.x;
+    const bool odd = FOLD && tn >= tiles_e;
+    const int c0 = odd ? ne_p + (tn - tiles_e) * BN : tn * BN;
+    const int cend = odd ? np : (FOLD ? ne_p : np);
+    const int m0 = blockIdx.y * BM;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(n_angp, kbeg + kchunk);
+
+    const int lr = t >> 2, lk = (t & 3) * 4;
+    const int row = m0 + lr;
+    const bool row_ok = row < rows;
+    const int f = row_ok ? row / n_r : 0, i = row_ok ? row - f * n_r : 0;
+    const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
+    const T *r0 = rho + f * fld + (size_t)i * n_ang;
+    const T *r1 = r0 + (size_t)n_r * n_ang;
+    const double *urow = Ut + (size_t)(c0 + lr) * n_angp;
+
+    v4d acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+    Slab sa, sb;
+    if (kbeg < kend) {
+        load_rho<T, FOLD>(sa, r0, r1, kbeg + lk, n_ang, row_ok, odd);
+        load_rowk(sb, urow, kbeg + lk, true);
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        __syncthreads();
+        store_slab(As, sa, lr, lk);
+        store_slab(Bs, sb, lr, lk);
+        __syncthreads();
+        if (k0 + BK < kend) {
+            load_rho<T, FOLD>(sa, r0, r1, k0 + BK + lk, n_ang, row_ok, odd);
+            load_rowk(sb, urow, k0 + BK + lk, true);
+        }
+        mma_slab(As, Bs, wm, wn, lane, acc);
+    }
+    double *out = Bpart + (size_t)blockIdx.z * rows * np;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int rr = m0 + wm + a * 16 + out_row(lane, r);
+                int cc = c0 + wn + b * 16 + out_col(lane, r);
+                if (rr < rows && cc < cend) out[(size_t)rr * np + cc] = acc[a][b][r];
+            }
+}
+
+// grid: x = row tile, y = angular tile
+template <typename T, bool FOLD>
+__global__ __launch_bounds__(256) void k_gemm2(const double *__restrict__ M, int rows, int np, int ne_p,
+                                               const double *__restrict__ Qt, int n_ang, int n_r,
+                                               T *__restrict__ phi) {
+    __shared__ double As[BK][LDP];
+    __shared__ double Bs[BK][LDP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int lr = t >> 2, lk = (t & 3) * 4;
+    const bool row_ok = m0 + lr < rows;
+    const double *arow = M + (size_t)(row_ok ? m0 + lr : 0) * np;
+    const double *brow = Qt + (size_t)(n0 + lr) * np;
+
+    v4d acc[2][2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[p][a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+    const int nblk = FOLD ? 2 : 1;
+#pragma unroll
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int kb = blk ? ne_p : 0, ke = (FOLD && !blk) ? ne_p : np;
+        Slab sa, sb;
+        if (kb < ke) {
+            load_rowk(sa, arow, kb + lk, row_ok);
+            load_rowk(sb, brow, kb + lk, true);
+        }
+        for (int k0 = kb; k0 < ke; k0 += BK) {
+            __syncthreads();
+            store_slab(As, sa, lr, lk);
+            store_slab(Bs, sb, lr, lk);
+            __syncthreads();
+            if (k0 + BK < ke) {
+                load_rowk(sa, arow, k0 + BK + lk, row_ok);
+                load_rowk(sb, brow, k0 + BK + lk, true);
+            }
+            mma_slab(As, Bs, wm, wn, lane, acc[blk]);
+        }
+    }
+    const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int rr = m0 + wm + a * 16 + out_row(lane, r);
+                int jk = n0 + wn + b * 16 + out_col(lane, r);
+                if (rr >= rows || jk >= n_ang) continue;
+                int f = rr / n_r, i = rr - f * n_r;
+                T *o = phi + f * fld + (size_t)i * n_ang + jk;
+                double e = acc[0][a][b][r];
+                if (FOLD) {
+                    double od = acc[1][a][b][r];
+                    o[0] = (T)(e + od);
+                    o[(size_t)n_r * n_ang] = (T)(e - od);
+                } else {
+                    o[0] = (T)e;
+                }
+            }
+}
+
+}  // namespace
+
+hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
+    const int rows = n_fields * p.n_r;
+    const int te = p.fold ? (p.ne_p + BN - 1) / BN : (p.np + BN - 1) / BN;
+    const int to = p.fold ? (p.no_p + BN - 1) / BN : 0;
+    const int kchunk = ((p.n_angp / p.splitk + BK - 1) / BK) * BK;
+    dim3 grid(te + to, (rows + BM - 1) / BM, p.splitk);
+    if (rho_dtype == MPG_F64) {
+        if (p.fold)
+            hipLaunchKernelGGL((k_gemm1<double, true>), grid, dim3(256), 0, p.stream, (const double *)rho, rows,
+                               p.n_r, p.n_ang, p.Ut, p.n_angp, p.np, p.ne_p, te, kchunk, p.Bpart);
+        else
+            hipLaunchKernelGGL((k_gemm1<double, false>), grid, dim3(256), 0, p.stream, (const double *)rho, rows,
+                               p.n_r, p.n_ang, p.Ut, p.n_angp, p.np, p.ne_p, te, kchunk, p.Bpart);
+    } else {
+        if (p.fold)
+            hipLaunchKernelGGL((k_gemm1<float, true>), grid, dim3(256), 0, p.stream, (const float *)rho, rows,
+                               p.n_r, p.n_ang, p.Ut, p.n_angp, p.np, p.ne_p, te, kchunk, p.Bpart);
+        else
+            hipLaunchKernelGGL((k_gemm1<float, false>), grid, dim3(256), 0, p.stream, (const float *)rho, rows,
+                               p.n_r, p.n_ang, p.Ut, p.n_angp, p.np, p.ne_p, te, kchunk, p.Bpart);
+    }
+    return hipGetLastError();
+}
+
+hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype) {
+    const int rows = n_fields * p.n_r;
+    dim3 grid((rows + BM - 1) / BM, p.n_angp / BN);
+    if (phi_dtype == MPG_F64) {
+        if (p.fold)
+            hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(256), 0, p.stream, p.M, rows, p.np, p.ne_p, p.Qt,
+                               p.n_ang, p.n_r, (double *)phi);
+        else
+            hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(256), 0, p.stream, p.M, rows, p.np, p.ne_p, p.Qt,
+                               p.n_ang, p.n_r, (double *)phi);
+    } else {
+        if (p.fold)
+            hipLaunchKernelGGL((k_gemm2<float, true>), grid, dim3(256), 0, p.stream, p.M, rows, p.np, p.ne_p, p.Qt,
+                               p.n_ang, p.n_r, (float *)phi);
+        else
+            hipLaunchKernelGGL((k_gemm2<float, false>), grid, dim3(256), 0, p.stream, p.M, rows, p.np, p.ne_p, p.Qt,
+                               p.n_ang, p.n_r, (float *)phi);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mpg

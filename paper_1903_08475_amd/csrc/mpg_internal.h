@@ -1,0 +1,98 @@
+// Internal declarations of the MI355X multipole gravity library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/mpg.h"
+
+namespace mpg {
+
+typedef __bf16 bf16;
+
+// Thread-local error text behind mpg_last_error().
+void set_error(const std::string &msg);
+
+// Tile constants shared by the plan layout and the kernels.
+constexpr int kColPad = 32;    // each m-parity column block is padded to this
+constexpr int kColSlack = 128; // zero rows after the last column block
+constexpr int kAngPad = 128;   // angular dimension padded to this
+
+// Table layout of a plan (all device arrays are owned by the plan).
+//
+// Columns are the real moment indices permuted so that even-m columns come
+// first (block E, padded to ne_p) and odd-m columns second (block O, padded
+// to no_p); np = ne_p + no_p.  Without the Yin/Yang fold there is a single
+// block holding every column (no_p = 0).
+struct Plan {
+    // grid
+    int n_patches = 0, n_r = 0, n_theta = 0, n_phi = 0, n_ang = 0;
+    double theta0 = 0, phi0 = 0, dtheta = 0, dphi = 0;
+    int lmax = 0, n_lm = 0, precision = MPG_FP64, max_fields = 1;
+    // overlap geometry of a symmetric Yin-Yang pair (used when no w is given)
+    double ovl_sc = 0, ovl_kap = 0;
+    int ovl_kap_inf = 0;
+    bool fold = false;
+    double G = 1.0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // column layout
+    int n_e = 0, n_o = 0, ne_p = 0, no_p = 0, np = 0, np_alloc = 0;
+    int n_angp = 0;            // n_ang padded to kAngPad
+
+    int *col_src = nullptr;    // [np_alloc] real index of a permuted column, -1 = pad
+    int *col_l = nullptr;      // [np_alloc] degree, -1 = pad
+    double *Ut = nullptr;      // [np_alloc][n_angp]  U of patch 0, K(angular)-contiguous
+    double *Qt = nullptr;      // [n_angp][np]        Q of patch 0, K(lm)-contiguous
+    double *coef = nullptr;    // [n_r][lmax+1][4] radial recurrence coefficients
+    double *w = nullptr;       // [n_ang] overlap weights
+    bf16 *Ut_hi = nullptr, *Ut_lo = nullptr;   // split copies of Ut
+    bf16 *Qt_hi = nullptr, *Qt_lo = nullptr;   // split copies of Qt
+
+    // work space (sized for max_fields)
+    int splitk = 1;
+    double *Bpart = nullptr;   // [splitk][rows][np]
+    double *Bred = nullptr;    // [rows][np]
+    double *M = nullptr;       // [rows][np]
+    bf16 *M_hi = nullptr, *M_lo = nullptr; // [rows][np]
+
+    // split-BF16 tier: columns of degree <= l_tier use an extra split term
+    int l_tier = 0;
+    int ntier_e = 0, ntier_o = 0;  // columns of the tier at the start of each block
+    bf16 *M_mid = nullptr;     // [rows][np] third split piece (tier columns only)
+    bf16 *Qt_mid = nullptr;    // [n_angp][np]
+
+    int rows_alloc() const { return max_fields * n_r; }
+};
+
+// ---- kernels launchers (each returns hipError_t of the launch) ----------
+
+// table build (tables.hip)
+hipError_t build_tables(Plan &p, const double *host_euler, const double *host_r_edges,
+                        const double *host_w);
+
+// copy the FP64 tables out in the real index (tables.hip)
+hipError_t export_tables(const Plan &p, double *U, double *Q, double *w);
+
+// FP64 path (gemm_f64.hip)
+hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype);
+hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype);
+
+// radial scans (scan.hip): Bpart -> Bred, M (and the split copies of M)
+hipError_t radial_scan(const Plan &p, int n_fields, bool split_out);
+
+// split-BF16 path (gemm_bf16.hip)
+hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
+hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype);
+
+// permuted [rows][np] -> real index [rows][n_lm]
+hipError_t unpermute(const Plan &p, int n_fields, const double *src, double *dst);
+
+}  // namespace mpg
+
+// The opaque handle of the C ABI is the plan itself.
+struct mpg_plan_s : mpg::Plan {};

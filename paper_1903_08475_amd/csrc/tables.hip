@@ -1,0 +1,577 @@
+// FP64 table build of a plan (Sec. 4.3 step 1): Wigner d at pi/2 by the
+// recursions of Sec. 3, d(beta) by their Fourier sum, the angular integrals
+// T, C, S (Eqs. T_lm, C_k^m, S_k^m), the normalisation factors
+// (Eqs. N_CC..N_SC), the angular weights U (Eqs. U_C/U_S), the prefactors Q
+// (Eqs. Q_C/Q_S), the overlap weights w (Sec. 4.2) and the radial
+// recurrence coefficients of Eq. M_C.  Everything runs on the device in
+// FP64; the host only validates, lays out columns and launches.
+#include <cmath>
+#include <vector>
+
+#include "mpg_internal.h"
+
+namespace mpg {
+namespace {
+
+__host__ __device__ inline int off_dh(int l) { return (l - 1) * l * (2 * l - 1) / 3 + 3 * l * (l - 1) / 2 + l; }
+__host__ __device__ inline int off_sq(int l) { return l * (l + 1) * (2 * l + 1) / 6; }
+__host__ __device__ inline int off_tri(int l) { return l * (l + 1) / 2; }
+
+__device__ inline int tri_row(int t) {
+    int l = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (off_tri(l + 1) <= t) ++l;
+    while (off_tri(l) > t) --l;
+    return l;
+}
+
+// d^l_{m'm}(pi/2) for -l <= m' <= l, 0 <= m <= l, stored at
+// dh[off_dh(l) + (m'+l)(l+1) + m].  Apex d^0_00 = 1; the diagonal seeds
+// d^l_{l0} = -sqrt((2l-1)/(2l)) d^{l-1}_{l-1,0} and
+// d^l_{lm} = +sqrt(l(2l-1)/(2(l+m)(l+m-1))) d^{l-1}_{l-1,m-1} (m >= 1; the
+// sign printed with this recursion in Sec. 3 gives the wrong sign of
+// d^1_11(pi/2) = 1/2 and is not used); the three-term recursion runs down
+// in m' only to m' = 0, and m' < 0 is filled from
+// d_{-m',m}(pi/2) = (-1)^{l+m} d_{m'm}(pi/2) (the second symmetry of
+// Sec. 3 at beta = pi/2), since continuing the recursion below 0 loses
+// all accuracy at high l.
+__global__ void k_dhalf(int L, double *dh) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= off_tri(L + 1)) return;
+    int l = tri_row(t), m = t - off_tri(l);
+    double v = 1.0;
+    for (int lp = 1; lp <= l - m; ++lp) v *= -sqrt((2.0 * lp - 1.0) / (2.0 * lp));
+    for (int k = 1; k <= m; ++k) {
+        int lp = l - m + k;
+        v *= sqrt(lp * (2.0 * lp - 1.0) / (2.0 * (lp + k) * (lp + k - 1.0)));
+    }
+    double *d = dh + off_dh(l);
+    const int W = l + 1;
+    d[(2 * l) * W + m] = v;
+    double n1 = v, n2 = 0.0;
+    for (int j = l - 1; j >= 0; --j) {
+        double q = (double)(l - j) * (l + j + 1);
+        double val = 2.0 * m / sqrt(q) * n1 - sqrt((double)(l - j - 1) * (l + j + 2) / q) * n2;
+        d[(j + l) * W + m] = val;
+        n2 = n1;
+        n1 = val;
+    }
+    double sgn = ((l + m) & 1) ? -1.0 : 1.0;
+    for (int j = 1; j <= l; ++j) d[(l - j) * W + m] = sgn * d[(l + j) * W + m];
+}
+
+// Re[i^n (x + i y)]
+__device__ inline double re_ipow(int n, double x, double y) {
+    n &= 3;
+    return n == 0 ? x : n == 1 ? -y : n == 2 ? -x : y;
+}
+
+// d^l_{m'm}(beta) = i^{m-m'} sum_u d_{u m'}(pi/2) d_{u m}(pi/2) e^{i u beta}
+// for 0 <= m', m <= l at two angles; db[b][off_sq(l) + m'(l+1) + m].
+__global__ void k_dbeta(int L, const double *dh, double beta0, double beta1, double *db) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int per = off_sq(L + 1);
+    if (t >= 2 * per) return;
+    int b = t / per, r = t - b * per;
+    int l = 0;
+    while (off_sq(l + 1) <= r) ++l;
+    int rr = r - off_sq(l), mp = rr / (l + 1), m = rr - mp * (l + 1);
+    double beta = b ? beta1 : beta0;
+    const double *d = dh + off_dh(l);
+    const int W = l + 1;
+    double x = 0.0, y = 0.0;
+    for (int u = -l; u <= l; ++u) {
+        double p = d[(u + l) * W + mp] * d[(u + l) * W + m];
+        double s, c;
+        sincos(u * beta, &s, &c);
+        x += p * c;
+        y += p * s;
+    }
+    db[b * per + r] = re_ipow(m - mp, x, y);
+}
+
+// Bracketed parts of Eqs. N_CC..N_SC (without 2/delta_m, mu_m and the
+// factor s_lu, which the T table carries): N4[(off_sq(l) + m(l+1) + u)*4 + c]
+// with c = CC, CS, SS, SC.
+__global__ void k_ncoef(int L, const double *db, double alpha, double gamma, double *N4) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int per = off_sq(L + 1);
+    if (t >= per) return;
+    int l = 0;
+    while (off_sq(l + 1) <= t) ++l;
+    int rr = t - off_sq(l), m = rr / (l + 1), u = rr - m * (l + 1);
+    double d0 = db[off_sq(l) + u * (l + 1) + m];        // d_{um}(beta)
+    double d1 = db[per + off_sq(l) + u * (l + 1) + m];  // d_{um}(pi - beta)
+    double mu = u > 0 ? 1.0 : 0.0;
+    double sg = ((l + m + u) & 1) ? -1.0 : 1.0;
+    double sp, cp, sm, cm;
+    sincos(m * gamma + u * alpha, &sp, &cp);
+    sincos(m * gamma - u * alpha, &sm, &cm);
+    double *o = N4 + 4 * (size_t)t;
+    o[0] = cp * d0 + mu * sg * cm * d1;
+    o[1] = sp * d0 - mu * sg * sm * d1;
+    o[2] = cp * d0 - mu * sg * cm * d1;
+    o[3] = sp * d0 + mu * sg * sm * d1;
+}
+
+// s_lu T_j^{lu} = int_{theta_j^-}^{theta_j^+} sin t d^l_{u0}(t) dt, with
+// d_{u0}(t) = s_lu P_l^u(cos t) written as its Fourier sum; each
+// int sin t e^{ivt} dt is closed form.  Tt[j][off_tri(l) + u].
+__global__ void k_ttilde(int L, const double *dh, int n_theta, double theta0, double dtheta, double *Tt) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int per = off_tri(L + 1);
+    if (t >= n_theta * per) return;
+    int j = t / per, r = t - j * per;
+    int l = tri_row(r), u = r - off_tri(l);
+    double h = 0.5 * dtheta, tm = theta0 + (j + 0.5) * dtheta;
+    const double *d = dh + off_dh(l);
+    const int W = l + 1;
+    double sx = 0.0, sy = 0.0;
+    for (int v = -l; v <= l; ++v) {
+        // E(k) = int e^{ikt} dt = e^{ik tm} 2 sin(kh)/k ; J = (E(v+1)-E(v-1))/(2i)
+        double er[2], ei[2];
+        for (int q = 0; q < 2; ++q) {
+            int k = q ? v - 1 : v + 1;
+            double amp = (k == 0) ? 2.0 * h : 2.0 * sin(k * h) / k;
+            double s, c;
+            sincos(k * tm, &s, &c);
+            er[q] = amp * c;
+            ei[q] = amp * s;
+        }
+        double jr = 0.5 * (ei[0] - ei[1]), ji = -0.5 * (er[0] - er[1]);
+        double p = d[(v + l) * W + u] * d[(v + l) * W + 0];
+        sx += p * jr;
+        sy += p * ji;
+    }
+    Tt[t] = re_ipow(-u, sx, sy);
+}
+
+// C_k^u and S_k^u (Eqs. C_k^m, S_k^m): CS[(k(L+1)+u)*2 + {0,1}]
+__global__ void k_cs(int L, int n_phi, double phi0, double dphi, double *CS) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_phi * (L + 1)) return;
+    int k = t / (L + 1), u = t - k * (L + 1);
+    double h = 0.5 * dphi, pm = phi0 + (k + 0.5) * dphi;
+    double c = dphi, s = 0.0;
+    if (u > 0) {
+        double a = 2.0 * sin(u * h) / u, sn, cs;
+        sincos(u * pm, &sn, &cs);
+        c = a * cs;
+        s = a * sn;
+    }
+    CS[2 * t] = c;
+    CS[2 * t + 1] = s;
+}
+
+__device__ inline void decode_col(int src, int &l, int &m, int &is_s) {
+    l = (int)sqrt((double)src);
+    while ((l + 1) * (l + 1) <= src) ++l;
+    while (l * l > src) --l;
+    int rem = src - l * l;
+    m = (rem + 1) / 2;
+    is_s = (rem > 0 && (rem & 1) == 0);
+}
+
+// Eqs. U_C/U_S with the prefactor 2/delta_m of Eq. del_m:
+//   U_C = (2/delta_m) w sum_u (N_CC C_k^u + N_CS S_k^u) s_lu T_j^{lu}
+//   U_S = 2 w sum_u (N_SS S_k^u - N_SC C_k^u) s_lu T_j^{lu}   (m >= 1)
+// (the text prints 2/lambda_{m'm}, which is 2 also for m = 0, m' > 0 and
+// then doubles those terms; 2/delta_m is what the real form of
+// Eq. phispherical requires).  Ut[q][jk], zero on padding.
+__global__ void k_U(int L, int np_alloc, int n_angp, int n_ang, int n_phi, const int *col_src,
+                    const double *Tt, const double *CS, const double *N4, const double *w, double *Ut) {
+    int jk = blockIdx.x * blockDim.x + threadIdx.x;
+    int q = blockIdx.y;
+    if (jk >= n_angp || q >= np_alloc) return;
+    int src = col_src[q];
+    double val = 0.0;
+    if (src >= 0 && jk < n_ang) {
+        int l, m, is_s;
+        decode_col(src, l, m, is_s);
+        int j = jk / n_phi, k = jk - j * n_phi;
+        const double *T = Tt + (size_t)j * off_tri(L + 1) + off_tri(l);
+        const double *cs = CS + (size_t)k * (L + 1) * 2;
+        const double *N = N4 + 4 * (size_t)(off_sq(l) + m * (l + 1));
+        double s = 0.0;
+        for (int u = 0; u <= l; ++u) {
+            double c = cs[2 * u], sn = cs[2 * u + 1];
+            double f = is_s ? (N[4 * u + 2] * sn - N[4 * u + 3] * c) : (N[4 * u + 0] * c + N[4 * u + 1] * sn);
+            s += f * T[u];
+        }
+        val = (m == 0 ? 1.0 : 2.0) * w[jk] * s;
+    }
+    Ut[(size_t)q * n_angp + jk] = val;
+}
+
+struct Rot {
+    double r[9];
+};
+
+// Eqs. Q_C/Q_S at the upper vertex of every cell of patch 0:
+//   Q = -G s_lm P_l^m(cos theta) {cos, sin}(m phi)
+// with (theta, phi) the global angles of x = R xi.  The normalised
+// functions s_lm P_l^m come from the recurrences of the normalised
+// associated Legendre functions (Condon-Shortley phase).  Qt[jk][perm].
+__global__ void k_Q(int L, int np, int n_angp, int n_ang, int n_phi, double theta0, double phi0,
+                    double dtheta, double dphi, Rot R, double G, const int *perm_of, double *Qt) {
+    int jk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (jk >= n_angp) return;
+    double *row = Qt + (size_t)jk * np;
+    if (jk >= n_ang) {
+        for (int q = 0; q < np; ++q) row[q] = 0.0;
+        return;
+    }
+    int j = jk / n_phi, k = jk - j * n_phi;
+    double st, ct, sp, cp;
+    sincos(theta0 + (j + 1) * dtheta, &st, &ct);
+    sincos(phi0 + (k + 1) * dphi, &sp, &cp);
+    double xi = st * cp, et = st * sp, ze = ct;
+    double x = R.r[0] * xi + R.r[1] * et + R.r[2] * ze;
+    double y = R.r[3] * xi + R.r[4] * et + R.r[5] * ze;
+    double z = R.r[6] * xi + R.r[7] * et + R.r[8] * ze;
+    double rho = sqrt(x * x + y * y), rr = sqrt(rho * rho + z * z);
+    double cth = z / rr, sth = rho / rr, ph = atan2(y, x);
+    double pmm = 1.0;
+    for (int m = 0; m <= L; ++m) {
+        if (m > 0) pmm *= -sqrt((2.0 * m - 1.0) / (2.0 * m)) * sth;
+        double sm, cm;
+        sincos(m * ph, &sm, &cm);
+        double p2 = 0.0, p1 = pmm;
+        for (int l = m; l <= L; ++l) {
+            double p;
+            if (l == m) p = pmm;
+            else if (l == m + 1) p = cth * sqrt(2.0 * m + 1.0) * pmm;
+            else p = (cth * (2.0 * l - 1.0) * p1 - sqrt((double)(l - 1) * (l - 1) - (double)m * m) * p2) /
+                     sqrt((double)l * l - (double)m * m);
+            if (l > m) { p2 = p1; p1 = p; }
+            if (m == 0) {
+                row[perm_of[l * l]] = -G * p;
+            } else {
+                row[perm_of[l * l + 2 * m - 1]] = -G * p * cm;
+                row[perm_of[l * l + 2 * m]] = -G * p * sm;
+            }
+        }
+    }
+}
+
+// ---- overlap weights -----------------------------------------------------
+// For a Yin point at local (theta, phi), the other patch's local
+// coordinates are (-xi, zeta, eta) (Eq. caryytransform).  For patches
+// spanning [pi/2-c, pi/2+c] x [-phe, phe] it is covered iff
+//   sin theta |sin phi| <= sc           (sc = cos(pi/2 - c))
+//   sin theta cos phi   <= kap |cos theta|   (kap = cot(pi - phe))
+// At fixed phi the covered colatitudes are [0, X] u [pi - X, pi] with
+// cos X = max(g1(phi), g2(phi)),
+//   g1 = sqrt(max(0, 1 - sc^2/sin^2 phi)),  g2 = max(0, cos phi)/sqrt(cos^2 phi + kap^2).
+// The covered area of a cell is the phi-integral of a piecewise function of
+// cos X, split where its form changes, each piece integrated in closed form:
+//   int g1 dphi = -+ G(cos phi),  G(u) = pi/2 - psi - sc atan2(sc cos psi, sin psi),
+//                                  u = a cos psi, a^2 = 1 - sc^2  (sign: -sin phi)
+//   int g2 dphi = asin(sin phi / sqrt(1 + kap^2)).
+struct OvlGeom {
+    double sc, kap;
+    int kap_inf;
+};
+
+__device__ inline double ovl_g1(double p, double sc) {
+    double s = sin(p);
+    double v = (s == 0.0) ? -1.0 : 1.0 - sc * sc / (s * s);
+    return v > 0.0 ? sqrt(v) : 0.0;
+}
+__device__ inline double ovl_g2(double p, const OvlGeom &o) {
+    if (o.kap_inf) return 0.0;
+    double c = cos(p);
+    return c > 0.0 ? c / sqrt(c * c + o.kap * o.kap) : 0.0;
+}
+__device__ inline double ovl_F1(double p, double sc) {
+    double a = sqrt(1.0 - sc * sc);
+    double u = cos(p) / a;
+    u = u > 1.0 ? 1.0 : (u < -1.0 ? -1.0 : u);
+    double psi = acos(u);
+    double G = 0.5 * M_PI - psi - sc * atan2(sc * cos(psi), sin(psi));
+    return sin(p) > 0.0 ? -G : G;
+}
+__device__ inline double ovl_F2(double p, double kap) { return asin(sin(p) / sqrt(1.0 + kap * kap)); }
+
+__device__ inline void push_s(double s, double *c, int &n) {
+    if (s >= 0.0 && s <= 1.0) {
+        double b = asin(s);
+        c[n++] = b; c[n++] = -b; c[n++] = M_PI - b; c[n++] = -M_PI + b;
+    }
+}
+__device__ inline void push_c(double v, double *c, int &n) {
+    if (v >= -1.0 && v <= 1.0) {
+        double b = acos(v);
+        c[n++] = b; c[n++] = -b;
+    }
+}
+
+__global__ void k_overlap(int n_theta, int n_phi, double theta0, double phi0, double dtheta, double dphi,
+                          OvlGeom o, double *w) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_theta * n_phi) return;
+    int j = t / n_phi, k = t - j * n_phi;
+    double t1 = theta0 + j * dtheta, t2 = t1 + dtheta;
+    double p1 = phi0 + k * dphi, p2 = p1 + dphi;
+    double c1 = cos(t1), c2 = cos(t2);
+    double cand[48];
+    int n = 0;
+    cand[n++] = p1;
+    cand[n++] = p2;
+    push_s(o.sc, cand, n);
+    push_c(0.0, cand, n);
+    if (!o.kap_inf) push_s(sqrt(o.sc * o.sc * (1.0 + o.kap * o.kap) / (o.kap * o.kap + o.sc * o.sc)), cand, n);
+    double vs[4] = {c1, c2, -c1, -c2};
+    for (int q = 0; q < 4; ++q) {
+        double v = vs[q];
+        if (v > 0.0 && v < 1.0) {
+            push_s(o.sc / sqrt(1.0 - v * v), cand, n);
+            if (!o.kap_inf) push_c(v * o.kap / sqrt(1.0 - v * v), cand, n);
+        }
+    }
+    // keep points inside [p1, p2], sort
+    int m = 0;
+    for (int q = 0; q < n; ++q)
+        if (cand[q] >= p1 && cand[q] <= p2) cand[m++] = cand[q];
+    for (int a = 1; a < m; ++a)
+        for (int b = a; b > 0 && cand[b - 1] > cand[b]; --b) {
+            double tmp = cand[b]; cand[b] = cand[b - 1]; cand[b - 1] = tmp;
+        }
+    double area = 0.0;
+    for (int q = 0; q + 1 < m; ++q) {
+        double pa = cand[q], pb = cand[q + 1];
+        if (!(pb > pa)) continue;
+        double pm = 0.5 * (pa + pb);
+        double x1 = ovl_g1(pm, o.sc), x2 = ovl_g2(pm, o);
+        int act = (x1 == 0.0 && x2 == 0.0) ? 0 : (x1 >= x2 ? 1 : 2);
+        double cx = x1 > x2 ? x1 : x2;
+        double C0 = 0.0;
+        int cnt = 0;
+        // [cos t1 - clamp(cX, c2, c1)] + [clamp(-cX, c2, c1) - cos t2]
+        if (cx < c2) C0 += c1 - c2;
+        else if (cx <= c1) { C0 += c1; ++cnt; }
+        if (-cx > c1) C0 += c1 - c2;
+        else if (-cx >= c2) { C0 += -c2; ++cnt; }
+        double I = 0.0;
+        if (cnt && act == 1) I = ovl_F1(pb, o.sc) - ovl_F1(pa, o.sc);
+        else if (cnt && act == 2) I = ovl_F2(pb, o.kap) - ovl_F2(pa, o.kap);
+        area += C0 * (pb - pa) - cnt * I;
+    }
+    w[t] = 1.0 - 0.5 * area / ((p2 - p1) * (c1 - c2));
+}
+
+__global__ void k_fill(double *p, size_t n, double v) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+// Radial recurrence coefficients (Eq. M_C written with ratios <= 1):
+//   y_n = a_n y_{n-1} + b_n B_n,   z_n = c_n z_{n+1} + e_n B_{n+1},  M_n = y_n + z_n
+//   a_n = (r_{n-1}^+/r_n^+)^{l+1},          b_n = R_in,n/(r_n^+)^{l+1}
+//   c_n = (r_n^+/r_{n+1}^+)^l,               e_n = (r_n^+)^l R_out,n+1
+// (Eqs. R_in, R_out; l = 2 gives the logarithm).  coef[(n(L+1)+l)*4 + .]
+__global__ void k_coef(int n_r, int L, const double *re, double *coef) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_r * (L + 1)) return;
+    int n = t / (L + 1), l = t - n * (L + 1);
+    double rm = re[n], rp = re[n + 1];
+    double ratio = rm / rp;
+    double a = pow(ratio, (double)(l + 1));
+    double b = (ratio == 0.0) ? rp * rp / (l + 3.0) : -rp * rp * expm1((l + 3.0) * log(ratio)) / (l + 3.0);
+    double c = 0.0, e = 0.0;
+    if (n + 1 < n_r) {
+        double rn = rp, rq = re[n + 2];
+        c = pow(rn / rq, (double)l);
+        double lg = log(rq / rn);
+        e = (l == 2) ? rn * rn * lg : rn * rn * expm1((2.0 - l) * lg) / (2.0 - l);
+    }
+    double *o = coef + 4 * (size_t)t;
+    o[0] = a; o[1] = b; o[2] = c; o[3] = e;
+}
+
+// x = hi + lo (+ mid) with each piece the round-to-nearest bf16 of the
+// remaining FP64 residual.
+__global__ void k_split2(const double *x, bf16 *hi, bf16 *lo, size_t n) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double v = x[t];
+    bf16 h = (bf16)(float)v;
+    double r = v - (double)(float)h;
+    hi[t] = h;
+    lo[t] = (bf16)(float)r;
+}
+
+__global__ void k_split3(const double *x, bf16 *hi, bf16 *mid, bf16 *lo, size_t n) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double v = x[t];
+    bf16 h = (bf16)(float)v;
+    double r = v - (double)(float)h;
+    bf16 m = (bf16)(float)r;
+    double r2 = r - (double)(float)m;
+    hi[t] = h;
+    mid[t] = m;
+    lo[t] = (bf16)(float)r2;
+}
+
+// Tables of every patch in the real index (patch 1 = (-1)^m patch 0 under
+// the fold): U[g][jk][n_lm] from Ut[q][jk], Q[g][jk][n_lm] from Qt[jk][q].
+__global__ void k_export(const double *Ut, const double *Qt, int np, int n_angp, int n_ang, int n_lm,
+                         int n_patches, const int *col_src, double *U, double *Q) {
+    int jk = blockIdx.x * blockDim.x + threadIdx.x;
+    int q = blockIdx.y;
+    if (jk >= n_ang || q >= np) return;
+    int src = col_src[q];
+    if (src < 0) return;
+    int l = (int)sqrt((double)src);
+    while ((l + 1) * (l + 1) <= src) ++l;
+    while (l * l > src) --l;
+    int m = (src - l * l + 1) / 2;
+    double u = Ut[(size_t)q * n_angp + jk], v = Qt[(size_t)jk * np + q];
+    for (int g = 0; g < n_patches; ++g) {
+        double sg = (g == 1 && (m & 1)) ? -1.0 : 1.0;
+        size_t o = ((size_t)g * n_ang + jk) * n_lm + src;
+        if (U) U[o] = sg * u;
+        if (Q) Q[o] = sg * v;
+    }
+}
+
+inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+static void rotation(double a, double b, double g, double R[9]) {
+    // Eq. rottransmatrix, x = R xi
+    double ca = cos(a), sa = sin(a), cb = cos(b), sb = sin(b), cg = cos(g), sg = sin(g);
+    R[0] = ca * cb * cg - sa * sg;  R[1] = sa * cb * cg + ca * sg;  R[2] = -sb * cg;
+    R[3] = -ca * cb * sg - sa * cg; R[4] = -sa * cb * sg + ca * cg; R[5] = sb * sg;
+    R[6] = ca * sb;                 R[7] = sa * sb;                 R[8] = cb;
+}
+
+hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, const double *host_w) {
+    const int L = p.lmax;
+    hipStream_t s = p.stream;
+    double R0[9];
+    rotation(euler[0], euler[1], euler[2], R0);
+
+    // column layout: even-m block first, odd-m block second (fold only)
+    std::vector<int> col_src(p.np_alloc, -1), col_l(p.np_alloc, -1), perm_of(p.n_lm, -1);
+    {
+        int qe = 0, qo = p.ne_p;
+        for (int l = 0; l <= L; ++l)
+            for (int m = 0; m <= l; ++m) {
+                int srcs[2] = {m == 0 ? l * l : l * l + 2 * m - 1, l * l + 2 * m};
+                for (int c = 0; c < (m == 0 ? 1 : 2); ++c) {
+                    int &q = (!p.fold || (m % 2 == 0)) ? qe : qo;
+                    col_src[q] = srcs[c];
+                    col_l[q] = l;
+                    perm_of[srcs[c]] = q;
+                    ++q;
+                }
+            }
+    }
+    hipError_t err = hipSuccess;
+    int *d_perm = nullptr;
+    double *d_re = nullptr, *dh = nullptr, *db = nullptr, *N4 = nullptr, *Tt = nullptr, *CS = nullptr;
+    const size_t nU = (size_t)p.np_alloc * p.n_angp, nQ = (size_t)p.n_angp * p.np;
+#define STEP(x)                             \
+    do {                                    \
+        err = (x);                          \
+        if (err != hipSuccess) goto done;   \
+    } while (0)
+    STEP(hipMalloc(&p.col_src, sizeof(int) * p.np_alloc));
+    STEP(hipMalloc(&p.col_l, sizeof(int) * p.np_alloc));
+    STEP(hipMalloc(&d_perm, sizeof(int) * p.n_lm));
+    STEP(hipMemcpyAsync(p.col_src, col_src.data(), sizeof(int) * p.np_alloc, hipMemcpyHostToDevice, s));
+    STEP(hipMemcpyAsync(p.col_l, col_l.data(), sizeof(int) * p.np_alloc, hipMemcpyHostToDevice, s));
+    STEP(hipMemcpyAsync(d_perm, perm_of.data(), sizeof(int) * p.n_lm, hipMemcpyHostToDevice, s));
+
+    // overlap weights w_jk (Sec. 4.2)
+    STEP(hipMalloc(&p.w, sizeof(double) * p.n_ang));
+    if (host_w) {
+        STEP(hipMemcpyAsync(p.w, host_w, sizeof(double) * p.n_ang, hipMemcpyHostToDevice, s));
+    } else if (p.n_patches == 1) {
+        hipLaunchKernelGGL(k_fill, dim3(blocks(p.n_ang, 256)), dim3(256), 0, s, p.w, (size_t)p.n_ang, 1.0);
+    } else {
+        OvlGeom o;
+        o.sc = p.ovl_sc;
+        o.kap = p.ovl_kap;
+        o.kap_inf = p.ovl_kap_inf;
+        hipLaunchKernelGGL(k_overlap, dim3(blocks(p.n_ang, 64)), dim3(64), 0, s, p.n_theta, p.n_phi, p.theta0,
+                           p.phi0, p.dtheta, p.dphi, o, p.w);
+    }
+    STEP(hipGetLastError());
+
+    // radial recurrence coefficients
+    STEP(hipMalloc(&d_re, sizeof(double) * (p.n_r + 1)));
+    STEP(hipMemcpyAsync(d_re, r_edges, sizeof(double) * (p.n_r + 1), hipMemcpyHostToDevice, s));
+    STEP(hipMalloc(&p.coef, sizeof(double) * 4 * (size_t)p.n_r * (L + 1)));
+    hipLaunchKernelGGL(k_coef, dim3(blocks((size_t)p.n_r * (L + 1), 128)), dim3(128), 0, s, p.n_r, L, d_re, p.coef);
+    STEP(hipGetLastError());
+
+    // Wigner d at pi/2; d at beta and pi - beta of patch 0; N; T; C/S
+    STEP(hipMalloc(&dh, sizeof(double) * off_dh(L + 1)));
+    STEP(hipMalloc(&db, sizeof(double) * 2 * off_sq(L + 1)));
+    STEP(hipMalloc(&N4, sizeof(double) * 4 * off_sq(L + 1)));
+    STEP(hipMalloc(&Tt, sizeof(double) * (size_t)p.n_theta * off_tri(L + 1)));
+    STEP(hipMalloc(&CS, sizeof(double) * 2 * (size_t)p.n_phi * (L + 1)));
+    hipLaunchKernelGGL(k_dhalf, dim3(blocks(off_tri(L + 1), 64)), dim3(64), 0, s, L, dh);
+    hipLaunchKernelGGL(k_dbeta, dim3(blocks(2 * off_sq(L + 1), 128)), dim3(128), 0, s, L, dh, euler[1],
+                       M_PI - euler[1], db);
+    hipLaunchKernelGGL(k_ncoef, dim3(blocks(off_sq(L + 1), 128)), dim3(128), 0, s, L, db, euler[0], euler[2], N4);
+    hipLaunchKernelGGL(k_ttilde, dim3(blocks((size_t)p.n_theta * off_tri(L + 1), 128)), dim3(128), 0, s, L, dh,
+                       p.n_theta, p.theta0, p.dtheta, Tt);
+    hipLaunchKernelGGL(k_cs, dim3(blocks((size_t)p.n_phi * (L + 1), 128)), dim3(128), 0, s, L, p.n_phi, p.phi0,
+                       p.dphi, CS);
+    STEP(hipGetLastError());
+
+    // U and Q of patch 0 (the fold derives patch 1 from them)
+    STEP(hipMalloc(&p.Ut, sizeof(double) * nU));
+    STEP(hipMalloc(&p.Qt, sizeof(double) * nQ));
+    hipLaunchKernelGGL(k_U, dim3(blocks(p.n_angp, 128), p.np_alloc), dim3(128), 0, s, L, p.np_alloc, p.n_angp,
+                       p.n_ang, p.n_phi, p.col_src, Tt, CS, N4, p.w, p.Ut);
+    STEP(hipGetLastError());
+    STEP(hipMemsetAsync(p.Qt, 0, sizeof(double) * nQ, s));
+    {
+        Rot R;
+        for (int i = 0; i < 9; ++i) R.r[i] = R0[i];
+        hipLaunchKernelGGL(k_Q, dim3(blocks(p.n_angp, 64)), dim3(64), 0, s, L, p.np, p.n_angp, p.n_ang, p.n_phi,
+                           p.theta0, p.phi0, p.dtheta, p.dphi, R, p.G, d_perm, p.Qt);
+    }
+    STEP(hipGetLastError());
+
+    // split-BF16 copies
+    if (p.precision == MPG_SPLIT_BF16) {
+        STEP(hipMalloc(&p.Ut_hi, sizeof(bf16) * nU));
+        STEP(hipMalloc(&p.Ut_lo, sizeof(bf16) * nU));
+        STEP(hipMalloc(&p.Qt_hi, sizeof(bf16) * nQ));
+        STEP(hipMalloc(&p.Qt_lo, sizeof(bf16) * nQ));
+        STEP(hipMalloc(&p.Qt_mid, sizeof(bf16) * nQ));
+        hipLaunchKernelGGL(k_split2, dim3(blocks(nU, 256)), dim3(256), 0, s, p.Ut, p.Ut_hi, p.Ut_lo, nU);
+        hipLaunchKernelGGL(k_split3, dim3(blocks(nQ, 256)), dim3(256), 0, s, p.Qt, p.Qt_hi, p.Qt_mid, p.Qt_lo, nQ);
+        STEP(hipGetLastError());
+    }
+    STEP(hipStreamSynchronize(s));
+done:
+#undef STEP
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(d_perm);
+    (void)hipFree(d_re);
+    (void)hipFree(dh);
+    (void)hipFree(db);
+    (void)hipFree(N4);
+    (void)hipFree(Tt);
+    (void)hipFree(CS);
+    return err;
+}
+
+hipError_t export_tables(const Plan &p, double *U, double *Q, double *w) {
+    if (U || Q)
+        hipLaunchKernelGGL(k_export, dim3(blocks(p.n_ang, 128), p.np), dim3(128), 0, p.stream, p.Ut, p.Qt, p.np,
+                           p.n_angp, p.n_ang, p.n_lm, p.n_patches, p.col_src, U, Q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (w) e = hipMemcpyAsync(w, p.w, sizeof(double) * p.n_ang, hipMemcpyDeviceToDevice, p.stream);
+    return e;
+}
+
+}  // namespace mpg

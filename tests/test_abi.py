@@ -1,0 +1,69 @@
+"""The C-ABI library loads and exports every symbol include/mpg.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1903_08475_amd as mpg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "mpg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpg_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared() == sorted(mpg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(mpg.LIB_PATH):
+        pytest.fail("libmpg.so is not built (run `python -m paper_1903_08475_amd.build`)")
+    L = ctypes.CDLL(mpg.LIB_PATH)
+    for name in declared():
+        assert hasattr(L, name), name
+
+
+def test_last_error_is_empty_string_initially():
+    L = mpg.lib()
+    assert isinstance(L.mpg_last_error(), bytes)
+
+
+def test_plan_rejects_bad_grids_on_host():
+    """Argument validation happens before any device call."""
+    import numpy as np
+    import workloads as W
+    L = mpg.lib()
+    g = W.config1()
+    r = np.ascontiguousarray(g.r_edges)
+    e = np.ascontiguousarray(g.euler.reshape(-1))
+    s = mpg._Grid()
+    s.n_patches, s.n_r, s.n_theta, s.n_phi = 2, g.n_r, g.n_theta, g.n_phi
+    s.r_edges = r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    s.euler = e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    s.theta0, s.phi0, s.dtheta, s.dphi, s.G = g.theta0, g.phi0, g.dtheta, g.dphi, 1.0
+    h = ctypes.c_void_p()
+    assert L.mpg_plan(ctypes.byref(s), -1, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
+    assert L.mpg_plan(ctypes.byref(s), 8, 7, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
+    assert L.mpg_plan(ctypes.byref(s), 8, 0, 0, None, ctypes.byref(h)) == mpg.MPG_EINVAL
+    bad = r.copy()
+    bad[5] = bad[4]
+    s.r_edges = bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.mpg_plan(ctypes.byref(s), 8, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
+    assert b"increase" in L.mpg_last_error()
+    s.r_edges = r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    s.n_patches = 3
+    assert L.mpg_plan(ctypes.byref(s), 8, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EUNSUPPORTED
+    s.n_patches = 2
+    e2 = e.copy()
+    e2[5] = 0.3  # Yang no longer Yin turned by pi about z
+    s.euler = e2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.mpg_plan(ctypes.byref(s), 8, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EUNSUPPORTED
+    assert h.value is None
+    assert L.mpg_moments(None, 1, None, 0, None, None) == mpg.MPG_EINVAL
+    assert L.mpg_potential(None, 1, None, 0, None, 0) == mpg.MPG_EINVAL
