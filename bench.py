@@ -1,0 +1,228 @@
+"""Benchmark of one solve step on one MI355X.
+
+A step is one pass of the whole hot path (moment contraction, radial scans,
+expansion) over one batch of 8 snapshots of the large workload: Yin-Yang grid
+at pi/256 (128x384 cells per patch), 1200 log-spaced shells, lmax 48,
+float32 densities, split-BF16 contractions.  Inputs are resident in HBM
+before the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line (see the fields below).  The FP64 path is timed on the
+same workload for comparison, and the CPU oracle on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid cells·(l,m) terms/s per solve, split-BF16 vs FP64 at ≤1e-6 rel err"
+PEAK_BF16 = 2.5e15     # dense bf16 MFMA, FLOP/s
+PEAK_FP64 = 78.6e12    # FP64 MFMA, FLOP/s
+HBM_PEAK = 8.0e12      # B/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("gemm_bf16.hip", "gemm_f64.hip", "scan.hip"):
+        with open(os.path.join(ROOT, "paper_1903_08475_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(stage, precision):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    key = f"{precision}:{stage}"
+    r = rec.get(key)
+    if not r or r.get("source_hash") != kernel_source_hash():
+        return None
+    return r.get("bytes_per_launch")
+
+
+def make_inputs(grid, n_snap, device):
+    import torch
+    import workloads as W
+    rho = torch.empty((n_snap,) + grid.shape, dtype=torch.float32, device=device)
+    for t in range(n_snap):
+        rho[t] = W.cell_average(grid, W.density5(t), sub=2, device=device, as_tensor=True,
+                                out_dtype=torch.float32)
+        log(f"[bench] snapshot {t} generated")
+    return rho
+
+
+def time_path(plan, rho, phi, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.potential(rho, out=phi)
+    torch.cuda.synchronize()
+    plan.timing(True)
+    plan.stage_times(reset=True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        plan.potential(rho, out=phi)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = plan.stage_times(reset=True)
+    plan.timing(False)
+    return start.elapsed_time(stop) / steps, wall, stages
+
+
+def cpu_baseline(lmax):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    the large workload's lmax and radial spacing law on a coarser angular
+    grid (pi/64, 32x96 per patch) and 64 shells.  Timed: moments, radial
+    sums and expansion (its table build excluded, as on the GPU)."""
+    import oracle as O
+    import workloads as W
+    g = W.yinyang(32, W.log_edges(64, 3.0), lmax)
+    rho = W.random_rho(g, 5005)
+    w = O.overlap_weights(g)
+    U, Q = O.tables(g, lmax, w)
+    t0 = time.perf_counter()
+    B = O.moments(g, lmax, U, rho)
+    M = O.radial(g, lmax, B)
+    O.expand(g, lmax, Q, M)
+    dt = time.perf_counter() - t0
+    terms = g.n_cells * g.n_lm
+    return {
+        "value": terms / dt,
+        "unit": "terms/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"lmax {lmax}, Yin-Yang pi/64 (2x32x96 cells), 64 log-spaced shells, "
+                   f"{terms:.3e} terms; moments + radial sums + expansion in {dt:.1f} s, "
+                   f"single thread ({os.cpu_count()} host cores)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--snapshots", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the solver has no multi-GPU path)", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_1903_08475_amd as mpg
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    grid = W.config5()
+    n = args.snapshots
+    rho = make_inputs(grid, n, dev)
+    phi = torch.empty_like(rho)
+    terms_per_step = grid.n_cells * grid.n_lm * n
+    rows, n_ang, n_lm = n * grid.n_r, grid.n_ang, grid.n_lm
+    alg_flops = 2.0 * rows * n_ang * n_lm  # per contraction launch (folded)
+
+    log("[bench] building split-BF16 plan")
+    plan = mpg.Plan(grid, precision="split_bf16", max_fields=n)
+    ms, wall, stages = time_path(plan, rho, phi, args.steps, args.warmup)
+    log(f"[bench] split-BF16: {ms:.3f} ms/step; stages {stages}")
+
+    out = {
+        "metric": METRIC,
+        "value": terms_per_step / (ms * 1e-3),
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": ("large: Yin-Yang pi/256 (2x128x384 cells), 1200 log-spaced shells over 3 decades, "
+                         "lmax 48, batch of 8 float32 snapshots (ellipsoid spun 0.05 rad/step + 64 drifting "
+                         "blobs)"),
+            "global_batch": n,
+            "n_cells_per_snapshot": grid.n_cells,
+            "n_lm": n_lm,
+            "terms_per_step": terms_per_step,
+            "precision": "split-BF16: three bf16 pieces per operand, six MFMA products, FP32 accumulate, "
+                         "FP64 flush, FP64 tables and scans",
+            "parallelism": "single GPU",
+        },
+    }
+
+    # dominant kernel and its roofline
+    per = {k: (v[0] / max(1, v[1])) for k, v in stages.items()}
+    dom = max(("moments", "expansion"), key=lambda k: per[k])
+    achieved = alg_flops / (per[dom] * 1e-3)
+    out["roofline"] = {
+        "bound": "mfma",
+        "kernel": "k_gemm1 (split-BF16 moment contraction)" if dom == "moments" else
+                  "k_gemm2 (split-BF16 expansion)",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_BF16 / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_BF16,
+        "traffic": traffic_record(dom, "split_bf16"),
+        "executed_mfma_frac": 6 * achieved / PEAK_BF16,
+        "avg_launch_ms": per[dom],
+        "stage_ms": {k: per[k] for k in per},
+    }
+
+    if not args.no_fp64:
+        log("[bench] FP64 path on the same workload")
+        ref = torch.empty_like(rho, dtype=torch.float64)
+        plan64 = mpg.Plan(grid, precision="fp64", max_fields=n)
+        ms64, _, st64 = time_path(plan64, rho, ref, args.fp64_steps, 1)
+        plan.potential(rho, out=phi)
+        torch.cuda.synchronize()
+        err = float((phi.to(torch.float64) - ref).abs().max() / ref.abs().max())
+        out["fp64_path"] = {
+            "value": terms_per_step / (ms64 * 1e-3),
+            "ms_per_step": ms64,
+            "stage_ms": {k: v[0] / max(1, v[1]) for k, v in st64.items()},
+            "fp64_mfma_frac": alg_flops / (st64["moments"][0] / max(1, st64["moments"][1]) * 1e-3) / PEAK_FP64,
+        }
+        out["split_vs_fp64_max_rel_err"] = err
+        out["speedup_vs_fp64"] = ms64 / ms
+        del plan64, ref
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(grid.lmax)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

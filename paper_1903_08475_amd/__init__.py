@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16}
 
 # Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
 EXPORTS = ("mpg_plan", "mpg_moments", "mpg_potential", "mpg_potential_batch", "mpg_tables",
-           "mpg_plan_info", "mpg_sync", "mpg_destroy", "mpg_last_error")
+           "mpg_plan_info", "mpg_timing", "mpg_stage_times", "mpg_sync", "mpg_destroy", "mpg_last_error")
+STAGES = ("moments", "radial_scan", "expansion")
 
 
 class MpgError(RuntimeError):
@@ -61,6 +62,8 @@ def lib():
         L.mpg_potential_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
         L.mpg_tables.argtypes = [vp, vp, vp, vp]
         L.mpg_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]
+        L.mpg_timing.argtypes = [vp, C.c_int]
+        L.mpg_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int]
         L.mpg_sync.argtypes = [vp]
         L.mpg_destroy.argtypes = [vp]
         L.mpg_destroy.restype = None
@@ -177,6 +180,17 @@ class Plan:
                                 C.c_void_p(w.data_ptr())))
         self.sync()
         return U, Q, w
+
+    def timing(self, enable=True):
+        """Record HIP events around every stage of later compute calls."""
+        _check(lib().mpg_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self, reset=True):
+        """{stage: (total ms, launches)} since the last reset."""
+        ms = (C.c_double * 3)()
+        n = (C.c_longlong * 3)()
+        _check(lib().mpg_stage_times(self._h, ms, n, 1 if reset else 0))
+        return {STAGES[i]: (ms[i], n[i]) for i in range(3)}
 
     def sync(self):
         _check(lib().mpg_sync(self._h))

@@ -37,13 +37,43 @@ void rot(const double *e, double R[9]) {
 
 int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
+// Record an event pair around one stage when timing is on; returns the stop
+// event to record after the launch (or nullptr).
+hipEvent_t stage_begin(const Plan &p, int stage) {
+    if (!p.timing) return nullptr;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return nullptr;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return nullptr;
+    }
+    (void)hipEventRecord(a, p.stream);
+    p.events[stage]->push_back(a);
+    p.events[stage]->push_back(b);
+    return b;
+}
+
+void stage_end(const Plan &p, hipEvent_t b) {
+    if (b) (void)hipEventRecord(b, p.stream);
+}
+
+void clear_events(Plan *p) {
+    for (int s = 0; s < 3; ++s)
+        if (p->events[s]) {
+            for (hipEvent_t e : *p->events[s]) (void)hipEventDestroy(e);
+            p->events[s]->clear();
+        }
+}
+
 void free_plan(mpg_plan_s *p) {
     if (!p) return;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    void *bufs[] = {p->col_src, p->col_l, p->Ut,   p->Qt,    p->coef, p->w,    p->Ut_hi, p->Ut_lo, p->Qt_hi,
-                    p->Qt_lo,   p->Bpart, p->Bred, p->M,     p->M_hi, p->M_lo, p->M_mid, p->Qt_mid};
+    void *bufs[] = {p->col_src, p->col_l, p->Ut,    p->Qt,   p->coef, p->w,    p->Ut_hi, p->Ut_mid, p->Ut_lo,
+                    p->Qt_hi,   p->Qt_mid, p->Qt_lo, p->Bpart, p->Bred, p->M, p->M_hi,  p->M_mid,  p->M_lo};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    clear_events(p);
+    for (int s = 0; s < 3; ++s) delete p->events[s];
     delete p;
 }
 
@@ -167,7 +197,6 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
     p->np = p->ne_p + p->no_p;
     p->np_alloc = p->np + kColSlack;
     p->n_angp = roundup(p->n_ang, kAngPad);
-    p->l_tier = lmax < 2 ? lmax : 2;
 
     // work space
     {
@@ -219,12 +248,17 @@ static int run_moments(const Plan *p, int n_fields, const void *rho, int rho_dty
     int sk = choose_splitk(*p, n_fields);
     Plan q = *p;
     q.splitk = sk;
+    hipEvent_t ev = stage_begin(q, 0);
     if (p->precision == MPG_SPLIT_BF16)
         e = gemm1_bf16(q, n_fields, rho, rho_dtype);
     else
         e = gemm1_f64(q, n_fields, rho, rho_dtype);
+    stage_end(q, ev);
     if (e != hipSuccess) return hip_fail(e, "moment contraction");
-    if ((e = radial_scan(q, n_fields, split_out)) != hipSuccess) return hip_fail(e, "radial scan");
+    ev = stage_begin(q, 1);
+    e = radial_scan(q, n_fields, split_out);
+    stage_end(q, ev);
+    if (e != hipSuccess) return hip_fail(e, "radial scan");
     return MPG_OK;
 }
 
@@ -242,7 +276,9 @@ static int solve(const Plan *p, int n_fields, const void *rho, int rho_dtype, vo
     int rc;
     bool split = p->precision == MPG_SPLIT_BF16;
     if ((rc = run_moments(p, n_fields, rho, rho_dtype, split))) return rc;
+    hipEvent_t ev = stage_begin(*p, 2);
     hipError_t e = split ? gemm2_bf16(*p, n_fields, phi, phi_dtype) : gemm2_f64(*p, n_fields, phi, phi_dtype);
+    stage_end(*p, ev);
     if (e != hipSuccess) return hip_fail(e, "expansion");
     return MPG_OK;
 }
@@ -283,6 +319,39 @@ int mpg_plan_info(mpg_plan_t p, int *n_lm, long long *field_elems) {
     if (!p) return fail(MPG_EINVAL, "mpg_plan_info: plan is NULL");
     if (n_lm) *n_lm = p->n_lm;
     if (field_elems) *field_elems = (long long)p->n_patches * p->n_r * p->n_ang;
+    return MPG_OK;
+}
+
+int mpg_timing(mpg_plan_t p, int enable) {
+    if (!p) return fail(MPG_EINVAL, "mpg_timing: plan is NULL");
+    for (int s = 0; s < 3; ++s)
+        if (!p->events[s]) {
+            p->events[s] = new (std::nothrow) std::vector<hipEvent_t>();
+            if (!p->events[s]) return fail(MPG_ENOMEM, "mpg_timing: host allocation");
+        }
+    p->timing = enable != 0;
+    return MPG_OK;
+}
+
+int mpg_stage_times(mpg_plan_t p, double ms[3], long long launches[3], int reset) {
+    if (!p) return fail(MPG_EINVAL, "mpg_stage_times: plan is NULL");
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "mpg_stage_times");
+    for (int s = 0; s < 3; ++s) {
+        double tot = 0.0;
+        long long n = 0;
+        if (p->events[s])
+            for (size_t k = 0; k + 1 < p->events[s]->size(); k += 2) {
+                float t = 0.0f;
+                if ((e = hipEventElapsedTime(&t, (*p->events[s])[k], (*p->events[s])[k + 1])) != hipSuccess)
+                    return hip_fail(e, "mpg_stage_times");
+                tot += t;
+                ++n;
+            }
+        if (ms) ms[s] = tot;
+        if (launches) launches[s] = n;
+    }
+    if (reset) clear_events(p);
     return MPG_OK;
 }
 

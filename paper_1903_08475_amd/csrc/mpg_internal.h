@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/mpg.h"
 
@@ -50,23 +51,21 @@ struct Plan {
     double *Qt = nullptr;      // [n_angp][np]        Q of patch 0, K(lm)-contiguous
     double *coef = nullptr;    // [n_r][lmax+1][4] radial recurrence coefficients
     double *w = nullptr;       // [n_ang] overlap weights
-    bf16 *Ut_hi = nullptr, *Ut_lo = nullptr;   // split copies of Ut
-    bf16 *Qt_hi = nullptr, *Qt_lo = nullptr;   // split copies of Qt
+    bf16 *Ut_hi = nullptr, *Ut_mid = nullptr, *Ut_lo = nullptr;  // three-piece bf16 copies of Ut
+    bf16 *Qt_hi = nullptr, *Qt_mid = nullptr, *Qt_lo = nullptr;  // three-piece bf16 copies of Qt
 
     // work space (sized for max_fields)
     int splitk = 1;
     double *Bpart = nullptr;   // [splitk][rows][np]
     double *Bred = nullptr;    // [rows][np]
     double *M = nullptr;       // [rows][np]
-    bf16 *M_hi = nullptr, *M_lo = nullptr; // [rows][np]
-
-    // split-BF16 tier: columns of degree <= l_tier use an extra split term
-    int l_tier = 0;
-    int ntier_e = 0, ntier_o = 0;  // columns of the tier at the start of each block
-    bf16 *M_mid = nullptr;     // [rows][np] third split piece (tier columns only)
-    bf16 *Qt_mid = nullptr;    // [n_angp][np]
+    bf16 *M_hi = nullptr, *M_mid = nullptr, *M_lo = nullptr; // [rows][np] three-piece bf16 M
 
     int rows_alloc() const { return max_fields * n_r; }
+
+    // optional stage timing (events recorded on the plan's stream)
+    bool timing = false;
+    std::vector<hipEvent_t> *events[3] = {nullptr, nullptr, nullptr};  // start/stop pairs
 };
 
 // ---- kernels launchers (each returns hipError_t of the launch) ----------

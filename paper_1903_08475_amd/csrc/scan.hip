@@ -27,7 +27,7 @@ __device__ inline double reduce_parts(const double *Bpart, size_t stride, int sp
 __global__ void k_scan(const double *__restrict__ Bpart, int splitk, int n_fields, int n_r, int np, int L,
                        const int *__restrict__ col_l, const double *__restrict__ coef, double *__restrict__ Bred,
                        double *__restrict__ M, bf16 *__restrict__ Mhi, bf16 *__restrict__ Mlo,
-                       bf16 *__restrict__ Mmid, int l_tier) {
+                       bf16 *__restrict__ Mmid) {
     __shared__ double sA[kMaxChunks][kLanes], sY[kMaxChunks][kLanes];
     __shared__ double sC[kMaxChunks][kLanes], sZ[kMaxChunks][kLanes];
     const int lane = threadIdx.x, ch = threadIdx.y, T = blockDim.y;
@@ -99,20 +99,14 @@ __global__ void k_scan(const double *__restrict__ Bpart, int splitk, int n_field
         double m = M[base + (size_t)n * np] + z;
         M[base + (size_t)n * np] = m;
         if (Mhi) {
-            // split copies for the BF16 contraction: hi + lo (+ mid on the tier)
+            // three-piece bf16 copy for the split contraction
             bf16 h = (bf16)(float)m;
             double r = m - (double)(float)h;
             bf16 md = (bf16)(float)r;
-            if (l <= l_tier) {
-                double r2 = r - (double)(float)md;
-                Mhi[base + (size_t)n * np] = h;
-                Mmid[base + (size_t)n * np] = md;
-                Mlo[base + (size_t)n * np] = (bf16)(float)r2;
-            } else {
-                Mhi[base + (size_t)n * np] = h;
-                Mlo[base + (size_t)n * np] = md;
-                Mmid[base + (size_t)n * np] = (bf16)0.0f;
-            }
+            double r2 = r - (double)(float)md;
+            Mhi[base + (size_t)n * np] = h;
+            Mmid[base + (size_t)n * np] = md;
+            Mlo[base + (size_t)n * np] = (bf16)(float)r2;
         }
     }
 }
@@ -133,7 +127,7 @@ hipError_t radial_scan(const Plan &p, int n_fields, bool split_out) {
     dim3 grid((n_fields * p.np + kLanes - 1) / kLanes);
     hipLaunchKernelGGL(k_scan, grid, block, 0, p.stream, p.Bpart, p.splitk, n_fields, p.n_r, p.np, p.lmax, p.col_l,
                        p.coef, p.Bred, p.M, split_out ? p.M_hi : nullptr, split_out ? p.M_lo : nullptr,
-                       split_out ? p.M_mid : nullptr, p.l_tier);
+                       split_out ? p.M_mid : nullptr);
     return hipGetLastError();
 }
 

@@ -388,18 +388,8 @@ __global__ void k_coef(int n_r, int L, const double *re, double *coef) {
     o[0] = a; o[1] = b; o[2] = c; o[3] = e;
 }
 
-// x = hi + lo (+ mid) with each piece the round-to-nearest bf16 of the
-// remaining FP64 residual.
-__global__ void k_split2(const double *x, bf16 *hi, bf16 *lo, size_t n) {
-    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    double v = x[t];
-    bf16 h = (bf16)(float)v;
-    double r = v - (double)(float)h;
-    hi[t] = h;
-    lo[t] = (bf16)(float)r;
-}
-
+// x = hi + mid + lo, each piece the round-to-nearest bf16 of the remaining
+// FP64 residual (24 significant bits in all).
 __global__ void k_split3(const double *x, bf16 *hi, bf16 *mid, bf16 *lo, size_t n) {
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
@@ -542,11 +532,12 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
     // split-BF16 copies
     if (p.precision == MPG_SPLIT_BF16) {
         STEP(hipMalloc(&p.Ut_hi, sizeof(bf16) * nU));
+        STEP(hipMalloc(&p.Ut_mid, sizeof(bf16) * nU));
         STEP(hipMalloc(&p.Ut_lo, sizeof(bf16) * nU));
         STEP(hipMalloc(&p.Qt_hi, sizeof(bf16) * nQ));
         STEP(hipMalloc(&p.Qt_lo, sizeof(bf16) * nQ));
         STEP(hipMalloc(&p.Qt_mid, sizeof(bf16) * nQ));
-        hipLaunchKernelGGL(k_split2, dim3(blocks(nU, 256)), dim3(256), 0, s, p.Ut, p.Ut_hi, p.Ut_lo, nU);
+        hipLaunchKernelGGL(k_split3, dim3(blocks(nU, 256)), dim3(256), 0, s, p.Ut, p.Ut_hi, p.Ut_mid, p.Ut_lo, nU);
         hipLaunchKernelGGL(k_split3, dim3(blocks(nQ, 256)), dim3(256), 0, s, p.Qt, p.Qt_hi, p.Qt_mid, p.Qt_lo, nQ);
         STEP(hipGetLastError());
     }

@@ -177,15 +177,20 @@ class Sum:
         return out
 
 
-def cell_average(grid: Grid, density, sub=4, device="cpu", dtype="float64", shells_per_chunk=None):
+def cell_average(grid: Grid, density, sub=4, device="cpu", shells_per_chunk=None, as_tensor=False,
+                 out_dtype=None):
     """Volume-weighted (r^2 sin theta) midpoint average of `density` over each
-    cell with sub^3 sub-samples.  Returns a float64 numpy array of grid.shape
-    (computed with torch on `device`)."""
+    cell with sub^3 sub-samples, computed with torch on `device`.  Returns a
+    float64 numpy array of grid.shape, or (as_tensor) a tensor on `device`
+    of out_dtype (default float64)."""
     import torch
 
     dev = torch.device(device)
     f64 = torch.float64
-    out = np.zeros(grid.shape, dtype=np.float64)
+    if as_tensor:
+        out = torch.empty(grid.shape, dtype=out_dtype or f64, device=dev)
+    else:
+        out = np.zeros(grid.shape, dtype=np.float64)
     s = (torch.arange(sub, dtype=f64, device=dev) + 0.5) / sub
     th = grid.theta0 + (torch.arange(grid.n_theta, dtype=f64, device=dev)[:, None] + s[None, :]) * grid.dtheta
     ph = grid.phi0 + (torch.arange(grid.n_phi, dtype=f64, device=dev)[:, None] + s[None, :]) * grid.dphi
@@ -198,7 +203,8 @@ def cell_average(grid: Grid, density, sub=4, device="cpu", dtype="float64", shel
     wang = st[:, :, None, None].expand_as(ux)
     if shells_per_chunk is None:
         per_shell = grid.n_ang * sub ** 3
-        shells_per_chunk = max(1, int(4e6 // per_shell))
+        budget = 3e7 if dev.type == "cuda" else 4e6
+        shells_per_chunk = max(1, int(budget // per_shell))
     r_edges = torch.tensor(grid.r_edges, dtype=f64, device=dev)
     for g in range(grid.n_patches):
         F = torch.tensor(grid.frames[g], dtype=f64, device=dev)
@@ -218,7 +224,10 @@ def cell_average(grid: Grid, density, sub=4, device="cpu", dtype="float64", shel
             wt = wr[:, :, None, None, None, None] * wang[None, None]
             num = (val * wt).sum(dim=(1, 3, 5))
             den = wt.sum(dim=(1, 3, 5))
-            out[g, i0:i1] = (num / den).cpu().numpy()
+            if as_tensor:
+                out[g, i0:i1] = (num / den).to(out.dtype)
+            else:
+                out[g, i0:i1] = (num / den).cpu().numpy()
     return out
 
 
