@@ -16,6 +16,8 @@ HIPCC_FLAGS = [
     # packed FP32 instructions stay off (hardware notes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    # private arrays stay in registers (or visibly in scratch), never in LDS
+    "-mllvm", "-disable-promote-alloca-to-lds",
 ]
 
 

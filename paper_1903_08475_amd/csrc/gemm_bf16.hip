@@ -1,8 +1,8 @@
 // Split-BF16 MFMA contractions of the solve (Sec. 4.3 steps 2 and 5).
 //
-// Each FP64 (or FP32) operand x is written as x = h + m + l, with h, m, l
-// the round-to-nearest bf16 of the successive residuals (24 significant
-// bits).  A product a*b is formed from the six partial products whose
+// Each operand x, taken in FP32, is written as x = h + m + l, with h, m, l
+// the round-to-nearest bf16 of the successive residuals (exact: 24
+// significant bits).  A product a*b is formed from the six partial products whose
 // combined weight is at least 2^-18 of the leading one:
 //   ah*bh + ah*bm + am*bh + ah*bl + am*bm + al*bh
 // on v_mfma_f32_32x32x16_bf16 (bf16 products are exact in FP32).  The FP32
@@ -11,8 +11,9 @@
 // moment count, short enough for FP32 sums).
 //
 // GEMM1 (moments, Eq. B_CS) folds and splits rho in its tile loader:
-// A = rho_Yin +- rho_Yang (U_Yang = (-1)^m U_Yin, Sec. 4.2), converted once
-// per element to three bf16 pieces in LDS; U comes pre-split from the plan.
+// A = rho_Yin +- rho_Yang (U_Yang = (-1)^m U_Yin, Sec. 4.2), rounded once
+// to FP32 and converted to three bf16 pieces in LDS; U comes pre-split from
+// the plan.
 // GEMM2 (expansion, Eq. gravpotmult) reads M pre-split by the radial scan
 // and Q pre-split by the plan, sums even- and odd-m columns separately and
 // writes Phi_Yin = E + O, Phi_Yang = E - O.  Its K loop runs from the
@@ -20,8 +21,9 @@
 // to the smallest partial sums last.
 //
 // Tiles: 128x128 per block of 256 threads (2x2 waves of 64x64 = 2x2 MFMA
-// blocks of 32x32), K slabs of 32, next slab prefetched into registers
-// while the current one is multiplied from LDS.
+// blocks of 32x32), K slabs of 32, double-buffered in LDS (120 KB): while the
+// waves multiply slab s from one buffer, slab s+1 is written to the other
+// from registers and slab s+2 is fetched from memory; one barrier per slab.
 #include "mpg_internal.h"
 
 namespace mpg {
@@ -29,6 +31,10 @@ namespace {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+// native vector types (HIP's uint4/float4 classes defeat register promotion)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 constexpr int TB = 128, TK = 32, LDK = TK + 8;
 
@@ -38,75 +44,148 @@ struct Pieces {
     bf16 l[TB][LDK];
 };
 
+struct Stage {
+    Pieces A, B;
+};
+
 // C/D layout of v_mfma_f32_32x32x16_bf16 (measured): register r of lane l
 // holds D[8(r/4) + 4(l/32) + r%4][l%32]; A rows are lane%32 with K elements
 // 8(l/32)..+7, B columns lane%32 with the same K elements.
 __device__ inline int d_row(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
 
-__device__ inline void split3(double v, bf16 &h, bf16 &m, bf16 &l) {
-    h = (bf16)(float)v;
-    double r = v - (double)(float)h;
-    m = (bf16)(float)r;
-    double r2 = r - (double)(float)m;
-    l = (bf16)(float)r2;
+// three bf16 pieces of an FP32 value (exact: 24 significant bits)
+__device__ inline void split3f(float v, bf16 &h, bf16 &m, bf16 &l) {
+    h = (bf16)v;
+    float r = v - (float)h;
+    m = (bf16)r;
+    l = (bf16)(r - (float)m);
 }
 
-template <typename T>
-__device__ inline double ldd(const T *p) { return (double)*p; }
+// rho_Yin +- rho_Yang rounded once to FP32 (the split path's input precision)
+__device__ inline float fold(float a, float b, bool odd) { return odd ? a - b : a + b; }
+__device__ inline float fold(double a, double b, bool odd) { return (float)(odd ? a - b : a + b); }
 
-// the six partial products of one 32x32x16 step into acc
-__device__ inline void mma6(v16f &acc, const v8bf &ah, const v8bf &am, const v8bf &al, const v8bf &bh,
-                            const v8bf &bm, const v8bf &bl) {
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-}
-
-// one 32-deep slab from LDS for a wave's 64x64 tile
+// one 32-deep slab from LDS for a wave's 64x64 tile: for each 16-deep step
+// the six partial products are issued product by product over the four
+// accumulators, smallest weight first, so consecutive MFMAs never depend on
+// each other.
 __device__ inline void mma_slab(const Pieces &A, const Pieces &B, int wm, int wn, int lane, v16f (&acc)[2][2]) {
     const int lr = lane & 31, lk = 8 * (lane >> 5);
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 16) {
-        v8bf ah[2], am[2], al[2], bh[2], bm[2], bl[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            ah[i] = *(const v8bf *)&A.h[wm + 32 * i + lr][ks + lk];
-            am[i] = *(const v8bf *)&A.m[wm + 32 * i + lr][ks + lk];
-            al[i] = *(const v8bf *)&A.l[wm + 32 * i + lr][ks + lk];
-            bh[i] = *(const v8bf *)&B.h[wn + 32 * i + lr][ks + lk];
-            bm[i] = *(const v8bf *)&B.m[wn + 32 * i + lr][ks + lk];
-            bl[i] = *(const v8bf *)&B.l[wn + 32 * i + lr][ks + lk];
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) mma6(acc[i][j], ah[i], am[i], al[i], bh[j], bm[j], bl[j]);
+        v8bf ah0, ah1, am0, am1, al0, al1, bh0, bh1, bm0, bm1, bl0, bl1;
+        ah0 = *(const v8bf *)&A.h[wm + lr][ks + lk];
+        ah1 = *(const v8bf *)&A.h[wm + 32 + lr][ks + lk];
+        am0 = *(const v8bf *)&A.m[wm + lr][ks + lk];
+        am1 = *(const v8bf *)&A.m[wm + 32 + lr][ks + lk];
+        al0 = *(const v8bf *)&A.l[wm + lr][ks + lk];
+        al1 = *(const v8bf *)&A.l[wm + 32 + lr][ks + lk];
+        bh0 = *(const v8bf *)&B.h[wn + lr][ks + lk];
+        bh1 = *(const v8bf *)&B.h[wn + 32 + lr][ks + lk];
+        bm0 = *(const v8bf *)&B.m[wn + lr][ks + lk];
+        bm1 = *(const v8bf *)&B.m[wn + 32 + lr][ks + lk];
+        bl0 = *(const v8bf *)&B.l[wn + lr][ks + lk];
+        bl1 = *(const v8bf *)&B.l[wn + 32 + lr][ks + lk];
+#define MM4(X0, X1, Y0, Y1)                                                              \
+    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X0, Y0, acc[0][0], 0, 0, 0); \
+    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X0, Y1, acc[0][1], 0, 0, 0); \
+    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X1, Y0, acc[1][0], 0, 0, 0); \
+    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X1, Y1, acc[1][1], 0, 0, 0)
+        MM4(al0, al1, bh0, bh1);
+        MM4(am0, am1, bm0, bm1);
+        MM4(ah0, ah1, bl0, bl1);
+        MM4(am0, am1, bh0, bh1);
+        MM4(ah0, ah1, bm0, bm1);
+        MM4(ah0, ah1, bh0, bh1);
+#undef MM4
     }
 }
 
+// 16 consecutive K values of the three pieces of one row, held in registers
 struct Raw16 {
-    uint4 v[2];  // 16 bf16
+    u32x4 h0, h1, m0, m1, l0, l1;
 };
 
-__device__ inline void load_pieces(Raw16 (&r)[3], const bf16 *h, const bf16 *m, const bf16 *l, size_t off) {
-    r[0].v[0] = *(const uint4 *)(h + off);
-    r[0].v[1] = *(const uint4 *)(h + off + 8);
-    r[1].v[0] = *(const uint4 *)(m + off);
-    r[1].v[1] = *(const uint4 *)(m + off + 8);
-    r[2].v[0] = *(const uint4 *)(l + off);
-    r[2].v[1] = *(const uint4 *)(l + off + 8);
+__device__ __forceinline__ void load_pieces(Raw16 &r, const bf16 *h, const bf16 *m, const bf16 *l, size_t off) {
+    r.h0 = *(const u32x4 *)(h + off);
+    r.h1 = *(const u32x4 *)(h + off + 8);
+    r.m0 = *(const u32x4 *)(m + off);
+    r.m1 = *(const u32x4 *)(m + off + 8);
+    r.l0 = *(const u32x4 *)(l + off);
+    r.l1 = *(const u32x4 *)(l + off + 8);
 }
 
-__device__ inline void store_pieces(Pieces &S, const Raw16 (&r)[3], int row, int k) {
-    *(uint4 *)&S.h[row][k] = r[0].v[0];
-    *(uint4 *)&S.h[row][k + 8] = r[0].v[1];
-    *(uint4 *)&S.m[row][k] = r[1].v[0];
-    *(uint4 *)&S.m[row][k + 8] = r[1].v[1];
-    *(uint4 *)&S.l[row][k] = r[2].v[0];
-    *(uint4 *)&S.l[row][k + 8] = r[2].v[1];
+__device__ __forceinline__ void store_pieces(Pieces &S, const Raw16 &r, int row, int k) {
+    *(u32x4 *)&S.h[row][k] = r.h0;
+    *(u32x4 *)&S.h[row][k + 8] = r.h1;
+    *(u32x4 *)&S.m[row][k] = r.m0;
+    *(u32x4 *)&S.m[row][k + 8] = r.m1;
+    *(u32x4 *)&S.l[row][k] = r.l0;
+    *(u32x4 *)&S.l[row][k + 8] = r.l1;
+}
+
+__device__ __forceinline__ uint32_t pack2(bf16 a, bf16 b) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+__device__ __forceinline__ void store_split(Pieces &S, const float (&av)[16], int row, int k) {
+    uint32_t h[8], m[8], l[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        bf16 h0, m0, l0, h1, m1, l1;
+        split3f(av[2 * q], h0, m0, l0);
+        split3f(av[2 * q + 1], h1, m1, l1);
+        h[q] = pack2(h0, h1);
+        m[q] = pack2(m0, m1);
+        l[q] = pack2(l0, l1);
+    }
+    *(u32x4 *)&S.h[row][k] = (u32x4){h[0], h[1], h[2], h[3]};
+    *(u32x4 *)&S.h[row][k + 8] = (u32x4){h[4], h[5], h[6], h[7]};
+    *(u32x4 *)&S.m[row][k] = (u32x4){m[0], m[1], m[2], m[3]};
+    *(u32x4 *)&S.m[row][k + 8] = (u32x4){m[4], m[5], m[6], m[7]};
+    *(u32x4 *)&S.l[row][k] = (u32x4){l[0], l[1], l[2], l[3]};
+    *(u32x4 *)&S.l[row][k + 8] = (u32x4){l[4], l[5], l[6], l[7]};
+}
+
+// 16 consecutive values of rho_Yin +- rho_Yang (or rho) of one row, in FP32.
+// vec: n_ang % 16 == 0, so the 16 values are all inside the row or all
+// outside it, and 16-byte aligned.
+template <typename T, bool FOLD>
+__device__ __forceinline__ void load_rho(float (&av)[16], const T *r0, const T *r1, int k, int n_ang, bool row_ok,
+                                         bool odd, bool vec) {
+    if (vec) {
+        if (row_ok && k < n_ang) {
+            if (sizeof(T) == 4) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    f32x4 x = *(const f32x4 *)(r0 + k + 4 * q);
+                    f32x4 y = FOLD ? *(const f32x4 *)(r1 + k + 4 * q) : (f32x4){0.f, 0.f, 0.f, 0.f};
+                    av[4 * q + 0] = FOLD ? fold(x.x, y.x, odd) : x.x;
+                    av[4 * q + 1] = FOLD ? fold(x.y, y.y, odd) : x.y;
+                    av[4 * q + 2] = FOLD ? fold(x.z, y.z, odd) : x.z;
+                    av[4 * q + 3] = FOLD ? fold(x.w, y.w, odd) : x.w;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    f64x2 x = *(const f64x2 *)(r0 + k + 2 * q);
+                    f64x2 y = FOLD ? *(const f64x2 *)(r1 + k + 2 * q) : (f64x2){0.0, 0.0};
+                    av[2 * q + 0] = FOLD ? fold(x.x, y.x, odd) : (float)x.x;
+                    av[2 * q + 1] = FOLD ? fold(x.y, y.y, odd) : (float)x.y;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) av[q] = 0.0f;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            float v = 0.0f;
+            if (row_ok && k + q < n_ang) v = FOLD ? fold(r0[k + q], r1[k + q], odd) : (float)r0[k + q];
+            av[q] = v;
+        }
+    }
 }
 
 __device__ inline void zero(v16f (&acc)[2][2]) {
@@ -126,7 +205,7 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
                                                const bf16 *__restrict__ Uh, const bf16 *__restrict__ Um,
                                                const bf16 *__restrict__ Ul, int n_angp, int np, int ne_p,
                                                int tiles_e, int kchunk, int flush, double *__restrict__ Bpart) {
-    __shared__ Pieces As, Bs;
+    __shared__ Stage st[2];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
     const int tn = blockIdx.x;
@@ -136,6 +215,7 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
     const int m0 = blockIdx.y * TB;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(n_angp, kbeg + kchunk);
+    const int nsl = kend > kbeg ? (kend - kbeg) / TK : 0;
 
     // loader: thread t covers row t/2 and 16 K values from 16*(t%2)
     const int lr = t >> 1, lk = (t & 1) * 16;
@@ -146,6 +226,9 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
     const T *r0 = rho + f * fld + (size_t)i * n_ang;
     const T *r1 = r0 + (size_t)n_r * n_ang;
     const size_t uoff = (size_t)(c0 + lr) * n_angp;
+    // n_ang % 16 == 0: a thread's 16 values are all inside the row or all
+    // outside, and aligned for vector loads
+    const bool vec = (n_ang & 15) == 0;
 
     v16f acc[2][2];
     double acc64[2][2][16];
@@ -157,33 +240,32 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
 
-    double av[16];
-    Raw16 bu[3];
-    auto load = [&](int k) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            double v = 0.0;
-            if (row_ok && k + q < n_ang) {
-                v = ldd(r0 + k + q);
-                if (FOLD) {
-                    double w = ldd(r1 + k + q);
-                    v = odd ? v - w : v + w;
-                }
-            }
-            av[q] = v;
+    float av[16];
+    Raw16 bu;
+    if (nsl > 0) {
+        load_rho<T, FOLD>(av, r0, r1, kbeg + lk, n_ang, row_ok, odd, vec);
+        load_pieces(bu, Uh, Um, Ul, uoff + kbeg + lk);
+        store_split(st[0].A, av, lr, lk);
+        store_pieces(st[0].B, bu, lr, lk);
+        if (nsl > 1) {
+            load_rho<T, FOLD>(av, r0, r1, kbeg + TK + lk, n_ang, row_ok, odd, vec);
+            load_pieces(bu, Uh, Um, Ul, uoff + kbeg + TK + lk);
         }
-        load_pieces(bu, Uh, Um, Ul, uoff + k);
-    };
-    if (kbeg < kend) load(kbeg + lk);
+    }
+    __syncthreads();
     int step = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 16; ++q) split3(av[q], As.h[lr][lk + q], As.m[lr][lk + q], As.l[lr][lk + q]);
-        store_pieces(Bs, bu, lr, lk);
-        __syncthreads();
-        if (k0 + TK < kend) load(k0 + TK + lk);
-        mma_slab(As, Bs, wm, wn, lane, acc);
+    for (int s = 0; s < nsl; ++s) {
+        const int cur = s & 1;
+        if (s + 1 < nsl) {
+            store_split(st[cur ^ 1].A, av, lr, lk);
+            store_pieces(st[cur ^ 1].B, bu, lr, lk);
+            if (s + 2 < nsl) {
+                const int k = kbeg + (s + 2) * TK + lk;
+                load_rho<T, FOLD>(av, r0, r1, k, n_ang, row_ok, odd, vec);
+                load_pieces(bu, Uh, Um, Ul, uoff + k);
+            }
+        }
+        mma_slab(st[cur].A, st[cur].B, wm, wn, lane, acc);
         if (++step == flush) {
             step = 0;
 #pragma unroll
@@ -194,6 +276,7 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
                     for (int r = 0; r < 16; ++r) acc64[a][b][r] += (double)acc[a][b][r];
             zero(acc);
         }
+        __syncthreads();
     }
     double *out = Bpart + (size_t)blockIdx.z * rows * np;
 #pragma unroll
@@ -209,14 +292,55 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
 }
 
 // ---------------------------------------------------------------------------
-// GEMM2: grid x = row tile, y = angular tile.
+// One column block of GEMM2 (nsl slabs starting at column cbase), walked
+// from its top slab down to cbase, double-buffered through st.
+__device__ __forceinline__ void gemm2_block(Stage (&st)[2], const bf16 *Mh, const bf16 *Mm, const bf16 *Ml,
+                                            const bf16 *Qh, const bf16 *Qm, const bf16 *Ql, size_t aoff,
+                                            size_t boff, bool row_ok, int cbase, int nsl, int lr, int lk, int wm,
+                                            int wn, int lane, v16f (&acc)[2][2]) {
+    Raw16 ra, rb;
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    ra.h0 = ra.h1 = ra.m0 = ra.m1 = ra.l0 = ra.l1 = z;
+    if (nsl > 0) {
+        int k = cbase + (nsl - 1) * TK + lk;
+        if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
+        load_pieces(rb, Qh, Qm, Ql, boff + k);
+        store_pieces(st[0].A, ra, lr, lk);
+        store_pieces(st[0].B, rb, lr, lk);
+        if (nsl > 1) {
+            k -= TK;
+            if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
+            load_pieces(rb, Qh, Qm, Ql, boff + k);
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < nsl; ++s) {
+        const int cur = s & 1;
+        if (s + 1 < nsl) {
+            store_pieces(st[cur ^ 1].A, ra, lr, lk);
+            store_pieces(st[cur ^ 1].B, rb, lr, lk);
+            if (s + 2 < nsl) {
+                const int k = cbase + (nsl - 3 - s) * TK + lk;
+                if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
+                load_pieces(rb, Qh, Qm, Ql, boff + k);
+            }
+        }
+        mma_slab(st[cur].A, st[cur].B, wm, wn, lane, acc);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM2: grid x = row tile, y = angular tile.  The K slabs of the even
+// block are followed by those of the odd block, each block walked from its
+// top down to its first column.
 template <typename T, bool FOLD>
 __global__ __launch_bounds__(256) void k_gemm2(const bf16 *__restrict__ Mh, const bf16 *__restrict__ Mm,
                                                const bf16 *__restrict__ Ml, int rows, int np, int ne_p,
                                                const bf16 *__restrict__ Qh, const bf16 *__restrict__ Qm,
                                                const bf16 *__restrict__ Ql, int n_ang, int n_r,
                                                T *__restrict__ phi) {
-    __shared__ Pieces As, Bs;
+    __shared__ Stage st[2];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
     const int m0 = blockIdx.x * TB, n0 = blockIdx.y * TB;
@@ -224,37 +348,15 @@ __global__ __launch_bounds__(256) void k_gemm2(const bf16 *__restrict__ Mh, cons
     const bool row_ok = m0 + lr < rows;
     const size_t aoff = (size_t)(row_ok ? m0 + lr : 0) * np;
     const size_t boff = (size_t)(n0 + lr) * np;
-
-    v16f acc[2][2][2];
-    zero(acc[0]);
-    zero(acc[1]);
-    const int nblk = FOLD ? 2 : 1;
-#pragma unroll
-    for (int blk = 0; blk < nblk; ++blk) {
-        const int kb = blk ? ne_p : 0, ke = (FOLD && !blk) ? ne_p : np;
-        Raw16 ra[3], rb[3];
-        // K slabs from the top of the block down to kb (columns are ordered
-        // by degree, so the largest terms are added last)
-        const int nsl = (ke - kb + TK - 1) / TK;
-        auto load = [&](int s) {
-            int k = kb + (nsl - 1 - s) * TK + lk;
-            if (row_ok) {
-                load_pieces(ra, Mh, Mm, Ml, aoff + k);
-            } else {
-#pragma unroll
-                for (int p = 0; p < 3; ++p) ra[p].v[0] = ra[p].v[1] = make_uint4(0, 0, 0, 0);
-            }
-            load_pieces(rb, Qh, Qm, Ql, boff + k);
-        };
-        if (nsl > 0) load(0);
-        for (int s = 0; s < nsl; ++s) {
-            __syncthreads();
-            store_pieces(As, ra, lr, lk);
-            store_pieces(Bs, rb, lr, lk);
-            __syncthreads();
-            if (s + 1 < nsl) load(s + 1);
-            mma_slab(As, Bs, wm, wn, lane, acc[blk]);
-        }
+    v16f acc_e[2][2], acc_o[2][2];
+    zero(acc_e);
+    zero(acc_o);
+    if (FOLD) {
+        gemm2_block(st, Mh, Mm, Ml, Qh, Qm, Ql, aoff, boff, row_ok, 0, ne_p / TK, lr, lk, wm, wn, lane, acc_e);
+        gemm2_block(st, Mh, Mm, Ml, Qh, Qm, Ql, aoff, boff, row_ok, ne_p, (np - ne_p) / TK, lr, lk, wm, wn, lane,
+                    acc_o);
+    } else {
+        gemm2_block(st, Mh, Mm, Ml, Qh, Qm, Ql, aoff, boff, row_ok, 0, np / TK, lr, lk, wm, wn, lane, acc_e);
     }
     const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
 #pragma unroll
@@ -268,9 +370,9 @@ __global__ __launch_bounds__(256) void k_gemm2(const bf16 *__restrict__ Mh, cons
                 if (rr >= rows || jk >= n_ang) continue;
                 int f = rr / n_r, i = rr - f * n_r;
                 T *o = phi + f * fld + (size_t)i * n_ang + jk;
-                double e = (double)acc[0][a][b][r];
+                double e = (double)acc_e[a][b][r];
                 if (FOLD) {
-                    double od = (double)acc[1][a][b][r];
+                    double od = (double)acc_o[a][b][r];
                     o[0] = (T)(e + od);
                     o[(size_t)n_r * n_ang] = (T)(e - od);
                 } else {

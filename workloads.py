@@ -143,14 +143,24 @@ class Blobs:
     amp: np.ndarray
 
     def __call__(self, x, y, z, xp):
+        if xp == "torch":
+            # all blobs at once, in groups that bound the temporary size
+            import torch
+            c = torch.tensor(np.asarray(self.centres), dtype=x.dtype, device=x.device)
+            inv = torch.tensor(-0.5 / np.asarray(self.sigma) ** 2, dtype=x.dtype, device=x.device)
+            amp = torch.tensor(np.asarray(self.amp), dtype=x.dtype, device=x.device)
+            xs, ys, zs = x.reshape(-1, 1), y.reshape(-1, 1), z.reshape(-1, 1)
+            out = torch.zeros(xs.shape[0], dtype=x.dtype, device=x.device)
+            step = 16
+            for b0 in range(0, c.shape[0], step):
+                b1 = min(c.shape[0], b0 + step)
+                d2 = (xs - c[b0:b1, 0]) ** 2 + (ys - c[b0:b1, 1]) ** 2 + (zs - c[b0:b1, 2]) ** 2
+                out += (amp[b0:b1] * torch.exp(d2 * inv[b0:b1])).sum(dim=1)
+            return out.reshape(x.shape)
         out = 0.0 * x
         for (cx, cy, cz), s, a in zip(self.centres, self.sigma, self.amp):
             d2 = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2
-            if xp == "torch":
-                import torch
-                out = out + a * torch.exp(-d2 / (2 * s * s))
-            else:
-                out = out + a * np.exp(-d2 / (2 * s * s))
+            out = out + a * np.exp(-d2 / (2 * s * s))
         return out
 
 
@@ -203,7 +213,7 @@ def cell_average(grid: Grid, density, sub=4, device="cpu", shells_per_chunk=None
     wang = st[:, :, None, None].expand_as(ux)
     if shells_per_chunk is None:
         per_shell = grid.n_ang * sub ** 3
-        budget = 3e7 if dev.type == "cuda" else 4e6
+        budget = 8e6 if dev.type == "cuda" else 4e6
         shells_per_chunk = max(1, int(budget // per_shell))
     r_edges = torch.tensor(grid.r_edges, dtype=f64, device=dev)
     for g in range(grid.n_patches):
