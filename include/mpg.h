@@ -107,14 +107,27 @@ int mpg_moments(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
 int mpg_potential(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
                   void *phi, int phi_dtype);
 
-/* Solve n independent fields with possibly different plans (grid sizes and
- * lmax) in one persistent kernel launch per step, so that small fields do
- * not each pay a launch.  rho[f] and phi[f] are device pointers of field f
- * (one field each), of element type dtype.  All plans must share precision
- * and stream; the work runs on plans[0]'s stream.
+/* Solve n independent fields with different plans (grid sizes and lmax)
+ * together: one persistent work-queue kernel per stage (moments, radial
+ * scans, expansion) holds the tiles of every field, longest first, and the
+ * three launches are captured once in a hipGraph (per set of plans and
+ * dtype) and replayed.  rho[f] and phi[f] are device pointers of field f
+ * (one field each), of element type dtype.  The plans must be distinct and
+ * share precision; the work runs on plans[0]'s stream.  Not for concurrent
+ * use from several host threads with the same plans.
  * Errors: MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE. */
 int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho,
                         void *const *phi, int dtype);
+
+/* Autotune the plan for n_fields fields: time the moment contraction for
+ * every K split the work space allows (powers of two and the default
+ * choice) and the radial scan for 4, 8 and 16 shell chunks per column, on
+ * the given device input, and keep the fastest for later calls (including
+ * mpg_potential_batch).  Blocks until done; overwrites the plan's work
+ * space.  splitk and chunks (may be NULL) receive the choices.
+ * Errors: as mpg_moments. */
+int mpg_autotune(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
+                 int *splitk, int *chunks);
 
 /* Copy the plan's FP64 tables to device buffers, in the real index:
  *   U : [n_patches][n_theta*n_phi][n_lm]   (Eqs. U_C/U_S), or NULL

@@ -23,7 +23,7 @@ MPG_F64, MPG_F32 = 0, 1
 PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16}
 
 # Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
-EXPORTS = ("mpg_plan", "mpg_moments", "mpg_potential", "mpg_potential_batch", "mpg_tables",
+EXPORTS = ("mpg_plan", "mpg_moments", "mpg_potential", "mpg_potential_batch", "mpg_autotune", "mpg_tables",
            "mpg_plan_info", "mpg_timing", "mpg_stage_times", "mpg_sync", "mpg_destroy", "mpg_last_error")
 STAGES = ("moments", "radial_scan", "expansion")
 
@@ -60,6 +60,7 @@ def lib():
         L.mpg_moments.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp]
         L.mpg_potential.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int]
         L.mpg_potential_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
+        L.mpg_autotune.argtypes = [vp, C.c_int, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.mpg_tables.argtypes = [vp, vp, vp, vp]
         L.mpg_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]
         L.mpg_timing.argtypes = [vp, C.c_int]
@@ -167,6 +168,15 @@ class Plan:
         _check(lib().mpg_moments(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
                                  C.c_void_p(B.data_ptr()), C.c_void_p(M.data_ptr())))
         return B, M
+
+    def autotune(self, rho):
+        """Time the K split of the moment contraction and the scan schedule
+        on this input and keep the fastest; returns (splitk, chunks)."""
+        n = self._fields(rho)
+        sk, ch = C.c_int(), C.c_int()
+        _check(lib().mpg_autotune(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
+                                  C.byref(sk), C.byref(ch)))
+        return sk.value, ch.value
 
     def tables(self):
         """(U, Q, w) as float64 device tensors [n_patches, n_ang, n_lm], [n_ang]."""

@@ -1,0 +1,222 @@
+// Batched solve of many independent fields with different plans (grid
+// sizes, lmax) through persistent work-queue kernels, one per stage
+// (moment contraction, radial scans, expansion).  Each stage's queue holds
+// the tiles of every field, ordered longest first; the persistent blocks
+// pull tiles until the queue is empty.  The three launches and the counter
+// reset are captured once in a hipGraph and replayed; a call only refreshes
+// the fields' rho/phi pointers (kept in device memory, read by the kernels)
+// and launches the graph on the caller's stream.
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "mpg_internal.h"
+
+namespace mpg {
+namespace {
+
+__global__ void k_zero_ints(int *p, int n) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0;
+}
+
+struct Batch {
+    std::vector<const Plan *> plans;
+    int dtype = MPG_F64, precision = MPG_FP64;
+    int n1 = 0, ns = 0, n2 = 0;
+    std::vector<SplitArgs> sa;
+    std::vector<F64Args> fa;
+    std::vector<ScanArgs> sc;
+    void *args_dev = nullptr;
+    ScanArgs *scan_dev = nullptr;
+    BatchItem *items_dev = nullptr;
+    int *heads = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~Batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (args_dev) (void)hipFree(args_dev);
+        if (scan_dev) (void)hipFree(scan_dev);
+        if (items_dev) (void)hipFree(items_dev);
+        if (heads) (void)hipFree(heads);
+    }
+};
+
+std::mutex g_mu;
+std::vector<Batch *> g_batches;
+
+int cu_count() {
+    static int n = 0;
+    if (!n) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            n = prop.multiProcessorCount;
+        if (n <= 0) n = 256;
+    }
+    return n;
+}
+
+#define CHECK(x)                                  \
+    do {                                          \
+        hipError_t e_ = (x);                      \
+        if (e_ != hipSuccess) return e_;          \
+    } while (0)
+
+hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
+    b.plans = plans;
+    b.dtype = dtype;
+    b.precision = plans[0]->precision;
+    const int n = (int)plans.size();
+    const bool split = b.precision == MPG_SPLIT_BF16;
+    const int T1 = split ? kSplitTile : kF64Tile;
+
+    // work items per stage, longest first
+    std::vector<int> order(n);
+    for (int f = 0; f < n; ++f) order[f] = f;
+    std::vector<BatchItem> i1, is, i2;
+    std::vector<int> kchunk(n), tiles_e(n), tiles_o(n);
+    std::vector<Plan> q(n);
+    for (int f = 0; f < n; ++f) {
+        q[f] = *plans[f];
+        q[f].splitk = choose_splitk(q[f], 1);
+        const Plan &p = q[f];
+        if (split) {
+            SplitArgs g = split_args(p, 1, nullptr, nullptr, dtype);
+            b.sa.push_back(g);
+            kchunk[f] = g.kchunk;
+            tiles_e[f] = g.tiles_e;
+            tiles_o[f] = g.tiles_o;
+        } else {
+            F64Args g = f64_args(p, 1, nullptr, nullptr, dtype);
+            b.fa.push_back(g);
+            kchunk[f] = g.kchunk;
+            tiles_e[f] = g.tiles_e;
+            tiles_o[f] = g.tiles_o;
+        }
+        b.sc.push_back(scan_args(p, 1, split));
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return kchunk[a] > kchunk[c]; });
+    for (int f : order) {
+        const Plan &p = q[f];
+        const int rt = (p.n_r + T1 - 1) / T1;
+        for (int z = 0; z < p.splitk; ++z)
+            for (int m = 0; m < rt; ++m)
+                for (int c = 0; c < tiles_e[f] + tiles_o[f]; ++c) i1.push_back({f, c, m, z});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return q[a].n_r * q[a].splitk > q[c].n_r * q[c].splitk; });
+    for (int f : order)
+        for (int x = 0; x < b.sc[f].col_blocks; ++x) is.push_back({f, x, 0, 0});
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return q[a].np > q[c].np; });
+    for (int f : order) {
+        const Plan &p = q[f];
+        const int rt = (p.n_r + T1 - 1) / T1;
+        const int at = p.n_angp / T1;
+        for (int a = 0; a < at; ++a)
+            for (int m = 0; m < rt; ++m) i2.push_back({f, m, a, 0});
+    }
+    b.n1 = (int)i1.size();
+    b.ns = (int)is.size();
+    b.n2 = (int)i2.size();
+    std::vector<BatchItem> all;
+    all.reserve(i1.size() + is.size() + i2.size());
+    all.insert(all.end(), i1.begin(), i1.end());
+    all.insert(all.end(), is.begin(), is.end());
+    all.insert(all.end(), i2.begin(), i2.end());
+
+    const size_t asz = split ? sizeof(SplitArgs) * n : sizeof(F64Args) * n;
+    CHECK(hipMalloc(&b.args_dev, asz));
+    CHECK(hipMalloc(&b.scan_dev, sizeof(ScanArgs) * n));
+    CHECK(hipMalloc(&b.items_dev, sizeof(BatchItem) * all.size()));
+    CHECK(hipMalloc(&b.heads, sizeof(int) * 4));
+    CHECK(hipMemcpy(b.scan_dev, b.sc.data(), sizeof(ScanArgs) * n, hipMemcpyHostToDevice));
+    CHECK(hipMemcpy(b.items_dev, all.data(), sizeof(BatchItem) * all.size(), hipMemcpyHostToDevice));
+
+    // capture: counter reset (a kernel, not a memset) and the three stages
+    CHECK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+    CHECK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
+    const int cus = cu_count();
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, b.cap, b.heads, 4);
+    const BatchItem *it1 = b.items_dev, *its = b.items_dev + b.n1, *it2 = b.items_dev + b.n1 + b.ns;
+    hipError_t e;
+    if (split) {
+        e = batch_gemm1_bf16((const SplitArgs *)b.args_dev, it1, b.n1, b.heads + 0, dtype, cus, b.cap);
+        if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);
+        if (e == hipSuccess) e = batch_gemm2_bf16((const SplitArgs *)b.args_dev, it2, b.n2, b.heads + 2, dtype, cus, b.cap);
+    } else {
+        e = batch_gemm1_f64((const F64Args *)b.args_dev, it1, b.n1, b.heads + 0, dtype, 4 * cus, b.cap);
+        if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);
+        if (e == hipSuccess) e = batch_gemm2_f64((const F64Args *)b.args_dev, it2, b.n2, b.heads + 2, dtype, 4 * cus, b.cap);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b.cap, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    CHECK(e2);
+    b.graph = g;
+    CHECK(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+    return hipSuccess;
+}
+
+Batch *find(const std::vector<const Plan *> &plans, int dtype) {
+    for (Batch *b : g_batches)
+        if (b->dtype == dtype && b->plans == plans) return b;
+    return nullptr;
+}
+
+}  // namespace
+
+hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *const *rho, void *const *phi,
+                           int dtype, hipStream_t stream) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    Batch *b = find(plans, dtype);
+    if (!b) {
+        b = new (std::nothrow) Batch();
+        if (!b) return hipErrorOutOfMemory;
+        hipError_t e = build(*b, plans, dtype);
+        if (e != hipSuccess) {
+            delete b;
+            return e;
+        }
+        g_batches.push_back(b);
+    }
+    const int n = (int)plans.size();
+    if (b->precision == MPG_SPLIT_BF16) {
+        for (int f = 0; f < n; ++f) {
+            b->sa[f].rho = rho[f];
+            b->sa[f].phi = phi[f];
+        }
+        CHECK(hipMemcpyAsync(b->args_dev, b->sa.data(), sizeof(SplitArgs) * n, hipMemcpyHostToDevice, stream));
+    } else {
+        for (int f = 0; f < n; ++f) {
+            b->fa[f].rho = rho[f];
+            b->fa[f].phi = phi[f];
+        }
+        CHECK(hipMemcpyAsync(b->args_dev, b->fa.data(), sizeof(F64Args) * n, hipMemcpyHostToDevice, stream));
+    }
+    return hipGraphLaunch(b->exec, stream);
+}
+
+void forget_plan(const Plan *p) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (size_t k = 0; k < g_batches.size();) {
+        Batch *b = g_batches[k];
+        if (std::find(b->plans.begin(), b->plans.end(), p) != b->plans.end()) {
+            (void)hipDeviceSynchronize();
+            delete b;
+            g_batches.erase(g_batches.begin() + k);
+        } else {
+            ++k;
+        }
+    }
+}
+
+}  // namespace mpg

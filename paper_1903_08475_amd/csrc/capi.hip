@@ -7,6 +7,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "mpg_internal.h"
 
@@ -67,6 +69,7 @@ void clear_events(Plan *p) {
 
 void free_plan(mpg_plan_s *p) {
     if (!p) return;
+    forget_plan(p);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *bufs[] = {p->col_src, p->col_l, p->Ut,    p->Qt,   p->coef, p->w,    p->Ut_hi, p->Ut_mid, p->Ut_lo,
                     p->Qt_hi,   p->Qt_mid, p->Qt_lo, p->Bpart, p->Bred, p->M, p->M_hi,  p->M_mid,  p->M_lo};
@@ -77,19 +80,26 @@ void free_plan(mpg_plan_s *p) {
     delete p;
 }
 
-// K splits of the moment contraction for n_fields fields: enough blocks to
-// cover the chip, never more than the plan's work space holds.
+}  // namespace
+
+// K splits of the moment contraction for n_fields fields: the autotuned
+// choice if there is one, else enough blocks to cover the chip; never more
+// than the plan's work space holds.
 int choose_splitk(const Plan &p, int n_fields) {
-    int col_tiles = p.fold ? (p.ne_p + 63) / 64 + (p.no_p + 63) / 64 : (p.np + 63) / 64;
-    int row_tiles = (n_fields * p.n_r + 63) / 64;
-    int tiles = col_tiles * row_tiles;
-    int s = (1024 + tiles - 1) / tiles;
+    int s;
+    if (p.splitk_sel > 0) {
+        s = p.splitk_sel;
+    } else {
+        int col_tiles = p.fold ? (p.ne_p + 63) / 64 + (p.no_p + 63) / 64 : (p.np + 63) / 64;
+        int row_tiles = (n_fields * p.n_r + 63) / 64;
+        int tiles = col_tiles * row_tiles;
+        s = (1024 + tiles - 1) / tiles;
+    }
     if (s > p.splitk) s = p.splitk;
     if (s < 1) s = 1;
     return s;
 }
 
-}  // namespace
 }  // namespace mpg
 
 using namespace mpg;
@@ -292,19 +302,89 @@ int mpg_potential(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, vo
 }
 
 int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho, void *const *phi, int dtype) {
-    if (n < 0 || (n > 0 && (!plans || !rho || !phi))) return fail(MPG_EINVAL, "mpg_potential_batch: bad arguments");
+    if (n < 1 || !plans || !rho || !phi) return fail(MPG_EINVAL, "mpg_potential_batch: bad arguments");
+    if (dtype != MPG_F64 && dtype != MPG_F32) return fail(MPG_EINVAL, "mpg_potential_batch: bad dtype");
+    std::vector<const Plan *> ps(n);
     for (int f = 0; f < n; ++f) {
         if (!plans[f]) return fail(MPG_EINVAL, "mpg_potential_batch: NULL plan");
+        if (!rho[f] || !phi[f]) return fail(MPG_EINVAL, "mpg_potential_batch: NULL field");
         if (plans[f]->precision != plans[0]->precision)
             return fail(MPG_EINVAL, "mpg_potential_batch: plans differ in precision");
+        for (int g = 0; g < f; ++g)
+            if (plans[g] == plans[f])
+                return fail(MPG_EINVAL, "mpg_potential_batch: a plan appears twice (they own their work space)");
+        ps[f] = plans[f];
     }
-    for (int f = 0; f < n; ++f) {
-        if (!rho[f] || !phi[f]) return fail(MPG_EINVAL, "mpg_potential_batch: NULL field");
-        Plan q = *plans[f];
-        q.stream = plans[0]->stream;
-        int rc = solve(&q, 1, rho[f], dtype, phi[f], dtype);
-        if (rc) return rc;
+    hipError_t e = potential_batch(ps, rho, phi, dtype, plans[0]->stream);
+    if (e != hipSuccess) return hip_fail(e, "mpg_potential_batch");
+    return MPG_OK;
+}
+
+int mpg_autotune(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, int *splitk, int *chunks) {
+    int rc = check_call(p, n_fields, rho, rho_dtype, "mpg_autotune");
+    if (rc) return rc;
+    hipEvent_t a, b;
+    hipError_t e;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, "mpg_autotune");
+    if ((e = hipEventCreate(&b)) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(e, "mpg_autotune");
     }
+    const bool split = p->precision == MPG_SPLIT_BF16;
+    auto time_stage = [&](int sk, int ch, bool scan, float *ms) -> hipError_t {
+        Plan q = *p;
+        q.splitk = sk;
+        q.scan_chunks = ch;
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {  // first run is a warm-up
+            hipError_t err;
+            if ((err = hipEventRecord(a, q.stream)) != hipSuccess) return err;
+            if (scan) err = radial_scan(q, n_fields, split);
+            else err = split ? gemm1_bf16(q, n_fields, rho, rho_dtype) : gemm1_f64(q, n_fields, rho, rho_dtype);
+            if (err != hipSuccess) return err;
+            if ((err = hipEventRecord(b, q.stream)) != hipSuccess) return err;
+            if ((err = hipEventSynchronize(b)) != hipSuccess) return err;
+            float t = 0.0f;
+            if ((err = hipEventElapsedTime(&t, a, b)) != hipSuccess) return err;
+            if (rep > 0 && t < best) best = t;
+        }
+        *ms = best;
+        return hipSuccess;
+    };
+    // K splits: powers of two up to the work space, plus the heuristic choice
+    std::vector<int> cands;
+    p->splitk_sel = 0;
+    int heur = choose_splitk(*p, n_fields);
+    for (int s = 1; s <= p->splitk; s *= 2) cands.push_back(s);
+    if (std::find(cands.begin(), cands.end(), heur) == cands.end()) cands.push_back(heur);
+    int best_s = heur;
+    float best_t = 1e30f;
+    for (int s : cands) {
+        float t;
+        if ((e = time_stage(s, p->scan_chunks, false, &t)) != hipSuccess) break;
+        if (t < best_t) { best_t = t; best_s = s; }
+    }
+    int best_c = p->scan_chunks;
+    if (e == hipSuccess) {
+        // scan schedule: shell chunks per column (the scan reads best_s partial sums)
+        float tc = 1e30f;
+        if ((e = time_stage(best_s, 16, false, &tc)) == hipSuccess) {  // leave matching partials in place
+            tc = 1e30f;
+            for (int ch : {4, 8, 16}) {
+                if (ch > p->n_r && ch != 4) continue;
+                float t;
+                if ((e = time_stage(best_s, ch, true, &t)) != hipSuccess) break;
+                if (t < tc) { tc = t; best_c = ch; }
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "mpg_autotune");
+    p->splitk_sel = best_s;
+    p->scan_chunks = best_c;
+    if (splitk) *splitk = best_s;
+    if (chunks) *chunks = best_c;
     return MPG_OK;
 }
 

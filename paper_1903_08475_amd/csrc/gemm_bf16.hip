@@ -36,7 +36,8 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-constexpr int TB = 128, TK = 32, LDK = TK + 8;
+constexpr int TB = kSplitTile, TK = 32, LDK = TK + 8;
+constexpr int kFlush1 = 16;  // GEMM1: FP32 runs of at most 512 terms
 
 struct Pieces {
     bf16 h[TB][LDK];
@@ -198,23 +199,20 @@ __device__ inline void zero(v16f (&acc)[2][2]) {
 }
 
 // ---------------------------------------------------------------------------
-// GEMM1: grid x = column tile (even-m tiles, then odd-m tiles), y = row tile,
-// z = K split.  Bpart[z][row][col] in FP64.
+// One output tile of GEMM1 (column tile tn: even-m tiles first, then odd-m
+// tiles; row tile tm; K split tz).  Writes Bpart[tz][row][col] in FP64.
 template <typename T, bool FOLD>
-__global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int rows, int n_r, int n_ang,
-                                               const bf16 *__restrict__ Uh, const bf16 *__restrict__ Um,
-                                               const bf16 *__restrict__ Ul, int n_angp, int np, int ne_p,
-                                               int tiles_e, int kchunk, int flush, double *__restrict__ Bpart) {
-    __shared__ Stage st[2];
+__device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, Stage (&st)[2]) {
+    const T *rho = (const T *)g.rho;
+    const int rows = g.rows, n_r = g.n_r, n_ang = g.n_ang, n_angp = g.n_angp, np = g.np, ne_p = g.ne_p;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-    const int tn = blockIdx.x;
-    const bool odd = FOLD && tn >= tiles_e;
-    const int c0 = odd ? ne_p + (tn - tiles_e) * TB : tn * TB;
+    const bool odd = FOLD && tn >= g.tiles_e;
+    const int c0 = odd ? ne_p + (tn - g.tiles_e) * TB : tn * TB;
     const int cend = odd ? np : (FOLD ? ne_p : np);
-    const int m0 = blockIdx.y * TB;
-    const int kbeg = blockIdx.z * kchunk;
-    const int kend = min(n_angp, kbeg + kchunk);
+    const int m0 = tm * TB;
+    const int kbeg = tz * g.kchunk;
+    const int kend = min(n_angp, kbeg + g.kchunk);
     const int nsl = kend > kbeg ? (kend - kbeg) / TK : 0;
 
     // loader: thread t covers row t/2 and 16 K values from 16*(t%2)
@@ -226,6 +224,7 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
     const T *r0 = rho + f * fld + (size_t)i * n_ang;
     const T *r1 = r0 + (size_t)n_r * n_ang;
     const size_t uoff = (size_t)(c0 + lr) * n_angp;
+    const bf16 *Uh = g.Uh, *Um = g.Um, *Ul = g.Ul;
     // n_ang % 16 == 0: a thread's 16 values are all inside the row or all
     // outside, and aligned for vector loads
     const bool vec = (n_ang & 15) == 0;
@@ -266,7 +265,7 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
             }
         }
         mma_slab(st[cur].A, st[cur].B, wm, wn, lane, acc);
-        if (++step == flush) {
+        if (++step == kFlush1) {
             step = 0;
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -278,7 +277,7 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
         }
         __syncthreads();
     }
-    double *out = Bpart + (size_t)blockIdx.z * rows * np;
+    double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -291,7 +290,6 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
             }
 }
 
-// ---------------------------------------------------------------------------
 // One column block of GEMM2 (nsl slabs starting at column cbase), walked
 // from its top slab down to cbase, double-buffered through st.
 __device__ __forceinline__ void gemm2_block(Stage (&st)[2], const bf16 *Mh, const bf16 *Mm, const bf16 *Ml,
@@ -330,33 +328,31 @@ __device__ __forceinline__ void gemm2_block(Stage (&st)[2], const bf16 *Mh, cons
     }
 }
 
-// ---------------------------------------------------------------------------
-// GEMM2: grid x = row tile, y = angular tile.  The K slabs of the even
-// block are followed by those of the odd block, each block walked from its
-// top down to its first column.
+// One output tile of GEMM2 (row tile tm, angular tile tn).  The K slabs of
+// the even block come first, then those of the odd block.
 template <typename T, bool FOLD>
-__global__ __launch_bounds__(256) void k_gemm2(const bf16 *__restrict__ Mh, const bf16 *__restrict__ Mm,
-                                               const bf16 *__restrict__ Ml, int rows, int np, int ne_p,
-                                               const bf16 *__restrict__ Qh, const bf16 *__restrict__ Qm,
-                                               const bf16 *__restrict__ Ql, int n_ang, int n_r,
-                                               T *__restrict__ phi) {
-    __shared__ Stage st[2];
+__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Stage (&st)[2]) {
+    T *phi = (T *)g.phi;
+    const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-    const int m0 = blockIdx.x * TB, n0 = blockIdx.y * TB;
+    const int m0 = tm * TB, n0 = tn * TB;
     const int lr = t >> 1, lk = (t & 1) * 16;
     const bool row_ok = m0 + lr < rows;
     const size_t aoff = (size_t)(row_ok ? m0 + lr : 0) * np;
     const size_t boff = (size_t)(n0 + lr) * np;
+
     v16f acc_e[2][2], acc_o[2][2];
     zero(acc_e);
     zero(acc_o);
     if (FOLD) {
-        gemm2_block(st, Mh, Mm, Ml, Qh, Qm, Ql, aoff, boff, row_ok, 0, ne_p / TK, lr, lk, wm, wn, lane, acc_e);
-        gemm2_block(st, Mh, Mm, Ml, Qh, Qm, Ql, aoff, boff, row_ok, ne_p, (np - ne_p) / TK, lr, lk, wm, wn, lane,
-                    acc_o);
+        gemm2_block(st, g.Mh, g.Mm, g.Ml, g.Qh, g.Qm, g.Ql, aoff, boff, row_ok, 0, ne_p / TK, lr, lk, wm, wn, lane,
+                    acc_e);
+        gemm2_block(st, g.Mh, g.Mm, g.Ml, g.Qh, g.Qm, g.Ql, aoff, boff, row_ok, ne_p, (np - ne_p) / TK, lr, lk, wm,
+                    wn, lane, acc_o);
     } else {
-        gemm2_block(st, Mh, Mm, Ml, Qh, Qm, Ql, aoff, boff, row_ok, 0, np / TK, lr, lk, wm, wn, lane, acc_e);
+        gemm2_block(st, g.Mh, g.Mm, g.Ml, g.Qh, g.Qm, g.Ql, aoff, boff, row_ok, 0, np / TK, lr, lk, wm, wn, lane,
+                    acc_e);
     }
     const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
 #pragma unroll
@@ -381,44 +377,131 @@ __global__ __launch_bounds__(256) void k_gemm2(const bf16 *__restrict__ Mh, cons
             }
 }
 
-constexpr int kFlush1 = 16;  // GEMM1: FP32 runs of at most 512 terms
+// ---------------------------------------------------------------------------
+// Grid launches for one plan: GEMM1 grid x = column tile, y = row tile,
+// z = K split; GEMM2 grid x = row tile, y = angular tile.
+template <typename T, bool FOLD>
+__global__ __launch_bounds__(256) void k_gemm1(SplitArgs g) {
+    __shared__ Stage st[2];
+    gemm1_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, st);
+}
+
+template <typename T, bool FOLD>
+__global__ __launch_bounds__(256) void k_gemm2(SplitArgs g) {
+    __shared__ Stage st[2];
+    gemm2_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, st);
+}
+
+// Persistent batch kernels: every block takes work items from a queue
+// (items[], ordered longest first) through an atomic head until the queue
+// is empty.  Item = (field, tile coordinates); args[] holds each field's
+// arguments.  No item waits on another, so every block exits.
+__device__ __forceinline__ int next_item(int *head, int *slot) {
+    if (threadIdx.x == 0) *slot = atomicAdd(head, 1);
+    __syncthreads();
+    int it = __builtin_amdgcn_readfirstlane(*slot);
+    __syncthreads();
+    return it;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_gemm1(const SplitArgs *__restrict__ args,
+                                                     const BatchItem *__restrict__ items, int n_items, int *head) {
+    __shared__ Stage st[2];
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(head, &slot);
+        if (it >= n_items) break;
+        const BatchItem w = items[it];
+        const SplitArgs g = args[w.f];
+        if (g.fold) gemm1_tile<T, true>(g, w.a, w.b, w.c, st);
+        else gemm1_tile<T, false>(g, w.a, w.b, w.c, st);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_gemm2(const SplitArgs *__restrict__ args,
+                                                     const BatchItem *__restrict__ items, int n_items, int *head) {
+    __shared__ Stage st[2];
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(head, &slot);
+        if (it >= n_items) break;
+        const BatchItem w = items[it];
+        const SplitArgs g = args[w.f];
+        if (g.fold) gemm2_tile<T, true>(g, w.a, w.b, st);
+        else gemm2_tile<T, false>(g, w.a, w.b, st);
+    }
+}
 
 }  // namespace
 
+SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype) {
+    SplitArgs g;
+    g.rho = rho;
+    g.phi = phi;
+    g.io_f64 = io_dtype == MPG_F64;
+    g.rows = n_fields * p.n_r;
+    g.n_r = p.n_r;
+    g.n_ang = p.n_ang;
+    g.n_angp = p.n_angp;
+    g.np = p.np;
+    g.ne_p = p.ne_p;
+    g.fold = p.fold;
+    g.tiles_e = p.fold ? (p.ne_p + TB - 1) / TB : (p.np + TB - 1) / TB;
+    g.tiles_o = p.fold ? (p.no_p + TB - 1) / TB : 0;
+    g.kchunk = ((p.n_angp / p.splitk + TK - 1) / TK) * TK;
+    g.splitk = p.splitk;
+    g.Uh = p.Ut_hi; g.Um = p.Ut_mid; g.Ul = p.Ut_lo;
+    g.Qh = p.Qt_hi; g.Qm = p.Qt_mid; g.Ql = p.Qt_lo;
+    g.Mh = p.M_hi; g.Mm = p.M_mid; g.Ml = p.M_lo;
+    g.Bpart = p.Bpart;
+    return g;
+}
+
+int split_tile_rows(int rows) { return (rows + TB - 1) / TB; }
+
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
-    const int rows = n_fields * p.n_r;
-    const int te = p.fold ? (p.ne_p + TB - 1) / TB : (p.np + TB - 1) / TB;
-    const int to = p.fold ? (p.no_p + TB - 1) / TB : 0;
-    const int kchunk = ((p.n_angp / p.splitk + TK - 1) / TK) * TK;
-    dim3 grid(te + to, (rows + TB - 1) / TB, p.splitk);
-#define L1(T, F)                                                                                              \
-    hipLaunchKernelGGL((k_gemm1<T, F>), grid, dim3(256), 0, p.stream, (const T *)rho, rows, p.n_r, p.n_ang,  \
-                       p.Ut_hi, p.Ut_mid, p.Ut_lo, p.n_angp, p.np, p.ne_p, te, kchunk, kFlush1, p.Bpart)
+    SplitArgs g = split_args(p, n_fields, rho, nullptr, rho_dtype);
+    dim3 grid(g.tiles_e + g.tiles_o, (g.rows + TB - 1) / TB, p.splitk);
     if (rho_dtype == MPG_F64) {
-        if (p.fold) L1(double, true);
-        else L1(double, false);
+        if (p.fold) hipLaunchKernelGGL((k_gemm1<double, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm1<double, false>), grid, dim3(256), 0, p.stream, g);
     } else {
-        if (p.fold) L1(float, true);
-        else L1(float, false);
+        if (p.fold) hipLaunchKernelGGL((k_gemm1<float, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm1<float, false>), grid, dim3(256), 0, p.stream, g);
     }
-#undef L1
     return hipGetLastError();
 }
 
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
-    const int rows = n_fields * p.n_r;
-    dim3 grid((rows + TB - 1) / TB, p.n_angp / TB);
-#define L2(T, F)                                                                                              \
-    hipLaunchKernelGGL((k_gemm2<T, F>), grid, dim3(256), 0, p.stream, p.M_hi, p.M_mid, p.M_lo, rows, p.np,    \
-                       p.ne_p, p.Qt_hi, p.Qt_mid, p.Qt_lo, p.n_ang, p.n_r, (T *)phi)
+    SplitArgs g = split_args(p, n_fields, nullptr, phi, phi_dtype);
+    dim3 grid((g.rows + TB - 1) / TB, p.n_angp / TB);
     if (phi_dtype == MPG_F64) {
-        if (p.fold) L2(double, true);
-        else L2(double, false);
+        if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(256), 0, p.stream, g);
     } else {
-        if (p.fold) L2(float, true);
-        else L2(float, false);
+        if (p.fold) hipLaunchKernelGGL((k_gemm2<float, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm2<float, false>), grid, dim3(256), 0, p.stream, g);
     }
-#undef L2
+    return hipGetLastError();
+}
+
+hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
+                            int blocks, hipStream_t s) {
+    if (io_dtype == MPG_F64)
+        hipLaunchKernelGGL((k_batch_gemm1<double>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+    else
+        hipLaunchKernelGGL((k_batch_gemm1<float>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+    return hipGetLastError();
+}
+
+hipError_t batch_gemm2_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
+                            int blocks, hipStream_t s) {
+    if (io_dtype == MPG_F64)
+        hipLaunchKernelGGL((k_batch_gemm2<double>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+    else
+        hipLaunchKernelGGL((k_batch_gemm2<float>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16, LDP = BM + 2;
+constexpr int BM = kF64Tile, BN = kF64Tile, BK = 16, LDP = BM + 2;
 
 // Lane layout of v_mfma_f64_16x16x4f64 on gfx950 (measured): lane l
 // supplies A[l%16][l/16] and B[l/16][l%16]; result register r of lane l is
@@ -79,22 +79,25 @@ __device__ inline void mma_slab(const double (*As)[LDP], const double (*Bs)[LDP]
     }
 }
 
-// grid: x = column tile (E tiles then O tiles), y = row tile, z = K split
+struct Smem {
+    double As[BK][LDP];
+    double Bs[BK][LDP];
+};
+
+// One output tile of GEMM1 (column tile tn: even-m tiles first, then
+// odd-m tiles; row tile tm; K split tz).
 template <typename T, bool FOLD>
-__global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int rows, int n_r, int n_ang,
-                                               const double *__restrict__ Ut, int n_angp, int np, int ne_p,
-                                               int tiles_e, int kchunk, double *__restrict__ Bpart) {
-    __shared__ double As[BK][LDP];
-    __shared__ double Bs[BK][LDP];
+__device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int tz, Smem &sm) {
+    const T *rho = (const T *)g.rho;
+    const int rows = g.rows, n_r = g.n_r, n_ang = g.n_ang, n_angp = g.n_angp, np = g.np, ne_p = g.ne_p;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-    const int tn = blockIdx.x;
-    const bool odd = FOLD && tn >= tiles_e;
-    const int c0 = odd ? ne_p + (tn - tiles_e) * BN : tn * BN;
+    const bool odd = FOLD && tn >= g.tiles_e;
+    const int c0 = odd ? ne_p + (tn - g.tiles_e) * BN : tn * BN;
     const int cend = odd ? np : (FOLD ? ne_p : np);
-    const int m0 = blockIdx.y * BM;
-    const int kbeg = blockIdx.z * kchunk;
-    const int kend = min(n_angp, kbeg + kchunk);
+    const int m0 = tm * BM;
+    const int kbeg = tz * g.kchunk;
+    const int kend = min(n_angp, kbeg + g.kchunk);
 
     const int lr = t >> 2, lk = (t & 3) * 4;
     const int row = m0 + lr;
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
     const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
     const T *r0 = rho + f * fld + (size_t)i * n_ang;
     const T *r1 = r0 + (size_t)n_r * n_ang;
-    const double *urow = Ut + (size_t)(c0 + lr) * n_angp;
+    const double *urow = g.Ut + (size_t)(c0 + lr) * n_angp;
 
     v4d acc[2][2];
 #pragma unroll
@@ -118,16 +121,17 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
     }
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
         __syncthreads();
-        store_slab(As, sa, lr, lk);
-        store_slab(Bs, sb, lr, lk);
+        store_slab(sm.As, sa, lr, lk);
+        store_slab(sm.Bs, sb, lr, lk);
         __syncthreads();
         if (k0 + BK < kend) {
             load_rho<T, FOLD>(sa, r0, r1, k0 + BK + lk, n_ang, row_ok, odd);
             load_rowk(sb, urow, k0 + BK + lk, true);
         }
-        mma_slab(As, Bs, wm, wn, lane, acc);
+        mma_slab(sm.As, sm.Bs, wm, wn, lane, acc);
     }
-    double *out = Bpart + (size_t)blockIdx.z * rows * np;
+    __syncthreads();
+    double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -140,20 +144,18 @@ __global__ __launch_bounds__(256) void k_gemm1(const T *__restrict__ rho, int ro
             }
 }
 
-// grid: x = row tile, y = angular tile
+// One output tile of GEMM2 (row tile tm, angular tile tn).
 template <typename T, bool FOLD>
-__global__ __launch_bounds__(256) void k_gemm2(const double *__restrict__ M, int rows, int np, int ne_p,
-                                               const double *__restrict__ Qt, int n_ang, int n_r,
-                                               T *__restrict__ phi) {
-    __shared__ double As[BK][LDP];
-    __shared__ double Bs[BK][LDP];
+__device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Smem &sm) {
+    T *phi = (T *)g.phi;
+    const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int m0 = tm * BM, n0 = tn * BN;
     const int lr = t >> 2, lk = (t & 3) * 4;
     const bool row_ok = m0 + lr < rows;
-    const double *arow = M + (size_t)(row_ok ? m0 + lr : 0) * np;
-    const double *brow = Qt + (size_t)(n0 + lr) * np;
+    const double *arow = g.M + (size_t)(row_ok ? m0 + lr : 0) * np;
+    const double *brow = g.Qt + (size_t)(n0 + lr) * np;
 
     v4d acc[2][2][2];
 #pragma unroll
@@ -174,16 +176,17 @@ __global__ __launch_bounds__(256) void k_gemm2(const double *__restrict__ M, int
         }
         for (int k0 = kb; k0 < ke; k0 += BK) {
             __syncthreads();
-            store_slab(As, sa, lr, lk);
-            store_slab(Bs, sb, lr, lk);
+            store_slab(sm.As, sa, lr, lk);
+            store_slab(sm.Bs, sb, lr, lk);
             __syncthreads();
             if (k0 + BK < ke) {
                 load_rowk(sa, arow, k0 + BK + lk, row_ok);
                 load_rowk(sb, brow, k0 + BK + lk, true);
             }
-            mma_slab(As, Bs, wm, wn, lane, acc[blk]);
+            mma_slab(sm.As, sm.Bs, wm, wn, lane, acc[blk]);
         }
     }
+    __syncthreads();
     const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -207,50 +210,126 @@ __global__ __launch_bounds__(256) void k_gemm2(const double *__restrict__ M, int
             }
 }
 
+// grid: x = column tile (E tiles then O tiles), y = row tile, z = K split
+template <typename T, bool FOLD>
+__global__ __launch_bounds__(256) void k_gemm1(F64Args g) {
+    __shared__ Smem sm;
+    gemm1_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, sm);
+}
+
+// grid: x = row tile, y = angular tile
+template <typename T, bool FOLD>
+__global__ __launch_bounds__(256) void k_gemm2(F64Args g) {
+    __shared__ Smem sm;
+    gemm2_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, sm);
+}
+
+// Persistent batch kernels (see the split-BF16 ones): items from a queue
+// through an atomic head until it is empty; no item waits on another.
+__device__ __forceinline__ int next_item(int *head, int *slot) {
+    if (threadIdx.x == 0) *slot = atomicAdd(head, 1);
+    __syncthreads();
+    int it = __builtin_amdgcn_readfirstlane(*slot);
+    __syncthreads();
+    return it;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_gemm1(const F64Args *__restrict__ args,
+                                                     const BatchItem *__restrict__ items, int n_items, int *head) {
+    __shared__ Smem sm;
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(head, &slot);
+        if (it >= n_items) break;
+        const BatchItem w = items[it];
+        const F64Args g = args[w.f];
+        if (g.fold) gemm1_tile<T, true>(g, w.a, w.b, w.c, sm);
+        else gemm1_tile<T, false>(g, w.a, w.b, w.c, sm);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_gemm2(const F64Args *__restrict__ args,
+                                                     const BatchItem *__restrict__ items, int n_items, int *head) {
+    __shared__ Smem sm;
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(head, &slot);
+        if (it >= n_items) break;
+        const BatchItem w = items[it];
+        const F64Args g = args[w.f];
+        if (g.fold) gemm2_tile<T, true>(g, w.a, w.b, sm);
+        else gemm2_tile<T, false>(g, w.a, w.b, sm);
+    }
+}
+
 }  // namespace
 
+F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype) {
+    F64Args g;
+    g.rho = rho;
+    g.phi = phi;
+    g.io_f64 = io_dtype == MPG_F64;
+    g.rows = n_fields * p.n_r;
+    g.n_r = p.n_r;
+    g.n_ang = p.n_ang;
+    g.n_angp = p.n_angp;
+    g.np = p.np;
+    g.ne_p = p.ne_p;
+    g.fold = p.fold;
+    g.tiles_e = p.fold ? (p.ne_p + BN - 1) / BN : (p.np + BN - 1) / BN;
+    g.tiles_o = p.fold ? (p.no_p + BN - 1) / BN : 0;
+    g.kchunk = ((p.n_angp / p.splitk + BK - 1) / BK) * BK;
+    g.splitk = p.splitk;
+    g.Ut = p.Ut;
+    g.Qt = p.Qt;
+    g.M = p.M;
+    g.Bpart = p.Bpart;
+    return g;
+}
+
 hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
-    const int rows = n_fields * p.n_r;
-    const int te = p.fold ? (p.ne_p + BN - 1) / BN : (p.np + BN - 1) / BN;
-    const int to = p.fold ? (p.no_p + BN - 1) / BN : 0;
-    const int kchunk = ((p.n_angp / p.splitk + BK - 1) / BK) * BK;
-    dim3 grid(te + to, (rows + BM - 1) / BM, p.splitk);
+    F64Args g = f64_args(p, n_fields, rho, nullptr, rho_dtype);
+    dim3 grid(g.tiles_e + g.tiles_o, (g.rows + BM - 1) / BM, p.splitk);
     if (rho_dtype == MPG_F64) {
-        if (p.fold)
-            hipLaunchKernelGGL((k_gemm1<double, true>), grid, dim3(256), 0, p.stream, (const double *)rho, rows,
-                               p.n_r, p.n_ang, p.Ut, p.n_angp, p.np, p.ne_p, te, kchunk, p.Bpart);
-        else
-            hipLaunchKernelGGL((k_gemm1<double, false>), grid, dim3(256), 0, p.stream, (const double *)rho, rows,
-                               p.n_r, p.n_ang, p.Ut, p.n_angp, p.np, p.ne_p, te, kchunk, p.Bpart);
+        if (p.fold) hipLaunchKernelGGL((k_gemm1<double, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm1<double, false>), grid, dim3(256), 0, p.stream, g);
     } else {
-        if (p.fold)
-            hipLaunchKernelGGL((k_gemm1<float, true>), grid, dim3(256), 0, p.stream, (const float *)rho, rows,
-                               p.n_r, p.n_ang, p.Ut, p.n_angp, p.np, p.ne_p, te, kchunk, p.Bpart);
-        else
-            hipLaunchKernelGGL((k_gemm1<float, false>), grid, dim3(256), 0, p.stream, (const float *)rho, rows,
-                               p.n_r, p.n_ang, p.Ut, p.n_angp, p.np, p.ne_p, te, kchunk, p.Bpart);
+        if (p.fold) hipLaunchKernelGGL((k_gemm1<float, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm1<float, false>), grid, dim3(256), 0, p.stream, g);
     }
     return hipGetLastError();
 }
 
 hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype) {
-    const int rows = n_fields * p.n_r;
-    dim3 grid((rows + BM - 1) / BM, p.n_angp / BN);
+    F64Args g = f64_args(p, n_fields, nullptr, phi, phi_dtype);
+    dim3 grid((g.rows + BM - 1) / BM, p.n_angp / BN);
     if (phi_dtype == MPG_F64) {
-        if (p.fold)
-            hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(256), 0, p.stream, p.M, rows, p.np, p.ne_p, p.Qt,
-                               p.n_ang, p.n_r, (double *)phi);
-        else
-            hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(256), 0, p.stream, p.M, rows, p.np, p.ne_p, p.Qt,
-                               p.n_ang, p.n_r, (double *)phi);
+        if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(256), 0, p.stream, g);
     } else {
-        if (p.fold)
-            hipLaunchKernelGGL((k_gemm2<float, true>), grid, dim3(256), 0, p.stream, p.M, rows, p.np, p.ne_p, p.Qt,
-                               p.n_ang, p.n_r, (float *)phi);
-        else
-            hipLaunchKernelGGL((k_gemm2<float, false>), grid, dim3(256), 0, p.stream, p.M, rows, p.np, p.ne_p, p.Qt,
-                               p.n_ang, p.n_r, (float *)phi);
+        if (p.fold) hipLaunchKernelGGL((k_gemm2<float, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm2<float, false>), grid, dim3(256), 0, p.stream, g);
     }
+    return hipGetLastError();
+}
+
+hipError_t batch_gemm1_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
+                           int blocks, hipStream_t s) {
+    if (io_dtype == MPG_F64)
+        hipLaunchKernelGGL((k_batch_gemm1<double>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+    else
+        hipLaunchKernelGGL((k_batch_gemm1<float>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+    return hipGetLastError();
+}
+
+hipError_t batch_gemm2_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
+                           int blocks, hipStream_t s) {
+    if (io_dtype == MPG_F64)
+        hipLaunchKernelGGL((k_batch_gemm2<double>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+    else
+        hipLaunchKernelGGL((k_batch_gemm2<float>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
     return hipGetLastError();
 }
 

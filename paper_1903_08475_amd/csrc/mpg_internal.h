@@ -18,6 +18,8 @@ typedef __bf16 bf16;
 void set_error(const std::string &msg);
 
 // Tile constants shared by the plan layout and the kernels.
+constexpr int kSplitTile = 128;  // split-BF16 GEMM tiles are kSplitTile x kSplitTile
+constexpr int kF64Tile = 64;     // FP64 GEMM tiles are kF64Tile x kF64Tile
 constexpr int kColPad = 32;    // each m-parity column block is padded to this
 constexpr int kColSlack = 128; // zero rows after the last column block
 constexpr int kAngPad = 128;   // angular dimension padded to this
@@ -55,7 +57,9 @@ struct Plan {
     bf16 *Qt_hi = nullptr, *Qt_mid = nullptr, *Qt_lo = nullptr;  // three-piece bf16 copies of Qt
 
     // work space (sized for max_fields)
-    int splitk = 1;
+    int splitk = 1;            // K splits of the moment contraction (work space holds this many)
+    int splitk_sel = 0;        // chosen by mpg_autotune (0: heuristic)
+    int scan_chunks = 16;      // shell chunks per column in the radial scan
     double *Bpart = nullptr;   // [splitk][rows][np]
     double *Bred = nullptr;    // [rows][np]
     double *M = nullptr;       // [rows][np]
@@ -66,6 +70,48 @@ struct Plan {
     // optional stage timing (events recorded on the plan's stream)
     bool timing = false;
     std::vector<hipEvent_t> *events[3] = {nullptr, nullptr, nullptr};  // start/stop pairs
+};
+
+// ---- batch work descriptions ---------------------------------------------
+
+// One work item of a persistent batch kernel: field f and tile coordinates.
+struct BatchItem {
+    int f, a, b, c;
+};
+
+// Arguments of one field's split-BF16 contractions.
+struct SplitArgs {
+    const void *rho;
+    void *phi;
+    int io_f64;
+    int rows, n_r, n_ang, n_angp, np, ne_p, fold;
+    int tiles_e, tiles_o;  // GEMM1 column tiles of the even / odd block
+    int kchunk, splitk;    // GEMM1 K per split, number of splits
+    const bf16 *Uh, *Um, *Ul, *Qh, *Qm, *Ql, *Mh, *Mm, *Ml;
+    double *Bpart;
+};
+
+// Arguments of one field's FP64 contractions.
+struct F64Args {
+    const void *rho;
+    void *phi;
+    int io_f64;
+    int rows, n_r, n_ang, n_angp, np, ne_p, fold;
+    int tiles_e, tiles_o;
+    int kchunk, splitk;
+    const double *Ut, *Qt, *M;
+    double *Bpart;
+};
+
+// Arguments of one field's radial scans.
+struct ScanArgs {
+    const double *Bpart;
+    int splitk, n_fields, n_r, np, L;
+    const int *col_l;
+    const double *coef;
+    double *Bred, *M;
+    bf16 *Mh, *Mm, *Ml;
+    int col_blocks;  // blocks of 64 columns
 };
 
 // ---- kernels launchers (each returns hipError_t of the launch) ----------
@@ -80,13 +126,33 @@ hipError_t export_tables(const Plan &p, double *U, double *Q, double *w);
 // FP64 path (gemm_f64.hip)
 hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype);
+F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype);
+hipError_t batch_gemm1_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
+                           int blocks, hipStream_t s);
+hipError_t batch_gemm2_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
+                           int blocks, hipStream_t s);
 
 // radial scans (scan.hip): Bpart -> Bred, M (and the split copies of M)
 hipError_t radial_scan(const Plan &p, int n_fields, bool split_out);
+ScanArgs scan_args(const Plan &p, int n_fields, bool split_out);
+hipError_t batch_scan(const ScanArgs *args, const BatchItem *items, int n_items, int *head, int blocks,
+                      hipStream_t s);
 
 // split-BF16 path (gemm_bf16.hip)
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype);
+SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype);
+hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
+                            int blocks, hipStream_t s);
+hipError_t batch_gemm2_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
+                            int blocks, hipStream_t s);
+
+// batched solve (batch.hip)
+hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *const *rho, void *const *phi,
+                           int dtype, hipStream_t stream);
+void forget_plan(const Plan *p);
+// K splits used for n_fields fields of a plan (autotuned or heuristic)
+int choose_splitk(const Plan &p, int n_fields);
 
 // permuted [rows][np] -> real index [rows][n_lm]
 hipError_t unpermute(const Plan &p, int n_fields, const double *src, double *dst);

@@ -24,14 +24,22 @@ __device__ inline double reduce_parts(const double *Bpart, size_t stride, int sp
     return s;
 }
 
-__global__ void k_scan(const double *__restrict__ Bpart, int splitk, int n_fields, int n_r, int np, int L,
-                       const int *__restrict__ col_l, const double *__restrict__ coef, double *__restrict__ Bred,
-                       double *__restrict__ M, bf16 *__restrict__ Mhi, bf16 *__restrict__ Mlo,
-                       bf16 *__restrict__ Mmid) {
+// One block of 64 columns.  Threads with lane >= the column count, and
+// chunks past the last shell, hold identity maps and write nothing.
+__device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
+    const double *__restrict__ Bpart = g.Bpart;
+    const int splitk = g.splitk, n_fields = g.n_fields, n_r = g.n_r, np = g.np, L = g.L;
+    const int *__restrict__ col_l = g.col_l;
+    const double *__restrict__ coef = g.coef;
+    double *__restrict__ Bred = g.Bred;
+    double *__restrict__ M = g.M;
+    bf16 *__restrict__ Mhi = g.Mh;
+    bf16 *__restrict__ Mlo = g.Ml;
+    bf16 *__restrict__ Mmid = g.Mm;
     __shared__ double sA[kMaxChunks][kLanes], sY[kMaxChunks][kLanes];
     __shared__ double sC[kMaxChunks][kLanes], sZ[kMaxChunks][kLanes];
     const int lane = threadIdx.x, ch = threadIdx.y, T = blockDim.y;
-    const int cidx = blockIdx.x * kLanes + lane;
+    const int cidx = bx * kLanes + lane;
     const bool active = cidx < n_fields * np;
     const int f = active ? cidx / np : 0, q = active ? cidx - f * np : 0;
     const int l = active ? col_l[q] : -1;
@@ -111,6 +119,28 @@ __global__ void k_scan(const double *__restrict__ Bpart, int splitk, int n_field
     }
 }
 
+__global__ __launch_bounds__(1024) void k_scan(ScanArgs g) {
+    scan_block(g, blockIdx.x);
+}
+
+// persistent batch version: items (field, column block) from a queue
+__global__ __launch_bounds__(1024) void k_batch_scan(const ScanArgs *__restrict__ args,
+                                                     const BatchItem *__restrict__ items, int n_items, int *head) {
+    __shared__ int slot;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    for (;;) {
+        if (tid == 0) slot = atomicAdd(head, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(slot);
+        __syncthreads();
+        if (it >= n_items) break;
+        const BatchItem w = items[it];
+        const ScanArgs g = args[w.f];
+        scan_block(g, w.a);
+        __syncthreads();
+    }
+}
+
 __global__ void k_unpermute(const double *src, int rows, int np, int n_lm, const int *col_src, double *dst) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     int row = blockIdx.y;
@@ -121,13 +151,38 @@ __global__ void k_unpermute(const double *src, int rows, int np, int n_lm, const
 
 }  // namespace
 
+ScanArgs scan_args(const Plan &p, int n_fields, bool split_out) {
+    ScanArgs g;
+    g.Bpart = p.Bpart;
+    g.splitk = p.splitk;
+    g.n_fields = n_fields;
+    g.n_r = p.n_r;
+    g.np = p.np;
+    g.L = p.lmax;
+    g.col_l = p.col_l;
+    g.coef = p.coef;
+    g.Bred = p.Bred;
+    g.M = p.M;
+    g.Mh = split_out ? p.M_hi : nullptr;
+    g.Mm = split_out ? p.M_mid : nullptr;
+    g.Ml = split_out ? p.M_lo : nullptr;
+    g.col_blocks = (n_fields * p.np + kLanes - 1) / kLanes;
+    return g;
+}
+
 hipError_t radial_scan(const Plan &p, int n_fields, bool split_out) {
-    int T = p.n_r < kMaxChunks ? p.n_r : kMaxChunks;
-    dim3 block(kLanes, T);
-    dim3 grid((n_fields * p.np + kLanes - 1) / kLanes);
-    hipLaunchKernelGGL(k_scan, grid, block, 0, p.stream, p.Bpart, p.splitk, n_fields, p.n_r, p.np, p.lmax, p.col_l,
-                       p.coef, p.Bred, p.M, split_out ? p.M_hi : nullptr, split_out ? p.M_lo : nullptr,
-                       split_out ? p.M_mid : nullptr);
+    ScanArgs g = scan_args(p, n_fields, split_out);
+    int T = p.scan_chunks;
+    if (T > p.n_r) T = p.n_r;
+    if (T < 1) T = 1;
+    if (T > kMaxChunks) T = kMaxChunks;
+    hipLaunchKernelGGL(k_scan, dim3(g.col_blocks), dim3(kLanes, T), 0, p.stream, g);
+    return hipGetLastError();
+}
+
+hipError_t batch_scan(const ScanArgs *args, const BatchItem *items, int n_items, int *head, int blocks,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_scan, dim3(blocks), dim3(kLanes, kMaxChunks), 0, s, args, items, n_items, head);
     return hipGetLastError();
 }
 

@@ -1,0 +1,109 @@
+"""Parity at the full size of the large workload (Yin-Yang pi/256, 1200 log
+shells, lmax 48, 8 float32 fields per call) in the launch configuration the
+benchmark times: on outputs the oracle can compute one by one, and through
+properties that hold at any size."""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import rel_err
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N_FIELDS = 8
+
+
+@functools.lru_cache(maxsize=1)
+def big():
+    g = W.config5()
+    w = O.overlap_weights(g)
+    U, Q = O.tables_parallel(g, g.lmax, w, workers=16, want_Q=False)
+    return g, w, U
+
+
+@functools.lru_cache(maxsize=2)
+def plan(precision):
+    import paper_1903_08475_amd as mpg
+    return mpg.Plan(W.config5(), precision=precision, max_fields=N_FIELDS)
+
+
+def sparse_rho(g, seed, shells):
+    """Random positive density on a few shells only (zero elsewhere)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = np.zeros(g.shape, dtype=np.float32)
+    for i in shells:
+        rho[:, i] = rng.uniform(0.0, 1.0, size=(2, g.n_theta, g.n_phi)).astype(np.float32)
+    return rho
+
+
+SHELLS = (7, 611, 1190)
+
+
+def sample_points(g, seed, n):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = rng.integers(0, 2, n)
+    i = np.concatenate([[0, g.n_r - 1, 6, 7, 8, 610, 611, 612, 1189, 1190, 1191],
+                        rng.integers(0, g.n_r, n - 11)])
+    c = rng.integers(0, g.n_ang, n)
+    return p, i, c
+
+
+@pytest.mark.parametrize("precision,tol", [("split_bf16", 1e-6), ("fp64", 1e-12)])
+def test_potential_at_sampled_vertices(precision, tol):
+    import torch
+    g, w, U = big()
+    rhos = np.stack([sparse_rho(g, 700 + f, SHELLS) for f in range(N_FIELDS)])
+    out = plan(precision).potential(torch.tensor(rhos, device="cuda"), out_dtype=torch.float64)
+    out = out.cpu().numpy().reshape(N_FIELDS, 2, g.n_r, -1)
+    worst = 0.0
+    for f in (0, 5, 7):
+        B = np.zeros((g.n_r, g.n_lm))
+        O.moments(g, g.lmax, U, rhos[f].astype(np.float64), shells=list(SHELLS), B=B)
+        p, i, c = sample_points(g, 900 + f, 48)
+        M = O.radial(g, g.lmax, B, shells=sorted(set(i.tolist())))
+        ref = O.phi_points(g, g.lmax, M, p, i, c)
+        err = rel_err(out[f][p, i, c], ref)
+        worst = max(worst, err)
+    print(f"{precision}: max rel err at sampled vertices {worst:.3e}")
+    assert worst < tol
+
+
+def test_moments_on_sampled_shells_of_the_benchmark_field():
+    """The benchmark's own density (snapshot 0 and 7 of the evolving field):
+    split-BF16 moments against the oracle on a few shells."""
+    import torch
+    g, w, U = big()
+    dev = torch.device("cuda")
+    rho = torch.empty((N_FIELDS,) + g.shape, dtype=torch.float32, device=dev)
+    for t in range(N_FIELDS):
+        rho[t] = W.cell_average(g, W.density5(t), sub=2, device=dev, as_tensor=True, out_dtype=torch.float32)
+    B, _ = plan("split_bf16").moments(rho)
+    B = B.cpu().numpy()
+    shells = [300, 900, 1100]
+    for f in (0, 7):
+        Bo = np.zeros((g.n_r, g.n_lm))
+        O.moments(g, g.lmax, U, rho[f].double().cpu().numpy(), shells=shells, B=Bo)
+        for i in shells:
+            assert rel_err(B[f, i], Bo[i]) < 1e-6, (f, i)
+
+
+def test_symmetries_at_full_size():
+    """Scaling the density by 2 scales the potential by 2 bit for bit (binary
+    scaling commutes with every rounding step).  Swapping the patches swaps
+    the potentials; odd-m terms change sign, so this holds to the rounding
+    of the FP32 accumulation (a few ulps of max |Phi|)."""
+    import torch
+    g = W.config5()
+    rng = np.random.Generator(np.random.PCG64(77))
+    rho = torch.tensor(rng.uniform(0, 1, size=(N_FIELDS,) + g.shape).astype(np.float32), device="cuda")
+    pl = plan("split_bf16")
+    a = pl.potential(rho)
+    d = pl.potential(2.0 * rho)
+    assert torch.equal(d, 2.0 * a)
+    s = pl.potential(rho.flip(1).contiguous())
+    diff = float((s.double() - a.flip(1).double()).abs().max() / a.double().abs().max())
+    print(f"swap symmetry: max rel difference {diff:.3e}")
+    assert diff < 3e-7
