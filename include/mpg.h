@@ -141,13 +141,14 @@ int mpg_plan_info(mpg_plan_t plan, int *n_lm, long long *field_elems);
 
 /* Per-stage device timing, for measurement.  With enable != 0 every later
  * compute call of the plan records HIP events on the plan's stream around
- * its three stages: 0 = moment contraction, 1 = radial scan,
- * 2 = expansion.  mpg_stage_times waits for the stream and returns the
- * summed milliseconds and launch counts per stage since the last reset
- * (reset != 0 clears them after reading); ms and launches may be NULL.
+ * its stages: 0 = input split (split-BF16 only: rho_Yin +- rho_Yang as bf16
+ * pieces), 1 = moment contraction, 2 = radial scan, 3 = expansion.
+ * mpg_stage_times waits for the stream and returns the summed milliseconds
+ * and launch counts per stage since the last reset (reset != 0 clears them
+ * after reading); ms and launches (4 entries each) may be NULL.
  * Errors: MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE. */
 int mpg_timing(mpg_plan_t plan, int enable);
-int mpg_stage_times(mpg_plan_t plan, double ms[3], long long launches[3], int reset);
+int mpg_stage_times(mpg_plan_t plan, double ms[4], long long launches[4], int reset);
 
 /* Wait for the plan's stream; reports device errors. */
 int mpg_sync(mpg_plan_t plan);

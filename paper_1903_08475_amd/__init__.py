@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16}
 # Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
 EXPORTS = ("mpg_plan", "mpg_moments", "mpg_potential", "mpg_potential_batch", "mpg_autotune", "mpg_tables",
            "mpg_plan_info", "mpg_timing", "mpg_stage_times", "mpg_sync", "mpg_destroy", "mpg_last_error")
-STAGES = ("moments", "radial_scan", "expansion")
+STAGES = ("input_split", "moments", "radial_scan", "expansion")
 
 
 class MpgError(RuntimeError):
@@ -197,10 +197,10 @@ class Plan:
 
     def stage_times(self, reset=True):
         """{stage: (total ms, launches)} since the last reset."""
-        ms = (C.c_double * 3)()
-        n = (C.c_longlong * 3)()
+        ms = (C.c_double * 4)()
+        n = (C.c_longlong * 4)()
         _check(lib().mpg_stage_times(self._h, ms, n, 1 if reset else 0))
-        return {STAGES[i]: (ms[i], n[i]) for i in range(3)}
+        return {STAGES[i]: (ms[i], n[i]) for i in range(4)}
 
     def sync(self):
         _check(lib().mpg_sync(self._h))

@@ -145,8 +145,13 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, b.cap, b.heads, 4);
     const BatchItem *it1 = b.items_dev, *its = b.items_dev + b.n1, *it2 = b.items_dev + b.n1 + b.ns;
     hipError_t e;
+    e = hipSuccess;
     if (split) {
-        e = batch_gemm1_bf16((const SplitArgs *)b.args_dev, it1, b.n1, b.heads + 0, dtype, cus, b.cap);
+        for (int f = 0; f < n && e == hipSuccess; ++f)
+            e = batch_split_input_bf16((const SplitArgs *)b.args_dev, f, (size_t)q[f].n_r * (q[f].n_angp / 8), dtype,
+                                       b.cap);
+        if (e == hipSuccess)
+            e = batch_gemm1_bf16((const SplitArgs *)b.args_dev, it1, b.n1, b.heads + 0, dtype, cus, b.cap);
         if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);
         if (e == hipSuccess) e = batch_gemm2_bf16((const SplitArgs *)b.args_dev, it2, b.n2, b.heads + 2, dtype, cus, b.cap);
     } else {

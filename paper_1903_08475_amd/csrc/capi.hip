@@ -60,7 +60,7 @@ void stage_end(const Plan &p, hipEvent_t b) {
 }
 
 void clear_events(Plan *p) {
-    for (int s = 0; s < 3; ++s)
+    for (int s = 0; s < 4; ++s)
         if (p->events[s]) {
             for (hipEvent_t e : *p->events[s]) (void)hipEventDestroy(e);
             p->events[s]->clear();
@@ -71,12 +71,13 @@ void free_plan(mpg_plan_s *p) {
     if (!p) return;
     forget_plan(p);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    void *bufs[] = {p->col_src, p->col_l, p->Ut,    p->Qt,   p->coef, p->w,    p->Ut_hi, p->Ut_mid, p->Ut_lo,
-                    p->Qt_hi,   p->Qt_mid, p->Qt_lo, p->Bpart, p->Bred, p->M, p->M_hi,  p->M_mid,  p->M_lo};
+    void *bufs[] = {p->col_src, p->col_l,  p->Ut,    p->Qt,    p->coef, p->w,    p->Ut_hi, p->Ut_mid,
+                    p->Ut_lo,   p->Qt_hi,  p->Qt_mid, p->Qt_lo, p->Bpart, p->Bred, p->M,     p->M_hi,
+                    p->M_mid,   p->M_lo,   p->A_split};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     clear_events(p);
-    for (int s = 0; s < 3; ++s) delete p->events[s];
+    for (int s = 0; s < 4; ++s) delete p->events[s];
     delete p;
 }
 
@@ -229,7 +230,8 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
     if (precision == MPG_SPLIT_BF16) {
         if ((e = hipMalloc(&p->M_hi, sizeof(bf16) * rows * p->np)) != hipSuccess ||
             (e = hipMalloc(&p->M_lo, sizeof(bf16) * rows * p->np)) != hipSuccess ||
-            (e = hipMalloc(&p->M_mid, sizeof(bf16) * rows * p->np)) != hipSuccess) {
+            (e = hipMalloc(&p->M_mid, sizeof(bf16) * rows * p->np)) != hipSuccess ||
+            (e = hipMalloc(&p->A_split, sizeof(bf16) * (p->fold ? 6 : 3) * rows * p->n_angp)) != hipSuccess) {
             int rc = hip_fail(e, "mpg_plan: split work space");
             free_plan(p);
             return rc;
@@ -258,14 +260,21 @@ static int run_moments(const Plan *p, int n_fields, const void *rho, int rho_dty
     int sk = choose_splitk(*p, n_fields);
     Plan q = *p;
     q.splitk = sk;
-    hipEvent_t ev = stage_begin(q, 0);
+    hipEvent_t ev;
+    if (p->precision == MPG_SPLIT_BF16) {
+        ev = stage_begin(q, 0);
+        e = split_input_bf16(q, n_fields, rho, rho_dtype);
+        stage_end(q, ev);
+        if (e != hipSuccess) return hip_fail(e, "input split");
+    }
+    ev = stage_begin(q, 1);
     if (p->precision == MPG_SPLIT_BF16)
         e = gemm1_bf16(q, n_fields, rho, rho_dtype);
     else
         e = gemm1_f64(q, n_fields, rho, rho_dtype);
     stage_end(q, ev);
     if (e != hipSuccess) return hip_fail(e, "moment contraction");
-    ev = stage_begin(q, 1);
+    ev = stage_begin(q, 2);
     e = radial_scan(q, n_fields, split_out);
     stage_end(q, ev);
     if (e != hipSuccess) return hip_fail(e, "radial scan");
@@ -286,7 +295,7 @@ static int solve(const Plan *p, int n_fields, const void *rho, int rho_dtype, vo
     int rc;
     bool split = p->precision == MPG_SPLIT_BF16;
     if ((rc = run_moments(p, n_fields, rho, rho_dtype, split))) return rc;
-    hipEvent_t ev = stage_begin(*p, 2);
+    hipEvent_t ev = stage_begin(*p, 3);
     hipError_t e = split ? gemm2_bf16(*p, n_fields, phi, phi_dtype) : gemm2_f64(*p, n_fields, phi, phi_dtype);
     stage_end(*p, ev);
     if (e != hipSuccess) return hip_fail(e, "expansion");
@@ -351,6 +360,11 @@ int mpg_autotune(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, int
         *ms = best;
         return hipSuccess;
     };
+    if (split && (e = split_input_bf16(*p, n_fields, rho, rho_dtype)) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return hip_fail(e, "mpg_autotune");
+    }
     // K splits: powers of two up to the work space, plus the heuristic choice
     std::vector<int> cands;
     p->splitk_sel = 0;
@@ -404,7 +418,7 @@ int mpg_plan_info(mpg_plan_t p, int *n_lm, long long *field_elems) {
 
 int mpg_timing(mpg_plan_t p, int enable) {
     if (!p) return fail(MPG_EINVAL, "mpg_timing: plan is NULL");
-    for (int s = 0; s < 3; ++s)
+    for (int s = 0; s < 4; ++s)
         if (!p->events[s]) {
             p->events[s] = new (std::nothrow) std::vector<hipEvent_t>();
             if (!p->events[s]) return fail(MPG_ENOMEM, "mpg_timing: host allocation");
@@ -413,11 +427,11 @@ int mpg_timing(mpg_plan_t p, int enable) {
     return MPG_OK;
 }
 
-int mpg_stage_times(mpg_plan_t p, double ms[3], long long launches[3], int reset) {
+int mpg_stage_times(mpg_plan_t p, double ms[4], long long launches[4], int reset) {
     if (!p) return fail(MPG_EINVAL, "mpg_stage_times: plan is NULL");
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail(e, "mpg_stage_times");
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < 4; ++s) {
         double tot = 0.0;
         long long n = 0;
         if (p->events[s])

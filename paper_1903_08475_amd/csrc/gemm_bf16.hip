@@ -100,6 +100,16 @@ __device__ inline void mma_slab(const Pieces &A, const Pieces &B, int wm, int wn
         MM4(ah0, ah1, bh0, bh1);
 #undef MM4
     }
+#ifdef MPG_SCHED
+    // issue the second step's fragment reads between the first step's MFMAs
+    __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 24, 0);
+#endif
 }
 
 // 16 consecutive K values of the three pieces of one row, held in registers
@@ -199,11 +209,97 @@ __device__ inline void zero(v16f (&acc)[2][2]) {
 }
 
 // ---------------------------------------------------------------------------
+// Input split: A = rho_Yin + rho_Yang (even-m block) and rho_Yin - rho_Yang
+// (odd-m block) under the fold (U_Yang = (-1)^m U_Yin, Sec. 4.2), else A =
+// rho, rounded once to FP32 and written as three bf16 pieces
+// A[parity][piece][row][k] (k < n_angp; zero past n_ang).  Thread = 8
+// consecutive k of one row.
+template <typename T, bool FOLD>
+__device__ __forceinline__ void fold_split_row8(const SplitArgs &g, size_t t) {
+    const int per_row = g.n_angp / 8;
+    const int row = (int)(t / per_row), k0 = (int)(t - (size_t)row * per_row) * 8;
+    if (row >= g.rows) return;
+    const int n_r = g.n_r, n_ang = g.n_ang;
+    const int f = row / n_r, i = row - f * n_r;
+    const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
+    const T *r0 = (const T *)g.rho + f * fld + (size_t)i * n_ang;
+    const T *r1 = r0 + (size_t)n_r * n_ang;
+    float v0[8], v1[8];
+    if ((n_ang & 7) == 0) {
+        if (k0 < n_ang) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                v0[q] = (float)0;
+                v1[q] = (float)0;
+            }
+            if (sizeof(T) == 4) {
+                f32x4 a0 = *(const f32x4 *)(r0 + k0), a1 = *(const f32x4 *)(r0 + k0 + 4);
+                v0[0] = a0.x; v0[1] = a0.y; v0[2] = a0.z; v0[3] = a0.w;
+                v0[4] = a1.x; v0[5] = a1.y; v0[6] = a1.z; v0[7] = a1.w;
+                if (FOLD) {
+                    f32x4 b0 = *(const f32x4 *)(r1 + k0), b1 = *(const f32x4 *)(r1 + k0 + 4);
+                    v1[0] = b0.x; v1[1] = b0.y; v1[2] = b0.z; v1[3] = b0.w;
+                    v1[4] = b1.x; v1[5] = b1.y; v1[6] = b1.z; v1[7] = b1.w;
+                }
+            }
+        }
+    }
+    // FP64 input (or unaligned rows): element by element in double
+    double d0[8], d1[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k = k0 + q;
+        const bool in = k < n_ang;
+        if (sizeof(T) == 4 && (n_ang & 7) == 0) {
+            d0[q] = in ? (double)v0[q] : 0.0;
+            d1[q] = in && FOLD ? (double)v1[q] : 0.0;
+        } else {
+            d0[q] = in ? (double)r0[k] : 0.0;
+            d1[q] = in && FOLD ? (double)r1[k] : 0.0;
+        }
+    }
+    const size_t plane = (size_t)g.rows_alloc * g.n_angp, off = (size_t)row * g.n_angp + k0;
+#pragma unroll
+    for (int par = 0; par < (FOLD ? 2 : 1); ++par) {
+        uint32_t h[4], m[4], l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float x0 = (float)(par ? d0[2 * q] - d1[2 * q] : d0[2 * q] + d1[2 * q]);
+            float x1 = (float)(par ? d0[2 * q + 1] - d1[2 * q + 1] : d0[2 * q + 1] + d1[2 * q + 1]);
+            bf16 h0, m0, l0, h1, m1, l1;
+            split3f(x0, h0, m0, l0);
+            split3f(x1, h1, m1, l1);
+            h[q] = pack2(h0, h1);
+            m[q] = pack2(m0, m1);
+            l[q] = pack2(l0, l1);
+        }
+        bf16 *base = g.A + (size_t)(3 * par) * plane + off;
+        *(u32x4 *)(base) = (u32x4){h[0], h[1], h[2], h[3]};
+        *(u32x4 *)(base + plane) = (u32x4){m[0], m[1], m[2], m[3]};
+        *(u32x4 *)(base + 2 * plane) = (u32x4){l[0], l[1], l[2], l[3]};
+    }
+}
+
+template <typename T, bool FOLD>
+__global__ __launch_bounds__(256) void k_fold_split(SplitArgs g) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    fold_split_row8<T, FOLD>(g, t);
+}
+
+// batch version: the field's arguments come from device memory
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *args, int f) {
+    const SplitArgs g = args[f];
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g.fold) fold_split_row8<T, true>(g, t);
+    else fold_split_row8<T, false>(g, t);
+}
+
+// ---------------------------------------------------------------------------
 // One output tile of GEMM1 (column tile tn: even-m tiles first, then odd-m
 // tiles; row tile tm; K split tz).  Writes Bpart[tz][row][col] in FP64.
-template <typename T, bool FOLD>
+template <bool FOLD>
 __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, Stage (&st)[2]) {
-    const T *rho = (const T *)g.rho;
     const int rows = g.rows, n_r = g.n_r, n_ang = g.n_ang, n_angp = g.n_angp, np = g.np, ne_p = g.ne_p;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
@@ -215,19 +311,20 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
     const int kend = min(n_angp, kbeg + g.kchunk);
     const int nsl = kend > kbeg ? (kend - kbeg) / TK : 0;
 
-    // loader: thread t covers row t/2 and 16 K values from 16*(t%2)
+    // loader: thread t covers row t/2 and 16 K values from 16*(t%2); A is
+    // the pre-split rho (+-) of this tile's column parity
     const int lr = t >> 1, lk = (t & 1) * 16;
     const int row = m0 + lr;
     const bool row_ok = row < rows;
-    const int f = row_ok ? row / n_r : 0, i = row_ok ? row - f * n_r : 0;
-    const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
-    const T *r0 = rho + f * fld + (size_t)i * n_ang;
-    const T *r1 = r0 + (size_t)n_r * n_ang;
+    const size_t plane = (size_t)g.rows_alloc * n_angp;
+    const bf16 *Ah = g.A + (size_t)(odd ? 3 : 0) * plane;
+    const bf16 *Am = Ah + plane, *Al = Am + plane;
+    const size_t aoff = (size_t)(row_ok ? row : 0) * n_angp;
     const size_t uoff = (size_t)(c0 + lr) * n_angp;
     const bf16 *Uh = g.Uh, *Um = g.Um, *Ul = g.Ul;
-    // n_ang % 16 == 0: a thread's 16 values are all inside the row or all
-    // outside, and aligned for vector loads
-    const bool vec = (n_ang & 15) == 0;
+    (void)n_r;
+    (void)n_ang;
+    const u32x4 z = {0u, 0u, 0u, 0u};
 
     v16f acc[2][2];
     double acc64[2][2][16];
@@ -239,15 +336,15 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
 
-    float av[16];
-    Raw16 bu;
+    Raw16 ra, bu;
+    ra.h0 = ra.h1 = ra.m0 = ra.m1 = ra.l0 = ra.l1 = z;
     if (nsl > 0) {
-        load_rho<T, FOLD>(av, r0, r1, kbeg + lk, n_ang, row_ok, odd, vec);
+        if (row_ok) load_pieces(ra, Ah, Am, Al, aoff + kbeg + lk);
         load_pieces(bu, Uh, Um, Ul, uoff + kbeg + lk);
-        store_split(st[0].A, av, lr, lk);
+        store_pieces(st[0].A, ra, lr, lk);
         store_pieces(st[0].B, bu, lr, lk);
         if (nsl > 1) {
-            load_rho<T, FOLD>(av, r0, r1, kbeg + TK + lk, n_ang, row_ok, odd, vec);
+            if (row_ok) load_pieces(ra, Ah, Am, Al, aoff + kbeg + TK + lk);
             load_pieces(bu, Uh, Um, Ul, uoff + kbeg + TK + lk);
         }
     }
@@ -256,11 +353,11 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
     for (int s = 0; s < nsl; ++s) {
         const int cur = s & 1;
         if (s + 1 < nsl) {
-            store_split(st[cur ^ 1].A, av, lr, lk);
+            store_pieces(st[cur ^ 1].A, ra, lr, lk);
             store_pieces(st[cur ^ 1].B, bu, lr, lk);
             if (s + 2 < nsl) {
                 const int k = kbeg + (s + 2) * TK + lk;
-                load_rho<T, FOLD>(av, r0, r1, k, n_ang, row_ok, odd, vec);
+                if (row_ok) load_pieces(ra, Ah, Am, Al, aoff + k);
                 load_pieces(bu, Uh, Um, Ul, uoff + k);
             }
         }
@@ -328,10 +425,40 @@ __device__ __forceinline__ void gemm2_block(Stage (&st)[2], const bf16 *Mh, cons
     }
 }
 
+#ifdef MPG_G2_OCC2
+// single-buffered variant (two blocks per CU hide each other's latency)
+__device__ __forceinline__ void gemm2_block_sb(Stage &st, const bf16 *Mh, const bf16 *Mm, const bf16 *Ml,
+                                               const bf16 *Qh, const bf16 *Qm, const bf16 *Ql, size_t aoff,
+                                               size_t boff, bool row_ok, int cbase, int nsl, int lr, int lk, int wm,
+                                               int wn, int lane, v16f (&acc)[2][2]) {
+    Raw16 ra, rb;
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    ra.h0 = ra.h1 = ra.m0 = ra.m1 = ra.l0 = ra.l1 = z;
+    if (nsl > 0) {
+        int k = cbase + (nsl - 1) * TK + lk;
+        if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
+        load_pieces(rb, Qh, Qm, Ql, boff + k);
+    }
+    for (int s = 0; s < nsl; ++s) {
+        __syncthreads();
+        store_pieces(st.A, ra, lr, lk);
+        store_pieces(st.B, rb, lr, lk);
+        __syncthreads();
+        if (s + 1 < nsl) {
+            const int k = cbase + (nsl - 2 - s) * TK + lk;
+            if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
+            load_pieces(rb, Qh, Qm, Ql, boff + k);
+        }
+        mma_slab(st.A, st.B, wm, wn, lane, acc);
+    }
+    __syncthreads();
+}
+#endif
+
 // One output tile of GEMM2 (row tile tm, angular tile tn).  The K slabs of
 // the even block come first, then those of the odd block.
-template <typename T, bool FOLD>
-__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Stage (&st)[2]) {
+template <typename T, bool FOLD, int NS>
+__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Stage (&st)[NS]) {
     T *phi = (T *)g.phi;
     const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -345,6 +472,9 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     v16f acc_e[2][2], acc_o[2][2];
     zero(acc_e);
     zero(acc_o);
+#ifdef MPG_G2_OCC2
+#define gemm2_block(ST, ...) gemm2_block_sb(ST[0], __VA_ARGS__)
+#endif
     if (FOLD) {
         gemm2_block(st, g.Mh, g.Mm, g.Ml, g.Qh, g.Qm, g.Ql, aoff, boff, row_ok, 0, ne_p / TK, lr, lk, wm, wn, lane,
                     acc_e);
@@ -354,6 +484,9 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
         gemm2_block(st, g.Mh, g.Mm, g.Ml, g.Qh, g.Qm, g.Ql, aoff, boff, row_ok, 0, np / TK, lr, lk, wm, wn, lane,
                     acc_e);
     }
+#ifdef MPG_G2_OCC2
+#undef gemm2_block
+#endif
     const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -380,16 +513,23 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 // ---------------------------------------------------------------------------
 // Grid launches for one plan: GEMM1 grid x = column tile, y = row tile,
 // z = K split; GEMM2 grid x = row tile, y = angular tile.
-template <typename T, bool FOLD>
+template <bool FOLD>
 __global__ __launch_bounds__(256) void k_gemm1(SplitArgs g) {
     __shared__ Stage st[2];
-    gemm1_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, st);
+    gemm1_tile<FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, st);
 }
 
+#ifdef MPG_G2_OCC2
+#define G2_BOUNDS __launch_bounds__(256, 2)
+#define G2_STAGES 1
+#else
+#define G2_BOUNDS __launch_bounds__(256)
+#define G2_STAGES 2
+#endif
 template <typename T, bool FOLD>
-__global__ __launch_bounds__(256) void k_gemm2(SplitArgs g) {
-    __shared__ Stage st[2];
-    gemm2_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, st);
+__global__ G2_BOUNDS void k_gemm2(SplitArgs g) {
+    __shared__ Stage st[G2_STAGES];
+    gemm2_tile<T, FOLD, G2_STAGES>(g, blockIdx.x, blockIdx.y, st);
 }
 
 // Persistent batch kernels: every block takes work items from a queue
@@ -404,7 +544,6 @@ __device__ __forceinline__ int next_item(int *head, int *slot) {
     return it;
 }
 
-template <typename T>
 __global__ __launch_bounds__(256) void k_batch_gemm1(const SplitArgs *__restrict__ args,
                                                      const BatchItem *__restrict__ items, int n_items, int *head) {
     __shared__ Stage st[2];
@@ -414,8 +553,8 @@ __global__ __launch_bounds__(256) void k_batch_gemm1(const SplitArgs *__restrict
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const SplitArgs g = args[w.f];
-        if (g.fold) gemm1_tile<T, true>(g, w.a, w.b, w.c, st);
-        else gemm1_tile<T, false>(g, w.a, w.b, w.c, st);
+        if (g.fold) gemm1_tile<true>(g, w.a, w.b, w.c, st);
+        else gemm1_tile<false>(g, w.a, w.b, w.c, st);
     }
 }
 
@@ -429,8 +568,8 @@ __global__ __launch_bounds__(256) void k_batch_gemm2(const SplitArgs *__restrict
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const SplitArgs g = args[w.f];
-        if (g.fold) gemm2_tile<T, true>(g, w.a, w.b, st);
-        else gemm2_tile<T, false>(g, w.a, w.b, st);
+        if (g.fold) gemm2_tile<T, true, 2>(g, w.a, w.b, st);
+        else gemm2_tile<T, false, 2>(g, w.a, w.b, st);
     }
 }
 
@@ -456,21 +595,32 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.Qh = p.Qt_hi; g.Qm = p.Qt_mid; g.Ql = p.Qt_lo;
     g.Mh = p.M_hi; g.Mm = p.M_mid; g.Ml = p.M_lo;
     g.Bpart = p.Bpart;
+    g.A = p.A_split;
+    g.rows_alloc = p.rows_alloc();
     return g;
 }
 
 int split_tile_rows(int rows) { return (rows + TB - 1) / TB; }
 
+hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
+    SplitArgs g = split_args(p, n_fields, rho, nullptr, rho_dtype);
+    const size_t threads = (size_t)g.rows * (g.n_angp / 8);
+    dim3 grid((unsigned)((threads + 255) / 256));
+    if (rho_dtype == MPG_F64) {
+        if (p.fold) hipLaunchKernelGGL((k_fold_split<double, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_fold_split<double, false>), grid, dim3(256), 0, p.stream, g);
+    } else {
+        if (p.fold) hipLaunchKernelGGL((k_fold_split<float, true>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_fold_split<float, false>), grid, dim3(256), 0, p.stream, g);
+    }
+    return hipGetLastError();
+}
+
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
     SplitArgs g = split_args(p, n_fields, rho, nullptr, rho_dtype);
     dim3 grid(g.tiles_e + g.tiles_o, (g.rows + TB - 1) / TB, p.splitk);
-    if (rho_dtype == MPG_F64) {
-        if (p.fold) hipLaunchKernelGGL((k_gemm1<double, true>), grid, dim3(256), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm1<double, false>), grid, dim3(256), 0, p.stream, g);
-    } else {
-        if (p.fold) hipLaunchKernelGGL((k_gemm1<float, true>), grid, dim3(256), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm1<float, false>), grid, dim3(256), 0, p.stream, g);
-    }
+    if (p.fold) hipLaunchKernelGGL((k_gemm1<true>), grid, dim3(256), 0, p.stream, g);
+    else hipLaunchKernelGGL((k_gemm1<false>), grid, dim3(256), 0, p.stream, g);
     return hipGetLastError();
 }
 
@@ -487,12 +637,19 @@ hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     return hipGetLastError();
 }
 
+hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t rows_x_cols8, int io_dtype, hipStream_t s) {
+    dim3 grid((unsigned)((rows_x_cols8 + 255) / 256));
+    if (io_dtype == MPG_F64)
+        hipLaunchKernelGGL((k_batch_fold_split<double>), grid, dim3(256), 0, s, args, f);
+    else
+        hipLaunchKernelGGL((k_batch_fold_split<float>), grid, dim3(256), 0, s, args, f);
+    return hipGetLastError();
+}
+
 hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                             int blocks, hipStream_t s) {
-    if (io_dtype == MPG_F64)
-        hipLaunchKernelGGL((k_batch_gemm1<double>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
-    else
-        hipLaunchKernelGGL((k_batch_gemm1<float>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+    (void)io_dtype;
+    hipLaunchKernelGGL(k_batch_gemm1, dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
     return hipGetLastError();
 }
 

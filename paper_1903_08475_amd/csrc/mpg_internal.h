@@ -64,12 +64,13 @@ struct Plan {
     double *Bred = nullptr;    // [rows][np]
     double *M = nullptr;       // [rows][np]
     bf16 *M_hi = nullptr, *M_mid = nullptr, *M_lo = nullptr; // [rows][np] three-piece bf16 M
+    bf16 *A_split = nullptr;   // [fold ? 2 : 1][3][rows][n_angp] split input (rho +-)
 
     int rows_alloc() const { return max_fields * n_r; }
 
     // optional stage timing (events recorded on the plan's stream)
     bool timing = false;
-    std::vector<hipEvent_t> *events[3] = {nullptr, nullptr, nullptr};  // start/stop pairs
+    std::vector<hipEvent_t> *events[4] = {nullptr, nullptr, nullptr, nullptr};  // start/stop pairs
 };
 
 // ---- batch work descriptions ---------------------------------------------
@@ -89,6 +90,8 @@ struct SplitArgs {
     int kchunk, splitk;    // GEMM1 K per split, number of splits
     const bf16 *Uh, *Um, *Ul, *Qh, *Qm, *Ql, *Mh, *Mm, *Ml;
     double *Bpart;
+    bf16 *A;        // split input [parity][piece][rows_alloc][n_angp]
+    int rows_alloc;
 };
 
 // Arguments of one field's FP64 contractions.
@@ -139,8 +142,10 @@ hipError_t batch_scan(const ScanArgs *args, const BatchItem *items, int n_items,
                       hipStream_t s);
 
 // split-BF16 path (gemm_bf16.hip)
+hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype);
+hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t rows_x_cols8, int io_dtype, hipStream_t s);
 SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype);
 hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                             int blocks, hipStream_t s);
