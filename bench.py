@@ -71,38 +71,43 @@ def make_inputs(grid, n_snap, device):
 
 
 def time_path(plan, rho, phi, steps, warmup):
+    """Mean ms/step over the timed region, per-step percentiles, wall time and
+    per-stage device times.  Every event is recorded on the plan's stream."""
     import torch
     for _ in range(warmup):
         plan.potential(rho, out=phi)
     torch.cuda.synchronize()
     plan.timing(True)
     plan.stage_times(reset=True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
-    for _ in range(steps):
+    ev[0].record(plan.stream)
+    for k in range(steps):
         plan.potential(rho, out=phi)
-    stop.record()
+        ev[k + 1].record(plan.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stages = plan.stage_times(reset=True)
     plan.timing(False)
-    return start.elapsed_time(stop) / steps, wall, stages
+    per_step = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    pct = {"p10": float(np.percentile(per_step, 10)), "median": float(np.median(per_step)),
+           "p90": float(np.percentile(per_step, 90))}
+    return ev[0].elapsed_time(ev[steps]) / steps, wall, stages, pct
 
 
 def cpu_baseline(lmax):
     """The oracle, as it stands, on a bounded sample of the same workload:
     the large workload's lmax and radial spacing law on a coarser angular
-    grid (pi/64, 32x96 per patch) and 64 shells.  Timed: moments, radial
-    sums and expansion (its table build excluded, as on the GPU)."""
+    grid (pi/96, 48x144 per patch) and 96 shells.  Timed: moments, radial
+    sums and expansion, single-threaded (its table build, run on a process
+    pool beforehand, is excluded, as on the GPU)."""
     import oracle as O
     import workloads as W
-    g = W.yinyang(32, W.log_edges(64, 3.0), lmax)
+    g = W.yinyang(48, W.log_edges(96, 3.0), lmax)
     rho = W.random_rho(g, 5005)
     w = O.overlap_weights(g)
-    U, Q = O.tables(g, lmax, w)
+    U, Q = O.tables_parallel(g, lmax, w, workers=max(1, min(16, os.cpu_count() or 1)))
     t0 = time.perf_counter()
     B = O.moments(g, lmax, U, rho)
     M = O.radial(g, lmax, B)
@@ -114,7 +119,7 @@ def cpu_baseline(lmax):
         "unit": "terms/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"lmax {lmax}, Yin-Yang pi/64 (2x32x96 cells), 64 log-spaced shells, "
+        "sample": (f"lmax {lmax}, Yin-Yang pi/96 (2x48x144 cells), 96 log-spaced shells, "
                    f"{terms:.3e} terms; moments + radial sums + expansion in {dt:.1f} s, "
                    f"single thread ({os.cpu_count()} host cores)"),
     }
@@ -123,7 +128,7 @@ def cpu_baseline(lmax):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--snapshots", type=int, default=8)
@@ -135,9 +140,16 @@ def main():
               "(the solver has no multi-GPU path)", file=sys.stderr)
         return 2
 
+    import workloads as W
+    cpu = None
+    if not args.no_cpu_baseline:
+        # first, before the GPU is initialised (the table build forks workers)
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(W.config5().lmax)
+        log(f"[bench] CPU oracle: {cpu['value']:.3e} terms/s")
+
     import torch
     import paper_1903_08475_amd as mpg
-    import workloads as W
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -151,8 +163,8 @@ def main():
 
     log("[bench] building split-BF16 plan")
     plan = mpg.Plan(grid, precision="split_bf16", max_fields=n)
-    ms, wall, stages = time_path(plan, rho, phi, args.steps, args.warmup)
-    log(f"[bench] split-BF16: {ms:.3f} ms/step; stages {stages}")
+    ms, wall, stages, pct = time_path(plan, rho, phi, args.steps, args.warmup)
+    log(f"[bench] split-BF16: {ms:.3f} ms/step ({pct}); stages {stages}")
 
     out = {
         "metric": METRIC,
@@ -162,6 +174,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_percentiles": pct,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -203,7 +216,7 @@ def main():
         log("[bench] FP64 path on the same workload")
         ref = torch.empty_like(rho, dtype=torch.float64)
         plan64 = mpg.Plan(grid, precision="fp64", max_fields=n)
-        ms64, _, st64 = time_path(plan64, rho, ref, args.fp64_steps, 1)
+        ms64, _, st64, _ = time_path(plan64, rho, ref, args.fp64_steps, 1)
         plan.potential(rho, out=phi)
         torch.cuda.synchronize()
         err = float((phi.to(torch.float64) - ref).abs().max() / ref.abs().max())
@@ -217,9 +230,8 @@ def main():
         out["speedup_vs_fp64"] = ms64 / ms
         del plan64, ref
 
-    if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(grid.lmax)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 
