@@ -2,18 +2,17 @@
 //
 // Each operand x, taken in FP32, is written as x = h + m + l, with h, m, l
 // the round-to-nearest bf16 of the successive residuals (exact: 24
-// significant bits).  A product a*b is formed from the six partial products whose
-// combined weight is at least 2^-18 of the leading one:
+// significant bits).  A product a*b is formed from the six partial products
+// whose combined weight is at least 2^-18 of the leading one:
 //   ah*bh + ah*bm + am*bh + ah*bl + am*bm + al*bh
-// on v_mfma_f32_32x32x16_bf16 (bf16 products are exact in FP32).  The FP32
-// accumulators are flushed into FP64 registers every `flush` K steps, so
-// no FP32 sum runs over more than flush*32 terms (GEMM1; GEMM2's K is the
-// moment count, short enough for FP32 sums).
+// on v_mfma_f32_32x32x16_bf16 (bf16 products are exact in FP32).  GEMM1's
+// FP32 accumulators are flushed into FP64 registers every kFlushSlabs K
+// slabs, so no FP32 sum runs over more than kFlushSlabs*32 terms (GEMM2's K
+// is the moment count, short enough for FP32 sums).
 //
-// GEMM1 (moments, Eq. B_CS) folds and splits rho in its tile loader:
-// A = rho_Yin +- rho_Yang (U_Yang = (-1)^m U_Yin, Sec. 4.2), rounded once
-// to FP32 and converted to three bf16 pieces in LDS; U comes pre-split from
-// the plan.
+// GEMM1 (moments, Eq. B_CS) reads A = rho_Yin +- rho_Yang (U_Yang =
+// (-1)^m U_Yin, Sec. 4.2) pre-split into three bf16 planes per parity by
+// k_fold_split, and U pre-split by the plan.
 // GEMM2 (expansion, Eq. gravpotmult) reads M pre-split by the radial scan
 // and Q pre-split by the plan, sums even- and odd-m columns separately and
 // writes Phi_Yin = E + O, Phi_Yang = E - O.  Its K loop runs from the
@@ -21,9 +20,15 @@
 // to the smallest partial sums last.
 //
 // Tiles: 128x128 per block of 256 threads (2x2 waves of 64x64 = 2x2 MFMA
-// blocks of 32x32), K slabs of 32, double-buffered in LDS (120 KB): while the
-// waves multiply slab s from one buffer, slab s+1 is written to the other
-// from registers and slab s+2 is fetched from memory; one barrier per slab.
+// blocks of 32x32), K slabs of 32.  A slab (both operands, three pieces:
+// 48 KB) is copied from global memory straight into LDS by
+// global_load_lds_dwordx4 (no staging registers) into a ring of three
+// slab buffers (144 KB): slab s+2 is in flight while slab s is multiplied,
+// with one barrier per slab.  Inside a buffer each piece is a [128][32]
+// bf16 array of 16-byte chunks stored at chunk position
+//   4*row + (kchunk ^ ((row >> 1) & 3)),
+// so that the eight lanes of each 128-byte LDS access phase of a fragment
+// read (eight consecutive rows, same kchunk) hit eight distinct bank groups.
 #include "mpg_internal.h"
 
 namespace mpg {
@@ -34,20 +39,24 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // native vector types (HIP's uint4/float4 classes defeat register promotion)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
 
-constexpr int TB = kSplitTile, TK = 32, LDK = TK + 8;
-constexpr int kFlush1 = 16;  // GEMM1: FP32 runs of at most 512 terms
+constexpr int TB = kSplitTile, TK = 32;
+constexpr int kPiece = TB * TK;       // bf16 elements of one piece of one operand in a slab
+constexpr int kFlushSlabs = 15;       // GEMM1: FP32 runs of at most 480 terms (a multiple of the ring size)
+constexpr int kLoadsPerSlab = 12;     // global_load_lds instructions per wave per slab
 
-struct Pieces {
-    bf16 h[TB][LDK];
-    bf16 m[TB][LDK];
-    bf16 l[TB][LDK];
+// one K slab of both operands, three pieces each, swizzled (see above)
+struct Slab {
+    bf16 a[3][kPiece];
+    bf16 b[3][kPiece];
 };
 
-struct Stage {
-    Pieces A, B;
-};
+// s_waitcnt immediates (gfx9 encoding): vmcnt <= n with the other counters
+// unconstrained, and lgkmcnt == 0 with the others unconstrained
+#define MPG_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15) | (((n) >> 4) << 14))
+#define MPG_WAIT_LGKM0() __builtin_amdgcn_s_waitcnt(0xC07F)
 
 // C/D layout of v_mfma_f32_32x32x16_bf16 (measured): register r of lane l
 // holds D[8(r/4) + 4(l/32) + r%4][l%32]; A rows are lane%32 with K elements
@@ -62,141 +71,8 @@ __device__ inline void split3f(float v, bf16 &h, bf16 &m, bf16 &l) {
     l = (bf16)(r - (float)m);
 }
 
-// rho_Yin +- rho_Yang rounded once to FP32 (the split path's input precision)
-__device__ inline float fold(float a, float b, bool odd) { return odd ? a - b : a + b; }
-__device__ inline float fold(double a, double b, bool odd) { return (float)(odd ? a - b : a + b); }
-
-// one 32-deep slab from LDS for a wave's 64x64 tile: for each 16-deep step
-// the six partial products are issued product by product over the four
-// accumulators, smallest weight first, so consecutive MFMAs never depend on
-// each other.
-__device__ inline void mma_slab(const Pieces &A, const Pieces &B, int wm, int wn, int lane, v16f (&acc)[2][2]) {
-    const int lr = lane & 31, lk = 8 * (lane >> 5);
-#pragma unroll
-    for (int ks = 0; ks < TK; ks += 16) {
-        v8bf ah0, ah1, am0, am1, al0, al1, bh0, bh1, bm0, bm1, bl0, bl1;
-        ah0 = *(const v8bf *)&A.h[wm + lr][ks + lk];
-        ah1 = *(const v8bf *)&A.h[wm + 32 + lr][ks + lk];
-        am0 = *(const v8bf *)&A.m[wm + lr][ks + lk];
-        am1 = *(const v8bf *)&A.m[wm + 32 + lr][ks + lk];
-        al0 = *(const v8bf *)&A.l[wm + lr][ks + lk];
-        al1 = *(const v8bf *)&A.l[wm + 32 + lr][ks + lk];
-        bh0 = *(const v8bf *)&B.h[wn + lr][ks + lk];
-        bh1 = *(const v8bf *)&B.h[wn + 32 + lr][ks + lk];
-        bm0 = *(const v8bf *)&B.m[wn + lr][ks + lk];
-        bm1 = *(const v8bf *)&B.m[wn + 32 + lr][ks + lk];
-        bl0 = *(const v8bf *)&B.l[wn + lr][ks + lk];
-        bl1 = *(const v8bf *)&B.l[wn + 32 + lr][ks + lk];
-#define MM4(X0, X1, Y0, Y1)                                                              \
-    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X0, Y0, acc[0][0], 0, 0, 0); \
-    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X0, Y1, acc[0][1], 0, 0, 0); \
-    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X1, Y0, acc[1][0], 0, 0, 0); \
-    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X1, Y1, acc[1][1], 0, 0, 0)
-        MM4(al0, al1, bh0, bh1);
-        MM4(am0, am1, bm0, bm1);
-        MM4(ah0, ah1, bl0, bl1);
-        MM4(am0, am1, bh0, bh1);
-        MM4(ah0, ah1, bm0, bm1);
-        MM4(ah0, ah1, bh0, bh1);
-#undef MM4
-    }
-#ifdef MPG_SCHED
-    // issue the second step's fragment reads between the first step's MFMAs
-    __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, 24, 0);
-#endif
-}
-
-// 16 consecutive K values of the three pieces of one row, held in registers
-struct Raw16 {
-    u32x4 h0, h1, m0, m1, l0, l1;
-};
-
-__device__ __forceinline__ void load_pieces(Raw16 &r, const bf16 *h, const bf16 *m, const bf16 *l, size_t off) {
-    r.h0 = *(const u32x4 *)(h + off);
-    r.h1 = *(const u32x4 *)(h + off + 8);
-    r.m0 = *(const u32x4 *)(m + off);
-    r.m1 = *(const u32x4 *)(m + off + 8);
-    r.l0 = *(const u32x4 *)(l + off);
-    r.l1 = *(const u32x4 *)(l + off + 8);
-}
-
-__device__ __forceinline__ void store_pieces(Pieces &S, const Raw16 &r, int row, int k) {
-    *(u32x4 *)&S.h[row][k] = r.h0;
-    *(u32x4 *)&S.h[row][k + 8] = r.h1;
-    *(u32x4 *)&S.m[row][k] = r.m0;
-    *(u32x4 *)&S.m[row][k + 8] = r.m1;
-    *(u32x4 *)&S.l[row][k] = r.l0;
-    *(u32x4 *)&S.l[row][k + 8] = r.l1;
-}
-
 __device__ __forceinline__ uint32_t pack2(bf16 a, bf16 b) {
     return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
-}
-
-__device__ __forceinline__ void store_split(Pieces &S, const float (&av)[16], int row, int k) {
-    uint32_t h[8], m[8], l[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        bf16 h0, m0, l0, h1, m1, l1;
-        split3f(av[2 * q], h0, m0, l0);
-        split3f(av[2 * q + 1], h1, m1, l1);
-        h[q] = pack2(h0, h1);
-        m[q] = pack2(m0, m1);
-        l[q] = pack2(l0, l1);
-    }
-    *(u32x4 *)&S.h[row][k] = (u32x4){h[0], h[1], h[2], h[3]};
-    *(u32x4 *)&S.h[row][k + 8] = (u32x4){h[4], h[5], h[6], h[7]};
-    *(u32x4 *)&S.m[row][k] = (u32x4){m[0], m[1], m[2], m[3]};
-    *(u32x4 *)&S.m[row][k + 8] = (u32x4){m[4], m[5], m[6], m[7]};
-    *(u32x4 *)&S.l[row][k] = (u32x4){l[0], l[1], l[2], l[3]};
-    *(u32x4 *)&S.l[row][k + 8] = (u32x4){l[4], l[5], l[6], l[7]};
-}
-
-// 16 consecutive values of rho_Yin +- rho_Yang (or rho) of one row, in FP32.
-// vec: n_ang % 16 == 0, so the 16 values are all inside the row or all
-// outside it, and 16-byte aligned.
-template <typename T, bool FOLD>
-__device__ __forceinline__ void load_rho(float (&av)[16], const T *r0, const T *r1, int k, int n_ang, bool row_ok,
-                                         bool odd, bool vec) {
-    if (vec) {
-        if (row_ok && k < n_ang) {
-            if (sizeof(T) == 4) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    f32x4 x = *(const f32x4 *)(r0 + k + 4 * q);
-                    f32x4 y = FOLD ? *(const f32x4 *)(r1 + k + 4 * q) : (f32x4){0.f, 0.f, 0.f, 0.f};
-                    av[4 * q + 0] = FOLD ? fold(x.x, y.x, odd) : x.x;
-                    av[4 * q + 1] = FOLD ? fold(x.y, y.y, odd) : x.y;
-                    av[4 * q + 2] = FOLD ? fold(x.z, y.z, odd) : x.z;
-                    av[4 * q + 3] = FOLD ? fold(x.w, y.w, odd) : x.w;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    f64x2 x = *(const f64x2 *)(r0 + k + 2 * q);
-                    f64x2 y = FOLD ? *(const f64x2 *)(r1 + k + 2 * q) : (f64x2){0.0, 0.0};
-                    av[2 * q + 0] = FOLD ? fold(x.x, y.x, odd) : (float)x.x;
-                    av[2 * q + 1] = FOLD ? fold(x.y, y.y, odd) : (float)x.y;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 16; ++q) av[q] = 0.0f;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            float v = 0.0f;
-            if (row_ok && k + q < n_ang) v = FOLD ? fold(r0[k + q], r1[k + q], odd) : (float)r0[k + q];
-            av[q] = v;
-        }
-    }
 }
 
 __device__ inline void zero(v16f (&acc)[2][2]) {
@@ -296,12 +172,150 @@ __global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *args,
 }
 
 // ---------------------------------------------------------------------------
+// Slab loader.  Wave w copies parts 2w and 2w+1 (16 rows each) of every
+// piece of both operands: lane l of part P loads row 16P + l/4 at kchunk
+// (l%4) ^ ((l/8)%4), which global_load_lds writes to chunk position
+// 64P + l, the swizzled slot of that (row, kchunk).
+struct Loader {
+    const bf16 *a[3], *b[3];  // piece planes of the two operands
+    size_t aoff[2], boff[2];  // element offsets of this lane's two rows, kchunk included
+    int part[2];              // element offset of the wave's two parts inside a piece (wave-uniform)
+};
+
+__device__ __forceinline__ void init_loader(Loader &L, int wave, int lane, int arow0, int arows, size_t lda,
+                                            int brow0, size_t ldb) {
+    const int kcl = ((lane & 3) ^ ((lane >> 3) & 3)) * 8;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int rr = (2 * wave + h) * 16 + (lane >> 2);
+        // rows past the end load the last row; their outputs are never stored
+        const int ar = min(arow0 + rr, arows - 1);
+        L.aoff[h] = (size_t)ar * lda + kcl;
+        L.boff[h] = (size_t)(brow0 + rr) * ldb + kcl;
+        L.part[h] = (2 * wave + h) * 512;
+    }
+}
+
+__device__ __forceinline__ void load_slab(Slab &S, const Loader &L, int k) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            __builtin_amdgcn_global_load_lds((glb_void *)(L.a[q] + L.aoff[h] + k), (lds_void *)(S.a[q] + L.part[h]),
+                                             16, 0, 0);
+            __builtin_amdgcn_global_load_lds((glb_void *)(L.b[q] + L.boff[h] + k), (lds_void *)(S.b[q] + L.part[h]),
+                                             16, 0, 0);
+        }
+}
+
+// 8 bf16 (16 bytes) of row `row`, kchunk kc of one swizzled piece
+__device__ __forceinline__ v8bf frag(const bf16 *piece, int row, int kc) {
+    return *(const v8bf *)(piece + (row * 4 + (kc ^ ((row >> 1) & 3))) * 8);
+}
+
+// one 32-deep slab for a wave's 64x64 tile: for each 16-deep step the six
+// partial products are issued product by product over the four
+// accumulators, smallest weight first, so consecutive MFMAs never depend on
+// each other.
+__device__ __forceinline__ void mma_slab(const Slab &S, int wm, int wn, int lane, v16f (&acc)[2][2]) {
+    const int r = lane & 31, kh = lane >> 5;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        const int kc = 2 * ks + kh;
+        const v8bf ah0 = frag(S.a[0], wm + r, kc), ah1 = frag(S.a[0], wm + 32 + r, kc);
+        const v8bf am0 = frag(S.a[1], wm + r, kc), am1 = frag(S.a[1], wm + 32 + r, kc);
+        const v8bf al0 = frag(S.a[2], wm + r, kc), al1 = frag(S.a[2], wm + 32 + r, kc);
+        const v8bf bh0 = frag(S.b[0], wn + r, kc), bh1 = frag(S.b[0], wn + 32 + r, kc);
+        const v8bf bm0 = frag(S.b[1], wn + r, kc), bm1 = frag(S.b[1], wn + 32 + r, kc);
+        const v8bf bl0 = frag(S.b[2], wn + r, kc), bl1 = frag(S.b[2], wn + 32 + r, kc);
+#define MM4(X0, X1, Y0, Y1)                                                              \
+    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X0, Y0, acc[0][0], 0, 0, 0); \
+    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X0, Y1, acc[0][1], 0, 0, 0); \
+    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X1, Y0, acc[1][0], 0, 0, 0); \
+    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X1, Y1, acc[1][1], 0, 0, 0)
+        MM4(al0, al1, bh0, bh1);
+        MM4(am0, am1, bm0, bm1);
+        MM4(ah0, ah1, bl0, bl1);
+        MM4(am0, am1, bh0, bh1);
+        MM4(ah0, ah1, bm0, bm1);
+        MM4(ah0, ah1, bh0, bh1);
+#undef MM4
+    }
+}
+
+// Workgroup barrier for the slab ring.  It waits for this wave's copies up
+// to the slab about to be read (at most `pending` copy instructions of the
+// next slab stay in flight), then joins the other waves.  The empty asm
+// statements keep the compiler from moving LDS accesses across it;
+// __syncthreads() is not used because its fence would also wait for the
+// copies still in flight.
+template <int pending>
+__device__ __forceinline__ void ring_barrier() {
+    asm volatile("" ::: "memory");
+    MPG_WAIT_VM(pending);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Multiplies nsl consecutive K slabs of the tile into acc through the ring
+// S0 -> S1 -> S2.  Slab t starts at K index k0 + t*dk (dk = +-TK).  With
+// FLUSH, acc is added into acc64 and cleared after every kFlushSlabs slabs.
+// Every step copies a slab two ahead; past the end it copies the last slab
+// again (same addresses, cache hits), so each step waits for the same count
+// of copies.
+// Every wave must call it with the same arguments; on return all copies
+// have landed, and the ring may be refilled after a barrier.
+template <bool FLUSH>
+__device__ __forceinline__ void run_ring(Slab &S0, Slab &S1, Slab &S2, const Loader &L, int k0, int dk, int nsl,
+                                         int wm, int wn, int lane, v16f (&acc)[2][2], double (&acc64)[2][2][16]) {
+    if (nsl <= 0) return;
+    const int last = nsl - 1;
+    load_slab(S0, L, k0);
+    load_slab(S1, L, k0 + min(1, last) * dk);
+#define RING_STEP(CUR, NXT, O)                                  \
+    ring_barrier<kLoadsPerSlab>();                              \
+    load_slab(NXT, L, k0 + min(t + O + 2, last) * dk);          \
+    if (t + O < nsl) mma_slab(CUR, wm, wn, lane, acc);
+    // A group of kFlushSlabs slabs is unrolled in full, and the barriers and
+    // copies of a turn of the ring run even where its last slabs lie past
+    // the end: the compiler then follows which buffer every LDS read and
+    // copy touches and adds no wait for copies still in flight.
+    for (int s = 0; s < nsl; s += kFlushSlabs) {
+#pragma unroll
+        for (int j = 0; j < kFlushSlabs / 3; ++j) {
+            const int t = s + 3 * j;
+            if (t < nsl) {
+                RING_STEP(S0, S2, 0)
+                RING_STEP(S1, S0, 1)
+                RING_STEP(S2, S1, 2)
+            }
+        }
+        if (FLUSH) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc64[a][b][r] += (double)acc[a][b][r];
+            zero(acc);
+        }
+    }
+#undef RING_STEP
+    // the two trailing copies land before anyone may reuse or free the LDS
+    asm volatile("" ::: "memory");
+    MPG_WAIT_VM(0);
+    asm volatile("" ::: "memory");
+}
+
+// ---------------------------------------------------------------------------
 // One output tile of GEMM1 (column tile tn: even-m tiles first, then odd-m
 // tiles; row tile tm; K split tz).  Writes Bpart[tz][row][col] in FP64.
 template <bool FOLD>
-__device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, Stage (&st)[2]) {
-    const int rows = g.rows, n_r = g.n_r, n_ang = g.n_ang, n_angp = g.n_angp, np = g.np, ne_p = g.ne_p;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+__device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, Slab &S0, Slab &S1,
+                                           Slab &S2) {
+    const int rows = g.rows, n_angp = g.n_angp, np = g.np, ne_p = g.ne_p;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
     const bool odd = FOLD && tn >= g.tiles_e;
     const int c0 = odd ? ne_p + (tn - g.tiles_e) * TB : tn * TB;
@@ -311,20 +325,17 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
     const int kend = min(n_angp, kbeg + g.kchunk);
     const int nsl = kend > kbeg ? (kend - kbeg) / TK : 0;
 
-    // loader: thread t covers row t/2 and 16 K values from 16*(t%2); A is
-    // the pre-split rho (+-) of this tile's column parity
-    const int lr = t >> 1, lk = (t & 1) * 16;
-    const int row = m0 + lr;
-    const bool row_ok = row < rows;
+    // A: the pre-split rho (+-) of this tile's column parity; B: U pieces
+    Loader L;
     const size_t plane = (size_t)g.rows_alloc * n_angp;
-    const bf16 *Ah = g.A + (size_t)(odd ? 3 : 0) * plane;
-    const bf16 *Am = Ah + plane, *Al = Am + plane;
-    const size_t aoff = (size_t)(row_ok ? row : 0) * n_angp;
-    const size_t uoff = (size_t)(c0 + lr) * n_angp;
-    const bf16 *Uh = g.Uh, *Um = g.Um, *Ul = g.Ul;
-    (void)n_r;
-    (void)n_ang;
-    const u32x4 z = {0u, 0u, 0u, 0u};
+    const bf16 *A0 = g.A + (size_t)(odd ? 3 : 0) * plane;
+    L.a[0] = A0;
+    L.a[1] = A0 + plane;
+    L.a[2] = A0 + 2 * plane;
+    L.b[0] = g.Uh;
+    L.b[1] = g.Um;
+    L.b[2] = g.Ul;
+    init_loader(L, wave, lane, m0, rows, n_angp, c0, n_angp);
 
     v16f acc[2][2];
     double acc64[2][2][16];
@@ -335,45 +346,8 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
+    run_ring<true>(S0, S1, S2, L, kbeg, TK, nsl, wm, wn, lane, acc, acc64);
 
-    Raw16 ra, bu;
-    ra.h0 = ra.h1 = ra.m0 = ra.m1 = ra.l0 = ra.l1 = z;
-    if (nsl > 0) {
-        if (row_ok) load_pieces(ra, Ah, Am, Al, aoff + kbeg + lk);
-        load_pieces(bu, Uh, Um, Ul, uoff + kbeg + lk);
-        store_pieces(st[0].A, ra, lr, lk);
-        store_pieces(st[0].B, bu, lr, lk);
-        if (nsl > 1) {
-            if (row_ok) load_pieces(ra, Ah, Am, Al, aoff + kbeg + TK + lk);
-            load_pieces(bu, Uh, Um, Ul, uoff + kbeg + TK + lk);
-        }
-    }
-    __syncthreads();
-    int step = 0;
-    for (int s = 0; s < nsl; ++s) {
-        const int cur = s & 1;
-        if (s + 1 < nsl) {
-            store_pieces(st[cur ^ 1].A, ra, lr, lk);
-            store_pieces(st[cur ^ 1].B, bu, lr, lk);
-            if (s + 2 < nsl) {
-                const int k = kbeg + (s + 2) * TK + lk;
-                if (row_ok) load_pieces(ra, Ah, Am, Al, aoff + k);
-                load_pieces(bu, Uh, Um, Ul, uoff + k);
-            }
-        }
-        mma_slab(st[cur].A, st[cur].B, wm, wn, lane, acc);
-        if (++step == kFlush1) {
-            step = 0;
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) acc64[a][b][r] += (double)acc[a][b][r];
-            zero(acc);
-        }
-        __syncthreads();
-    }
     double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -383,110 +357,46 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
             for (int r = 0; r < 16; ++r) {
                 int rr = m0 + wm + 32 * a + d_row(lane, r);
                 int cc = c0 + wn + 32 * b + (lane & 31);
-                if (rr < rows && cc < cend) out[(size_t)rr * np + cc] = acc64[a][b][r] + (double)acc[a][b][r];
+                if (rr < rows && cc < cend) out[(size_t)rr * np + cc] = acc64[a][b][r];
             }
 }
 
-// One column block of GEMM2 (nsl slabs starting at column cbase), walked
-// from its top slab down to cbase, double-buffered through st.
-__device__ __forceinline__ void gemm2_block(Stage (&st)[2], const bf16 *Mh, const bf16 *Mm, const bf16 *Ml,
-                                            const bf16 *Qh, const bf16 *Qm, const bf16 *Ql, size_t aoff,
-                                            size_t boff, bool row_ok, int cbase, int nsl, int lr, int lk, int wm,
-                                            int wn, int lane, v16f (&acc)[2][2]) {
-    Raw16 ra, rb;
-    const u32x4 z = {0u, 0u, 0u, 0u};
-    ra.h0 = ra.h1 = ra.m0 = ra.m1 = ra.l0 = ra.l1 = z;
-    if (nsl > 0) {
-        int k = cbase + (nsl - 1) * TK + lk;
-        if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
-        load_pieces(rb, Qh, Qm, Ql, boff + k);
-        store_pieces(st[0].A, ra, lr, lk);
-        store_pieces(st[0].B, rb, lr, lk);
-        if (nsl > 1) {
-            k -= TK;
-            if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
-            load_pieces(rb, Qh, Qm, Ql, boff + k);
-        }
-    }
-    __syncthreads();
-    for (int s = 0; s < nsl; ++s) {
-        const int cur = s & 1;
-        if (s + 1 < nsl) {
-            store_pieces(st[cur ^ 1].A, ra, lr, lk);
-            store_pieces(st[cur ^ 1].B, rb, lr, lk);
-            if (s + 2 < nsl) {
-                const int k = cbase + (nsl - 3 - s) * TK + lk;
-                if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
-                load_pieces(rb, Qh, Qm, Ql, boff + k);
-            }
-        }
-        mma_slab(st[cur].A, st[cur].B, wm, wn, lane, acc);
-        __syncthreads();
-    }
-}
-
-#ifdef MPG_G2_OCC2
-// single-buffered variant (two blocks per CU hide each other's latency)
-__device__ __forceinline__ void gemm2_block_sb(Stage &st, const bf16 *Mh, const bf16 *Mm, const bf16 *Ml,
-                                               const bf16 *Qh, const bf16 *Qm, const bf16 *Ql, size_t aoff,
-                                               size_t boff, bool row_ok, int cbase, int nsl, int lr, int lk, int wm,
-                                               int wn, int lane, v16f (&acc)[2][2]) {
-    Raw16 ra, rb;
-    const u32x4 z = {0u, 0u, 0u, 0u};
-    ra.h0 = ra.h1 = ra.m0 = ra.m1 = ra.l0 = ra.l1 = z;
-    if (nsl > 0) {
-        int k = cbase + (nsl - 1) * TK + lk;
-        if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
-        load_pieces(rb, Qh, Qm, Ql, boff + k);
-    }
-    for (int s = 0; s < nsl; ++s) {
-        __syncthreads();
-        store_pieces(st.A, ra, lr, lk);
-        store_pieces(st.B, rb, lr, lk);
-        __syncthreads();
-        if (s + 1 < nsl) {
-            const int k = cbase + (nsl - 2 - s) * TK + lk;
-            if (row_ok) load_pieces(ra, Mh, Mm, Ml, aoff + k);
-            load_pieces(rb, Qh, Qm, Ql, boff + k);
-        }
-        mma_slab(st.A, st.B, wm, wn, lane, acc);
-    }
-    __syncthreads();
-}
-#endif
-
-// One output tile of GEMM2 (row tile tm, angular tile tn).  The K slabs of
-// the even block come first, then those of the odd block.
-template <typename T, bool FOLD, int NS>
-__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Stage (&st)[NS]) {
+// One output tile of GEMM2 (row tile tm, angular tile tn): the even-m K
+// block into acc_e, then the odd-m block into acc_o, each walked from its
+// top slab down.
+template <typename T, bool FOLD>
+__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Slab &S0, Slab &S1, Slab &S2) {
     T *phi = (T *)g.phi;
     const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
     const int m0 = tm * TB, n0 = tn * TB;
-    const int lr = t >> 1, lk = (t & 1) * 16;
-    const bool row_ok = m0 + lr < rows;
-    const size_t aoff = (size_t)(row_ok ? m0 + lr : 0) * np;
-    const size_t boff = (size_t)(n0 + lr) * np;
+
+    Loader L;
+    L.a[0] = g.Mh;
+    L.a[1] = g.Mm;
+    L.a[2] = g.Ml;
+    L.b[0] = g.Qh;
+    L.b[1] = g.Qm;
+    L.b[2] = g.Ql;
+    init_loader(L, wave, lane, m0, rows, np, n0, np);
 
     v16f acc_e[2][2], acc_o[2][2];
+    double unused[2][2][16];
     zero(acc_e);
     zero(acc_o);
-#ifdef MPG_G2_OCC2
-#define gemm2_block(ST, ...) gemm2_block_sb(ST[0], __VA_ARGS__)
-#endif
     if (FOLD) {
-        gemm2_block(st, g.Mh, g.Mm, g.Ml, g.Qh, g.Qm, g.Ql, aoff, boff, row_ok, 0, ne_p / TK, lr, lk, wm, wn, lane,
-                    acc_e);
-        gemm2_block(st, g.Mh, g.Mm, g.Ml, g.Qh, g.Qm, g.Ql, aoff, boff, row_ok, ne_p, (np - ne_p) / TK, lr, lk, wm,
-                    wn, lane, acc_o);
+        const int ne = ne_p / TK, no = (np - ne_p) / TK;
+        run_ring<false>(S0, S1, S2, L, (ne - 1) * TK, -TK, ne, wm, wn, lane, acc_e, unused);
+        // the odd block refills buffers the even block's last slabs were read from
+        __syncthreads();
+        run_ring<false>(S0, S1, S2, L, ne_p + (no - 1) * TK, -TK, no, wm, wn, lane, acc_o, unused);
     } else {
-        gemm2_block(st, g.Mh, g.Mm, g.Ml, g.Qh, g.Qm, g.Ql, aoff, boff, row_ok, 0, np / TK, lr, lk, wm, wn, lane,
-                    acc_e);
+        const int ns = np / TK;
+        run_ring<false>(S0, S1, S2, L, (ns - 1) * TK, -TK, ns, wm, wn, lane, acc_e, unused);
     }
-#ifdef MPG_G2_OCC2
-#undef gemm2_block
-#endif
+
     const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -515,61 +425,55 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 // z = K split; GEMM2 grid x = row tile, y = angular tile.
 template <bool FOLD>
 __global__ __launch_bounds__(256) void k_gemm1(SplitArgs g) {
-    __shared__ Stage st[2];
-    gemm1_tile<FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, st);
+    __shared__ Slab s0, s1, s2;
+    gemm1_tile<FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, s0, s1, s2);
 }
 
-#ifdef MPG_G2_OCC2
-#define G2_BOUNDS __launch_bounds__(256, 2)
-#define G2_STAGES 1
-#else
-#define G2_BOUNDS __launch_bounds__(256)
-#define G2_STAGES 2
-#endif
 template <typename T, bool FOLD>
-__global__ G2_BOUNDS void k_gemm2(SplitArgs g) {
-    __shared__ Stage st[G2_STAGES];
-    gemm2_tile<T, FOLD, G2_STAGES>(g, blockIdx.x, blockIdx.y, st);
+__global__ __launch_bounds__(256) void k_gemm2(SplitArgs g) {
+    __shared__ Slab s0, s1, s2;
+    gemm2_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, s0, s1, s2);
 }
 
 // Persistent batch kernels: every block takes work items from a queue
 // (items[], ordered longest first) through an atomic head until the queue
 // is empty.  Item = (field, tile coordinates); args[] holds each field's
-// arguments.  No item waits on another, so every block exits.
+// arguments.  No item waits on another, so every block exits.  The barrier
+// in next_item also keeps the next tile's first copies from overwriting
+// slabs other waves are still reading.
 __device__ __forceinline__ int next_item(int *head, int *slot) {
+    __syncthreads();
     if (threadIdx.x == 0) *slot = atomicAdd(head, 1);
     __syncthreads();
-    int it = __builtin_amdgcn_readfirstlane(*slot);
-    __syncthreads();
-    return it;
+    return __builtin_amdgcn_readfirstlane(*slot);
 }
 
 __global__ __launch_bounds__(256) void k_batch_gemm1(const SplitArgs *__restrict__ args,
                                                      const BatchItem *__restrict__ items, int n_items, int *head) {
-    __shared__ Stage st[2];
+    __shared__ Slab s0, s1, s2;
     __shared__ int slot;
     for (;;) {
         const int it = next_item(head, &slot);
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const SplitArgs g = args[w.f];
-        if (g.fold) gemm1_tile<true>(g, w.a, w.b, w.c, st);
-        else gemm1_tile<false>(g, w.a, w.b, w.c, st);
+        if (g.fold) gemm1_tile<true>(g, w.a, w.b, w.c, s0, s1, s2);
+        else gemm1_tile<false>(g, w.a, w.b, w.c, s0, s1, s2);
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_gemm2(const SplitArgs *__restrict__ args,
                                                      const BatchItem *__restrict__ items, int n_items, int *head) {
-    __shared__ Stage st[2];
+    __shared__ Slab s0, s1, s2;
     __shared__ int slot;
     for (;;) {
         const int it = next_item(head, &slot);
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const SplitArgs g = args[w.f];
-        if (g.fold) gemm2_tile<T, true, 2>(g, w.a, w.b, st);
-        else gemm2_tile<T, false, 2>(g, w.a, w.b, st);
+        if (g.fold) gemm2_tile<T, true>(g, w.a, w.b, s0, s1, s2);
+        else gemm2_tile<T, false>(g, w.a, w.b, s0, s1, s2);
     }
 }
 
