@@ -26,9 +26,11 @@
 // slab buffers (144 KB): slab s+2 is in flight while slab s is multiplied,
 // with one barrier per slab.  Inside a buffer each piece is a [128][32]
 // bf16 array of 16-byte chunks stored at chunk position
-//   4*row + (kchunk ^ ((row >> 1) & 3)),
-// so that the eight lanes of each 128-byte LDS access phase of a fragment
-// read (eight consecutive rows, same kchunk) hit eight distinct bank groups.
+//   4*row + (kchunk ^ ((row >> 2) & 3)).
+// The LDS serves a 16-byte-per-lane read 16 lanes per clock over 64 banks
+// (measured: a group is conflict-free when its 16 chunk positions differ
+// modulo 16); the lanes of a fragment read cover 16 consecutive rows at one
+// kchunk, whose positions modulo 16 are then all distinct.
 #include "mpg_internal.h"
 
 namespace mpg {
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *args,
 // ---------------------------------------------------------------------------
 // Slab loader.  Wave w copies parts 2w and 2w+1 (16 rows each) of every
 // piece of both operands: lane l of part P loads row 16P + l/4 at kchunk
-// (l%4) ^ ((l/8)%4), which global_load_lds writes to chunk position
+// (l%4) ^ ((l/16)%4), which global_load_lds writes to chunk position
 // 64P + l, the swizzled slot of that (row, kchunk).
 struct Loader {
     const bf16 *a[3], *b[3];  // piece planes of the two operands
@@ -184,7 +186,7 @@ struct Loader {
 
 __device__ __forceinline__ void init_loader(Loader &L, int wave, int lane, int arow0, int arows, size_t lda,
                                             int brow0, size_t ldb) {
-    const int kcl = ((lane & 3) ^ ((lane >> 3) & 3)) * 8;
+    const int kcl = ((lane & 3) ^ ((lane >> 4) & 3)) * 8;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int rr = (2 * wave + h) * 16 + (lane >> 2);
@@ -210,7 +212,7 @@ __device__ __forceinline__ void load_slab(Slab &S, const Loader &L, int k) {
 
 // 8 bf16 (16 bytes) of row `row`, kchunk kc of one swizzled piece
 __device__ __forceinline__ v8bf frag(const bf16 *piece, int row, int kc) {
-    return *(const v8bf *)(piece + (row * 4 + (kc ^ ((row >> 1) & 3))) * 8);
+    return *(const v8bf *)(piece + (row * 4 + (kc ^ ((row >> 2) & 3))) * 8);
 }
 
 // one 32-deep slab for a wave's 64x64 tile: for each 16-deep step the six
