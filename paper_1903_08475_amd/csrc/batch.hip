@@ -148,8 +148,7 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     e = hipSuccess;
     if (split) {
         for (int f = 0; f < n && e == hipSuccess; ++f)
-            e = batch_split_input_bf16((const SplitArgs *)b.args_dev, f, (size_t)q[f].n_r * (q[f].n_angp / 8), dtype,
-                                       b.cap);
+            e = batch_split_input_bf16((const SplitArgs *)b.args_dev, f, split_input_threads(q[f], 1), dtype, b.cap);
         if (e == hipSuccess)
             e = batch_gemm1_bf16((const SplitArgs *)b.args_dev, it1, b.n1, b.heads + 0, dtype, cus, b.cap);
         if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);

@@ -71,9 +71,8 @@ void free_plan(mpg_plan_s *p) {
     if (!p) return;
     forget_plan(p);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    void *bufs[] = {p->col_src, p->col_l,  p->Ut,    p->Qt,    p->coef, p->w,    p->Ut_hi, p->Ut_mid,
-                    p->Ut_lo,   p->Qt_hi,  p->Qt_mid, p->Qt_lo, p->Bpart, p->Bred, p->M,     p->M_hi,
-                    p->M_mid,   p->M_lo,   p->A_split};
+    void *bufs[] = {p->col_src, p->col_l, p->Ut,   p->Qt, p->coef, p->w,
+                    p->Us,      p->Qs,    p->Bpart, p->Bred, p->M,  p->Ms, p->A_split};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     clear_events(p);
@@ -228,10 +227,13 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
         return rc;
     }
     if (precision == MPG_SPLIT_BF16) {
-        if ((e = hipMalloc(&p->M_hi, sizeof(bf16) * rows * p->np)) != hipSuccess ||
-            (e = hipMalloc(&p->M_lo, sizeof(bf16) * rows * p->np)) != hipSuccess ||
-            (e = hipMalloc(&p->M_mid, sizeof(bf16) * rows * p->np)) != hipSuccess ||
-            (e = hipMalloc(&p->A_split, sizeof(bf16) * (p->fold ? 6 : 3) * rows * p->n_angp)) != hipSuccess) {
+        // tile-slab blocks; rows past the last field stay zero (finite)
+        const size_t nM = (size_t)p->row_tiles() * (p->np / kSlabK) * 3 * kBlk;
+        const size_t nA = (size_t)(p->fold ? 2 : 1) * p->row_tiles() * (p->n_angp / kSlabK) * 3 * kBlk;
+        if ((e = hipMalloc(&p->Ms, sizeof(bf16) * nM)) != hipSuccess ||
+            (e = hipMalloc(&p->A_split, sizeof(bf16) * nA)) != hipSuccess ||
+            (e = hipMemset(p->Ms, 0, sizeof(bf16) * nM)) != hipSuccess ||
+            (e = hipMemset(p->A_split, 0, sizeof(bf16) * nA)) != hipSuccess) {
             int rc = hip_fail(e, "mpg_plan: split work space");
             free_plan(p);
             return rc;

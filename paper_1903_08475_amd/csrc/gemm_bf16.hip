@@ -89,54 +89,49 @@ __device__ inline void zero(v16f (&acc)[2][2]) {
 // ---------------------------------------------------------------------------
 // Input split: A = rho_Yin + rho_Yang (even-m block) and rho_Yin - rho_Yang
 // (odd-m block) under the fold (U_Yang = (-1)^m U_Yin, Sec. 4.2), else A =
-// rho, rounded once to FP32 and written as three bf16 pieces
-// A[parity][piece][row][k] (k < n_angp; zero past n_ang).  Thread = 8
-// consecutive k of one row.
+// rho, rounded once to FP32 and written as three bf16 pieces in tile-slab
+// blocks (one plane per parity; zero past n_ang and past the last row).
+// Thread = one 16-byte chunk (8 consecutive K of one row) of one block, so
+// consecutive threads write consecutive chunks.
 template <typename T, bool FOLD>
-__device__ __forceinline__ void fold_split_row8(const SplitArgs &g, size_t t) {
-    const int per_row = g.n_angp / 8;
-    const int row = (int)(t / per_row), k0 = (int)(t - (size_t)row * per_row) * 8;
-    if (row >= g.rows) return;
+__device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
+    const size_t blk = t / 512;
+    const int c = (int)(t - blk * 512);
+    const int tile = (int)(blk / g.ks1), slab = (int)(blk - (size_t)tile * g.ks1);
+    const int r = c >> 2, kc = (c & 3) ^ ((r >> 2) & 3);
+    const int row = tile * TB + r, k0 = slab * TK + kc * 8;
     const int n_r = g.n_r, n_ang = g.n_ang;
-    const int f = row / n_r, i = row - f * n_r;
+    const bool row_ok = row < g.rows;
+    const int f = row_ok ? row / n_r : 0, i = row_ok ? row - f * n_r : 0;
     const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
     const T *r0 = (const T *)g.rho + f * fld + (size_t)i * n_ang;
     const T *r1 = r0 + (size_t)n_r * n_ang;
-    float v0[8], v1[8];
-    if ((n_ang & 7) == 0) {
-        if (k0 < n_ang) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                v0[q] = (float)0;
-                v1[q] = (float)0;
-            }
-            if (sizeof(T) == 4) {
-                f32x4 a0 = *(const f32x4 *)(r0 + k0), a1 = *(const f32x4 *)(r0 + k0 + 4);
-                v0[0] = a0.x; v0[1] = a0.y; v0[2] = a0.z; v0[3] = a0.w;
-                v0[4] = a1.x; v0[5] = a1.y; v0[6] = a1.z; v0[7] = a1.w;
-                if (FOLD) {
-                    f32x4 b0 = *(const f32x4 *)(r1 + k0), b1 = *(const f32x4 *)(r1 + k0 + 4);
-                    v1[0] = b0.x; v1[1] = b0.y; v1[2] = b0.z; v1[3] = b0.w;
-                    v1[4] = b1.x; v1[5] = b1.y; v1[6] = b1.z; v1[7] = b1.w;
-                }
-            }
-        }
-    }
-    // FP64 input (or unaligned rows): element by element in double
     double d0[8], d1[8];
+    if (sizeof(T) == 4 && (n_ang & 7) == 0) {
+        // whole chunk inside or outside the row; 32-byte aligned
+        f32x4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, b0 = a0, b1 = a0;
+        if (row_ok && k0 < n_ang) {
+            a0 = *(const f32x4 *)(r0 + k0);
+            a1 = *(const f32x4 *)(r0 + k0 + 4);
+            if (FOLD) {
+                b0 = *(const f32x4 *)(r1 + k0);
+                b1 = *(const f32x4 *)(r1 + k0 + 4);
+            }
+        }
+        d0[0] = a0.x; d0[1] = a0.y; d0[2] = a0.z; d0[3] = a0.w;
+        d0[4] = a1.x; d0[5] = a1.y; d0[6] = a1.z; d0[7] = a1.w;
+        d1[0] = b0.x; d1[1] = b0.y; d1[2] = b0.z; d1[3] = b0.w;
+        d1[4] = b1.x; d1[5] = b1.y; d1[6] = b1.z; d1[7] = b1.w;
+    } else {
+        // FP64 input (or rows not a multiple of 8): element by element
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int k = k0 + q;
-        const bool in = k < n_ang;
-        if (sizeof(T) == 4 && (n_ang & 7) == 0) {
-            d0[q] = in ? (double)v0[q] : 0.0;
-            d1[q] = in && FOLD ? (double)v1[q] : 0.0;
-        } else {
-            d0[q] = in ? (double)r0[k] : 0.0;
-            d1[q] = in && FOLD ? (double)r1[k] : 0.0;
+        for (int q = 0; q < 8; ++q) {
+            const bool in = row_ok && k0 + q < n_ang;
+            d0[q] = in ? (double)r0[k0 + q] : 0.0;
+            d1[q] = in && FOLD ? (double)r1[k0 + q] : 0.0;
         }
     }
-    const size_t plane = (size_t)g.rows_alloc * g.n_angp, off = (size_t)row * g.n_angp + k0;
+    const size_t plane = (size_t)g.row_tiles * g.ks1 * 3 * kBlk;
 #pragma unroll
     for (int par = 0; par < (FOLD ? 2 : 1); ++par) {
         uint32_t h[4], m[4], l[4];
@@ -151,61 +146,59 @@ __device__ __forceinline__ void fold_split_row8(const SplitArgs &g, size_t t) {
             m[q] = pack2(m0, m1);
             l[q] = pack2(l0, l1);
         }
-        bf16 *base = g.A + (size_t)(3 * par) * plane + off;
-        *(u32x4 *)(base) = (u32x4){h[0], h[1], h[2], h[3]};
-        *(u32x4 *)(base + plane) = (u32x4){m[0], m[1], m[2], m[3]};
-        *(u32x4 *)(base + 2 * plane) = (u32x4){l[0], l[1], l[2], l[3]};
+        bf16 *o = g.A + par * plane + blk * 3 * kBlk + (size_t)c * 8;
+        *(u32x4 *)(o) = (u32x4){h[0], h[1], h[2], h[3]};
+        *(u32x4 *)(o + kBlk) = (u32x4){m[0], m[1], m[2], m[3]};
+        *(u32x4 *)(o + 2 * kBlk) = (u32x4){l[0], l[1], l[2], l[3]};
     }
 }
 
 template <typename T, bool FOLD>
-__global__ __launch_bounds__(256) void k_fold_split(SplitArgs g) {
+__global__ __launch_bounds__(256) void k_fold_split(SplitArgs g, size_t n_threads) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    fold_split_row8<T, FOLD>(g, t);
+    if (t < n_threads) fold_split_chunk<T, FOLD>(g, t);
 }
 
 // batch version: the field's arguments come from device memory
 template <typename T>
-__global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *args, int f) {
+__global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *args, int f, size_t n_threads) {
     const SplitArgs g = args[f];
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g.fold) fold_split_row8<T, true>(g, t);
-    else fold_split_row8<T, false>(g, t);
+    if (t >= n_threads) return;
+    if (g.fold) fold_split_chunk<T, true>(g, t);
+    else fold_split_chunk<T, false>(g, t);
 }
 
 // ---------------------------------------------------------------------------
-// Slab loader.  Wave w copies parts 2w and 2w+1 (16 rows each) of every
-// piece of both operands: lane l of part P loads row 16P + l/4 at kchunk
-// (l%4) ^ ((l/16)%4), which global_load_lds writes to chunk position
-// 64P + l, the swizzled slot of that (row, kchunk).
+// Slab loader.  A slab of an operand tile is one tile-slab block, already
+// in LDS order: wave w copies chunks 64P .. 64P+63 (P = 2w, 2w+1) of every
+// piece of both operands, lane l copying chunk 64P + l, so that each copy
+// instruction moves 1 KB of consecutive global memory into consecutive LDS.
 struct Loader {
-    const bf16 *a[3], *b[3];  // piece planes of the two operands
-    size_t aoff[2], boff[2];  // element offsets of this lane's two rows, kchunk included
-    int part[2];              // element offset of the wave's two parts inside a piece (wave-uniform)
+    const bf16 *a, *b;  // first block (slab 0) of the A and B tiles
+    int lo[2];          // element offsets of this lane's two chunks in a piece
+    int part[2];        // element offsets of the wave's two parts in a piece (wave-uniform)
 };
 
-__device__ __forceinline__ void init_loader(Loader &L, int wave, int lane, int arow0, int arows, size_t lda,
-                                            int brow0, size_t ldb) {
-    const int kcl = ((lane & 3) ^ ((lane >> 4) & 3)) * 8;
+__device__ __forceinline__ void init_loader(Loader &L, int wave, int lane, const bf16 *a, const bf16 *b) {
+    L.a = a;
+    L.b = b;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int rr = (2 * wave + h) * 16 + (lane >> 2);
-        // rows past the end load the last row; their outputs are never stored
-        const int ar = min(arow0 + rr, arows - 1);
-        L.aoff[h] = (size_t)ar * lda + kcl;
-        L.boff[h] = (size_t)(brow0 + rr) * ldb + kcl;
         L.part[h] = (2 * wave + h) * 512;
+        L.lo[h] = L.part[h] + lane * 8;
     }
 }
 
-__device__ __forceinline__ void load_slab(Slab &S, const Loader &L, int k) {
+__device__ __forceinline__ void load_slab(Slab &S, const Loader &L, int slab) {
+    const bf16 *a = L.a + (size_t)slab * 3 * kBlk, *b = L.b + (size_t)slab * 3 * kBlk;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            __builtin_amdgcn_global_load_lds((glb_void *)(L.a[q] + L.aoff[h] + k), (lds_void *)(S.a[q] + L.part[h]),
+            __builtin_amdgcn_global_load_lds((glb_void *)(a + q * kBlk + L.lo[h]), (lds_void *)(S.a[q] + L.part[h]),
                                              16, 0, 0);
-            __builtin_amdgcn_global_load_lds((glb_void *)(L.b[q] + L.boff[h] + k), (lds_void *)(S.b[q] + L.part[h]),
+            __builtin_amdgcn_global_load_lds((glb_void *)(b + q * kBlk + L.lo[h]), (lds_void *)(S.b[q] + L.part[h]),
                                              16, 0, 0);
         }
 }
@@ -260,7 +253,7 @@ __device__ __forceinline__ void ring_barrier() {
 }
 
 // Multiplies nsl consecutive K slabs of the tile into acc through the ring
-// S0 -> S1 -> S2.  Slab t starts at K index k0 + t*dk (dk = +-TK).  With
+// S0 -> S1 -> S2.  Slab t is block k0 + t*dk of the tiles (dk = +-1).  With
 // FLUSH, acc is added into acc64 and cleared after every kFlushSlabs slabs.
 // Every step copies a slab two ahead; past the end it copies the last slab
 // again (same addresses, cache hits), so each step waits for the same count
@@ -327,17 +320,11 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
     const int kend = min(n_angp, kbeg + g.kchunk);
     const int nsl = kend > kbeg ? (kend - kbeg) / TK : 0;
 
-    // A: the pre-split rho (+-) of this tile's column parity; B: U pieces
+    // A: the pre-split rho (+-) of this tile's column parity; B: split U
     Loader L;
-    const size_t plane = (size_t)g.rows_alloc * n_angp;
-    const bf16 *A0 = g.A + (size_t)(odd ? 3 : 0) * plane;
-    L.a[0] = A0;
-    L.a[1] = A0 + plane;
-    L.a[2] = A0 + 2 * plane;
-    L.b[0] = g.Uh;
-    L.b[1] = g.Um;
-    L.b[2] = g.Ul;
-    init_loader(L, wave, lane, m0, rows, n_angp, c0, n_angp);
+    const size_t tstride = (size_t)g.ks1 * 3 * kBlk;
+    const bf16 *A0 = g.A + (odd ? (size_t)g.row_tiles * tstride : 0) + (size_t)tm * tstride;
+    init_loader(L, wave, lane, A0, g.U + (size_t)tn * tstride);
 
     v16f acc[2][2];
     double acc64[2][2][16];
@@ -348,7 +335,7 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
-    run_ring<true>(S0, S1, S2, L, kbeg, TK, nsl, wm, wn, lane, acc, acc64);
+    run_ring<true>(S0, S1, S2, L, kbeg / TK, 1, nsl, wm, wn, lane, acc, acc64);
 
     double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
@@ -376,13 +363,8 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     const int m0 = tm * TB, n0 = tn * TB;
 
     Loader L;
-    L.a[0] = g.Mh;
-    L.a[1] = g.Mm;
-    L.a[2] = g.Ml;
-    L.b[0] = g.Qh;
-    L.b[1] = g.Qm;
-    L.b[2] = g.Ql;
-    init_loader(L, wave, lane, m0, rows, np, n0, np);
+    const size_t tstride = (size_t)g.ks2 * 3 * kBlk;
+    init_loader(L, wave, lane, g.M + (size_t)tm * tstride, g.Q + (size_t)tn * tstride);
 
     v16f acc_e[2][2], acc_o[2][2];
     double unused[2][2][16];
@@ -390,13 +372,13 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     zero(acc_o);
     if (FOLD) {
         const int ne = ne_p / TK, no = (np - ne_p) / TK;
-        run_ring<false>(S0, S1, S2, L, (ne - 1) * TK, -TK, ne, wm, wn, lane, acc_e, unused);
+        run_ring<false>(S0, S1, S2, L, ne - 1, -1, ne, wm, wn, lane, acc_e, unused);
         // the odd block refills buffers the even block's last slabs were read from
         __syncthreads();
-        run_ring<false>(S0, S1, S2, L, ne_p + (no - 1) * TK, -TK, no, wm, wn, lane, acc_o, unused);
+        run_ring<false>(S0, S1, S2, L, ne + no - 1, -1, no, wm, wn, lane, acc_o, unused);
     } else {
         const int ns = np / TK;
-        run_ring<false>(S0, S1, S2, L, (ns - 1) * TK, -TK, ns, wm, wn, lane, acc_e, unused);
+        run_ring<false>(S0, S1, S2, L, ns - 1, -1, ns, wm, wn, lane, acc_e, unused);
     }
 
     const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
@@ -493,31 +475,36 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.np = p.np;
     g.ne_p = p.ne_p;
     g.fold = p.fold;
-    g.tiles_e = p.fold ? (p.ne_p + TB - 1) / TB : (p.np + TB - 1) / TB;
-    g.tiles_o = p.fold ? (p.no_p + TB - 1) / TB : 0;
+    g.tiles_e = p.tiles_e();
+    g.tiles_o = p.tiles_o();
     g.kchunk = ((p.n_angp / p.splitk + TK - 1) / TK) * TK;
     g.splitk = p.splitk;
-    g.Uh = p.Ut_hi; g.Um = p.Ut_mid; g.Ul = p.Ut_lo;
-    g.Qh = p.Qt_hi; g.Qm = p.Qt_mid; g.Ql = p.Qt_lo;
-    g.Mh = p.M_hi; g.Mm = p.M_mid; g.Ml = p.M_lo;
+    g.U = p.Us;
+    g.Q = p.Qs;
+    g.M = p.Ms;
     g.Bpart = p.Bpart;
     g.A = p.A_split;
-    g.rows_alloc = p.rows_alloc();
+    g.row_tiles = p.row_tiles();
+    g.ks1 = p.n_angp / TK;
+    g.ks2 = p.np / TK;
     return g;
 }
 
-int split_tile_rows(int rows) { return (rows + TB - 1) / TB; }
+// one thread per 16-byte chunk of the row tiles holding the fields' rows
+size_t split_input_threads(const Plan &p, int n_fields) {
+    return (size_t)((n_fields * p.n_r + TB - 1) / TB) * (p.n_angp / TK) * 512;
+}
 
 hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
     SplitArgs g = split_args(p, n_fields, rho, nullptr, rho_dtype);
-    const size_t threads = (size_t)g.rows * (g.n_angp / 8);
+    const size_t threads = split_input_threads(p, n_fields);
     dim3 grid((unsigned)((threads + 255) / 256));
     if (rho_dtype == MPG_F64) {
-        if (p.fold) hipLaunchKernelGGL((k_fold_split<double, true>), grid, dim3(256), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_fold_split<double, false>), grid, dim3(256), 0, p.stream, g);
+        if (p.fold) hipLaunchKernelGGL((k_fold_split<double, true>), grid, dim3(256), 0, p.stream, g, threads);
+        else hipLaunchKernelGGL((k_fold_split<double, false>), grid, dim3(256), 0, p.stream, g, threads);
     } else {
-        if (p.fold) hipLaunchKernelGGL((k_fold_split<float, true>), grid, dim3(256), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_fold_split<float, false>), grid, dim3(256), 0, p.stream, g);
+        if (p.fold) hipLaunchKernelGGL((k_fold_split<float, true>), grid, dim3(256), 0, p.stream, g, threads);
+        else hipLaunchKernelGGL((k_fold_split<float, false>), grid, dim3(256), 0, p.stream, g, threads);
     }
     return hipGetLastError();
 }
@@ -543,12 +530,12 @@ hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     return hipGetLastError();
 }
 
-hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t rows_x_cols8, int io_dtype, hipStream_t s) {
-    dim3 grid((unsigned)((rows_x_cols8 + 255) / 256));
+hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t n_threads, int io_dtype, hipStream_t s) {
+    dim3 grid((unsigned)((n_threads + 255) / 256));
     if (io_dtype == MPG_F64)
-        hipLaunchKernelGGL((k_batch_fold_split<double>), grid, dim3(256), 0, s, args, f);
+        hipLaunchKernelGGL((k_batch_fold_split<double>), grid, dim3(256), 0, s, args, f, n_threads);
     else
-        hipLaunchKernelGGL((k_batch_fold_split<float>), grid, dim3(256), 0, s, args, f);
+        hipLaunchKernelGGL((k_batch_fold_split<float>), grid, dim3(256), 0, s, args, f, n_threads);
     return hipGetLastError();
 }
 

@@ -24,6 +24,18 @@ constexpr int kColPad = 32;    // each m-parity column block is padded to this
 constexpr int kColSlack = 128; // zero rows after the last column block
 constexpr int kAngPad = 128;   // angular dimension padded to this
 
+// Split-BF16 operands (rho+-, U, M, Q) are stored as tile-slab blocks: an
+// operand with tiles of kSplitTile rows and K slabs of kSlabK holds, for
+// each (tile, slab), the three bf16 pieces (h, m, l) of that 128x32
+// submatrix one after the other, block after block in slab order:
+//   element (tile, slab, piece, r, k) at ((tile*slabs + slab)*3 + piece)*kBlk + blk_pos(r, k).
+// Inside a piece the 16-byte chunk (r, k/8) sits at 4r + ((k/8) ^ ((r/4)%4)):
+// a block is copied to LDS as is, and the GEMMs' fragment reads of 16
+// consecutive rows at one k chunk then fall into distinct LDS banks.
+constexpr int kSlabK = 32;
+constexpr int kBlk = kSplitTile * kSlabK;
+__host__ __device__ inline int blk_pos(int r, int k) { return (4 * r + ((k >> 3) ^ ((r >> 2) & 3))) * 8 + (k & 7); }
+
 // Table layout of a plan (all device arrays are owned by the plan).
 //
 // Columns are the real moment indices permuted so that even-m columns come
@@ -53,8 +65,8 @@ struct Plan {
     double *Qt = nullptr;      // [n_angp][np]        Q of patch 0, K(lm)-contiguous
     double *coef = nullptr;    // [n_r][lmax+1][4] radial recurrence coefficients
     double *w = nullptr;       // [n_ang] overlap weights
-    bf16 *Ut_hi = nullptr, *Ut_mid = nullptr, *Ut_lo = nullptr;  // three-piece bf16 copies of Ut
-    bf16 *Qt_hi = nullptr, *Qt_mid = nullptr, *Qt_lo = nullptr;  // three-piece bf16 copies of Qt
+    bf16 *Us = nullptr;        // split U: tiles = GEMM1 column tiles, slabs = n_angp/32 (tile-slab blocks)
+    bf16 *Qs = nullptr;        // split Q: tiles = n_angp/128 angular tiles, slabs = np/32
 
     // work space (sized for max_fields)
     int splitk = 1;            // K splits of the moment contraction (work space holds this many)
@@ -63,10 +75,14 @@ struct Plan {
     double *Bpart = nullptr;   // [splitk][rows][np]
     double *Bred = nullptr;    // [rows][np]
     double *M = nullptr;       // [rows][np]
-    bf16 *M_hi = nullptr, *M_mid = nullptr, *M_lo = nullptr; // [rows][np] three-piece bf16 M
-    bf16 *A_split = nullptr;   // [fold ? 2 : 1][3][rows][n_angp] split input (rho +-)
+    bf16 *Ms = nullptr;        // split M: tiles = row tiles, slabs = np/32
+    bf16 *A_split = nullptr;   // split input rho (+-): [fold ? 2 : 1] planes of row tiles x n_angp/32 slabs
 
     int rows_alloc() const { return max_fields * n_r; }
+    int row_tiles() const { return (rows_alloc() + kSplitTile - 1) / kSplitTile; }
+    // GEMM1 column tiles: even-m block tiles, then odd-m block tiles
+    int tiles_e() const { return fold ? (ne_p + kSplitTile - 1) / kSplitTile : (np + kSplitTile - 1) / kSplitTile; }
+    int tiles_o() const { return fold ? (no_p + kSplitTile - 1) / kSplitTile : 0; }
 
     // optional stage timing (events recorded on the plan's stream)
     bool timing = false;
@@ -88,10 +104,11 @@ struct SplitArgs {
     int rows, n_r, n_ang, n_angp, np, ne_p, fold;
     int tiles_e, tiles_o;  // GEMM1 column tiles of the even / odd block
     int kchunk, splitk;    // GEMM1 K per split, number of splits
-    const bf16 *Uh, *Um, *Ul, *Qh, *Qm, *Ql, *Mh, *Mm, *Ml;
+    const bf16 *U, *Q, *M;  // split tables and moments (tile-slab blocks)
     double *Bpart;
-    bf16 *A;        // split input [parity][piece][rows_alloc][n_angp]
-    int rows_alloc;
+    bf16 *A;                // split input (tile-slab blocks, one plane per parity)
+    int row_tiles;          // row tiles of a plane of A (and of M)
+    int ks1, ks2;           // slabs of GEMM1 (n_angp/32) and GEMM2 (np/32)
 };
 
 // Arguments of one field's FP64 contractions.
@@ -113,7 +130,8 @@ struct ScanArgs {
     const int *col_l;
     const double *coef;
     double *Bred, *M;
-    bf16 *Mh, *Mm, *Ml;
+    bf16 *Ms;        // split copy of M (tile-slab blocks), or null
+    int ks2;         // its slabs per row tile (np/32)
     int col_blocks;  // blocks of 64 columns
 };
 
@@ -145,7 +163,9 @@ hipError_t batch_scan(const ScanArgs *args, const BatchItem *items, int n_items,
 hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype);
-hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t rows_x_cols8, int io_dtype, hipStream_t s);
+hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t n_threads, int io_dtype, hipStream_t s);
+// threads of the input split of n_fields fields of a plan
+size_t split_input_threads(const Plan &p, int n_fields);
 SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype);
 hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                             int blocks, hipStream_t s);

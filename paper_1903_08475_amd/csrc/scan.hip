@@ -18,6 +18,12 @@ namespace {
 
 constexpr int kLanes = 64, kMaxChunks = 16;
 
+// element (row, col) of piece 0 of the tile-slab split copy of M
+__device__ inline size_t split_offset(int row, int col, int ks2) {
+    const size_t blk = (size_t)(row / kSplitTile) * ks2 + col / kSlabK;
+    return blk * 3 * kBlk + blk_pos(row % kSplitTile, col % kSlabK);
+}
+
 __device__ inline double reduce_parts(const double *Bpart, size_t stride, int splitk, size_t idx) {
     double s = 0.0;
     for (int k = 0; k < splitk; ++k) s += Bpart[k * stride + idx];
@@ -33,9 +39,7 @@ __device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
     const double *__restrict__ coef = g.coef;
     double *__restrict__ Bred = g.Bred;
     double *__restrict__ M = g.M;
-    bf16 *__restrict__ Mhi = g.Mh;
-    bf16 *__restrict__ Mlo = g.Ml;
-    bf16 *__restrict__ Mmid = g.Mm;
+    bf16 *__restrict__ Ms = g.Ms;
     __shared__ double sA[kMaxChunks][kLanes], sY[kMaxChunks][kLanes];
     __shared__ double sC[kMaxChunks][kLanes], sZ[kMaxChunks][kLanes];
     const int lane = threadIdx.x, ch = threadIdx.y, T = blockDim.y;
@@ -85,10 +89,9 @@ __device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
         for (int n = lo; n < hi; ++n) {
             M[base + (size_t)n * np] = 0.0;
             Bred[base + (size_t)n * np] = 0.0;
-            if (Mhi) {
-                Mhi[base + (size_t)n * np] = (bf16)0.0f;
-                Mlo[base + (size_t)n * np] = (bf16)0.0f;
-                Mmid[base + (size_t)n * np] = (bf16)0.0f;
+            if (Ms) {
+                bf16 *o = Ms + split_offset(f * n_r + n, q, g.ks2);
+                o[0] = o[kBlk] = o[2 * kBlk] = (bf16)0.0f;
             }
         }
         return;
@@ -106,15 +109,16 @@ __device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
         z = c[2] * z + c[3] * Bn1;
         double m = M[base + (size_t)n * np] + z;
         M[base + (size_t)n * np] = m;
-        if (Mhi) {
+        if (Ms) {
             // three-piece bf16 copy for the split contraction
             bf16 h = (bf16)(float)m;
             double r = m - (double)(float)h;
             bf16 md = (bf16)(float)r;
             double r2 = r - (double)(float)md;
-            Mhi[base + (size_t)n * np] = h;
-            Mmid[base + (size_t)n * np] = md;
-            Mlo[base + (size_t)n * np] = (bf16)(float)r2;
+            bf16 *o = Ms + split_offset(f * n_r + n, q, g.ks2);
+            o[0] = h;
+            o[kBlk] = md;
+            o[2 * kBlk] = (bf16)(float)r2;
         }
     }
 }
@@ -163,9 +167,8 @@ ScanArgs scan_args(const Plan &p, int n_fields, bool split_out) {
     g.coef = p.coef;
     g.Bred = p.Bred;
     g.M = p.M;
-    g.Mh = split_out ? p.M_hi : nullptr;
-    g.Mm = split_out ? p.M_mid : nullptr;
-    g.Ml = split_out ? p.M_lo : nullptr;
+    g.Ms = split_out ? p.Ms : nullptr;
+    g.ks2 = p.np / kSlabK;
     g.col_blocks = (n_fields * p.np + kLanes - 1) / kLanes;
     return g;
 }

@@ -389,18 +389,44 @@ __global__ void k_coef(int n_r, int L, const double *re, double *coef) {
 }
 
 // x = hi + mid + lo, each piece the round-to-nearest bf16 of the remaining
-// FP64 residual (24 significant bits in all).
-__global__ void k_split3(const double *x, bf16 *hi, bf16 *mid, bf16 *lo, size_t n) {
-    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    double v = x[t];
-    bf16 h = (bf16)(float)v;
-    double r = v - (double)(float)h;
-    bf16 m = (bf16)(float)r;
-    double r2 = r - (double)(float)m;
-    hi[t] = h;
-    mid[t] = m;
-    lo[t] = (bf16)(float)r2;
+// FP64 residual (24 significant bits in all), written as tile-slab blocks.
+// Thread = one 16-byte chunk (8 consecutive K) of one row of a block.  Tile
+// t < tiles_e holds source rows t*128 .. (end e_end), tile t >= tiles_e
+// rows o0 + (t - tiles_e)*128 .. (end o_end); rows past a tile's end are 0.
+__global__ void k_tile_split(const double *__restrict__ src, size_t ld, int slabs, int tiles_e, int e_end, int o0,
+                             int o_end, size_t n_threads, bf16 *__restrict__ dst) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_threads) return;
+    const size_t blk = t / 512;
+    const int c = (int)(t - blk * 512);
+    const int tile = (int)(blk / slabs), slab = (int)(blk - (size_t)tile * slabs);
+    const int r = c >> 2, kc = (c & 3) ^ ((r >> 2) & 3);
+    const int row = (tile < tiles_e ? tile * kSplitTile : o0 + (tile - tiles_e) * kSplitTile) + r;
+    const int end = tile < tiles_e ? e_end : o_end;
+    const double *x = src + (size_t)row * ld + (size_t)slab * kSlabK + kc * 8;
+    uint32_t hm[3][4];
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+        uint32_t w[3] = {0u, 0u, 0u};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const double v = row < end ? x[q + u] : 0.0;
+            const bf16 h = (bf16)(float)v;
+            const double r1 = v - (double)(float)h;
+            const bf16 m = (bf16)(float)r1;
+            const bf16 l = (bf16)(float)(r1 - (double)(float)m);
+            w[0] |= (uint32_t)__builtin_bit_cast(uint16_t, h) << (16 * u);
+            w[1] |= (uint32_t)__builtin_bit_cast(uint16_t, m) << (16 * u);
+            w[2] |= (uint32_t)__builtin_bit_cast(uint16_t, l) << (16 * u);
+        }
+        hm[0][q / 2] = w[0];
+        hm[1][q / 2] = w[1];
+        hm[2][q / 2] = w[2];
+    }
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    bf16 *o = dst + blk * 3 * kBlk + (size_t)c * 8;
+#pragma unroll
+    for (int pc = 0; pc < 3; ++pc) *(u32x4 *)(o + pc * kBlk) = (u32x4){hm[pc][0], hm[pc][1], hm[pc][2], hm[pc][3]};
 }
 
 // Tables of every patch in the real index (patch 1 = (-1)^m patch 0 under
@@ -531,14 +557,17 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
 
     // split-BF16 copies
     if (p.precision == MPG_SPLIT_BF16) {
-        STEP(hipMalloc(&p.Ut_hi, sizeof(bf16) * nU));
-        STEP(hipMalloc(&p.Ut_mid, sizeof(bf16) * nU));
-        STEP(hipMalloc(&p.Ut_lo, sizeof(bf16) * nU));
-        STEP(hipMalloc(&p.Qt_hi, sizeof(bf16) * nQ));
-        STEP(hipMalloc(&p.Qt_lo, sizeof(bf16) * nQ));
-        STEP(hipMalloc(&p.Qt_mid, sizeof(bf16) * nQ));
-        hipLaunchKernelGGL(k_split3, dim3(blocks(nU, 256)), dim3(256), 0, s, p.Ut, p.Ut_hi, p.Ut_mid, p.Ut_lo, nU);
-        hipLaunchKernelGGL(k_split3, dim3(blocks(nQ, 256)), dim3(256), 0, s, p.Qt, p.Qt_hi, p.Qt_mid, p.Qt_lo, nQ);
+        // U: GEMM1 column tiles over the K = n_angp slabs
+        const int ks1 = p.n_angp / kSlabK, ks2 = p.np / kSlabK;
+        const size_t tU = (size_t)(p.tiles_e() + p.tiles_o()) * ks1 * 512;
+        const size_t tQ = (size_t)(p.n_angp / kSplitTile) * ks2 * 512;
+        STEP(hipMalloc(&p.Us, sizeof(bf16) * tU * 24));
+        STEP(hipMalloc(&p.Qs, sizeof(bf16) * tQ * 24));
+        hipLaunchKernelGGL(k_tile_split, dim3(blocks(tU, 256)), dim3(256), 0, s, p.Ut, (size_t)p.n_angp, ks1,
+                           p.tiles_e(), p.fold ? p.ne_p : p.np, p.ne_p, p.np, tU, p.Us);
+        // Q: angular tiles over the K = np slabs
+        hipLaunchKernelGGL(k_tile_split, dim3(blocks(tQ, 256)), dim3(256), 0, s, p.Qt, (size_t)p.np, ks2,
+                           p.n_angp / kSplitTile, p.n_angp, 0, p.n_angp, tQ, p.Qs);
         STEP(hipGetLastError());
     }
     STEP(hipStreamSynchronize(s));
