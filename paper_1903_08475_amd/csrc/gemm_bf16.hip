@@ -19,8 +19,9 @@
 // highest degree down to l = 0, so the dominant low-degree terms are added
 // to the smallest partial sums last.
 //
-// Tiles: 128x128 per block of 256 threads (2x2 waves of 64x64 = 2x2 MFMA
-// blocks of 32x32), K slabs of 32.  A slab (both operands, three pieces:
+// Tiles: 128x128 per block of 512 threads (2x4 waves of 64x32, each 2x1
+// MFMA blocks of 32x32: two waves per SIMD, so one wave's barrier, copy
+// issue and LDS reads overlap the other's MFMAs), K slabs of 32.  A slab (both operands, three pieces:
 // 48 KB) is copied from global memory straight into LDS by
 // global_load_lds_dwordx4 (no staging registers) into a ring of three
 // slab buffers (144 KB): slab s+2 is in flight while slab s is multiplied,
@@ -47,7 +48,14 @@ typedef __attribute__((address_space(1))) void glb_void;
 constexpr int TB = kSplitTile, TK = 32;
 constexpr int kPiece = TB * TK;       // bf16 elements of one piece of one operand in a slab
 constexpr int kFlushSlabs = 15;       // GEMM1: FP32 runs of at most 480 terms (a multiple of the ring size)
-constexpr int kLoadsPerSlab = 12;     // global_load_lds instructions per wave per slab
+#ifndef MPG_WAVES
+#define MPG_WAVES 8
+#endif
+// 2 x (kWaves/2) waves per block; a wave owns a 64 x kWN output tile
+constexpr int kWaves = MPG_WAVES, kThreads = 64 * kWaves;
+constexpr int kWN = TB / (kWaves / 2), kNB = kWN / 32;  // wave tile width, its 32-wide MFMA blocks
+constexpr int kParts = 8 / kWaves;                      // 64-chunk parts of each piece a wave copies
+constexpr int kLoadsPerSlab = 6 * kParts;               // global_load_lds instructions per wave per slab
 
 // one K slab of both operands, three pieces each, swizzled (see above)
 struct Slab {
@@ -77,11 +85,11 @@ __device__ __forceinline__ uint32_t pack2(bf16 a, bf16 b) {
     return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
 
-__device__ inline void zero(v16f (&acc)[2][2]) {
+__device__ inline void zero(v16f (&acc)[2][kNB]) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < kNB; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 }
@@ -171,21 +179,22 @@ __global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *args,
 
 // ---------------------------------------------------------------------------
 // Slab loader.  A slab of an operand tile is one tile-slab block, already
-// in LDS order: wave w copies chunks 64P .. 64P+63 (P = 2w, 2w+1) of every
-// piece of both operands, lane l copying chunk 64P + l, so that each copy
-// instruction moves 1 KB of consecutive global memory into consecutive LDS.
+// in LDS order: wave w copies chunks 64P .. 64P+63 (P = kParts*w + h) of
+// every piece of both operands, lane l copying chunk 64P + l, so that each
+// copy instruction moves 1 KB of consecutive global memory into
+// consecutive LDS.
 struct Loader {
     const bf16 *a, *b;  // first block (slab 0) of the A and B tiles
-    int lo[2];          // element offsets of this lane's two chunks in a piece
-    int part[2];        // element offsets of the wave's two parts in a piece (wave-uniform)
+    int lo[kParts];     // element offsets of this lane's chunks in a piece
+    int part[kParts];   // element offsets of the wave's parts in a piece (wave-uniform)
 };
 
 __device__ __forceinline__ void init_loader(Loader &L, int wave, int lane, const bf16 *a, const bf16 *b) {
     L.a = a;
     L.b = b;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        L.part[h] = (2 * wave + h) * 512;
+    for (int h = 0; h < kParts; ++h) {
+        L.part[h] = (kParts * wave + h) * 512;
         L.lo[h] = L.part[h] + lane * 8;
     }
 }
@@ -193,7 +202,7 @@ __device__ __forceinline__ void init_loader(Loader &L, int wave, int lane, const
 __device__ __forceinline__ void load_slab(Slab &S, const Loader &L, int slab) {
     const bf16 *a = L.a + (size_t)slab * 3 * kBlk, *b = L.b + (size_t)slab * 3 * kBlk;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < kParts; ++h)
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             __builtin_amdgcn_global_load_lds((glb_void *)(a + q * kBlk + L.lo[h]), (lds_void *)(S.a[q] + L.part[h]),
@@ -208,33 +217,37 @@ __device__ __forceinline__ v8bf frag(const bf16 *piece, int row, int kc) {
     return *(const v8bf *)(piece + (row * 4 + (kc ^ ((row >> 2) & 3))) * 8);
 }
 
-// one 32-deep slab for a wave's 64x64 tile: for each 16-deep step the six
-// partial products are issued product by product over the four
-// accumulators, smallest weight first, so consecutive MFMAs never depend on
-// each other.
-__device__ __forceinline__ void mma_slab(const Slab &S, int wm, int wn, int lane, v16f (&acc)[2][2]) {
+// one 32-deep slab for a wave's 64 x kWN tile: for each 16-deep step the
+// six partial products are issued product by product over the wave's
+// accumulators, smallest weight first.
+__device__ __forceinline__ void mma_slab(const Slab &S, int wm, int wn, int lane, v16f (&acc)[2][kNB]) {
     const int r = lane & 31, kh = lane >> 5;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
         const int kc = 2 * ks + kh;
-        const v8bf ah0 = frag(S.a[0], wm + r, kc), ah1 = frag(S.a[0], wm + 32 + r, kc);
-        const v8bf am0 = frag(S.a[1], wm + r, kc), am1 = frag(S.a[1], wm + 32 + r, kc);
-        const v8bf al0 = frag(S.a[2], wm + r, kc), al1 = frag(S.a[2], wm + 32 + r, kc);
-        const v8bf bh0 = frag(S.b[0], wn + r, kc), bh1 = frag(S.b[0], wn + 32 + r, kc);
-        const v8bf bm0 = frag(S.b[1], wn + r, kc), bm1 = frag(S.b[1], wn + 32 + r, kc);
-        const v8bf bl0 = frag(S.b[2], wn + r, kc), bl1 = frag(S.b[2], wn + 32 + r, kc);
-#define MM4(X0, X1, Y0, Y1)                                                              \
-    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X0, Y0, acc[0][0], 0, 0, 0); \
-    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X0, Y1, acc[0][1], 0, 0, 0); \
-    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X1, Y0, acc[1][0], 0, 0, 0); \
-    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X1, Y1, acc[1][1], 0, 0, 0)
-        MM4(al0, al1, bh0, bh1);
-        MM4(am0, am1, bm0, bm1);
-        MM4(ah0, ah1, bl0, bl1);
-        MM4(am0, am1, bh0, bh1);
-        MM4(ah0, ah1, bm0, bm1);
-        MM4(ah0, ah1, bh0, bh1);
-#undef MM4
+        v8bf ah[2], am[2], al[2], bh[kNB], bm[kNB], bl[kNB];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            ah[i] = frag(S.a[0], wm + 32 * i + r, kc);
+            am[i] = frag(S.a[1], wm + 32 * i + r, kc);
+            al[i] = frag(S.a[2], wm + 32 * i + r, kc);
+        }
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) {
+            bh[j] = frag(S.b[0], wn + 32 * j + r, kc);
+            bm[j] = frag(S.b[1], wn + 32 * j + r, kc);
+            bl[j] = frag(S.b[2], wn + 32 * j + r, kc);
+        }
+#define MMP(X, Y)                                                                           \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < kNB; ++j) \
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X[i], Y[j], acc[i][j], 0, 0, 0);
+        MMP(al, bh)
+        MMP(am, bm)
+        MMP(ah, bl)
+        MMP(am, bh)
+        MMP(ah, bm)
+        MMP(ah, bh)
+#undef MMP
     }
 }
 
@@ -262,7 +275,7 @@ __device__ __forceinline__ void ring_barrier() {
 // have landed, and the ring may be refilled after a barrier.
 template <bool FLUSH>
 __device__ __forceinline__ void run_ring(Slab &S0, Slab &S1, Slab &S2, const Loader &L, int k0, int dk, int nsl,
-                                         int wm, int wn, int lane, v16f (&acc)[2][2], double (&acc64)[2][2][16]) {
+                                         int wm, int wn, int lane, v16f (&acc)[2][kNB], double (&acc64)[2][kNB][16]) {
     if (nsl <= 0) return;
     const int last = nsl - 1;
     load_slab(S0, L, k0);
@@ -289,7 +302,7 @@ __device__ __forceinline__ void run_ring(Slab &S0, Slab &S1, Slab &S2, const Loa
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < kNB; ++b)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc64[a][b][r] += (double)acc[a][b][r];
             zero(acc);
@@ -311,7 +324,7 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
     const int rows = g.rows, n_angp = g.n_angp, np = g.np, ne_p = g.ne_p;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * kWN;
     const bool odd = FOLD && tn >= g.tiles_e;
     const int c0 = odd ? ne_p + (tn - g.tiles_e) * TB : tn * TB;
     const int cend = odd ? np : (FOLD ? ne_p : np);
@@ -326,13 +339,13 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
     const bf16 *A0 = g.A + (odd ? (size_t)g.row_tiles * tstride : 0) + (size_t)tm * tstride;
     init_loader(L, wave, lane, A0, g.U + (size_t)tn * tstride);
 
-    v16f acc[2][2];
-    double acc64[2][2][16];
+    v16f acc[2][kNB];
+    double acc64[2][kNB][16];
     zero(acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < kNB; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
     run_ring<true>(S0, S1, S2, L, kbeg / TK, 1, nsl, wm, wn, lane, acc, acc64);
@@ -341,7 +354,7 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < kNB; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 int rr = m0 + wm + 32 * a + d_row(lane, r);
@@ -359,15 +372,15 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * kWN;
     const int m0 = tm * TB, n0 = tn * TB;
 
     Loader L;
     const size_t tstride = (size_t)g.ks2 * 3 * kBlk;
     init_loader(L, wave, lane, g.M + (size_t)tm * tstride, g.Q + (size_t)tn * tstride);
 
-    v16f acc_e[2][2], acc_o[2][2];
-    double unused[2][2][16];
+    v16f acc_e[2][kNB], acc_o[2][kNB];
+    double unused[2][kNB][16];
     zero(acc_e);
     zero(acc_o);
     if (FOLD) {
@@ -385,7 +398,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < kNB; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 int rr = m0 + wm + 32 * a + d_row(lane, r);
@@ -408,13 +421,13 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 // Grid launches for one plan: GEMM1 grid x = column tile, y = row tile,
 // z = K split; GEMM2 grid x = row tile, y = angular tile.
 template <bool FOLD>
-__global__ __launch_bounds__(256) void k_gemm1(SplitArgs g) {
+__global__ __launch_bounds__(kThreads) void k_gemm1(SplitArgs g) {
     __shared__ Slab s0, s1, s2;
     gemm1_tile<FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, s0, s1, s2);
 }
 
 template <typename T, bool FOLD>
-__global__ __launch_bounds__(256) void k_gemm2(SplitArgs g) {
+__global__ __launch_bounds__(kThreads) void k_gemm2(SplitArgs g) {
     __shared__ Slab s0, s1, s2;
     gemm2_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, s0, s1, s2);
 }
@@ -432,7 +445,7 @@ __device__ __forceinline__ int next_item(int *head, int *slot) {
     return __builtin_amdgcn_readfirstlane(*slot);
 }
 
-__global__ __launch_bounds__(256) void k_batch_gemm1(const SplitArgs *__restrict__ args,
+__global__ __launch_bounds__(kThreads) void k_batch_gemm1(const SplitArgs *__restrict__ args,
                                                      const BatchItem *__restrict__ items, int n_items, int *head) {
     __shared__ Slab s0, s1, s2;
     __shared__ int slot;
@@ -447,7 +460,7 @@ __global__ __launch_bounds__(256) void k_batch_gemm1(const SplitArgs *__restrict
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_batch_gemm2(const SplitArgs *__restrict__ args,
+__global__ __launch_bounds__(kThreads) void k_batch_gemm2(const SplitArgs *__restrict__ args,
                                                      const BatchItem *__restrict__ items, int n_items, int *head) {
     __shared__ Slab s0, s1, s2;
     __shared__ int slot;
@@ -512,8 +525,8 @@ hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rh
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
     SplitArgs g = split_args(p, n_fields, rho, nullptr, rho_dtype);
     dim3 grid(g.tiles_e + g.tiles_o, (g.rows + TB - 1) / TB, p.splitk);
-    if (p.fold) hipLaunchKernelGGL((k_gemm1<true>), grid, dim3(256), 0, p.stream, g);
-    else hipLaunchKernelGGL((k_gemm1<false>), grid, dim3(256), 0, p.stream, g);
+    if (p.fold) hipLaunchKernelGGL((k_gemm1<true>), grid, dim3(kThreads), 0, p.stream, g);
+    else hipLaunchKernelGGL((k_gemm1<false>), grid, dim3(kThreads), 0, p.stream, g);
     return hipGetLastError();
 }
 
@@ -521,11 +534,11 @@ hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     SplitArgs g = split_args(p, n_fields, nullptr, phi, phi_dtype);
     dim3 grid((g.rows + TB - 1) / TB, p.n_angp / TB);
     if (phi_dtype == MPG_F64) {
-        if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(256), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(256), 0, p.stream, g);
+        if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(kThreads), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(kThreads), 0, p.stream, g);
     } else {
-        if (p.fold) hipLaunchKernelGGL((k_gemm2<float, true>), grid, dim3(256), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm2<float, false>), grid, dim3(256), 0, p.stream, g);
+        if (p.fold) hipLaunchKernelGGL((k_gemm2<float, true>), grid, dim3(kThreads), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm2<float, false>), grid, dim3(kThreads), 0, p.stream, g);
     }
     return hipGetLastError();
 }
@@ -542,16 +555,16 @@ hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t n_threads
 hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                             int blocks, hipStream_t s) {
     (void)io_dtype;
-    hipLaunchKernelGGL(k_batch_gemm1, dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+    hipLaunchKernelGGL(k_batch_gemm1, dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head);
     return hipGetLastError();
 }
 
 hipError_t batch_gemm2_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                             int blocks, hipStream_t s) {
     if (io_dtype == MPG_F64)
-        hipLaunchKernelGGL((k_batch_gemm2<double>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+        hipLaunchKernelGGL((k_batch_gemm2<double>), dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head);
     else
-        hipLaunchKernelGGL((k_batch_gemm2<float>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+        hipLaunchKernelGGL((k_batch_gemm2<float>), dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head);
     return hipGetLastError();
 }
 
