@@ -99,12 +99,12 @@ def time_path(plan, rho, phi, steps, warmup):
 def cpu_baseline(lmax):
     """The oracle, as it stands, on a bounded sample of the same workload:
     the large workload's lmax and radial spacing law on a coarser angular
-    grid (pi/96, 48x144 per patch) and 96 shells.  Timed: moments, radial
+    grid (pi/128, 64x192 per patch) and 144 shells.  Timed: moments, radial
     sums and expansion, single-threaded (its table build, run on a process
     pool beforehand, is excluded, as on the GPU)."""
     import oracle as O
     import workloads as W
-    g = W.yinyang(48, W.log_edges(96, 3.0), lmax)
+    g = W.yinyang(64, W.log_edges(144, 3.0), lmax)
     rho = W.random_rho(g, 5005)
     w = O.overlap_weights(g)
     U, Q = O.tables_parallel(g, lmax, w, workers=max(1, min(16, os.cpu_count() or 1)))
@@ -119,10 +119,72 @@ def cpu_baseline(lmax):
         "unit": "terms/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"lmax {lmax}, Yin-Yang pi/96 (2x48x144 cells), 96 log-spaced shells, "
+        "sample": (f"lmax {lmax}, Yin-Yang pi/128 (2x64x192 cells), 144 log-spaced shells, "
                    f"{terms:.3e} terms; moments + radial sums + expansion in {dt:.1f} s, "
                    f"single thread ({os.cpu_count()} host cores)"),
     }
+
+
+def batch_workload(dev, reps):
+    """The batching workload: 64 seeded fields of uneven sizes (shells
+    U{100..800}, Delta in {pi/64, pi/128, pi/256}, lmax U{12..32}; ellipsoid
+    with random semi-axes plus 4-32 blobs), solved in one batched call (one
+    persistent launch per stage, replayed from a captured hipGraph), in
+    split-BF16 on the float32-rounded densities and in FP64.  Reports the
+    batch makespan, its throughput, and per-field single-solve latencies
+    (p50/p99) beside it."""
+    import torch
+    import paper_1903_08475_amd as mpg
+    import workloads as W
+    fields = W.config4_fields()
+    rho64 = []
+    for k, (g, d) in enumerate(fields):
+        rho64.append(W.cell_average(g, d, sub=2, device=dev, as_tensor=True))
+        if k % 16 == 15:
+            log(f"[bench] batch: {k + 1} fields generated")
+    terms = sum(g.n_cells * g.n_lm for g, _ in fields)
+    res = {"fields": len(fields), "terms_per_batch": terms,
+           "cells_per_batch": sum(g.n_cells for g, _ in fields)}
+    phis = {}
+    for prec, dtype in (("split_bf16", torch.float32), ("fp64", torch.float64)):
+        plans = [mpg.Plan(g, precision=prec) for g, _ in fields]
+        rhos = [r.to(dtype) for r in rho64]
+        out = [torch.empty_like(r) for r in rhos]
+        mpg.potential_batch(plans, rhos, out)  # builds and captures the graph
+        torch.cuda.synchronize()
+        stream = plans[0].stream
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            mpg.potential_batch(plans, rhos, out)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        lat = []
+        for p, r, o in zip(plans, rhos, out):
+            p.potential(r, out=o)  # warm
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(p.stream)
+            p.potential(r, out=o)
+            e1.record(p.stream)
+            torch.cuda.synchronize()
+            lat.append(e0.elapsed_time(e1))
+        lat = np.array(lat)
+        res[prec] = {"batch_ms": ms, "value": terms / (ms * 1e-3), "unit": "terms/s",
+                     "single_field_ms_p50": float(np.percentile(lat, 50)),
+                     "single_field_ms_p99": float(np.percentile(lat, 99)),
+                     "sum_single_field_ms": float(lat.sum())}
+        log(f"[bench] batch {prec}: {ms:.2f} ms per batch, singles p50 {res[prec]['single_field_ms_p50']:.3f} "
+            f"p99 {res[prec]['single_field_ms_p99']:.3f} ms")
+        mpg.potential_batch(plans, rhos, out)
+        torch.cuda.synchronize()
+        phis[prec] = out
+        del plans
+    err = 0.0
+    for x, y in zip(phis["split_bf16"], phis["fp64"]):
+        err = max(err, float((x.double() - y).abs().max() / y.abs().max()))
+    res["split_vs_fp64_max_rel_err"] = err
+    return res
 
 
 def main():
@@ -134,6 +196,9 @@ def main():
     ap.add_argument("--snapshots", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time the 64-field uneven batch (one batched call per precision)")
+    ap.add_argument("--batch-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -229,6 +294,12 @@ def main():
         out["split_vs_fp64_max_rel_err"] = err
         out["speedup_vs_fp64"] = ms64 / ms
         del plan64, ref
+
+    if args.batch:
+        log("[bench] 64-field batch")
+        del rho, phi
+        torch.cuda.empty_cache()
+        out["batch"] = batch_workload(dev, args.batch_reps)
 
     if cpu is not None:
         out["cpu_baseline"] = cpu
