@@ -63,15 +63,20 @@ extern "C" {
  * [phi0, phi0 + n_phi*dphi]; shells are [r_edges[i], r_edges[i+1]].
  * All pointers are host pointers, read during mpg_plan only. */
 typedef struct mpg_grid {
-    int n_patches;              /* 1 (one patch) or 2 (Yin-Yang, Sec. 4)     */
+    int n_patches;              /* 1 .. MPG_MAX_PATCHES patches (Sec. 3)     */
     int n_r, n_theta, n_phi;    /* cells per patch                           */
     const double *r_edges;      /* n_r+1, strictly increasing, r_edges[0]>=0 */
     double theta0, phi0;        /* local lower corner                        */
     double dtheta, dphi;        /* local spacing                             */
     const double *euler;        /* n_patches x (alpha, beta, gamma)          */
-    const double *overlap_w;    /* n_theta*n_phi cell weights w_jk, or NULL  */
+    const double *overlap_w;    /* cell weights w_jk (see w_per_patch), or NULL */
     double G;                   /* gravitational constant                    */
+    int w_per_patch;            /* 0: overlap_w holds n_theta*n_phi weights
+                                   shared by every patch; 1: it holds
+                                   n_patches*n_theta*n_phi, patch-major      */
 } mpg_grid;
+
+#define MPG_MAX_PATCHES 16
 
 typedef struct mpg_plan_s *mpg_plan_t;
 
@@ -84,11 +89,17 @@ typedef struct mpg_plan_s *mpg_plan_t;
  *   max_fields : largest n_fields later passed to the compute calls (>= 1);
  *                sizes the work space
  *   stream     : hipStream_t on which the plan runs (NULL: default stream)
- * Two patches use the Yin/Yang parity fold (Q_Yang = (-1)^m Q_Yin, Sec. 4.2),
- * which requires Euler angles that differ only by pi in gamma; other
- * two-patch orientations return MPG_EUNSUPPORTED.  Computing overlap
- * weights needs a Yin-Yang grid symmetric about the patch centre; otherwise
- * pass overlap_w.  Blocks until the tables are built.
+ * Two patches whose rotations differ by pi about the local polar axis
+ * (R^(1) = diag(-1,-1,1) R^(0), as for Yin and Yang) use the parity fold
+ * (U_Yang = (-1)^m U_Yin, Sec. 4.2): one table and contractions over
+ * rho_Yin +- rho_Yang.  Every other set of patches (any n_patches, any
+ * Euler angles; Sec. 3) takes the general path: tables of every patch and
+ * contractions over all patches' cells at once.
+ * Overlap weights: NULL gives w = 1 for one patch, and the closed-form
+ * Yin-Yang weights for two patches related by the Yin<->Yang map
+ * (R^(0)T R^(1) = P of Eq. caryytransform) with extents symmetric about
+ * the patch centre; other grids must pass overlap_w (else
+ * MPG_EUNSUPPORTED).  Blocks until the tables are built.
  * Errors: MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE, MPG_EUNSUPPORTED. */
 int mpg_plan(const mpg_grid *grid, int lmax, int precision, int max_fields,
              void *stream, mpg_plan_t *out);
@@ -132,7 +143,7 @@ int mpg_autotune(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
 /* Copy the plan's FP64 tables to device buffers, in the real index:
  *   U : [n_patches][n_theta*n_phi][n_lm]   (Eqs. U_C/U_S), or NULL
  *   Q : [n_patches][n_theta*n_phi][n_lm]   (Eqs. Q_C/Q_S), or NULL
- *   w : [n_theta*n_phi] overlap weights, or NULL
+ *   w : [n_patches][n_theta*n_phi] overlap weights, or NULL
  * For checking the table build; not needed for solving. */
 int mpg_tables(mpg_plan_t plan, double *U, double *Q, double *w);
 

@@ -40,6 +40,7 @@ class _OrcGrid(C.Structure):
         ("theta0", C.c_double), ("phi0", C.c_double), ("dtheta", C.c_double), ("dphi", C.c_double),
         ("euler", C.POINTER(C.c_double)),
         ("G", C.c_double),
+        ("w_stride", C.c_int),
     ]
 
 
@@ -101,6 +102,12 @@ class _G:
         s.G = grid.G
         self.s = s
 
+    def set_w_stride(self, w, n_ang):
+        """Weights given per patch ([n_patches, n_ang]) or one set for all."""
+        if w is not None and w.size not in (n_ang, self.s.n_patches * n_ang):
+            raise ValueError("overlap weights must have n_ang or n_patches*n_ang entries")
+        self.s.w_stride = n_ang if (w is not None and w.size != n_ang) else 0
+
     @property
     def ref(self):
         return C.byref(self.s)
@@ -153,6 +160,7 @@ def tables(grid, lmax, w=None, cells=None, want_U=True, want_Q=True):
     Q = np.zeros((grid.n_patches, n_ang, n_lm(lmax))) if want_Q else None
     c0, c1 = (0, n_ang) if cells is None else cells
     wv = None if w is None else _f64(w)
+    g.set_w_stride(wv, n_ang)
     _check(lib().orc_tables_range(g.ref, lmax, _dp(wv), c0, c1, _dp(U), _dp(Q)), "tables")
     return U, Q
 
@@ -223,6 +231,7 @@ def brute_phi(grid, lmax, w, rho, p, i, c, nq=12):
     g = _G(grid)
     rho = _f64(rho)
     wv = None if w is None else _f64(w)
+    g.set_w_stride(wv, grid.n_theta * grid.n_phi)
     p, i, c = _i32(p), _i32(i), _i32(c)
     out = np.zeros(len(p))
     _check(lib().orc_brute_phi(g.ref, lmax, _dp(wv), _dp(rho), nq, len(p), _ip(p), _ip(i), _ip(c), _dp(out)),

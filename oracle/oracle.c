@@ -294,7 +294,7 @@ int orc_tables_range(const orc_grid *g, int lmax, const double *w,
                         }
                     }
                 }
-                double wc = w ? w[c] : 1.0;
+                double wc = w ? w[(size_t)p * g->w_stride + c] : 1.0;
                 double *row = U + ((size_t)p * n_ang + c) * nlm;
                 for (int l = 0; l <= lmax; ++l) {
                     row[idx_c(l, 0)] = wc * acc[idx_c(l, 0)];          /* 2/delta_0 = 1 */
@@ -513,7 +513,7 @@ int orc_brute_phi(const orc_grid *g, int lmax, const double *w,
                         }
                     }
                 }
-                double wc = w ? w[c] : 1.0;
+                double wc = w ? w[(size_t)p * g->w_stride + c] : 1.0;
                 for (int i = 0; i < nr; ++i) {
                     double r = rho[((size_t)p * nr + i) * n_ang + c];
                     if (r == 0.0) continue;

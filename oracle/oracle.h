@@ -51,6 +51,8 @@ typedef struct {
     double dtheta, dphi;    /* local angular spacing                        */
     const double *euler;    /* n_patches*3 Euler angles (alpha,beta,gamma)  */
     double G;               /* gravitational constant                       */
+    int w_stride;           /* overlap weights of patch p start at
+                               w + p*w_stride (0: one set for all patches) */
 } orc_grid;
 
 /* Eq. rottransmatrix: R = R_z''(gamma) R_y'(beta) R_z(alpha), x = R xi. */

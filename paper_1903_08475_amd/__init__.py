@@ -42,6 +42,7 @@ class _Grid(C.Structure):
         ("euler", C.POINTER(C.c_double)),
         ("overlap_w", C.POINTER(C.c_double)),
         ("G", C.c_double),
+        ("w_per_patch", C.c_int),
     ]
 
 
@@ -111,7 +112,10 @@ class Plan:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._r = np.ascontiguousarray(grid.r_edges, dtype=np.float64)
         self._e = np.ascontiguousarray(np.asarray(grid.euler).reshape(-1), dtype=np.float64)
+        n_ang = grid.n_theta * grid.n_phi
         self._w = None if overlap_w is None else np.ascontiguousarray(overlap_w, dtype=np.float64)
+        if self._w is not None and self._w.size not in (n_ang, grid.n_patches * n_ang):
+            raise ValueError("overlap_w must hold n_theta*n_phi or n_patches*n_theta*n_phi weights")
         g = _Grid()
         g.n_patches, g.n_r, g.n_theta, g.n_phi = grid.n_patches, grid.n_r, grid.n_theta, grid.n_phi
         g.r_edges = self._r.ctypes.data_as(C.POINTER(C.c_double))
@@ -119,6 +123,7 @@ class Plan:
         g.euler = self._e.ctypes.data_as(C.POINTER(C.c_double))
         g.overlap_w = None if self._w is None else self._w.ctypes.data_as(C.POINTER(C.c_double))
         g.G = grid.G
+        g.w_per_patch = int(self._w is not None and self._w.size != n_ang)
         h = C.c_void_p()
         _check(lib().mpg_plan(C.byref(g), self.lmax, PRECISIONS[precision], max_fields,
                               _stream_handle(self.stream), C.byref(h)))
@@ -179,13 +184,14 @@ class Plan:
         return sk.value, ch.value
 
     def tables(self):
-        """(U, Q, w) as float64 device tensors [n_patches, n_ang, n_lm], [n_ang]."""
+        """(U, Q, w) as float64 device tensors [n_patches, n_ang, n_lm] (twice)
+        and [n_patches, n_ang]."""
         import torch
         n_ang = self.shape[2] * self.shape[3]
         dev = torch.device("cuda", torch.cuda.current_device())
         U = torch.zeros((self.shape[0], n_ang, self.n_lm), dtype=torch.float64, device=dev)
         Q = torch.zeros_like(U)
-        w = torch.zeros(n_ang, dtype=torch.float64, device=dev)
+        w = torch.zeros((self.shape[0], n_ang), dtype=torch.float64, device=dev)
         _check(lib().mpg_tables(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(Q.data_ptr()),
                                 C.c_void_p(w.data_ptr())))
         self.sync()

@@ -117,7 +117,7 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     for (int f : order) {
         const Plan &p = q[f];
         const int rt = (p.n_r + T1 - 1) / T1;
-        const int at = p.n_angp / T1;
+        const int at = p.kang() / T1;
         for (int a = 0; a < at; ++a)
             for (int m = 0; m < rt; ++m) i2.push_back({f, m, a, 0});
     }

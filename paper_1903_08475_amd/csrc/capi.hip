@@ -112,7 +112,8 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
     if (!out) return fail(MPG_EINVAL, "mpg_plan: out is NULL");
     *out = nullptr;
     if (!g) return fail(MPG_EINVAL, "mpg_plan: grid is NULL");
-    if (g->n_patches != 1 && g->n_patches != 2) return fail(MPG_EUNSUPPORTED, "mpg_plan: n_patches must be 1 or 2");
+    if (g->n_patches < 1 || g->n_patches > MPG_MAX_PATCHES)
+        return fail(MPG_EINVAL, "mpg_plan: n_patches outside [1, MPG_MAX_PATCHES]");
     if (g->n_r < 1 || g->n_theta < 1 || g->n_phi < 1) return fail(MPG_EINVAL, "mpg_plan: empty grid");
     if ((long long)g->n_theta * g->n_phi > (1 << 26)) return fail(MPG_EINVAL, "mpg_plan: too many angular cells");
     if (!g->r_edges || !g->euler) return fail(MPG_EINVAL, "mpg_plan: r_edges/euler is NULL");
@@ -157,11 +158,12 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
         double dev = 0.0;
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) dev = fmax(dev, fabs(R1[3 * i + j] - D[i] * R0[3 * i + j]));
-        if (dev > 1e-12) {
-            free_plan(p);
-            return fail(MPG_EUNSUPPORTED, "mpg_plan: two patches must differ by a rotation of pi about z");
+        p->fold = dev <= 1e-12;
+        // per-patch weights can only be folded when both patches carry the same
+        if (p->fold && g->overlap_w && g->w_per_patch) {
+            const size_t n = (size_t)g->n_theta * g->n_phi;
+            for (size_t c = 0; c < n && p->fold; ++c) p->fold = g->overlap_w[c] == g->overlap_w[n + c];
         }
-        p->fold = true;
         if (!g->overlap_w) {
             // overlap weights need the Yin<->Yang relation R0^T R1 = P and
             // extents symmetric about the patch centre
@@ -180,14 +182,20 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
             if (d2 > 1e-12 || !sym) {
                 free_plan(p);
                 return fail(MPG_EUNSUPPORTED,
-                            "mpg_plan: overlap weights are computed only for symmetric Yin-Yang extents; pass "
-                            "overlap_w");
+                            "mpg_plan: overlap weights are computed only for the Yin<->Yang relation with symmetric "
+                            "extents; pass overlap_w");
             }
             p->ovl_sc = cos(g->theta0);
             p->ovl_kap_inf = ph_hi >= M_PI - 1e-15;
             p->ovl_kap = p->ovl_kap_inf ? 0.0 : 1.0 / tan(M_PI - ph_hi);
         }
     }
+
+    if (g->n_patches > 2 && !g->overlap_w) {
+        free_plan(p);
+        return fail(MPG_EUNSUPPORTED, "mpg_plan: more than two patches need overlap_w");
+    }
+    p->npat = p->fold ? 1 : g->n_patches;
 
     // column layout
     if (p->fold) {
@@ -213,7 +221,7 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
         int col_tiles = p->fold ? (p->ne_p + 63) / 64 + (p->no_p + 63) / 64 : (p->np + 63) / 64;
         int tiles = col_tiles * ((p->n_r + 63) / 64);
         int s = (1024 + tiles - 1) / tiles;
-        int kmax = p->n_angp / 64;
+        int kmax = p->kang() / 64;
         p->splitk = s < 1 ? 1 : (s > kmax ? kmax : s);
         if (p->splitk < 1) p->splitk = 1;
     }
@@ -229,7 +237,7 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
     if (precision == MPG_SPLIT_BF16) {
         // tile-slab blocks; rows past the last field stay zero (finite)
         const size_t nM = (size_t)p->row_tiles() * (p->np / kSlabK) * 3 * kBlk;
-        const size_t nA = (size_t)(p->fold ? 2 : 1) * p->row_tiles() * (p->n_angp / kSlabK) * 3 * kBlk;
+        const size_t nA = (size_t)(p->fold ? 2 : 1) * p->row_tiles() * (p->kang() / kSlabK) * 3 * kBlk;
         if ((e = hipMalloc(&p->Ms, sizeof(bf16) * nM)) != hipSuccess ||
             (e = hipMalloc(&p->A_split, sizeof(bf16) * nA)) != hipSuccess ||
             (e = hipMemset(p->Ms, 0, sizeof(bf16) * nM)) != hipSuccess ||
@@ -239,7 +247,7 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
             return rc;
         }
     }
-    if ((e = build_tables(*p, g->euler, g->r_edges, g->overlap_w)) != hipSuccess) {
+    if ((e = build_tables(*p, g->euler, g->r_edges, g->overlap_w, g->w_per_patch)) != hipSuccess) {
         int rc = hip_fail(e, "mpg_plan: table build");
         free_plan(p);
         return rc;

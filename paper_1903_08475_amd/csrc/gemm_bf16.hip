@@ -107,13 +107,17 @@ __device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
     const int c = (int)(t - blk * 512);
     const int tile = (int)(blk / g.ks1), slab = (int)(blk - (size_t)tile * g.ks1);
     const int r = c >> 2, kc = (c & 3) ^ ((r >> 2) & 3);
-    const int row = tile * TB + r, k0 = slab * TK + kc * 8;
+    const int row = tile * TB + r;
+    int k0 = slab * TK + kc * 8;
     const int n_r = g.n_r, n_ang = g.n_ang;
     const bool row_ok = row < g.rows;
     const int f = row_ok ? row / n_r : 0, i = row_ok ? row - f * n_r : 0;
-    const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
-    const T *r0 = (const T *)g.rho + f * fld + (size_t)i * n_ang;
-    const T *r1 = r0 + (size_t)n_r * n_ang;
+    const size_t pstride = (size_t)n_r * n_ang, fld = (size_t)g.n_patches * pstride;
+    // without the fold K runs over every patch's cells (k = patch*n_angp + cell)
+    const int gp = FOLD ? 0 : k0 / g.n_angp;
+    k0 -= gp * g.n_angp;
+    const T *r0 = (const T *)g.rho + f * fld + gp * pstride + (size_t)i * n_ang;
+    const T *r1 = r0 + pstride;
     double d0[8], d1[8];
     if (sizeof(T) == 4 && (n_ang & 7) == 0) {
         // whole chunk inside or outside the row; 32-byte aligned
@@ -321,7 +325,7 @@ __device__ __forceinline__ void run_ring(Slab &S0, Slab &S1, Slab &S2, const Loa
 template <bool FOLD>
 __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, Slab &S0, Slab &S1,
                                            Slab &S2) {
-    const int rows = g.rows, n_angp = g.n_angp, np = g.np, ne_p = g.ne_p;
+    const int rows = g.rows, np = g.np, ne_p = g.ne_p;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * kWN;
@@ -330,7 +334,7 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
     const int cend = odd ? np : (FOLD ? ne_p : np);
     const int m0 = tm * TB;
     const int kbeg = tz * g.kchunk;
-    const int kend = min(n_angp, kbeg + g.kchunk);
+    const int kend = min(g.kang, kbeg + g.kchunk);
     const int nsl = kend > kbeg ? (kend - kbeg) / TK : 0;
 
     // A: the pre-split rho (+-) of this tile's column parity; B: split U
@@ -394,7 +398,8 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
         run_ring<false>(S0, S1, S2, L, ns - 1, -1, ns, wm, wn, lane, acc_e, unused);
     }
 
-    const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
+    const size_t pstride = (size_t)n_r * n_ang, fld = (size_t)g.n_patches * pstride;
+    const int n_angp = g.n_angp;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -402,15 +407,16 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 int rr = m0 + wm + 32 * a + d_row(lane, r);
-                int jk = n0 + wn + 32 * b + (lane & 31);
+                int kk = n0 + wn + 32 * b + (lane & 31);
+                const int gp = kk / n_angp, jk = kk - gp * n_angp;
                 if (rr >= rows || jk >= n_ang) continue;
                 int f = rr / n_r, i = rr - f * n_r;
-                T *o = phi + f * fld + (size_t)i * n_ang + jk;
+                T *o = phi + f * fld + gp * pstride + (size_t)i * n_ang + jk;
                 double e = (double)acc_e[a][b][r];
                 if (FOLD) {
                     double od = (double)acc_o[a][b][r];
                     o[0] = (T)(e + od);
-                    o[(size_t)n_r * n_ang] = (T)(e - od);
+                    o[pstride] = (T)(e - od);
                 } else {
                     o[0] = (T)e;
                 }
@@ -488,9 +494,11 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.np = p.np;
     g.ne_p = p.ne_p;
     g.fold = p.fold;
+    g.n_patches = p.n_patches;
+    g.kang = p.kang();
     g.tiles_e = p.tiles_e();
     g.tiles_o = p.tiles_o();
-    g.kchunk = ((p.n_angp / p.splitk + TK - 1) / TK) * TK;
+    g.kchunk = ((g.kang / p.splitk + TK - 1) / TK) * TK;
     g.splitk = p.splitk;
     g.U = p.Us;
     g.Q = p.Qs;
@@ -498,14 +506,14 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.Bpart = p.Bpart;
     g.A = p.A_split;
     g.row_tiles = p.row_tiles();
-    g.ks1 = p.n_angp / TK;
+    g.ks1 = g.kang / TK;
     g.ks2 = p.np / TK;
     return g;
 }
 
 // one thread per 16-byte chunk of the row tiles holding the fields' rows
 size_t split_input_threads(const Plan &p, int n_fields) {
-    return (size_t)((n_fields * p.n_r + TB - 1) / TB) * (p.n_angp / TK) * 512;
+    return (size_t)((n_fields * p.n_r + TB - 1) / TB) * (p.kang() / TK) * 512;
 }
 
 hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
@@ -532,7 +540,7 @@ hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtyp
 
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     SplitArgs g = split_args(p, n_fields, nullptr, phi, phi_dtype);
-    dim3 grid((g.rows + TB - 1) / TB, p.n_angp / TB);
+    dim3 grid((g.rows + TB - 1) / TB, g.kang / TB);
     if (phi_dtype == MPG_F64) {
         if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(kThreads), 0, p.stream, g);
         else hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(kThreads), 0, p.stream, g);

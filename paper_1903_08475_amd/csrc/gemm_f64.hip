@@ -1,14 +1,16 @@
 // FP64 MFMA contractions of the solve (Sec. 4.3 steps 2 and 5).
 //
-// GEMM1 (moments, Eq. B_CS):  B[row][q] = sum_jk A[row][jk] U[q][jk]
+// GEMM1 (moments, Eq. B_CS):  B[row][q] = sum_k A[row][k] U[q][k]
 //   with A = rho_Yin + rho_Yang for even-m columns and rho_Yin - rho_Yang
 //   for odd-m columns under the Yin/Yang fold (U_Yang = (-1)^m U_Yin,
-//   Sec. 4.2), A = rho for one patch.  Split over K (the angular cells); the
-//   partial sums go to a work array that the radial scan reduces in a fixed
-//   order.
-// GEMM2 (expansion, Eq. gravpotmult):  Phi[row][jk] = sum_q M[row][q] Q[jk][q]
+//   Sec. 4.2).  Otherwise k runs over the cells of every patch, patch after
+//   patch (k = g*n_angp + jk), and A = rho (the sum over patches of Eq. B_CS
+//   is part of the contraction).  Split over K; the partial sums go to a
+//   work array that the radial scan reduces in a fixed order.
+// GEMM2 (expansion, Eq. gravpotmult):  Phi[row][k] = sum_q M[row][q] Q[k][q]
 //   accumulated separately over even- and odd-m columns, written as
-//   Phi_Yin = E + O and Phi_Yang = E - O under the fold.
+//   Phi_Yin = E + O and Phi_Yang = E - O under the fold; otherwise k runs
+//   over the cells of every patch as in GEMM1.
 //
 // Rows are (field, shell) pairs; tiles are 64x64x16 on 256 threads (four
 // waves of 32x32, v_mfma_f64_16x16x4f64), with the next K slab loaded into
@@ -37,8 +39,17 @@ struct Slab {
     double v[4];
 };
 
+// four consecutive K of one row of A; k = patch*n_angp + cell (the four
+// never straddle a patch), r0/r1 the row in patch 0 and 1, pstride the
+// distance between patches of a field
 template <typename T, bool FOLD>
-__device__ inline void load_rho(Slab &s, const T *r0, const T *r1, int k, int n_ang, bool row_ok, bool odd) {
+__device__ inline void load_rho(Slab &s, const T *r0, const T *r1, int k, int n_ang, int n_angp, size_t pstride,
+                                bool row_ok, bool odd) {
+    if (!FOLD) {
+        const int gp = k / n_angp;
+        r0 += gp * pstride;
+        k -= gp * n_angp;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         double a = 0.0;
@@ -97,16 +108,16 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
     const int cend = odd ? np : (FOLD ? ne_p : np);
     const int m0 = tm * BM;
     const int kbeg = tz * g.kchunk;
-    const int kend = min(n_angp, kbeg + g.kchunk);
+    const int kend = min(g.kang, kbeg + g.kchunk);
 
     const int lr = t >> 2, lk = (t & 3) * 4;
     const int row = m0 + lr;
     const bool row_ok = row < rows;
     const int f = row_ok ? row / n_r : 0, i = row_ok ? row - f * n_r : 0;
-    const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
+    const size_t pstride = (size_t)n_r * n_ang, fld = (size_t)g.n_patches * pstride;
     const T *r0 = rho + f * fld + (size_t)i * n_ang;
-    const T *r1 = r0 + (size_t)n_r * n_ang;
-    const double *urow = g.Ut + (size_t)(c0 + lr) * n_angp;
+    const T *r1 = r0 + pstride;
+    const double *urow = g.Ut + (size_t)(c0 + lr) * g.kang;
 
     v4d acc[2][2];
 #pragma unroll
@@ -116,7 +127,7 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
 
     Slab sa, sb;
     if (kbeg < kend) {
-        load_rho<T, FOLD>(sa, r0, r1, kbeg + lk, n_ang, row_ok, odd);
+        load_rho<T, FOLD>(sa, r0, r1, kbeg + lk, n_ang, n_angp, pstride, row_ok, odd);
         load_rowk(sb, urow, kbeg + lk, true);
     }
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
@@ -125,7 +136,7 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
         store_slab(sm.Bs, sb, lr, lk);
         __syncthreads();
         if (k0 + BK < kend) {
-            load_rho<T, FOLD>(sa, r0, r1, k0 + BK + lk, n_ang, row_ok, odd);
+            load_rho<T, FOLD>(sa, r0, r1, k0 + BK + lk, n_ang, n_angp, pstride, row_ok, odd);
             load_rowk(sb, urow, k0 + BK + lk, true);
         }
         mma_slab(sm.As, sm.Bs, wm, wn, lane, acc);
@@ -187,7 +198,8 @@ __device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Sme
         }
     }
     __syncthreads();
-    const size_t fld = (size_t)(FOLD ? 2 : 1) * n_r * n_ang;
+    const size_t pstride = (size_t)n_r * n_ang, fld = (size_t)g.n_patches * pstride;
+    const int n_angp = g.n_angp;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -195,15 +207,16 @@ __device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Sme
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int rr = m0 + wm + a * 16 + out_row(lane, r);
-                int jk = n0 + wn + b * 16 + out_col(lane, r);
+                int kk = n0 + wn + b * 16 + out_col(lane, r);
+                const int gp = kk / n_angp, jk = kk - gp * n_angp;
                 if (rr >= rows || jk >= n_ang) continue;
                 int f = rr / n_r, i = rr - f * n_r;
-                T *o = phi + f * fld + (size_t)i * n_ang + jk;
+                T *o = phi + f * fld + gp * pstride + (size_t)i * n_ang + jk;
                 double e = acc[0][a][b][r];
                 if (FOLD) {
                     double od = acc[1][a][b][r];
                     o[0] = (T)(e + od);
-                    o[(size_t)n_r * n_ang] = (T)(e - od);
+                    o[pstride] = (T)(e - od);
                 } else {
                     o[0] = (T)e;
                 }
@@ -278,9 +291,11 @@ F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io
     g.np = p.np;
     g.ne_p = p.ne_p;
     g.fold = p.fold;
+    g.n_patches = p.n_patches;
+    g.kang = p.kang();
     g.tiles_e = p.fold ? (p.ne_p + BN - 1) / BN : (p.np + BN - 1) / BN;
     g.tiles_o = p.fold ? (p.no_p + BN - 1) / BN : 0;
-    g.kchunk = ((p.n_angp / p.splitk + BK - 1) / BK) * BK;
+    g.kchunk = ((g.kang / p.splitk + BK - 1) / BK) * BK;
     g.splitk = p.splitk;
     g.Ut = p.Ut;
     g.Qt = p.Qt;
@@ -304,7 +319,7 @@ hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype
 
 hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     F64Args g = f64_args(p, n_fields, nullptr, phi, phi_dtype);
-    dim3 grid((g.rows + BM - 1) / BM, p.n_angp / BN);
+    dim3 grid((g.rows + BM - 1) / BM, g.kang / BN);
     if (phi_dtype == MPG_F64) {
         if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(256), 0, p.stream, g);
         else hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(256), 0, p.stream, g);

@@ -58,15 +58,20 @@ struct Plan {
     // column layout
     int n_e = 0, n_o = 0, ne_p = 0, no_p = 0, np = 0, np_alloc = 0;
     int n_angp = 0;            // n_ang padded to kAngPad
+    // patch blocks of the contractions: 1 under the fold (and for one
+    // patch), n_patches on the general path, whose GEMM1 K and GEMM2 N run
+    // over the cells of every patch, patch after patch (kang = npat*n_angp)
+    int npat = 1;
+    int kang() const { return npat * n_angp; }
 
     int *col_src = nullptr;    // [np_alloc] real index of a permuted column, -1 = pad
     int *col_l = nullptr;      // [np_alloc] degree, -1 = pad
-    double *Ut = nullptr;      // [np_alloc][n_angp]  U of patch 0, K(angular)-contiguous
-    double *Qt = nullptr;      // [n_angp][np]        Q of patch 0, K(lm)-contiguous
+    double *Ut = nullptr;      // [np_alloc][kang]  U of the npat patch blocks, K(angular)-contiguous
+    double *Qt = nullptr;      // [kang][np]        Q of the npat patch blocks, K(lm)-contiguous
     double *coef = nullptr;    // [n_r][lmax+1][4] radial recurrence coefficients
-    double *w = nullptr;       // [n_ang] overlap weights
-    bf16 *Us = nullptr;        // split U: tiles = GEMM1 column tiles, slabs = n_angp/32 (tile-slab blocks)
-    bf16 *Qs = nullptr;        // split Q: tiles = n_angp/128 angular tiles, slabs = np/32
+    double *w = nullptr;       // [npat][n_ang] overlap weights
+    bf16 *Us = nullptr;        // split U: tiles = GEMM1 column tiles, slabs = kang/32 (tile-slab blocks)
+    bf16 *Qs = nullptr;        // split Q: tiles = kang/128 angular tiles, slabs = np/32
 
     // work space (sized for max_fields)
     int splitk = 1;            // K splits of the moment contraction (work space holds this many)
@@ -76,7 +81,7 @@ struct Plan {
     double *Bred = nullptr;    // [rows][np]
     double *M = nullptr;       // [rows][np]
     bf16 *Ms = nullptr;        // split M: tiles = row tiles, slabs = np/32
-    bf16 *A_split = nullptr;   // split input rho (+-): [fold ? 2 : 1] planes of row tiles x n_angp/32 slabs
+    bf16 *A_split = nullptr;   // split input rho (+-): [fold ? 2 : 1] planes of row tiles x kang/32 slabs
 
     int rows_alloc() const { return max_fields * n_r; }
     int row_tiles() const { return (rows_alloc() + kSplitTile - 1) / kSplitTile; }
@@ -102,13 +107,14 @@ struct SplitArgs {
     void *phi;
     int io_f64;
     int rows, n_r, n_ang, n_angp, np, ne_p, fold;
+    int n_patches, kang;  // patches of a field; npat*n_angp (GEMM1 K, GEMM2 N)
     int tiles_e, tiles_o;  // GEMM1 column tiles of the even / odd block
     int kchunk, splitk;    // GEMM1 K per split, number of splits
     const bf16 *U, *Q, *M;  // split tables and moments (tile-slab blocks)
     double *Bpart;
     bf16 *A;                // split input (tile-slab blocks, one plane per parity)
     int row_tiles;          // row tiles of a plane of A (and of M)
-    int ks1, ks2;           // slabs of GEMM1 (n_angp/32) and GEMM2 (np/32)
+    int ks1, ks2;           // slabs of GEMM1 (kang/32) and GEMM2 (np/32)
 };
 
 // Arguments of one field's FP64 contractions.
@@ -117,6 +123,7 @@ struct F64Args {
     void *phi;
     int io_f64;
     int rows, n_r, n_ang, n_angp, np, ne_p, fold;
+    int n_patches, kang;  // patches of a field; npat*n_angp (GEMM1 K, GEMM2 N)
     int tiles_e, tiles_o;
     int kchunk, splitk;
     const double *Ut, *Qt, *M;
@@ -138,8 +145,10 @@ struct ScanArgs {
 // ---- kernels launchers (each returns hipError_t of the launch) ----------
 
 // table build (tables.hip)
+// host_w: NULL, or n_ang weights shared by every patch block, or
+// (w_per_patch) npat*n_ang
 hipError_t build_tables(Plan &p, const double *host_euler, const double *host_r_edges,
-                        const double *host_w);
+                        const double *host_w, int w_per_patch);
 
 // copy the FP64 tables out in the real index (tables.hip)
 hipError_t export_tables(const Plan &p, double *U, double *Q, double *w);

@@ -176,9 +176,11 @@ __device__ inline void decode_col(int src, int &l, int &m, int &is_s) {
 //   U_S = 2 w sum_u (N_SS S_k^u - N_SC C_k^u) s_lu T_j^{lu}   (m >= 1)
 // (the text prints 2/lambda_{m'm}, which is 2 also for m = 0, m' > 0 and
 // then doubles those terms; 2/delta_m is what the real form of
-// Eq. phispherical requires).  Ut[q][jk], zero on padding.
+// Eq. phispherical requires).  Ut[q][off + jk] (row length ld), zero on
+// padding; w holds the n_ang weights of this patch.
 __global__ void k_U(int L, int np_alloc, int n_angp, int n_ang, int n_phi, const int *col_src,
-                    const double *Tt, const double *CS, const double *N4, const double *w, double *Ut) {
+                    const double *Tt, const double *CS, const double *N4, const double *w, size_t ld,
+                    size_t off, double *Ut) {
     int jk = blockIdx.x * blockDim.x + threadIdx.x;
     int q = blockIdx.y;
     if (jk >= n_angp || q >= np_alloc) return;
@@ -199,7 +201,7 @@ __global__ void k_U(int L, int np_alloc, int n_angp, int n_ang, int n_phi, const
         }
         val = (m == 0 ? 1.0 : 2.0) * w[jk] * s;
     }
-    Ut[(size_t)q * n_angp + jk] = val;
+    Ut[(size_t)q * ld + off + jk] = val;
 }
 
 struct Rot {
@@ -431,8 +433,10 @@ __global__ void k_tile_split(const double *__restrict__ src, size_t ld, int slab
 
 // Tables of every patch in the real index (patch 1 = (-1)^m patch 0 under
 // the fold): U[g][jk][n_lm] from Ut[q][jk], Q[g][jk][n_lm] from Qt[jk][q].
+// Under the fold (npat = 1, two patches) patch 1 is (-1)^m patch 0;
+// otherwise patch g is column block g of Ut and row block g of Qt.
 __global__ void k_export(const double *Ut, const double *Qt, int np, int n_angp, int n_ang, int n_lm,
-                         int n_patches, const int *col_src, double *U, double *Q) {
+                         int n_patches, int npat, const int *col_src, double *U, double *Q) {
     int jk = blockIdx.x * blockDim.x + threadIdx.x;
     int q = blockIdx.y;
     if (jk >= n_ang || q >= np) return;
@@ -442,9 +446,11 @@ __global__ void k_export(const double *Ut, const double *Qt, int np, int n_angp,
     while ((l + 1) * (l + 1) <= src) ++l;
     while (l * l > src) --l;
     int m = (src - l * l + 1) / 2;
-    double u = Ut[(size_t)q * n_angp + jk], v = Qt[(size_t)jk * np + q];
+    const size_t kang = (size_t)npat * n_angp;
     for (int g = 0; g < n_patches; ++g) {
-        double sg = (g == 1 && (m & 1)) ? -1.0 : 1.0;
+        const int b = npat == 1 ? 0 : g;
+        double sg = (npat == 1 && g == 1 && (m & 1)) ? -1.0 : 1.0;
+        double u = Ut[(size_t)q * kang + (size_t)b * n_angp + jk], v = Qt[((size_t)b * n_angp + jk) * np + q];
         size_t o = ((size_t)g * n_ang + jk) * n_lm + src;
         if (U) U[o] = sg * u;
         if (Q) Q[o] = sg * v;
@@ -463,11 +469,10 @@ static void rotation(double a, double b, double g, double R[9]) {
     R[6] = ca * sb;                 R[7] = sa * sb;                 R[8] = cb;
 }
 
-hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, const double *host_w) {
+hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, const double *host_w,
+                        int w_per_patch) {
     const int L = p.lmax;
     hipStream_t s = p.stream;
-    double R0[9];
-    rotation(euler[0], euler[1], euler[2], R0);
 
     // column layout: even-m block first, odd-m block second (fold only)
     std::vector<int> col_src(p.np_alloc, -1), col_l(p.np_alloc, -1), perm_of(p.n_lm, -1);
@@ -488,7 +493,8 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
     hipError_t err = hipSuccess;
     int *d_perm = nullptr;
     double *d_re = nullptr, *dh = nullptr, *db = nullptr, *N4 = nullptr, *Tt = nullptr, *CS = nullptr;
-    const size_t nU = (size_t)p.np_alloc * p.n_angp, nQ = (size_t)p.n_angp * p.np;
+    const size_t kang = (size_t)p.kang();
+    const size_t nU = (size_t)p.np_alloc * kang, nQ = kang * p.np;
 #define STEP(x)                             \
     do {                                    \
         err = (x);                          \
@@ -501,19 +507,23 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
     STEP(hipMemcpyAsync(p.col_l, col_l.data(), sizeof(int) * p.np_alloc, hipMemcpyHostToDevice, s));
     STEP(hipMemcpyAsync(d_perm, perm_of.data(), sizeof(int) * p.n_lm, hipMemcpyHostToDevice, s));
 
-    // overlap weights w_jk (Sec. 4.2)
-    STEP(hipMalloc(&p.w, sizeof(double) * p.n_ang));
-    if (host_w) {
-        STEP(hipMemcpyAsync(p.w, host_w, sizeof(double) * p.n_ang, hipMemcpyHostToDevice, s));
-    } else if (p.n_patches == 1) {
-        hipLaunchKernelGGL(k_fill, dim3(blocks(p.n_ang, 256)), dim3(256), 0, s, p.w, (size_t)p.n_ang, 1.0);
-    } else {
-        OvlGeom o;
-        o.sc = p.ovl_sc;
-        o.kap = p.ovl_kap;
-        o.kap_inf = p.ovl_kap_inf;
-        hipLaunchKernelGGL(k_overlap, dim3(blocks(p.n_ang, 64)), dim3(64), 0, s, p.n_theta, p.n_phi, p.theta0,
-                           p.phi0, p.dtheta, p.dphi, o, p.w);
+    // overlap weights w_jk (Sec. 4.2), one row per patch block
+    STEP(hipMalloc(&p.w, sizeof(double) * p.npat * p.n_ang));
+    for (int b = 0; b < p.npat; ++b) {
+        double *wb = p.w + (size_t)b * p.n_ang;
+        if (host_w) {
+            const double *src = host_w + (w_per_patch ? (size_t)b * p.n_ang : 0);
+            STEP(hipMemcpyAsync(wb, src, sizeof(double) * p.n_ang, hipMemcpyHostToDevice, s));
+        } else if (p.n_patches == 1) {
+            hipLaunchKernelGGL(k_fill, dim3(blocks(p.n_ang, 256)), dim3(256), 0, s, wb, (size_t)p.n_ang, 1.0);
+        } else {
+            OvlGeom o;
+            o.sc = p.ovl_sc;
+            o.kap = p.ovl_kap;
+            o.kap_inf = p.ovl_kap_inf;
+            hipLaunchKernelGGL(k_overlap, dim3(blocks(p.n_ang, 64)), dim3(64), 0, s, p.n_theta, p.n_phi,
+                               p.theta0, p.phi0, p.dtheta, p.dphi, o, wb);
+        }
     }
     STEP(hipGetLastError());
 
@@ -524,50 +534,54 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
     hipLaunchKernelGGL(k_coef, dim3(blocks((size_t)p.n_r * (L + 1), 128)), dim3(128), 0, s, p.n_r, L, d_re, p.coef);
     STEP(hipGetLastError());
 
-    // Wigner d at pi/2; d at beta and pi - beta of patch 0; N; T; C/S
+    // Wigner d at pi/2, T and C/S (the same for every patch: they depend on
+    // the local extents only)
     STEP(hipMalloc(&dh, sizeof(double) * off_dh(L + 1)));
     STEP(hipMalloc(&db, sizeof(double) * 2 * off_sq(L + 1)));
     STEP(hipMalloc(&N4, sizeof(double) * 4 * off_sq(L + 1)));
     STEP(hipMalloc(&Tt, sizeof(double) * (size_t)p.n_theta * off_tri(L + 1)));
     STEP(hipMalloc(&CS, sizeof(double) * 2 * (size_t)p.n_phi * (L + 1)));
     hipLaunchKernelGGL(k_dhalf, dim3(blocks(off_tri(L + 1), 64)), dim3(64), 0, s, L, dh);
-    hipLaunchKernelGGL(k_dbeta, dim3(blocks(2 * off_sq(L + 1), 128)), dim3(128), 0, s, L, dh, euler[1],
-                       M_PI - euler[1], db);
-    hipLaunchKernelGGL(k_ncoef, dim3(blocks(off_sq(L + 1), 128)), dim3(128), 0, s, L, db, euler[0], euler[2], N4);
     hipLaunchKernelGGL(k_ttilde, dim3(blocks((size_t)p.n_theta * off_tri(L + 1), 128)), dim3(128), 0, s, L, dh,
                        p.n_theta, p.theta0, p.dtheta, Tt);
     hipLaunchKernelGGL(k_cs, dim3(blocks((size_t)p.n_phi * (L + 1), 128)), dim3(128), 0, s, L, p.n_phi, p.phi0,
                        p.dphi, CS);
     STEP(hipGetLastError());
 
-    // U and Q of patch 0 (the fold derives patch 1 from them)
+    // U and Q of every patch block (under the fold, patch 0 only: patch 1
+    // is derived from it); d at beta and pi - beta and the N factors come
+    // from the block's own Euler angles
     STEP(hipMalloc(&p.Ut, sizeof(double) * nU));
     STEP(hipMalloc(&p.Qt, sizeof(double) * nQ));
-    hipLaunchKernelGGL(k_U, dim3(blocks(p.n_angp, 128), p.np_alloc), dim3(128), 0, s, L, p.np_alloc, p.n_angp,
-                       p.n_ang, p.n_phi, p.col_src, Tt, CS, N4, p.w, p.Ut);
-    STEP(hipGetLastError());
     STEP(hipMemsetAsync(p.Qt, 0, sizeof(double) * nQ, s));
-    {
+    for (int b = 0; b < p.npat; ++b) {
+        const double *e = euler + 3 * b;
+        hipLaunchKernelGGL(k_dbeta, dim3(blocks(2 * off_sq(L + 1), 128)), dim3(128), 0, s, L, dh, e[1],
+                           M_PI - e[1], db);
+        hipLaunchKernelGGL(k_ncoef, dim3(blocks(off_sq(L + 1), 128)), dim3(128), 0, s, L, db, e[0], e[2], N4);
+        hipLaunchKernelGGL(k_U, dim3(blocks(p.n_angp, 128), p.np_alloc), dim3(128), 0, s, L, p.np_alloc, p.n_angp,
+                           p.n_ang, p.n_phi, p.col_src, Tt, CS, N4, p.w + (size_t)b * p.n_ang, kang,
+                           (size_t)b * p.n_angp, p.Ut);
         Rot R;
-        for (int i = 0; i < 9; ++i) R.r[i] = R0[i];
+        rotation(e[0], e[1], e[2], R.r);
         hipLaunchKernelGGL(k_Q, dim3(blocks(p.n_angp, 64)), dim3(64), 0, s, L, p.np, p.n_angp, p.n_ang, p.n_phi,
-                           p.theta0, p.phi0, p.dtheta, p.dphi, R, p.G, d_perm, p.Qt);
+                           p.theta0, p.phi0, p.dtheta, p.dphi, R, p.G, d_perm, p.Qt + (size_t)b * p.n_angp * p.np);
+        STEP(hipGetLastError());
     }
-    STEP(hipGetLastError());
 
     // split-BF16 copies
     if (p.precision == MPG_SPLIT_BF16) {
         // U: GEMM1 column tiles over the K = n_angp slabs
-        const int ks1 = p.n_angp / kSlabK, ks2 = p.np / kSlabK;
+        const int ks1 = (int)(kang / kSlabK), ks2 = p.np / kSlabK;
         const size_t tU = (size_t)(p.tiles_e() + p.tiles_o()) * ks1 * 512;
-        const size_t tQ = (size_t)(p.n_angp / kSplitTile) * ks2 * 512;
+        const size_t tQ = (kang / kSplitTile) * ks2 * 512;
         STEP(hipMalloc(&p.Us, sizeof(bf16) * tU * 24));
         STEP(hipMalloc(&p.Qs, sizeof(bf16) * tQ * 24));
-        hipLaunchKernelGGL(k_tile_split, dim3(blocks(tU, 256)), dim3(256), 0, s, p.Ut, (size_t)p.n_angp, ks1,
+        hipLaunchKernelGGL(k_tile_split, dim3(blocks(tU, 256)), dim3(256), 0, s, p.Ut, kang, ks1,
                            p.tiles_e(), p.fold ? p.ne_p : p.np, p.ne_p, p.np, tU, p.Us);
         // Q: angular tiles over the K = np slabs
         hipLaunchKernelGGL(k_tile_split, dim3(blocks(tQ, 256)), dim3(256), 0, s, p.Qt, (size_t)p.np, ks2,
-                           p.n_angp / kSplitTile, p.n_angp, 0, p.n_angp, tQ, p.Qs);
+                           (int)(kang / kSplitTile), (int)kang, 0, (int)kang, tQ, p.Qs);
         STEP(hipGetLastError());
     }
     STEP(hipStreamSynchronize(s));
@@ -587,10 +601,11 @@ done:
 hipError_t export_tables(const Plan &p, double *U, double *Q, double *w) {
     if (U || Q)
         hipLaunchKernelGGL(k_export, dim3(blocks(p.n_ang, 128), p.np), dim3(128), 0, p.stream, p.Ut, p.Qt, p.np,
-                           p.n_angp, p.n_ang, p.n_lm, p.n_patches, p.col_src, U, Q);
+                           p.n_angp, p.n_ang, p.n_lm, p.n_patches, p.npat, p.col_src, U, Q);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (w) e = hipMemcpyAsync(w, p.w, sizeof(double) * p.n_ang, hipMemcpyDeviceToDevice, p.stream);
+    for (int g = 0; w && e == hipSuccess && g < p.n_patches; ++g)
+        e = hipMemcpyAsync(w + (size_t)g * p.n_ang, p.w + (size_t)(p.npat == 1 ? 0 : g) * p.n_ang,
+                           sizeof(double) * p.n_ang, hipMemcpyDeviceToDevice, p.stream);
     return e;
 }
 

@@ -57,13 +57,20 @@ def test_plan_rejects_bad_grids_on_host():
     assert L.mpg_plan(ctypes.byref(s), 8, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
     assert b"increase" in L.mpg_last_error()
     s.r_edges = r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    s.n_patches = 3
+    e3 = np.concatenate([e, [0.1, 0.2, 0.3]])
+    s.euler = e3.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    s.n_patches = 3  # general path: more than two patches need overlap weights
     assert L.mpg_plan(ctypes.byref(s), 8, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EUNSUPPORTED
+    assert b"overlap_w" in L.mpg_last_error()
+    for n in (0, 17):
+        s.n_patches = n
+        assert L.mpg_plan(ctypes.byref(s), 8, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
     s.n_patches = 2
     e2 = e.copy()
-    e2[5] = 0.3  # Yang no longer Yin turned by pi about z
+    e2[5] = 0.3  # Yang no longer Yin turned by pi about z, nor related by the Yin<->Yang map
     s.euler = e2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     assert L.mpg_plan(ctypes.byref(s), 8, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EUNSUPPORTED
+    assert b"overlap_w" in L.mpg_last_error()
     assert h.value is None
     assert L.mpg_moments(None, 1, None, 0, None, None) == mpg.MPG_EINVAL
     assert L.mpg_potential(None, 1, None, 0, None, 0) == mpg.MPG_EINVAL

@@ -351,3 +351,20 @@ def test_ellipsoid_potential_converges_to_closed_form():
             err = max(err, np.abs(phi[0, n].reshape(-1) - ref).max() / np.abs(ref).max())
         errs.append(err)
     assert errs[1] < errs[0] and errs[1] < 2e-2, errs
+
+
+def test_per_patch_overlap_weights_scale_each_patch_own_rows():
+    """U is w_jk times the cell integral of the patch's own harmonics
+    (Eqs. U_C/U_S): weights given per patch scale only that patch's rows;
+    equal per-patch weights reproduce the shared-weight tables exactly."""
+    g = W.config1()
+    rng = np.random.Generator(np.random.PCG64(3))
+    w = rng.uniform(0.2, 1.0, size=(2, g.n_ang))
+    U1, Q1 = O.tables(g, 6, None)
+    Uw, Qw = O.tables(g, 6, w)
+    assert np.array_equal(Qw, Q1)
+    for p in range(2):
+        assert np.abs(Uw[p] - w[p][:, None] * U1[p]).max() < 1e-15 * np.abs(U1).max()
+    Us, _ = O.tables(g, 6, w[0])
+    Ue, _ = O.tables(g, 6, np.stack([w[0], w[0]]))
+    assert np.array_equal(Us, Ue)

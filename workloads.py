@@ -83,6 +83,16 @@ def polar(n_theta, n_phi, r_edges, lmax, G=1.0, euler=(0.0, 0.0, 0.0), frame=Non
                 [np.eye(3) if frame is None else np.asarray(frame, dtype=np.float64)], name)
 
 
+def patches(euler, n_theta, n_phi, theta0, phi0, dtheta, dphi, r_edges, lmax, G=1.0, name=""):
+    """A general set of geometrically identical patches (Sec. 3), one row of
+    Euler angles per patch.  No density frames are attached: such grids take
+    plain seeded cell values (random_rho)."""
+    euler = np.asarray(euler, dtype=np.float64).reshape(-1, 3)
+    r_edges = np.asarray(r_edges, dtype=np.float64)
+    return Grid(len(euler), len(r_edges) - 1, n_theta, n_phi, r_edges, theta0, phi0, dtheta, dphi, euler, G, lmax,
+                [], name)
+
+
 def uniform_edges(n_r, r_max=1.0):
     return np.linspace(0.0, r_max, n_r + 1)
 
