@@ -104,6 +104,27 @@ typedef struct mpg_plan_s *mpg_plan_t;
 int mpg_plan(const mpg_grid *grid, int lmax, int precision, int max_fields,
              void *stream, mpg_plan_t *out);
 
+/* methods of mpg_plan_method */
+#define MPG_METHOD_GLOBAL    0  /* the paper's method (mpg_plan): one moment set
+                                   in the common frame for all patches       */
+#define MPG_METHOD_PER_PATCH 1  /* the comparison method the paper sets its
+                                   own against (Sec. 1, Sec. 4.3): moments of
+                                   every patch in its own frame, radial sums
+                                   per patch, and an expansion that adds the
+                                   potentials of every patch's source        */
+
+/* As mpg_plan, with the method chosen.  The per-patch method gives the same
+ * potential up to rounding (the degree-l part of each patch's expansion
+ * does not depend on the frame) at about twice the moment work and four
+ * times the expansion work for two patches; it is here for the comparison.
+ * It uses one table U for every patch (so per-patch weights must agree),
+ * mpg_moments returns B and M per patch ([n_fields][n_patches][n_r][n_lm],
+ * each in the patch's own frame), and mpg_potential_batch rejects it
+ * (MPG_EUNSUPPORTED).  Errors: as mpg_plan, MPG_EINVAL for an unknown
+ * method. */
+int mpg_plan_method(const mpg_grid *grid, int lmax, int precision, int max_fields,
+                    int method, void *stream, mpg_plan_t *out);
+
 /* Moments only (Eq. B_CS and Eq. M_C).
  *   rho   : device, n_fields fields of rho_dtype
  *   B, M  : device FP64 [n_fields][n_r][n_lm] in the real index, or NULL

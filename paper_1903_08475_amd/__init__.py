@@ -21,9 +21,12 @@ MPG_FP64, MPG_SPLIT_BF16 = 0, 1
 MPG_F64, MPG_F32 = 0, 1
 
 PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16}
+# "global": the paper's method; "per_patch": the comparison method (moments
+# of every patch in its own frame, potentials of the patches added)
+METHODS = {"global": 0, "per_patch": 1}
 
 # Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
-EXPORTS = ("mpg_plan", "mpg_moments", "mpg_potential", "mpg_potential_batch", "mpg_autotune", "mpg_tables",
+EXPORTS = ("mpg_plan", "mpg_plan_method", "mpg_moments", "mpg_potential", "mpg_potential_batch", "mpg_autotune", "mpg_tables",
            "mpg_plan_info", "mpg_timing", "mpg_stage_times", "mpg_sync", "mpg_destroy", "mpg_last_error")
 STAGES = ("input_split", "moments", "radial_scan", "expansion")
 
@@ -58,6 +61,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, dp = C.c_void_p, C.POINTER(C.c_double)
         L.mpg_plan.argtypes = [C.POINTER(_Grid), C.c_int, C.c_int, C.c_int, vp, C.POINTER(vp)]
+        L.mpg_plan_method.argtypes = [C.POINTER(_Grid), C.c_int, C.c_int, C.c_int, C.c_int, vp, C.POINTER(vp)]
         L.mpg_moments.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp]
         L.mpg_potential.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int]
         L.mpg_potential_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
@@ -101,12 +105,14 @@ class Plan:
     phi0, dtheta, dphi, euler, G (e.g. ``workloads.Grid``).
     """
 
-    def __init__(self, grid, lmax=None, precision="fp64", max_fields=1, stream=None, overlap_w=None):
+    def __init__(self, grid, lmax=None, precision="fp64", max_fields=1, stream=None, overlap_w=None,
+                 method="global"):
         import torch
         self.lmax = grid.lmax if lmax is None else lmax
         self.grid = grid
         self.precision = precision
         self.max_fields = max_fields
+        self.method = method
         self.shape = (grid.n_patches, grid.n_r, grid.n_theta, grid.n_phi)
         self.n_lm = (self.lmax + 1) ** 2
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -125,8 +131,8 @@ class Plan:
         g.G = grid.G
         g.w_per_patch = int(self._w is not None and self._w.size != n_ang)
         h = C.c_void_p()
-        _check(lib().mpg_plan(C.byref(g), self.lmax, PRECISIONS[precision], max_fields,
-                              _stream_handle(self.stream), C.byref(h)))
+        _check(lib().mpg_plan_method(C.byref(g), self.lmax, PRECISIONS[precision], max_fields, METHODS[method],
+                                     _stream_handle(self.stream), C.byref(h)))
         self._h = h
 
     @property
@@ -165,10 +171,12 @@ class Plan:
         return out
 
     def moments(self, rho):
-        """(B, M) in the real moment index, float64 [n_fields, n_r, n_lm]."""
+        """(B, M) in the real moment index, float64 [n_fields, n_r, n_lm]
+        ([n_fields, n_patches, n_r, n_lm] for the per-patch method)."""
         import torch
         n = self._fields(rho)
-        B = torch.zeros((n, self.shape[1], self.n_lm), dtype=torch.float64, device=rho.device)
+        lead = (n, self.shape[0]) if self.method == "per_patch" else (n,)
+        B = torch.zeros(lead + (self.shape[1], self.n_lm), dtype=torch.float64, device=rho.device)
         M = torch.zeros_like(B)
         _check(lib().mpg_moments(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
                                  C.c_void_p(B.data_ptr()), C.c_void_p(M.data_ptr())))

@@ -109,7 +109,14 @@ extern "C" {
 const char *mpg_last_error(void) { return g_err.c_str(); }
 
 int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *stream, mpg_plan_t *out) {
+    return mpg_plan_method(g, lmax, precision, max_fields, MPG_METHOD_GLOBAL, stream, out);
+}
+
+int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, int method, void *stream,
+                    mpg_plan_t *out) {
     if (!out) return fail(MPG_EINVAL, "mpg_plan: out is NULL");
+    if (method != MPG_METHOD_GLOBAL && method != MPG_METHOD_PER_PATCH)
+        return fail(MPG_EINVAL, "mpg_plan: unknown method");
     *out = nullptr;
     if (!g) return fail(MPG_EINVAL, "mpg_plan: grid is NULL");
     if (g->n_patches < 1 || g->n_patches > MPG_MAX_PATCHES)
@@ -147,6 +154,7 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
     p->max_fields = max_fields;
     p->G = g->G;
     p->stream = (hipStream_t)stream;
+    p->per_patch = method == MPG_METHOD_PER_PATCH;
     (void)hipGetDevice(&p->device);
 
     if (g->n_patches == 2) {
@@ -158,7 +166,7 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
         double dev = 0.0;
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) dev = fmax(dev, fabs(R1[3 * i + j] - D[i] * R0[3 * i + j]));
-        p->fold = dev <= 1e-12;
+        p->fold = dev <= 1e-12 && !p->per_patch;
         // per-patch weights can only be folded when both patches carry the same
         if (p->fold && g->overlap_w && g->w_per_patch) {
             const size_t n = (size_t)g->n_theta * g->n_phi;
@@ -195,7 +203,16 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
         free_plan(p);
         return fail(MPG_EUNSUPPORTED, "mpg_plan: more than two patches need overlap_w");
     }
-    p->npat = p->fold ? 1 : g->n_patches;
+    if (p->per_patch && g->overlap_w && g->w_per_patch) {
+        // one local table U serves every patch: the weights must agree
+        const size_t n = (size_t)g->n_theta * g->n_phi;
+        for (size_t c = 0; c < n * g->n_patches; ++c)
+            if (g->overlap_w[c] != g->overlap_w[c % n]) {
+                free_plan(p);
+                return fail(MPG_EUNSUPPORTED, "mpg_plan: the per-patch method needs one weight set for all patches");
+            }
+    }
+    p->npat = (p->fold || p->per_patch) ? 1 : g->n_patches;
 
     // column layout
     if (p->fold) {
@@ -236,7 +253,7 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
     }
     if (precision == MPG_SPLIT_BF16) {
         // tile-slab blocks; rows past the last field stay zero (finite)
-        const size_t nM = (size_t)p->row_tiles() * (p->np / kSlabK) * 3 * kBlk;
+        const size_t nM = (size_t)p->out_row_tiles() * (p->kq() / kSlabK) * 3 * kBlk;
         const size_t nA = (size_t)(p->fold ? 2 : 1) * p->row_tiles() * (p->kang() / kSlabK) * 3 * kBlk;
         if ((e = hipMalloc(&p->Ms, sizeof(bf16) * nM)) != hipSuccess ||
             (e = hipMalloc(&p->A_split, sizeof(bf16) * nA)) != hipSuccess ||
@@ -265,8 +282,11 @@ static int check_call(mpg_plan_t p, int n_fields, const void *rho, int dt, const
     return MPG_OK;
 }
 
-static int run_moments(const Plan *p, int n_fields, const void *rho, int rho_dtype, bool split_out) {
+// GEMM1 and the scans of n_fields fields (for the per-patch method:
+// n_patches single-patch fields per field, each patch in its own frame)
+static int run_moments(const Plan *p, int n_fields_in, const void *rho, int rho_dtype, bool split_out) {
     hipError_t e;
+    const int n_fields = p->vfields(n_fields_in);
     int sk = choose_splitk(*p, n_fields);
     Plan q = *p;
     q.splitk = sk;
@@ -296,8 +316,9 @@ int mpg_moments(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, doub
     if (rc) return rc;
     if ((rc = run_moments(p, n_fields, rho, rho_dtype, false))) return rc;
     hipError_t e;
-    if (B && (e = unpermute(*p, n_fields, p->Bred, B)) != hipSuccess) return hip_fail(e, "mpg_moments: B");
-    if (M && (e = unpermute(*p, n_fields, p->M, M)) != hipSuccess) return hip_fail(e, "mpg_moments: M");
+    const int vf = p->vfields(n_fields);
+    if (B && (e = unpermute(*p, vf, p->Bred, B)) != hipSuccess) return hip_fail(e, "mpg_moments: B");
+    if (M && (e = unpermute(*p, vf, p->M, M)) != hipSuccess) return hip_fail(e, "mpg_moments: M");
     return MPG_OK;
 }
 
@@ -329,6 +350,8 @@ int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho, 
         if (!rho[f] || !phi[f]) return fail(MPG_EINVAL, "mpg_potential_batch: NULL field");
         if (plans[f]->precision != plans[0]->precision)
             return fail(MPG_EINVAL, "mpg_potential_batch: plans differ in precision");
+        if (plans[f]->per_patch)
+            return fail(MPG_EUNSUPPORTED, "mpg_potential_batch: per-patch-method plans are solved one by one");
         for (int g = 0; g < f; ++g)
             if (plans[g] == plans[f])
                 return fail(MPG_EINVAL, "mpg_potential_batch: a plan appears twice (they own their work space)");
@@ -339,9 +362,10 @@ int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho, 
     return MPG_OK;
 }
 
-int mpg_autotune(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, int *splitk, int *chunks) {
-    int rc = check_call(p, n_fields, rho, rho_dtype, "mpg_autotune");
+int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, int *splitk, int *chunks) {
+    int rc = check_call(p, n_fields_in, rho, rho_dtype, "mpg_autotune");
     if (rc) return rc;
+    const int n_fields = p->vfields(n_fields_in);
     hipEvent_t a, b;
     hipError_t e;
     if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, "mpg_autotune");

@@ -394,7 +394,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
         __syncthreads();
         run_ring<false>(S0, S1, S2, L, ne + no - 1, -1, no, wm, wn, lane, acc_o, unused);
     } else {
-        const int ns = np / TK;
+        const int ns = g.ks2;
         run_ring<false>(S0, S1, S2, L, ns - 1, -1, ns, wm, wn, lane, acc_e, unused);
     }
 
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_gemm2(const SplitArgs *__res
 
 }  // namespace
 
-SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype) {
+SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype, bool expansion) {
     SplitArgs g;
     g.rho = rho;
     g.phi = phi;
@@ -494,11 +494,16 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.np = p.np;
     g.ne_p = p.ne_p;
     g.fold = p.fold;
-    g.n_patches = p.n_patches;
-    g.kang = p.kang();
+    // per-patch method: GEMM1 sees single-patch fields; GEMM2 writes every
+    // patch and reads every patch's moment set
+    const bool pp2 = p.per_patch && expansion;
+    g.n_patches = p.per_patch && !expansion ? 1 : p.n_patches;
+    g.kang = pp2 ? p.n2() : p.kang();
+    g.nq = pp2 ? p.nq() : 1;
+    g.kq = pp2 ? p.kq() : p.np;
     g.tiles_e = p.tiles_e();
     g.tiles_o = p.tiles_o();
-    g.kchunk = ((g.kang / p.splitk + TK - 1) / TK) * TK;
+    g.kchunk = ((p.kang() / p.splitk + TK - 1) / TK) * TK;
     g.splitk = p.splitk;
     g.U = p.Us;
     g.Q = p.Qs;
@@ -506,8 +511,8 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.Bpart = p.Bpart;
     g.A = p.A_split;
     g.row_tiles = p.row_tiles();
-    g.ks1 = g.kang / TK;
-    g.ks2 = p.np / TK;
+    g.ks1 = p.kang() / TK;
+    g.ks2 = p.kq() / TK;
     return g;
 }
 
@@ -539,7 +544,7 @@ hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtyp
 }
 
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
-    SplitArgs g = split_args(p, n_fields, nullptr, phi, phi_dtype);
+    SplitArgs g = split_args(p, n_fields, nullptr, phi, phi_dtype, true);
     dim3 grid((g.rows + TB - 1) / TB, g.kang / TB);
     if (phi_dtype == MPG_F64) {
         if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(kThreads), 0, p.stream, g);

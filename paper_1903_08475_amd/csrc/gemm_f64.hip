@@ -165,8 +165,8 @@ __device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Sme
     const int m0 = tm * BM, n0 = tn * BN;
     const int lr = t >> 2, lk = (t & 3) * 4;
     const bool row_ok = m0 + lr < rows;
-    const double *arow = g.M + (size_t)(row_ok ? m0 + lr : 0) * np;
-    const double *brow = g.Qt + (size_t)(n0 + lr) * np;
+    const int arw = row_ok ? m0 + lr : 0;
+    const double *brow = g.Qt + (size_t)(n0 + lr) * g.kq;
 
     v4d acc[2][2][2];
 #pragma unroll
@@ -176,14 +176,12 @@ __device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Sme
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[p][a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    const int nblk = FOLD ? 2 : 1;
-#pragma unroll
-    for (int blk = 0; blk < nblk; ++blk) {
-        const int kb = blk ? ne_p : 0, ke = (FOLD && !blk) ? ne_p : np;
+    // one K block [kb, ke) of A row `arow` against Q row `brow`, into acc[blk]
+    auto kblock = [&](const double *arow, const double *bq, int kb, int ke, v4d(&ac)[2][2]) {
         Slab sa, sb;
         if (kb < ke) {
             load_rowk(sa, arow, kb + lk, row_ok);
-            load_rowk(sb, brow, kb + lk, true);
+            load_rowk(sb, bq, kb + lk, true);
         }
         for (int k0 = kb; k0 < ke; k0 += BK) {
             __syncthreads();
@@ -192,10 +190,23 @@ __device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Sme
             __syncthreads();
             if (k0 + BK < ke) {
                 load_rowk(sa, arow, k0 + BK + lk, row_ok);
-                load_rowk(sb, brow, k0 + BK + lk, true);
+                load_rowk(sb, bq, k0 + BK + lk, true);
             }
-            mma_slab(sm.As, sm.Bs, wm, wn, lane, acc[blk]);
+            mma_slab(sm.As, sm.Bs, wm, wn, lane, ac);
         }
+    };
+    if (FOLD) {
+        const double *arow = g.M + (size_t)arw * np;
+        kblock(arow, brow, 0, ne_p, acc[0]);
+        kblock(arow, brow, ne_p, np, acc[1]);
+    } else if (g.nq == 1) {
+        kblock(g.M + (size_t)arw * np, brow, 0, np, acc[0]);
+    } else {
+        // per-patch method: K runs over the moment sets of every patch, set gq
+        // at row (field, gq, shell) of M
+        const int f = arw / n_r, i = arw - f * n_r;
+        for (int gq = 0; gq < g.nq; ++gq)
+            kblock(g.M + ((size_t)(f * g.nq + gq) * n_r + i) * np, brow + (size_t)gq * np, 0, np, acc[0]);
     }
     __syncthreads();
     const size_t pstride = (size_t)n_r * n_ang, fld = (size_t)g.n_patches * pstride;
@@ -279,7 +290,7 @@ __global__ __launch_bounds__(256) void k_batch_gemm2(const F64Args *__restrict__
 
 }  // namespace
 
-F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype) {
+F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype, bool expansion) {
     F64Args g;
     g.rho = rho;
     g.phi = phi;
@@ -291,11 +302,16 @@ F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io
     g.np = p.np;
     g.ne_p = p.ne_p;
     g.fold = p.fold;
-    g.n_patches = p.n_patches;
-    g.kang = p.kang();
+    // per-patch method: GEMM1 sees single-patch fields; GEMM2 writes every
+    // patch and reads every patch's moment set
+    const bool pp2 = p.per_patch && expansion;
+    g.n_patches = p.per_patch && !expansion ? 1 : p.n_patches;
+    g.kang = pp2 ? p.n2() : p.kang();
+    g.nq = pp2 ? p.nq() : 1;
+    g.kq = pp2 ? p.kq() : p.np;
     g.tiles_e = p.fold ? (p.ne_p + BN - 1) / BN : (p.np + BN - 1) / BN;
     g.tiles_o = p.fold ? (p.no_p + BN - 1) / BN : 0;
-    g.kchunk = ((g.kang / p.splitk + BK - 1) / BK) * BK;
+    g.kchunk = ((p.kang() / p.splitk + BK - 1) / BK) * BK;
     g.splitk = p.splitk;
     g.Ut = p.Ut;
     g.Qt = p.Qt;
@@ -318,7 +334,7 @@ hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype
 }
 
 hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype) {
-    F64Args g = f64_args(p, n_fields, nullptr, phi, phi_dtype);
+    F64Args g = f64_args(p, n_fields, nullptr, phi, phi_dtype, true);
     dim3 grid((g.rows + BM - 1) / BM, g.kang / BN);
     if (phi_dtype == MPG_F64) {
         if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(256), 0, p.stream, g);

@@ -63,15 +63,27 @@ struct Plan {
     // over the cells of every patch, patch after patch (kang = npat*n_angp)
     int npat = 1;
     int kang() const { return npat * n_angp; }
+    // per-patch method (the comparison method of Sec. 4.3): the moments of
+    // every patch in its own frame (GEMM1 and the scans see n_patches
+    // single-patch fields per field), and an expansion whose K runs over
+    // the moment sets of every patch (kq = n_patches*np) and whose N runs
+    // over the cells of every patch
+    bool per_patch = false;
+    int nq() const { return per_patch ? n_patches : 1; }
+    int kq() const { return nq() * np; }
+    int n2() const { return per_patch ? n_patches * n_angp : kang(); }
+    // single-patch fields that GEMM1 and the scans see for n_fields fields
+    int vfields(int n_fields) const { return per_patch ? n_fields * n_patches : n_fields; }
 
     int *col_src = nullptr;    // [np_alloc] real index of a permuted column, -1 = pad
     int *col_l = nullptr;      // [np_alloc] degree, -1 = pad
     double *Ut = nullptr;      // [np_alloc][kang]  U of the npat patch blocks, K(angular)-contiguous
-    double *Qt = nullptr;      // [kang][np]        Q of the npat patch blocks, K(lm)-contiguous
+    double *Qt = nullptr;      // [n2][kq]          Q of the npat patch blocks (per patch: Q of patch p's
+                               //                   cells in patch g's frame at [p][jk][g][q]), K(lm)-contiguous
     double *coef = nullptr;    // [n_r][lmax+1][4] radial recurrence coefficients
     double *w = nullptr;       // [npat][n_ang] overlap weights
     bf16 *Us = nullptr;        // split U: tiles = GEMM1 column tiles, slabs = kang/32 (tile-slab blocks)
-    bf16 *Qs = nullptr;        // split Q: tiles = kang/128 angular tiles, slabs = np/32
+    bf16 *Qs = nullptr;        // split Q: tiles = n2/128 angular tiles, slabs = kq/32
 
     // work space (sized for max_fields)
     int splitk = 1;            // K splits of the moment contraction (work space holds this many)
@@ -80,11 +92,14 @@ struct Plan {
     double *Bpart = nullptr;   // [splitk][rows][np]
     double *Bred = nullptr;    // [rows][np]
     double *M = nullptr;       // [rows][np]
-    bf16 *Ms = nullptr;        // split M: tiles = row tiles, slabs = np/32
+    bf16 *Ms = nullptr;        // split M: tiles = row tiles of (field, shell), slabs = kq/32
     bf16 *A_split = nullptr;   // split input rho (+-): [fold ? 2 : 1] planes of row tiles x kang/32 slabs
 
-    int rows_alloc() const { return max_fields * n_r; }
+    // rows of GEMM1 and the scans (per patch: n_patches per field and shell)
+    int rows_alloc() const { return vfields(max_fields) * n_r; }
     int row_tiles() const { return (rows_alloc() + kSplitTile - 1) / kSplitTile; }
+    // row tiles of the expansion's (field, shell) rows
+    int out_row_tiles() const { return (max_fields * n_r + kSplitTile - 1) / kSplitTile; }
     // GEMM1 column tiles: even-m block tiles, then odd-m block tiles
     int tiles_e() const { return fold ? (ne_p + kSplitTile - 1) / kSplitTile : (np + kSplitTile - 1) / kSplitTile; }
     int tiles_o() const { return fold ? (no_p + kSplitTile - 1) / kSplitTile : 0; }
@@ -108,6 +123,7 @@ struct SplitArgs {
     int io_f64;
     int rows, n_r, n_ang, n_angp, np, ne_p, fold;
     int n_patches, kang;  // patches of a field; npat*n_angp (GEMM1 K, GEMM2 N)
+    int nq, kq;           // GEMM2 K: moment sets (per-patch method) and their total length
     int tiles_e, tiles_o;  // GEMM1 column tiles of the even / odd block
     int kchunk, splitk;    // GEMM1 K per split, number of splits
     const bf16 *U, *Q, *M;  // split tables and moments (tile-slab blocks)
@@ -124,6 +140,7 @@ struct F64Args {
     int io_f64;
     int rows, n_r, n_ang, n_angp, np, ne_p, fold;
     int n_patches, kang;  // patches of a field; npat*n_angp (GEMM1 K, GEMM2 N)
+    int nq, kq;           // GEMM2 K: moment sets (per-patch method) and their total length
     int tiles_e, tiles_o;
     int kchunk, splitk;
     const double *Ut, *Qt, *M;
@@ -138,7 +155,9 @@ struct ScanArgs {
     const double *coef;
     double *Bred, *M;
     bf16 *Ms;        // split copy of M (tile-slab blocks), or null
-    int ks2;         // its slabs per row tile (np/32)
+    int ks2;         // its slabs per row tile (kq/32)
+    int pp;          // per-patch method: single-patch fields per field (its row (f, shell), column
+                     // (patch, q) in Ms), else 0
     int col_blocks;  // blocks of 64 columns
 };
 
@@ -156,7 +175,9 @@ hipError_t export_tables(const Plan &p, double *U, double *Q, double *w);
 // FP64 path (gemm_f64.hip)
 hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype);
-F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype);
+// expansion = true: the arguments of GEMM2 (they differ from GEMM1's only
+// for the per-patch method, whose GEMM1 sees single-patch fields)
+F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype, bool expansion = false);
 hipError_t batch_gemm1_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                            int blocks, hipStream_t s);
 hipError_t batch_gemm2_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
@@ -175,7 +196,7 @@ hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype);
 hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t n_threads, int io_dtype, hipStream_t s);
 // threads of the input split of n_fields fields of a plan
 size_t split_input_threads(const Plan &p, int n_fields);
-SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype);
+SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype, bool expansion = false);
 hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                             int blocks, hipStream_t s);
 hipError_t batch_gemm2_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,

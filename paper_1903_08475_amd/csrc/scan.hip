@@ -24,6 +24,15 @@ __device__ inline size_t split_offset(int row, int col, int ks2) {
     return blk * 3 * kBlk + blk_pos(row % kSplitTile, col % kSlabK);
 }
 
+// where moment q of shell n of (single-patch) field f goes in the split
+// copy: row (f, n), column q; for the per-patch method field f is patch
+// f % pp of field f / pp, and its moments go to row (f / pp, n), column
+// (f % pp, q), the expansion's K
+__device__ inline size_t split_offset_of(int f, int n, int q, int n_r, int np, int pp, int ks2) {
+    if (pp) return split_offset((f / pp) * n_r + n, (f % pp) * np + q, ks2);
+    return split_offset(f * n_r + n, q, ks2);
+}
+
 __device__ inline double reduce_parts(const double *Bpart, size_t stride, int splitk, size_t idx) {
     double s = 0.0;
     for (int k = 0; k < splitk; ++k) s += Bpart[k * stride + idx];
@@ -90,7 +99,7 @@ __device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
             M[base + (size_t)n * np] = 0.0;
             Bred[base + (size_t)n * np] = 0.0;
             if (Ms) {
-                bf16 *o = Ms + split_offset(f * n_r + n, q, g.ks2);
+                bf16 *o = Ms + split_offset_of(f, n, q, n_r, np, g.pp, g.ks2);
                 o[0] = o[kBlk] = o[2 * kBlk] = (bf16)0.0f;
             }
         }
@@ -115,7 +124,7 @@ __device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
             double r = m - (double)(float)h;
             bf16 md = (bf16)(float)r;
             double r2 = r - (double)(float)md;
-            bf16 *o = Ms + split_offset(f * n_r + n, q, g.ks2);
+            bf16 *o = Ms + split_offset_of(f, n, q, n_r, np, g.pp, g.ks2);
             o[0] = h;
             o[kBlk] = md;
             o[2 * kBlk] = (bf16)(float)r2;
@@ -168,7 +177,8 @@ ScanArgs scan_args(const Plan &p, int n_fields, bool split_out) {
     g.Bred = p.Bred;
     g.M = p.M;
     g.Ms = split_out ? p.Ms : nullptr;
-    g.ks2 = p.np / kSlabK;
+    g.ks2 = p.kq() / kSlabK;
+    g.pp = p.per_patch ? p.n_patches : 0;
     g.col_blocks = (n_fields * p.np + kLanes - 1) / kLanes;
     return g;
 }

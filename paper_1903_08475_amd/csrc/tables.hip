@@ -214,10 +214,10 @@ struct Rot {
 // functions s_lm P_l^m come from the recurrences of the normalised
 // associated Legendre functions (Condon-Shortley phase).  Qt[jk][perm].
 __global__ void k_Q(int L, int np, int n_angp, int n_ang, int n_phi, double theta0, double phi0,
-                    double dtheta, double dphi, Rot R, double G, const int *perm_of, double *Qt) {
+                    double dtheta, double dphi, Rot R, double G, const int *perm_of, size_t ld, double *Qt) {
     int jk = blockIdx.x * blockDim.x + threadIdx.x;
     if (jk >= n_angp) return;
-    double *row = Qt + (size_t)jk * np;
+    double *row = Qt + (size_t)jk * ld;
     if (jk >= n_ang) {
         for (int q = 0; q < np; ++q) row[q] = 0.0;
         return;
@@ -433,10 +433,13 @@ __global__ void k_tile_split(const double *__restrict__ src, size_t ld, int slab
 
 // Tables of every patch in the real index (patch 1 = (-1)^m patch 0 under
 // the fold): U[g][jk][n_lm] from Ut[q][jk], Q[g][jk][n_lm] from Qt[jk][q].
-// Under the fold (npat = 1, two patches) patch 1 is (-1)^m patch 0;
-// otherwise patch g is column block g of Ut and row block g of Qt.
+// Under the fold patch 1 is (-1)^m patch 0; on the general path patch g
+// is column block g of Ut and row block g of Qt; for the per-patch method
+// every patch has the one local U, and its Q in its own frame sits at row
+// block g, column block g.
 __global__ void k_export(const double *Ut, const double *Qt, int np, int n_angp, int n_ang, int n_lm,
-                         int n_patches, int npat, const int *col_src, double *U, double *Q) {
+                         int n_patches, int npat, int fold, int per_patch, size_t ldq, const int *col_src,
+                         double *U, double *Q) {
     int jk = blockIdx.x * blockDim.x + threadIdx.x;
     int q = blockIdx.y;
     if (jk >= n_ang || q >= np) return;
@@ -446,11 +449,12 @@ __global__ void k_export(const double *Ut, const double *Qt, int np, int n_angp,
     while ((l + 1) * (l + 1) <= src) ++l;
     while (l * l > src) --l;
     int m = (src - l * l + 1) / 2;
-    const size_t kang = (size_t)npat * n_angp;
+    const size_t ldu = (size_t)npat * n_angp;
     for (int g = 0; g < n_patches; ++g) {
-        const int b = npat == 1 ? 0 : g;
-        double sg = (npat == 1 && g == 1 && (m & 1)) ? -1.0 : 1.0;
-        double u = Ut[(size_t)q * kang + (size_t)b * n_angp + jk], v = Qt[((size_t)b * n_angp + jk) * np + q];
+        const int ub = npat == 1 ? 0 : g, qr = (npat > 1 || per_patch) ? g : 0, qc = per_patch ? g : 0;
+        double sg = (fold && g == 1 && (m & 1)) ? -1.0 : 1.0;
+        double u = Ut[(size_t)q * ldu + (size_t)ub * n_angp + jk];
+        double v = Qt[((size_t)qr * n_angp + jk) * ldq + (size_t)qc * np + q];
         size_t o = ((size_t)g * n_ang + jk) * n_lm + src;
         if (U) U[o] = sg * u;
         if (Q) Q[o] = sg * v;
@@ -494,7 +498,7 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
     int *d_perm = nullptr;
     double *d_re = nullptr, *dh = nullptr, *db = nullptr, *N4 = nullptr, *Tt = nullptr, *CS = nullptr;
     const size_t kang = (size_t)p.kang();
-    const size_t nU = (size_t)p.np_alloc * kang, nQ = kang * p.np;
+    const size_t nU = (size_t)p.np_alloc * kang, nQ = (size_t)p.n2() * p.kq();
 #define STEP(x)                             \
     do {                                    \
         err = (x);                          \
@@ -555,33 +559,55 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
     STEP(hipMalloc(&p.Qt, sizeof(double) * nQ));
     STEP(hipMemsetAsync(p.Qt, 0, sizeof(double) * nQ, s));
     for (int b = 0; b < p.npat; ++b) {
-        const double *e = euler + 3 * b;
+        // the per-patch method takes every patch's harmonics in its own frame
+        const double ident[3] = {0.0, 0.0, 0.0};
+        const double *e = p.per_patch ? ident : euler + 3 * b;
         hipLaunchKernelGGL(k_dbeta, dim3(blocks(2 * off_sq(L + 1), 128)), dim3(128), 0, s, L, dh, e[1],
                            M_PI - e[1], db);
         hipLaunchKernelGGL(k_ncoef, dim3(blocks(off_sq(L + 1), 128)), dim3(128), 0, s, L, db, e[0], e[2], N4);
         hipLaunchKernelGGL(k_U, dim3(blocks(p.n_angp, 128), p.np_alloc), dim3(128), 0, s, L, p.np_alloc, p.n_angp,
                            p.n_ang, p.n_phi, p.col_src, Tt, CS, N4, p.w + (size_t)b * p.n_ang, kang,
                            (size_t)b * p.n_angp, p.Ut);
-        Rot R;
-        rotation(e[0], e[1], e[2], R.r);
-        hipLaunchKernelGGL(k_Q, dim3(blocks(p.n_angp, 64)), dim3(64), 0, s, L, p.np, p.n_angp, p.n_ang, p.n_phi,
-                           p.theta0, p.phi0, p.dtheta, p.dphi, R, p.G, d_perm, p.Qt + (size_t)b * p.n_angp * p.np);
         STEP(hipGetLastError());
     }
+    // Q at the cells of patch b in the frame of patch c: xi_c = R_c^T R_b xi_b
+    // (per-patch method, all pairs); else in the common frame, x = R_b xi_b
+    for (int b = 0; b < (p.per_patch ? p.n_patches : p.npat); ++b)
+        for (int c = 0; c < p.nq(); ++c) {
+            double Rb[9], Rc[9];
+            rotation(euler[3 * b], euler[3 * b + 1], euler[3 * b + 2], Rb);
+            Rot R;
+            if (p.per_patch) {
+                rotation(euler[3 * c], euler[3 * c + 1], euler[3 * c + 2], Rc);
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        double v = 0.0;
+                        for (int k = 0; k < 3; ++k) v += Rc[3 * k + i] * Rb[3 * k + j];
+                        R.r[3 * i + j] = v;
+                    }
+            } else {
+                for (int i = 0; i < 9; ++i) R.r[i] = Rb[i];
+            }
+            const size_t ldq = (size_t)p.kq();
+            hipLaunchKernelGGL(k_Q, dim3(blocks(p.n_angp, 64)), dim3(64), 0, s, L, p.np, p.n_angp, p.n_ang, p.n_phi,
+                               p.theta0, p.phi0, p.dtheta, p.dphi, R, p.G, d_perm, ldq,
+                               p.Qt + (size_t)b * p.n_angp * ldq + (size_t)c * p.np);
+            STEP(hipGetLastError());
+        }
 
     // split-BF16 copies
     if (p.precision == MPG_SPLIT_BF16) {
         // U: GEMM1 column tiles over the K = n_angp slabs
-        const int ks1 = (int)(kang / kSlabK), ks2 = p.np / kSlabK;
+        const int ks1 = (int)(kang / kSlabK), ks2 = p.kq() / kSlabK;
         const size_t tU = (size_t)(p.tiles_e() + p.tiles_o()) * ks1 * 512;
-        const size_t tQ = (kang / kSplitTile) * ks2 * 512;
+        const size_t tQ = (size_t)(p.n2() / kSplitTile) * ks2 * 512;
         STEP(hipMalloc(&p.Us, sizeof(bf16) * tU * 24));
         STEP(hipMalloc(&p.Qs, sizeof(bf16) * tQ * 24));
         hipLaunchKernelGGL(k_tile_split, dim3(blocks(tU, 256)), dim3(256), 0, s, p.Ut, kang, ks1,
                            p.tiles_e(), p.fold ? p.ne_p : p.np, p.ne_p, p.np, tU, p.Us);
         // Q: angular tiles over the K = np slabs
-        hipLaunchKernelGGL(k_tile_split, dim3(blocks(tQ, 256)), dim3(256), 0, s, p.Qt, (size_t)p.np, ks2,
-                           (int)(kang / kSplitTile), (int)kang, 0, (int)kang, tQ, p.Qs);
+        hipLaunchKernelGGL(k_tile_split, dim3(blocks(tQ, 256)), dim3(256), 0, s, p.Qt, (size_t)p.kq(), ks2,
+                           p.n2() / kSplitTile, p.n2(), 0, p.n2(), tQ, p.Qs);
         STEP(hipGetLastError());
     }
     STEP(hipStreamSynchronize(s));
@@ -601,7 +627,8 @@ done:
 hipError_t export_tables(const Plan &p, double *U, double *Q, double *w) {
     if (U || Q)
         hipLaunchKernelGGL(k_export, dim3(blocks(p.n_ang, 128), p.np), dim3(128), 0, p.stream, p.Ut, p.Qt, p.np,
-                           p.n_angp, p.n_ang, p.n_lm, p.n_patches, p.npat, p.col_src, U, Q);
+                           p.n_angp, p.n_ang, p.n_lm, p.n_patches, p.npat, (int)p.fold, (int)p.per_patch,
+                           (size_t)p.kq(), p.col_src, U, Q);
     hipError_t e = hipGetLastError();
     for (int g = 0; w && e == hipSuccess && g < p.n_patches; ++g)
         e = hipMemcpyAsync(w + (size_t)g * p.n_ang, p.w + (size_t)(p.npat == 1 ? 0 : g) * p.n_ang,
