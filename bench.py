@@ -196,6 +196,7 @@ def main():
     ap.add_argument("--snapshots", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the per-patch comparison method")
     ap.add_argument("--batch", action="store_true",
                     help="also time the 64-field uneven batch (one batched call per precision)")
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -294,6 +295,26 @@ def main():
         out["split_vs_fp64_max_rel_err"] = err
         out["speedup_vs_fp64"] = ms64 / ms
         del plan64, ref
+
+    if not args.no_compare:
+        # the comparison method of the paper: every patch's moments in its own
+        # frame, potentials of the patches added (same result up to rounding)
+        log("[bench] per-patch comparison method (split-BF16)")
+        pp = mpg.Plan(grid, precision="split_bf16", max_fields=n, method="per_patch")
+        phi_pp = torch.empty_like(rho)
+        ms_pp, _, st_pp, _ = time_path(pp, rho, phi_pp, args.fp64_steps, 1)
+        plan.potential(rho, out=phi)
+        torch.cuda.synchronize()
+        out["per_patch_method"] = {
+            "value": terms_per_step / (ms_pp * 1e-3),
+            "ms_per_step": ms_pp,
+            "stage_ms": {k: v[0] / max(1, v[1]) for k, v in st_pp.items()},
+            "max_rel_diff_vs_paper_method": float((phi_pp.double() - phi.double()).abs().max()
+                                                  / phi.double().abs().max()),
+            "paper_method_speedup": ms_pp / ms,
+        }
+        log(f"[bench] per-patch method: {ms_pp:.2f} ms/step ({ms_pp / ms:.2f}x the paper's method)")
+        del pp, phi_pp
 
     if args.batch:
         log("[bench] 64-field batch")

@@ -384,18 +384,33 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     init_loader(L, wave, lane, g.M + (size_t)tm * tstride, g.Q + (size_t)tn * tstride);
 
     v16f acc_e[2][kNB], acc_o[2][kNB];
-    double unused[2][kNB][16];
+    double acc64[2][kNB][16];
     zero(acc_e);
     zero(acc_o);
+    const bool pp = !FOLD && g.nq > 1;
     if (FOLD) {
         const int ne = ne_p / TK, no = (np - ne_p) / TK;
-        run_ring<false>(S0, S1, S2, L, ne - 1, -1, ne, wm, wn, lane, acc_e, unused);
+        run_ring<false>(S0, S1, S2, L, ne - 1, -1, ne, wm, wn, lane, acc_e, acc64);
         // the odd block refills buffers the even block's last slabs were read from
         __syncthreads();
-        run_ring<false>(S0, S1, S2, L, ne + no - 1, -1, no, wm, wn, lane, acc_o, unused);
-    } else {
+        run_ring<false>(S0, S1, S2, L, ne + no - 1, -1, no, wm, wn, lane, acc_o, acc64);
+    } else if (!pp) {
         const int ns = g.ks2;
-        run_ring<false>(S0, S1, S2, L, ns - 1, -1, ns, wm, wn, lane, acc_e, unused);
+        run_ring<false>(S0, S1, S2, L, ns - 1, -1, ns, wm, wn, lane, acc_e, acc64);
+    } else {
+        // per-patch method: the moment sets of the patches one after the
+        // other, each from its highest degree down, each flushed into FP64
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < kNB; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
+        const int nsb = np / TK;
+        for (int gq = 0; gq < g.nq; ++gq) {
+            if (gq) __syncthreads();
+            run_ring<true>(S0, S1, S2, L, (gq + 1) * nsb - 1, -1, nsb, wm, wn, lane, acc_e, acc64);
+        }
     }
 
     const size_t pstride = (size_t)n_r * n_ang, fld = (size_t)g.n_patches * pstride;
@@ -413,6 +428,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
                 int f = rr / n_r, i = rr - f * n_r;
                 T *o = phi + f * fld + gp * pstride + (size_t)i * n_ang + jk;
                 double e = (double)acc_e[a][b][r];
+                if (!FOLD && pp) e = acc64[a][b][r];
                 if (FOLD) {
                     double od = (double)acc_o[a][b][r];
                     o[0] = (T)(e + od);

@@ -25,9 +25,9 @@ def big():
 
 
 @functools.lru_cache(maxsize=2)
-def plan(precision):
+def plan(precision, method="global"):
     import paper_1903_08475_amd as mpg
-    return mpg.Plan(W.config5(), precision=precision, max_fields=N_FIELDS)
+    return mpg.Plan(W.config5(), precision=precision, max_fields=N_FIELDS, method=method)
 
 
 def sparse_rho(g, seed, shells):
@@ -51,12 +51,17 @@ def sample_points(g, seed, n):
     return p, i, c
 
 
-@pytest.mark.parametrize("precision,tol", [("split_bf16", 1e-6), ("fp64", 1e-12)])
-def test_potential_at_sampled_vertices(precision, tol):
+@pytest.mark.parametrize("precision,tol,method", [("split_bf16", 1e-6, "global"), ("fp64", 1e-12, "global"),
+                                                  ("split_bf16", 1e-6, "per_patch")])
+def test_potential_at_sampled_vertices(precision, tol, method):
     import torch
     g, w, U = big()
     rhos = np.stack([sparse_rho(g, 700 + f, SHELLS) for f in range(N_FIELDS)])
-    out = plan(precision).potential(torch.tensor(rhos, device="cuda"), out_dtype=torch.float64)
+    pl = plan(precision, method)
+    out = pl.potential(torch.tensor(rhos, device="cuda"), out_dtype=torch.float64)
+    if method != "global":
+        pl.close()
+        plan.cache_clear()
     out = out.cpu().numpy().reshape(N_FIELDS, 2, g.n_r, -1)
     worst = 0.0
     for f in (0, 5, 7):
@@ -67,7 +72,7 @@ def test_potential_at_sampled_vertices(precision, tol):
         ref = O.phi_points(g, g.lmax, M, p, i, c)
         err = rel_err(out[f][p, i, c], ref)
         worst = max(worst, err)
-    print(f"{precision}: max rel err at sampled vertices {worst:.3e}")
+    print(f"{precision} {method}: max rel err at sampled vertices {worst:.3e}")
     assert worst < tol
 
 
