@@ -105,9 +105,11 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     for (int f : order) {
         const Plan &p = q[f];
         const int rt = (p.n_r + T1 - 1) / T1;
+        // the split GEMM1 takes column tiles in pairs (per parity block)
+        const int ct = split ? (tiles_e[f] + 1) / 2 + (tiles_o[f] + 1) / 2 : tiles_e[f] + tiles_o[f];
         for (int z = 0; z < p.splitk; ++z)
             for (int m = 0; m < rt; ++m)
-                for (int c = 0; c < tiles_e[f] + tiles_o[f]; ++c) i1.push_back({f, c, m, z});
+                for (int c = 0; c < ct; ++c) i1.push_back({f, c, m, z});
     }
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return q[a].n_r * q[a].splitk > q[c].n_r * q[c].splitk; });
@@ -116,8 +118,9 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return q[a].np > q[c].np; });
     for (int f : order) {
         const Plan &p = q[f];
-        const int rt = (p.n_r + T1 - 1) / T1;
-        const int at = p.kang() / T1;
+        // the split GEMM2 takes row tiles in pairs
+        const int rt = split ? (p.n_r + 2 * T1 - 1) / (2 * T1) : (p.n_r + T1 - 1) / T1;
+        const int at = p.n2() / T1;
         for (int a = 0; a < at; ++a)
             for (int m = 0; m < rt; ++m) i2.push_back({f, m, a, 0});
     }

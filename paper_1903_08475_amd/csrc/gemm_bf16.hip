@@ -19,14 +19,15 @@
 // highest degree down to l = 0, so the dominant low-degree terms are added
 // to the smallest partial sums last.
 //
-// Tiles: 128x128 per block of 512 threads (2x4 waves of 64x32, each 2x1
-// MFMA blocks of 32x32: two waves per SIMD, so one wave's barrier, copy
-// issue and LDS reads overlap the other's MFMAs), K slabs of 32.  A slab (both operands, three pieces:
-// 48 KB) is copied from global memory straight into LDS by
-// global_load_lds_dwordx4 (no staging registers) into a ring of three
-// slab buffers (144 KB): slab s+2 is in flight while slab s is multiplied,
-// with one barrier per slab.  Inside a buffer each piece is a [128][32]
-// bf16 array of 16-byte chunks stored at chunk position
+// Tiles: GEMM1 128x256 (rows x moment columns: two column tiles, so every
+// rho+- slab serves 256 columns), GEMM2 256x128 (two row tiles x one
+// angular tile); 512 threads = 8 waves of 64x64 (2x2 MFMA blocks of 32x32,
+// two waves per SIMD); K slabs of 32.  A slab of a block (both operands,
+// three pieces, 72 KB) is copied from global memory straight into LDS by
+// global_load_lds_dwordx4 (no staging registers) into two slab buffers
+// (144 KB of the 160 KB LDS): slab s+1 is in flight while slab s is
+// multiplied, one barrier per slab.  Inside a buffer each piece is a
+// [128][32] bf16 array of 16-byte chunks at chunk position
 //   4*row + (kchunk ^ ((row >> 2) & 3)).
 // The LDS serves a 16-byte-per-lane read 16 lanes per clock over 64 banks
 // (measured: a group is conflict-free when its 16 chunk positions differ
@@ -46,22 +47,9 @@ typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void glb_void;
 
 constexpr int TB = kSplitTile, TK = 32;
-constexpr int kPiece = TB * TK;       // bf16 elements of one piece of one operand in a slab
-constexpr int kFlushSlabs = 15;       // GEMM1: FP32 runs of at most 480 terms (a multiple of the ring size)
-#ifndef MPG_WAVES
-#define MPG_WAVES 8
-#endif
-// 2 x (kWaves/2) waves per block; a wave owns a 64 x kWN output tile
-constexpr int kWaves = MPG_WAVES, kThreads = 64 * kWaves;
-constexpr int kWN = TB / (kWaves / 2), kNB = kWN / 32;  // wave tile width, its 32-wide MFMA blocks
-constexpr int kParts = 8 / kWaves;                      // 64-chunk parts of each piece a wave copies
-constexpr int kLoadsPerSlab = 6 * kParts;               // global_load_lds instructions per wave per slab
-
-// one K slab of both operands, three pieces each, swizzled (see above)
-struct Slab {
-    bf16 a[3][kPiece];
-    bf16 b[3][kPiece];
-};
+constexpr int kPiece = TB * TK;  // bf16 elements of one piece of one 128-row block in a slab
+constexpr int kFlushSlabs = 16;  // GEMM1: FP32 runs of at most 512 terms (a multiple of the ring size)
+constexpr int kThreads = 512;    // 8 waves of 64x64
 
 // s_waitcnt immediates (gfx9 encoding): vmcnt <= n with the other counters
 // unconstrained, and lgkmcnt == 0 with the others unconstrained
@@ -85,11 +73,11 @@ __device__ __forceinline__ uint32_t pack2(bf16 a, bf16 b) {
     return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
 
-__device__ inline void zero(v16f (&acc)[2][kNB]) {
+__device__ inline void zero(v16f (&acc)[2][2]) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < kNB; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 }
@@ -182,38 +170,38 @@ __global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *args,
 }
 
 // ---------------------------------------------------------------------------
-// Slab loader.  A slab of an operand tile is one tile-slab block, already
-// in LDS order: wave w copies chunks 64P .. 64P+63 (P = kParts*w + h) of
-// every piece of both operands, lane l copying chunk 64P + l, so that each
-// copy instruction moves 1 KB of consecutive global memory into
-// consecutive LDS.
-struct Loader {
-    const bf16 *a, *b;  // first block (slab 0) of the A and B tiles
-    int lo[kParts];     // element offsets of this lane's chunks in a piece
-    int part[kParts];   // element offsets of the wave's parts in a piece (wave-uniform)
+// One K slab of a block: NA 128-row blocks of A and NB of B, three pieces
+// each, in the layout of the tile-slab blocks (see above).
+template <int NA, int NB>
+struct SlabT {
+    bf16 a[3][NA * kPiece];
+    bf16 b[3][NB * kPiece];
 };
 
-__device__ __forceinline__ void init_loader(Loader &L, int wave, int lane, const bf16 *a, const bf16 *b) {
-    L.a = a;
-    L.b = b;
-#pragma unroll
-    for (int h = 0; h < kParts; ++h) {
-        L.part[h] = (kParts * wave + h) * 512;
-        L.lo[h] = L.part[h] + lane * 8;
-    }
-}
+// Slab loader.  Every 128-row block of a slab is one tile-slab block,
+// already in LDS order: wave w copies chunks 64w .. 64w+63 of every piece,
+// lane l copying chunk 64w + l, so each copy instruction moves 1 KB of
+// consecutive global memory into consecutive LDS (9 per wave per slab).
+template <int NA, int NB>
+struct LoaderT {
+    const bf16 *a[NA], *b[NB];  // slab-0 blocks of the A and B row tiles
+    int lo, part;               // this lane's / this wave's element offsets in a piece
+};
 
-__device__ __forceinline__ void load_slab(Slab &S, const Loader &L, int slab) {
-    const bf16 *a = L.a + (size_t)slab * 3 * kBlk, *b = L.b + (size_t)slab * 3 * kBlk;
+template <int NA, int NB>
+__device__ __forceinline__ void load_slab(SlabT<NA, NB> &S, const LoaderT<NA, NB> &L, int slab) {
+    const size_t o = (size_t)slab * 3 * kBlk;
 #pragma unroll
-    for (int h = 0; h < kParts; ++h)
+    for (int q = 0; q < 3; ++q) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            __builtin_amdgcn_global_load_lds((glb_void *)(a + q * kBlk + L.lo[h]), (lds_void *)(S.a[q] + L.part[h]),
-                                             16, 0, 0);
-            __builtin_amdgcn_global_load_lds((glb_void *)(b + q * kBlk + L.lo[h]), (lds_void *)(S.b[q] + L.part[h]),
-                                             16, 0, 0);
-        }
+        for (int i = 0; i < NA; ++i)
+            __builtin_amdgcn_global_load_lds((glb_void *)(L.a[i] + o + q * kBlk + L.lo),
+                                             (lds_void *)(S.a[q] + i * kPiece + L.part), 16, 0, 0);
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            __builtin_amdgcn_global_load_lds((glb_void *)(L.b[j] + o + q * kBlk + L.lo),
+                                             (lds_void *)(S.b[q] + j * kPiece + L.part), 16, 0, 0);
+    }
 }
 
 // 8 bf16 (16 bytes) of row `row`, kchunk kc of one swizzled piece
@@ -221,29 +209,29 @@ __device__ __forceinline__ v8bf frag(const bf16 *piece, int row, int kc) {
     return *(const v8bf *)(piece + (row * 4 + (kc ^ ((row >> 2) & 3))) * 8);
 }
 
-// one 32-deep slab for a wave's 64 x kWN tile: for each 16-deep step the
-// six partial products are issued product by product over the wave's
-// accumulators, smallest weight first.
-__device__ __forceinline__ void mma_slab(const Slab &S, int wm, int wn, int lane, v16f (&acc)[2][kNB]) {
+// one 32-deep slab for a wave's 64x64 tile at (wm, wn) of the block: for
+// each 16-deep step the six partial products are issued product by
+// product over the four accumulators, smallest weight first, so
+// consecutive MFMAs never depend on each other.
+template <int NA, int NB>
+__device__ __forceinline__ void mma_slab(const SlabT<NA, NB> &S, int wm, int wn, int lane, v16f (&acc)[2][2]) {
     const int r = lane & 31, kh = lane >> 5;
+    const int ao = (wm >> 7) * kPiece, ar = wm & 127, bo = (wn >> 7) * kPiece, br = wn & 127;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
         const int kc = 2 * ks + kh;
-        v8bf ah[2], am[2], al[2], bh[kNB], bm[kNB], bl[kNB];
+        v8bf ah[2], am[2], al[2], bh[2], bm[2], bl[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            ah[i] = frag(S.a[0], wm + 32 * i + r, kc);
-            am[i] = frag(S.a[1], wm + 32 * i + r, kc);
-            al[i] = frag(S.a[2], wm + 32 * i + r, kc);
+            ah[i] = frag(S.a[0] + ao, ar + 32 * i + r, kc);
+            am[i] = frag(S.a[1] + ao, ar + 32 * i + r, kc);
+            al[i] = frag(S.a[2] + ao, ar + 32 * i + r, kc);
+            bh[i] = frag(S.b[0] + bo, br + 32 * i + r, kc);
+            bm[i] = frag(S.b[1] + bo, br + 32 * i + r, kc);
+            bl[i] = frag(S.b[2] + bo, br + 32 * i + r, kc);
         }
-#pragma unroll
-        for (int j = 0; j < kNB; ++j) {
-            bh[j] = frag(S.b[0], wn + 32 * j + r, kc);
-            bm[j] = frag(S.b[1], wn + 32 * j + r, kc);
-            bl[j] = frag(S.b[2], wn + 32 * j + r, kc);
-        }
-#define MMP(X, Y)                                                                           \
-    _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < kNB; ++j) \
+#define MMP(X, Y)                                                                              \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) \
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X[i], Y[j], acc[i][j], 0, 0, 0);
         MMP(al, bh)
         MMP(am, bm)
@@ -255,12 +243,11 @@ __device__ __forceinline__ void mma_slab(const Slab &S, int wm, int wn, int lane
     }
 }
 
-// Workgroup barrier for the slab ring.  It waits for this wave's copies up
-// to the slab about to be read (at most `pending` copy instructions of the
-// next slab stay in flight), then joins the other waves.  The empty asm
+// Workgroup barrier for the slab ring: waits for this wave's copies of the
+// slab about to be read, then joins the other waves.  The empty asm
 // statements keep the compiler from moving LDS accesses across it;
-// __syncthreads() is not used because its fence would also wait for the
-// copies still in flight.
+// __syncthreads() is not used because its fence would also wait for copies
+// still in flight.
 template <int pending>
 __device__ __forceinline__ void ring_barrier() {
     asm volatile("" ::: "memory");
@@ -269,96 +256,104 @@ __device__ __forceinline__ void ring_barrier() {
     asm volatile("" ::: "memory");
 }
 
-// Multiplies nsl consecutive K slabs of the tile into acc through the ring
-// S0 -> S1 -> S2.  Slab t is block k0 + t*dk of the tiles (dk = +-1).  With
-// FLUSH, acc is added into acc64 and cleared after every kFlushSlabs slabs.
-// Every step copies a slab two ahead; past the end it copies the last slab
-// again (same addresses, cache hits), so each step waits for the same count
-// of copies.
+// Multiplies nsl consecutive K slabs of the block into acc through the two
+// buffers S0, S1.  Slab t is block k0 + t*dk of the tiles (dk = +-1).  Each
+// step waits for the one copy in flight (its slab), then, once every wave
+// is past the barrier, copies the next slab into the buffer the previous
+// step read; past the end it copies the last slab again (same addresses,
+// cache hits), so the steps are alike.  With FLUSH, acc is added into
+// acc64 and cleared after every kFlushSlabs slabs and at the end.  A group
+// of kFlushSlabs slabs is unrolled in full so the compiler can tell which
+// buffer every LDS read and copy touches (and adds no wait of its own).
 // Every wave must call it with the same arguments; on return all copies
-// have landed, and the ring may be refilled after a barrier.
-template <bool FLUSH>
-__device__ __forceinline__ void run_ring(Slab &S0, Slab &S1, Slab &S2, const Loader &L, int k0, int dk, int nsl,
-                                         int wm, int wn, int lane, v16f (&acc)[2][kNB], double (&acc64)[2][kNB][16]) {
+// have landed, and the buffers may be refilled after a barrier.
+template <int NA, int NB, bool FLUSH>
+__device__ __forceinline__ void run_ring(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
+                                         int dk, int nsl, int wm, int wn, int lane, v16f (&acc)[2][2],
+                                         double (&acc64)[2][2][16]) {
     if (nsl <= 0) return;
     const int last = nsl - 1;
     load_slab(S0, L, k0);
-    load_slab(S1, L, k0 + min(1, last) * dk);
-#define RING_STEP(CUR, NXT, O)                                  \
-    ring_barrier<kLoadsPerSlab>();                              \
-    load_slab(NXT, L, k0 + min(t + O + 2, last) * dk);          \
+#define RING_STEP(CUR, NXT, O)                             \
+    ring_barrier<0>();                                     \
+    load_slab(NXT, L, k0 + min(t + O + 1, last) * dk);     \
     if (t + O < nsl) mma_slab(CUR, wm, wn, lane, acc);
-    // A group of kFlushSlabs slabs is unrolled in full, and the barriers and
-    // copies of a turn of the ring run even where its last slabs lie past
-    // the end: the compiler then follows which buffer every LDS read and
-    // copy touches and adds no wait for copies still in flight.
     for (int s = 0; s < nsl; s += kFlushSlabs) {
 #pragma unroll
-        for (int j = 0; j < kFlushSlabs / 3; ++j) {
-            const int t = s + 3 * j;
+        for (int j = 0; j < kFlushSlabs / 2; ++j) {
+            const int t = s + 2 * j;
             if (t < nsl) {
-                RING_STEP(S0, S2, 0)
+                RING_STEP(S0, S1, 0)
                 RING_STEP(S1, S0, 1)
-                RING_STEP(S2, S1, 2)
             }
         }
         if (FLUSH) {
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < kNB; ++b)
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc64[a][b][r] += (double)acc[a][b][r];
             zero(acc);
         }
     }
 #undef RING_STEP
-    // the two trailing copies land before anyone may reuse or free the LDS
+    // the trailing copy lands before anyone may reuse or free the LDS
     asm volatile("" ::: "memory");
     MPG_WAIT_VM(0);
     asm volatile("" ::: "memory");
 }
 
+typedef SlabT<1, 2> Slab1;  // GEMM1: 128 rows of rho+-, 256 columns of U
+typedef SlabT<2, 1> Slab2;  // GEMM2: 256 rows of M, 128 angular cells of Q
+
 // ---------------------------------------------------------------------------
-// One output tile of GEMM1 (column tile tn: even-m tiles first, then odd-m
-// tiles; row tile tm; K split tz).  Writes Bpart[tz][row][col] in FP64.
+// One output block of GEMM1: column pair tn (two 128-column tiles; pairs of
+// the even-m block first, then of the odd-m block), row tile tm, K split
+// tz.  Writes Bpart[tz][row][col] in FP64.
 template <bool FOLD>
-__device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, Slab &S0, Slab &S1,
-                                           Slab &S2) {
+__device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, Slab1 &S0, Slab1 &S1) {
     const int rows = g.rows, np = g.np, ne_p = g.ne_p;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = (wave & 1) * 64, wn = (wave >> 1) * kWN;
-    const bool odd = FOLD && tn >= g.tiles_e;
-    const int c0 = odd ? ne_p + (tn - g.tiles_e) * TB : tn * TB;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const int pe = (g.tiles_e + 1) / 2;  // column pairs of the even block
+    const bool odd = FOLD && tn >= pe;
+    const int ct0 = odd ? g.tiles_e + 2 * (tn - pe) : 2 * tn;
+    // a second tile past the block's end: in bounds, and its columns are never stored
+    const int ct1 = min(ct0 + 1, g.tiles_e + g.tiles_o - 1);
+    const int c0 = odd ? ne_p + 2 * (tn - pe) * TB : 2 * tn * TB;
     const int cend = odd ? np : (FOLD ? ne_p : np);
     const int m0 = tm * TB;
     const int kbeg = tz * g.kchunk;
     const int kend = min(g.kang, kbeg + g.kchunk);
     const int nsl = kend > kbeg ? (kend - kbeg) / TK : 0;
 
-    // A: the pre-split rho (+-) of this tile's column parity; B: split U
-    Loader L;
+    // A: the pre-split rho (+-) of this block's column parity; B: split U
+    LoaderT<1, 2> L;
     const size_t tstride = (size_t)g.ks1 * 3 * kBlk;
-    const bf16 *A0 = g.A + (odd ? (size_t)g.row_tiles * tstride : 0) + (size_t)tm * tstride;
-    init_loader(L, wave, lane, A0, g.U + (size_t)tn * tstride);
+    L.a[0] = g.A + (odd ? (size_t)g.row_tiles * tstride : 0) + (size_t)tm * tstride;
+    L.b[0] = g.U + (size_t)ct0 * tstride;
+    L.b[1] = g.U + (size_t)ct1 * tstride;
+    L.part = wave * 512;
+    L.lo = L.part + lane * 8;
 
-    v16f acc[2][kNB];
-    double acc64[2][kNB][16];
+    v16f acc[2][2];
+    double acc64[2][2][16];
     zero(acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < kNB; ++b)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
-    run_ring<true>(S0, S1, S2, L, kbeg / TK, 1, nsl, wm, wn, lane, acc, acc64);
+    run_ring<1, 2, true>(S0, S1, L, kbeg / TK, 1, nsl, wm, wn, lane, acc, acc64);
 
     double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < kNB; ++b)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 int rr = m0 + wm + 32 * a + d_row(lane, r);
@@ -367,49 +362,53 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
             }
 }
 
-// One output tile of GEMM2 (row tile tm, angular tile tn): the even-m K
-// block into acc_e, then the odd-m block into acc_o, each walked from its
-// top slab down.
+// One output block of GEMM2 (row pair tm: two 128-row tiles; angular tile
+// tn): the even-m K block into acc_e, then the odd-m block into acc_o, each
+// walked from its top slab down; per-patch method: the moment sets of the
+// patches one after the other, each flushed into FP64.
 template <typename T, bool FOLD>
-__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Slab &S0, Slab &S1, Slab &S2) {
+__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Slab2 &S0, Slab2 &S1) {
     T *phi = (T *)g.phi;
     const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = (wave & 1) * 64, wn = (wave >> 1) * kWN;
-    const int m0 = tm * TB, n0 = tn * TB;
+    const int wm = (wave & 3) * 64, wn = (wave >> 2) * 64;
+    const int m0 = tm * 2 * TB, n0 = tn * TB;
 
-    Loader L;
+    LoaderT<2, 1> L;
     const size_t tstride = (size_t)g.ks2 * 3 * kBlk;
-    init_loader(L, wave, lane, g.M + (size_t)tm * tstride, g.Q + (size_t)tn * tstride);
+    const int rt_used = (rows + TB - 1) / TB;  // row tiles holding this call's rows
+    L.a[0] = g.M + (size_t)(2 * tm) * tstride;
+    L.a[1] = g.M + (size_t)min(2 * tm + 1, rt_used - 1) * tstride;  // past the end: rows never stored
+    L.b[0] = g.Q + (size_t)tn * tstride;
+    L.part = wave * 512;
+    L.lo = L.part + lane * 8;
 
-    v16f acc_e[2][kNB], acc_o[2][kNB];
-    double acc64[2][kNB][16];
+    v16f acc_e[2][2], acc_o[2][2];
+    double acc64[2][2][16];
     zero(acc_e);
     zero(acc_o);
     const bool pp = !FOLD && g.nq > 1;
     if (FOLD) {
         const int ne = ne_p / TK, no = (np - ne_p) / TK;
-        run_ring<false>(S0, S1, S2, L, ne - 1, -1, ne, wm, wn, lane, acc_e, acc64);
+        run_ring<2, 1, false>(S0, S1, L, ne - 1, -1, ne, wm, wn, lane, acc_e, acc64);
         // the odd block refills buffers the even block's last slabs were read from
         __syncthreads();
-        run_ring<false>(S0, S1, S2, L, ne + no - 1, -1, no, wm, wn, lane, acc_o, acc64);
+        run_ring<2, 1, false>(S0, S1, L, ne + no - 1, -1, no, wm, wn, lane, acc_o, acc64);
     } else if (!pp) {
         const int ns = g.ks2;
-        run_ring<false>(S0, S1, S2, L, ns - 1, -1, ns, wm, wn, lane, acc_e, acc64);
+        run_ring<2, 1, false>(S0, S1, L, ns - 1, -1, ns, wm, wn, lane, acc_e, acc64);
     } else {
-        // per-patch method: the moment sets of the patches one after the
-        // other, each from its highest degree down, each flushed into FP64
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < kNB; ++b)
+            for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
         const int nsb = np / TK;
         for (int gq = 0; gq < g.nq; ++gq) {
             if (gq) __syncthreads();
-            run_ring<true>(S0, S1, S2, L, (gq + 1) * nsb - 1, -1, nsb, wm, wn, lane, acc_e, acc64);
+            run_ring<2, 1, true>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, wm, wn, lane, acc_e, acc64);
         }
     }
 
@@ -418,7 +417,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < kNB; ++b)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 int rr = m0 + wm + 32 * a + d_row(lane, r);
@@ -440,18 +439,18 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 }
 
 // ---------------------------------------------------------------------------
-// Grid launches for one plan: GEMM1 grid x = column tile, y = row tile,
-// z = K split; GEMM2 grid x = row tile, y = angular tile.
+// Grid launches for one plan: GEMM1 grid x = column pair, y = row tile,
+// z = K split; GEMM2 grid x = row pair, y = angular tile.
 template <bool FOLD>
 __global__ __launch_bounds__(kThreads) void k_gemm1(SplitArgs g) {
-    __shared__ Slab s0, s1, s2;
-    gemm1_tile<FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, s0, s1, s2);
+    __shared__ Slab1 s0, s1;
+    gemm1_tile<FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, s0, s1);
 }
 
 template <typename T, bool FOLD>
 __global__ __launch_bounds__(kThreads) void k_gemm2(SplitArgs g) {
-    __shared__ Slab s0, s1, s2;
-    gemm2_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, s0, s1, s2);
+    __shared__ Slab2 s0, s1;
+    gemm2_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, s0, s1);
 }
 
 // Persistent batch kernels: every block takes work items from a queue
@@ -468,31 +467,33 @@ __device__ __forceinline__ int next_item(int *head, int *slot) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_batch_gemm1(const SplitArgs *__restrict__ args,
-                                                     const BatchItem *__restrict__ items, int n_items, int *head) {
-    __shared__ Slab s0, s1, s2;
+                                                          const BatchItem *__restrict__ items, int n_items,
+                                                          int *head) {
+    __shared__ Slab1 s0, s1;
     __shared__ int slot;
     for (;;) {
         const int it = next_item(head, &slot);
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const SplitArgs g = args[w.f];
-        if (g.fold) gemm1_tile<true>(g, w.a, w.b, w.c, s0, s1, s2);
-        else gemm1_tile<false>(g, w.a, w.b, w.c, s0, s1, s2);
+        if (g.fold) gemm1_tile<true>(g, w.a, w.b, w.c, s0, s1);
+        else gemm1_tile<false>(g, w.a, w.b, w.c, s0, s1);
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_batch_gemm2(const SplitArgs *__restrict__ args,
-                                                     const BatchItem *__restrict__ items, int n_items, int *head) {
-    __shared__ Slab s0, s1, s2;
+                                                          const BatchItem *__restrict__ items, int n_items,
+                                                          int *head) {
+    __shared__ Slab2 s0, s1;
     __shared__ int slot;
     for (;;) {
         const int it = next_item(head, &slot);
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const SplitArgs g = args[w.f];
-        if (g.fold) gemm2_tile<T, true>(g, w.a, w.b, s0, s1, s2);
-        else gemm2_tile<T, false>(g, w.a, w.b, s0, s1, s2);
+        if (g.fold) gemm2_tile<T, true>(g, w.a, w.b, s0, s1);
+        else gemm2_tile<T, false>(g, w.a, w.b, s0, s1);
     }
 }
 
@@ -553,7 +554,7 @@ hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rh
 
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
     SplitArgs g = split_args(p, n_fields, rho, nullptr, rho_dtype);
-    dim3 grid(g.tiles_e + g.tiles_o, (g.rows + TB - 1) / TB, p.splitk);
+    dim3 grid((g.tiles_e + 1) / 2 + (g.tiles_o + 1) / 2, (g.rows + TB - 1) / TB, p.splitk);
     if (p.fold) hipLaunchKernelGGL((k_gemm1<true>), grid, dim3(kThreads), 0, p.stream, g);
     else hipLaunchKernelGGL((k_gemm1<false>), grid, dim3(kThreads), 0, p.stream, g);
     return hipGetLastError();
@@ -561,7 +562,7 @@ hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtyp
 
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     SplitArgs g = split_args(p, n_fields, nullptr, phi, phi_dtype, true);
-    dim3 grid((g.rows + TB - 1) / TB, g.kang / TB);
+    dim3 grid((g.rows + 2 * TB - 1) / (2 * TB), g.kang / TB);
     if (phi_dtype == MPG_F64) {
         if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(kThreads), 0, p.stream, g);
         else hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(kThreads), 0, p.stream, g);
