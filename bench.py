@@ -3,13 +3,16 @@
 A step is one pass of the whole hot path (moment contraction, radial scans,
 expansion) over one batch of 8 snapshots of the large workload: Yin-Yang grid
 at pi/256 (128x384 cells per patch), 1200 log-spaced shells, lmax 48,
-float32 densities, split-BF16 contractions.  Inputs are resident in HBM
-before the timed region starts.
+float32 densities, split-BF16 contractions in the tiered form (three bf16
+products per product, six on the moments of degree <= 21).  Inputs are
+resident in HBM before the timed region starts.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line (see the fields below).  The FP64 path is timed on the
-same workload for comparison, and the CPU oracle on a bounded sample.
+Prints one JSON line (see the fields below).  The six-product split form and
+the FP64 path are timed on the same workload for comparison (with the
+max-norm relative difference of each split form to the FP64 result), and the
+CPU oracle on a bounded sample.
 """
 import argparse
 import hashlib
@@ -57,6 +60,44 @@ def traffic_record(stage, precision):
     if not r or r.get("source_hash") != kernel_source_hash():
         return None
     return r.get("bytes_per_launch")
+
+
+TIER_LMAX = 21  # MPG_TIER_LMAX
+
+
+def products_per_term(lmax, precision, tier_lmax=TIER_LMAX, blk=256, slab=32):
+    """bf16 MFMA products per algorithmic product, averaged over the moment
+    columns of the folded contractions (even and odd m blocks): six for the
+    six-product form; for the tiered form six on the columns of a moment
+    contraction block of 256 columns (or an expansion K slab of 32) that
+    reaches into degrees <= tier_lmax, else three."""
+    if precision != "split_bf16_tiered":
+        return {"moments": 6.0, "expansion": 6.0}
+    cols = {0: 0, 1: 0}
+    tier = {0: 0, 1: 0}
+    for l in range(lmax + 1):
+        for m in range(l + 1):
+            c = 1 if m == 0 else 2
+            cols[m % 2] += c
+            if l <= tier_lmax:
+                tier[m % 2] += c
+    res = {}
+    for stage, gran in (("moments", blk), ("expansion", slab)):
+        tot = prod = 0.0
+        for par in (0, 1):
+            n, t = cols[par], tier[par]
+            t6 = min(n, -(-t // slab) * slab)  # tier columns rounded up to K slabs
+            if stage == "moments":
+                t6 = min(n, -(-t6 // gran) * gran)
+            else:
+                n_sl = -(-n // slab)
+                n3 = max(n_sl - t6 // slab, 0)
+                n3 = n3 if n3 == n_sl else n3 & ~1
+                t6 = min(n, (n_sl - n3) * slab)
+            tot += n
+            prod += 6 * t6 + 3 * (n - t6)
+        res[stage] = prod / tot
+    return res
 
 
 def make_inputs(grid, n_snap, device):
@@ -146,7 +187,8 @@ def batch_workload(dev, reps):
     res = {"fields": len(fields), "terms_per_batch": terms,
            "cells_per_batch": sum(g.n_cells for g, _ in fields)}
     phis = {}
-    for prec, dtype in (("split_bf16", torch.float32), ("fp64", torch.float64)):
+    for prec, dtype in (("split_bf16_tiered", torch.float32), ("split_bf16", torch.float32),
+                        ("fp64", torch.float64)):
         plans = [mpg.Plan(g, precision=prec) for g, _ in fields]
         rhos = [r.to(dtype) for r in rho64]
         out = [torch.empty_like(r) for r in rhos]
@@ -180,10 +222,11 @@ def batch_workload(dev, reps):
         torch.cuda.synchronize()
         phis[prec] = out
         del plans
-    err = 0.0
-    for x, y in zip(phis["split_bf16"], phis["fp64"]):
-        err = max(err, float((x.double() - y).abs().max() / y.abs().max()))
-    res["split_vs_fp64_max_rel_err"] = err
+    for prec in ("split_bf16_tiered", "split_bf16"):
+        err = 0.0
+        for x, y in zip(phis[prec], phis["fp64"]):
+            err = max(err, float((x.double() - y).abs().max() / y.abs().max()))
+        res[prec]["vs_fp64_max_rel_err"] = err
     return res
 
 
@@ -196,6 +239,9 @@ def main():
     ap.add_argument("--snapshots", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--precision", default="split_bf16_tiered", choices=["split_bf16_tiered", "split_bf16"],
+                    help="split form of the timed step (the other one is timed beside it)")
+    ap.add_argument("--no-other-split", action="store_true", help="skip timing the other split form")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-patch comparison method")
     ap.add_argument("--batch", action="store_true",
                     help="also time the 64-field uneven batch (one batched call per precision)")
@@ -227,10 +273,16 @@ def main():
     rows, n_ang, n_lm = n * grid.n_r, grid.n_ang, grid.n_lm
     alg_flops = 2.0 * rows * n_ang * n_lm  # per contraction launch (folded)
 
-    log("[bench] building split-BF16 plan")
-    plan = mpg.Plan(grid, precision="split_bf16", max_fields=n)
+    prec = args.precision
+    other = "split_bf16" if prec == "split_bf16_tiered" else "split_bf16_tiered"
+    log(f"[bench] building {prec} plan")
+    plan = mpg.Plan(grid, precision=prec, max_fields=n)
     ms, wall, stages, pct = time_path(plan, rho, phi, args.steps, args.warmup)
-    log(f"[bench] split-BF16: {ms:.3f} ms/step ({pct}); stages {stages}")
+    log(f"[bench] {prec}: {ms:.3f} ms/step ({pct}); stages {stages}")
+    prods = products_per_term(grid.lmax, prec)
+    desc = {"split_bf16": "six MFMA products per product",
+            "split_bf16_tiered": (f"three MFMA products per product (h*h + h*m + m*h), six on the moments of "
+                                  f"degree <= {TIER_LMAX} ({prods['moments']:.2f} per product on average)")}
 
     out = {
         "metric": METRIC,
@@ -254,8 +306,8 @@ def main():
             "n_cells_per_snapshot": grid.n_cells,
             "n_lm": n_lm,
             "terms_per_step": terms_per_step,
-            "precision": "split-BF16: three bf16 pieces per operand, six MFMA products, FP32 accumulate, "
-                         "FP64 flush, FP64 tables and scans",
+            "precision": (f"{prec}: three bf16 pieces per operand, {desc[prec]}, FP32 accumulate, "
+                          "FP64 flush, FP64 tables and scans"),
             "parallelism": "single GPU",
         },
     }
@@ -272,11 +324,28 @@ def main():
         "peak": PEAK_BF16 / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_BF16,
-        "traffic": traffic_record(dom, "split_bf16"),
-        "executed_mfma_frac": 6 * achieved / PEAK_BF16,
+        "traffic": traffic_record(dom, prec),
+        "executed_mfma_frac": prods[dom] * achieved / PEAK_BF16,
+        "products_per_term": prods[dom],
         "avg_launch_ms": per[dom],
         "stage_ms": {k: per[k] for k in per},
     }
+
+    phi_other = None
+    if not args.no_other_split:
+        log(f"[bench] {other} on the same workload")
+        po = mpg.Plan(grid, precision=other, max_fields=n)
+        phi_other = torch.empty_like(rho)
+        ms_o, _, st_o, _ = time_path(po, rho, phi_other, args.steps, 1)
+        out["other_split_form"] = {
+            "precision": other,
+            "value": terms_per_step / (ms_o * 1e-3),
+            "ms_per_step": ms_o,
+            "stage_ms": {k: v[0] / max(1, v[1]) for k, v in st_o.items()},
+            "products_per_term": products_per_term(grid.lmax, other),
+        }
+        log(f"[bench] {other}: {ms_o:.3f} ms/step")
+        del po
 
     if not args.no_fp64:
         log("[bench] FP64 path on the same workload")
@@ -294,13 +363,16 @@ def main():
         }
         out["split_vs_fp64_max_rel_err"] = err
         out["speedup_vs_fp64"] = ms64 / ms
+        if phi_other is not None:
+            out["other_split_form"]["vs_fp64_max_rel_err"] = float(
+                (phi_other.to(torch.float64) - ref).abs().max() / ref.abs().max())
         del plan64, ref
 
     if not args.no_compare:
         # the comparison method of the paper: every patch's moments in its own
         # frame, potentials of the patches added (same result up to rounding)
-        log("[bench] per-patch comparison method (split-BF16)")
-        pp = mpg.Plan(grid, precision="split_bf16", max_fields=n, method="per_patch")
+        log(f"[bench] per-patch comparison method ({prec})")
+        pp = mpg.Plan(grid, precision=prec, max_fields=n, method="per_patch")
         phi_pp = torch.empty_like(rho)
         ms_pp, _, st_pp, _ = time_path(pp, rho, phi_pp, args.fp64_steps, 1)
         plan.potential(rho, out=phi)

@@ -52,7 +52,12 @@ extern "C" {
 
 /* arithmetic of the two contractions */
 #define MPG_FP64        0     /* FP64 MFMA GEMMs                           */
-#define MPG_SPLIT_BF16  1     /* split-BF16 MFMA GEMMs, FP32 accumulation  */
+#define MPG_SPLIT_BF16  1     /* split-BF16 MFMA GEMMs, FP32 accumulation:
+                                 six bf16 products per product          */
+#define MPG_SPLIT_BF16_TIERED 2 /* as MPG_SPLIT_BF16 with three products
+                                 (h*h, h*m, m*h) per product, six on the
+                                 moments of degree <= MPG_TIER_LMAX      */
+#define MPG_TIER_LMAX   21
 
 /* element types of rho / Phi */
 #define MPG_F64 0
@@ -85,7 +90,19 @@ typedef struct mpg_plan_s *mpg_plan_t;
  * overlap_w is NULL) and the radial recurrence coefficients on the device
  * (Sec. 4.3 step 1), plus their split-BF16 copies for MPG_SPLIT_BF16.
  *   lmax       : truncation degree, 0 <= lmax <= 64
- *   precision  : MPG_FP64 or MPG_SPLIT_BF16
+ *   precision  : MPG_FP64, MPG_SPLIT_BF16 or MPG_SPLIT_BF16_TIERED.  The
+ *                split forms write each FP32 operand as three bf16 pieces
+ *                h + m + l (exact).  MPG_SPLIT_BF16 forms every product
+ *                from the six piece products of weight >= 2^-18 of h*h.
+ *                MPG_SPLIT_BF16_TIERED keeps those six for the moments of
+ *                degree l <= MPG_TIER_LMAX (and the others that share
+ *                their 256-column moment tile in the moment contraction or
+ *                their 32-moment K slab in the expansion) and uses the three
+ *                products h*h + h*m + m*h (16-bit operands) for the rest:
+ *                about 40% less MFMA work at lmax 48.  Its potential stays
+ *                within 1e-6 (max-norm relative) of the FP64 result on the
+ *                test workloads; its moments B and M of high degree carry
+ *                errors of a few 1e-6 of max|B|.
  *   max_fields : largest n_fields later passed to the compute calls (>= 1);
  *                sizes the work space
  *   stream     : hipStream_t on which the plan runs (NULL: default stream)

@@ -17,10 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpg.so")
 
 MPG_OK, MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE, MPG_EUNSUPPORTED = 0, -1, -2, -3, -4
-MPG_FP64, MPG_SPLIT_BF16 = 0, 1
+MPG_FP64, MPG_SPLIT_BF16, MPG_SPLIT_BF16_TIERED = 0, 1, 2
 MPG_F64, MPG_F32 = 0, 1
 
-PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16}
+PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16, "split_bf16_tiered": MPG_SPLIT_BF16_TIERED}
 # "global": the paper's method; "per_patch": the comparison method (moments
 # of every patch in its own frame, potentials of the patches added)
 METHODS = {"global": 0, "per_patch": 1}

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "mpg_internal.h"
@@ -73,7 +74,7 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     b.dtype = dtype;
     b.precision = plans[0]->precision;
     const int n = (int)plans.size();
-    const bool split = b.precision == MPG_SPLIT_BF16;
+    const bool split = b.precision != MPG_FP64;
     const int T1 = split ? kSplitTile : kF64Tile;
 
     // work items per stage, longest first
@@ -101,16 +102,26 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
         }
         b.sc.push_back(scan_args(p, 1, split));
     }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return kchunk[a] > kchunk[c]; });
-    for (int f : order) {
+    // GEMM1 items, longest first: K per item, times the products per
+    // product of the split forms (six, or three off the tier's column pairs)
+    std::vector<std::pair<long long, BatchItem>> c1;
+    for (int f = 0; f < n; ++f) {
         const Plan &p = q[f];
         const int rt = (p.n_r + T1 - 1) / T1;
         // the split GEMM1 takes column tiles in pairs (per parity block)
-        const int ct = split ? (tiles_e[f] + 1) / 2 + (tiles_o[f] + 1) / 2 : tiles_e[f] + tiles_o[f];
+        const int pe = (tiles_e[f] + 1) / 2, po = (tiles_o[f] + 1) / 2;
+        const int ct = split ? pe + po : tiles_e[f] + tiles_o[f];
         for (int z = 0; z < p.splitk; ++z)
             for (int m = 0; m < rt; ++m)
-                for (int c = 0; c < ct; ++c) i1.push_back({f, c, m, z});
+                for (int c = 0; c < ct; ++c) {
+                    bool six = true;
+                    if (split) six = c < pe ? c < six_pairs(p.six_e, pe) : c - pe < six_pairs(p.six_o, po);
+                    c1.push_back({(long long)kchunk[f] * (six ? 6 : 3), BatchItem{f, c, m, z}});
+                }
     }
+    std::stable_sort(c1.begin(), c1.end(), [](const std::pair<long long, BatchItem> &a,
+                                              const std::pair<long long, BatchItem> &b) { return a.first > b.first; });
+    for (const auto &it : c1) i1.push_back(it.second);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return q[a].n_r * q[a].splitk > q[c].n_r * q[c].splitk; });
     for (int f : order)
@@ -196,7 +207,7 @@ hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *c
         g_batches.push_back(b);
     }
     const int n = (int)plans.size();
-    if (b->precision == MPG_SPLIT_BF16) {
+    if (b->precision != MPG_FP64) {
         for (int f = 0; f < n; ++f) {
             b->sa[f].rho = rho[f];
             b->sa[f].phi = phi[f];

@@ -132,7 +132,8 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
     if (g->theta0 < -1e-12 || g->theta0 + g->n_theta * g->dtheta > M_PI + 1e-12)
         return fail(MPG_EINVAL, "mpg_plan: colatitudes outside [0, pi]");
     if (lmax < 0 || lmax > 64) return fail(MPG_EINVAL, "mpg_plan: lmax outside [0, 64]");
-    if (precision != MPG_FP64 && precision != MPG_SPLIT_BF16) return fail(MPG_EINVAL, "mpg_plan: bad precision");
+    if (precision != MPG_FP64 && precision != MPG_SPLIT_BF16 && precision != MPG_SPLIT_BF16_TIERED)
+        return fail(MPG_EINVAL, "mpg_plan: bad precision");
     if (max_fields < 1 || max_fields > 4096) return fail(MPG_EINVAL, "mpg_plan: max_fields outside [1, 4096]");
     for (int i = 0; i < 3 * g->n_patches; ++i)
         if (!std::isfinite(g->euler[i])) return fail(MPG_EINVAL, "mpg_plan: non-finite Euler angle");
@@ -251,7 +252,23 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
         free_plan(p);
         return rc;
     }
-    if (precision == MPG_SPLIT_BF16) {
+    if (precision == MPG_SPLIT_BF16_TIERED) {
+        // leading columns of each block up to degree MPG_TIER_LMAX (columns
+        // keep the order of the real index inside a block)
+        int ce = 0, co = 0;
+        for (int l = 0; l <= lmax && l <= MPG_TIER_LMAX; ++l)
+            for (int m = 0; m <= l; ++m) {
+                const int c = m == 0 ? 1 : 2;
+                if (!p->fold || m % 2 == 0) ce += c;
+                else co += c;
+            }
+        p->six_e = std::min(roundup(ce, kSlabK), p->ne_p);
+        p->six_o = std::min(roundup(co, kSlabK), p->no_p);
+    } else {
+        p->six_e = p->ne_p;
+        p->six_o = p->no_p;
+    }
+    if (p->split()) {
         // tile-slab blocks; rows past the last field stay zero (finite)
         const size_t nM = (size_t)p->out_row_tiles() * (p->kq() / kSlabK) * 3 * kBlk;
         const size_t nA = (size_t)(p->fold ? 2 : 1) * p->row_tiles() * (p->kang() / kSlabK) * 3 * kBlk;
@@ -291,14 +308,14 @@ static int run_moments(const Plan *p, int n_fields_in, const void *rho, int rho_
     Plan q = *p;
     q.splitk = sk;
     hipEvent_t ev;
-    if (p->precision == MPG_SPLIT_BF16) {
+    if (p->split()) {
         ev = stage_begin(q, 0);
         e = split_input_bf16(q, n_fields, rho, rho_dtype);
         stage_end(q, ev);
         if (e != hipSuccess) return hip_fail(e, "input split");
     }
     ev = stage_begin(q, 1);
-    if (p->precision == MPG_SPLIT_BF16)
+    if (p->split())
         e = gemm1_bf16(q, n_fields, rho, rho_dtype);
     else
         e = gemm1_f64(q, n_fields, rho, rho_dtype);
@@ -324,7 +341,7 @@ int mpg_moments(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, doub
 
 static int solve(const Plan *p, int n_fields, const void *rho, int rho_dtype, void *phi, int phi_dtype) {
     int rc;
-    bool split = p->precision == MPG_SPLIT_BF16;
+    bool split = p->split();
     if ((rc = run_moments(p, n_fields, rho, rho_dtype, split))) return rc;
     hipEvent_t ev = stage_begin(*p, 3);
     hipError_t e = split ? gemm2_bf16(*p, n_fields, phi, phi_dtype) : gemm2_f64(*p, n_fields, phi, phi_dtype);
@@ -373,7 +390,7 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
         (void)hipEventDestroy(a);
         return hip_fail(e, "mpg_autotune");
     }
-    const bool split = p->precision == MPG_SPLIT_BF16;
+    const bool split = p->split();
     auto time_stage = [&](int sk, int ch, bool scan, float *ms) -> hipError_t {
         Plan q = *p;
         q.splitk = sk;

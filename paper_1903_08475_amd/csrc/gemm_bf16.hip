@@ -5,7 +5,12 @@
 // significant bits).  A product a*b is formed from the six partial products
 // whose combined weight is at least 2^-18 of the leading one:
 //   ah*bh + ah*bm + am*bh + ah*bl + am*bm + al*bh
-// on v_mfma_f32_32x32x16_bf16 (bf16 products are exact in FP32).  GEMM1's
+// on v_mfma_f32_32x32x16_bf16 (bf16 products are exact in FP32).  The
+// tiered form keeps the six for the leading (low-degree) columns of each
+// m-parity block (six_e, six_o) and forms the others from the three
+// products of weight >= 2^-9, ah*bh + ah*bm + am*bh, i.e. with 16-bit
+// operands h + m: whole GEMM1 blocks of 256 moment columns, and whole K
+// slabs of GEMM2, take one form or the other.  GEMM1's
 // FP32 accumulators are flushed into FP64 registers every kFlushSlabs K
 // slabs, so no FP32 sum runs over more than kFlushSlabs*32 terms (GEMM2's K
 // is the moment count, short enough for FP32 sums).
@@ -189,10 +194,12 @@ struct LoaderT {
 };
 
 template <int NA, int NB>
-__device__ __forceinline__ void load_slab(SlabT<NA, NB> &S, const LoaderT<NA, NB> &L, int slab) {
+__device__ __forceinline__ void load_slab(SlabT<NA, NB> &S, const LoaderT<NA, NB> &L, int slab, bool six) {
     const size_t o = (size_t)slab * 3 * kBlk;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
+        // the three-product form reads no l piece
+        if (q == 2 && !six) break;
 #pragma unroll
         for (int i = 0; i < NA; ++i)
             __builtin_amdgcn_global_load_lds((glb_void *)(L.a[i] + o + q * kBlk + L.lo),
@@ -210,10 +217,11 @@ __device__ __forceinline__ v8bf frag(const bf16 *piece, int row, int kc) {
 }
 
 // one 32-deep slab for a wave's 64x64 tile at (wm, wn) of the block: for
-// each 16-deep step the six partial products are issued product by
-// product over the four accumulators, smallest weight first, so
-// consecutive MFMAs never depend on each other.
-template <int NA, int NB>
+// each 16-deep step the partial products (six, or with SIX false the three
+// h*h + h*m + m*h) are issued product by product over the four
+// accumulators, smallest weight first, so consecutive MFMAs never depend on
+// each other.
+template <int NA, int NB, bool SIX>
 __device__ __forceinline__ void mma_slab(const SlabT<NA, NB> &S, int wm, int wn, int lane, v16f (&acc)[2][2]) {
     const int r = lane & 31, kh = lane >> 5;
     const int ao = (wm >> 7) * kPiece, ar = wm & 127, bo = (wn >> 7) * kPiece, br = wn & 127;
@@ -225,17 +233,21 @@ __device__ __forceinline__ void mma_slab(const SlabT<NA, NB> &S, int wm, int wn,
         for (int i = 0; i < 2; ++i) {
             ah[i] = frag(S.a[0] + ao, ar + 32 * i + r, kc);
             am[i] = frag(S.a[1] + ao, ar + 32 * i + r, kc);
-            al[i] = frag(S.a[2] + ao, ar + 32 * i + r, kc);
             bh[i] = frag(S.b[0] + bo, br + 32 * i + r, kc);
             bm[i] = frag(S.b[1] + bo, br + 32 * i + r, kc);
-            bl[i] = frag(S.b[2] + bo, br + 32 * i + r, kc);
+            if (SIX) {
+                al[i] = frag(S.a[2] + ao, ar + 32 * i + r, kc);
+                bl[i] = frag(S.b[2] + bo, br + 32 * i + r, kc);
+            }
         }
 #define MMP(X, Y)                                                                              \
     _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) \
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X[i], Y[j], acc[i][j], 0, 0, 0);
-        MMP(al, bh)
-        MMP(am, bm)
-        MMP(ah, bl)
+        if (SIX) {
+            MMP(al, bh)
+            MMP(am, bm)
+            MMP(ah, bl)
+        }
         MMP(am, bh)
         MMP(ah, bm)
         MMP(ah, bh)
@@ -256,33 +268,21 @@ __device__ __forceinline__ void ring_barrier() {
     asm volatile("" ::: "memory");
 }
 
-// Multiplies nsl consecutive K slabs of the block into acc through the two
-// buffers S0, S1.  Slab t is block k0 + t*dk of the tiles (dk = +-1).  Each
-// step waits for the one copy in flight (its slab), then, once every wave
-// is past the barrier, copies the next slab into the buffer the previous
-// step read; past the end it copies the last slab again (same addresses,
-// cache hits), so the steps are alike.  With FLUSH, acc is added into
-// acc64 and cleared after every kFlushSlabs slabs and at the end.  A group
-// of kFlushSlabs slabs is unrolled in full so the compiler can tell which
-// buffer every LDS read and copy touches (and adds no wait of its own).
-// Every wave must call it with the same arguments; on return all copies
-// have landed, and the buffers may be refilled after a barrier.
-template <int NA, int NB, bool FLUSH>
-__device__ __forceinline__ void run_ring(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
-                                         int dk, int nsl, int wm, int wn, int lane, v16f (&acc)[2][2],
-                                         double (&acc64)[2][2][16]) {
-    if (nsl <= 0) return;
-    const int last = nsl - 1;
-    load_slab(S0, L, k0);
-#define RING_STEP(CUR, NXT, O)                             \
-    ring_barrier<0>();                                     \
-    load_slab(NXT, L, k0 + min(t + O + 1, last) * dk);     \
-    if (t + O < nsl) mma_slab(CUR, wm, wn, lane, acc);
-    for (int s = 0; s < nsl; s += kFlushSlabs) {
+// Steps t0 <= t < t1 of run_ring (below), all with six products (SIX) or
+// all with three.
+template <int NA, int NB, bool FLUSH, bool SIX>
+__device__ __forceinline__ void ring_phase(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
+                                           int dk, int t0, int t1, int last, int n3, int wm, int wn, int lane,
+                                           v16f (&acc)[2][2], double (&acc64)[2][2][16]) {
+#define RING_STEP(CUR, NXT, O)                                       \
+    ring_barrier<0>();                                               \
+    load_slab(NXT, L, k0 + min(t + O + 1, last) * dk, t + O + 1 >= n3); \
+    if (t + O < t1) mma_slab<NA, NB, SIX>(CUR, wm, wn, lane, acc);
+    for (int s = t0; s < t1; s += kFlushSlabs) {
 #pragma unroll
         for (int j = 0; j < kFlushSlabs / 2; ++j) {
             const int t = s + 2 * j;
-            if (t < nsl) {
+            if (t < t1) {
                 RING_STEP(S0, S1, 0)
                 RING_STEP(S1, S0, 1)
             }
@@ -298,10 +298,42 @@ __device__ __forceinline__ void run_ring(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, c
         }
     }
 #undef RING_STEP
+}
+
+// Multiplies nsl consecutive K slabs of the block into acc through the two
+// buffers S0, S1.  Slab t is block k0 + t*dk of the tiles (dk = +-1); slabs
+// t < n3 take three products (their copies skip the l pieces), the others
+// six; n3 is even or nsl, so slab n3 always lands in S0.  Each step waits
+// for the one copy in flight (its slab), then, once every wave is past the
+// barrier, copies the next slab into the buffer the previous step read;
+// past the end it copies the last slab again (same addresses, cache hits),
+// so the steps are alike.  With FLUSH, acc is added into acc64 and cleared
+// after every kFlushSlabs slabs of a phase and at the end.  A group of
+// kFlushSlabs slabs is unrolled in full so the compiler can tell which
+// buffer every LDS read and copy touches (and adds no wait of its own).
+// Every wave must call it with the same arguments; on return all copies
+// have landed, and the buffers may be refilled after a barrier.
+template <int NA, int NB, bool FLUSH>
+__device__ __forceinline__ void run_ring(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
+                                         int dk, int nsl, int n3, int wm, int wn, int lane, v16f (&acc)[2][2],
+                                         double (&acc64)[2][2][16]) {
+    if (nsl <= 0) return;
+    const int last = nsl - 1;
+    load_slab(S0, L, k0, n3 == 0);
+    ring_phase<NA, NB, FLUSH, false>(S0, S1, L, k0, dk, 0, n3, last, n3, wm, wn, lane, acc, acc64);
+    ring_phase<NA, NB, FLUSH, true>(S0, S1, L, k0, dk, n3, nsl, last, n3, wm, wn, lane, acc, acc64);
     // the trailing copy lands before anyone may reuse or free the LDS
     asm volatile("" ::: "memory");
     MPG_WAIT_VM(0);
     asm volatile("" ::: "memory");
+}
+
+// Leading three-product slabs of a K walk of nsl slabs that runs from the
+// top of a column block down, whose lowest six_sl slabs take six products:
+// rounded down to an even count (so one more slab may take six).
+__device__ __forceinline__ int three_slabs(int nsl, int six_sl) {
+    const int n3 = max(nsl - six_sl, 0);
+    return n3 == nsl ? n3 : (n3 & ~1);
 }
 
 typedef SlabT<1, 2> Slab1;  // GEMM1: 128 rows of rho+-, 256 columns of U
@@ -347,7 +379,10 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
-    run_ring<1, 2, true>(S0, S1, L, kbeg / TK, 1, nsl, wm, wn, lane, acc, acc64);
+    // six products when the block's first column lies in its parity block's tier
+    const int cl = odd ? 2 * (tn - pe) * TB : 2 * tn * TB;
+    const bool six = cl < (odd ? g.six_o : g.six_e);
+    run_ring<1, 2, true>(S0, S1, L, kbeg / TK, 1, nsl, six ? 0 : nsl, wm, wn, lane, acc, acc64);
 
     double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
@@ -366,7 +401,7 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
 // tn): the even-m K block into acc_e, then the odd-m block into acc_o, each
 // walked from its top slab down; per-patch method: the moment sets of the
 // patches one after the other, each flushed into FP64.
-template <typename T, bool FOLD>
+template <typename T, bool FOLD, bool PP>
 __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Slab2 &S0, Slab2 &S1) {
     T *phi = (T *)g.phi;
     const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
@@ -388,16 +423,17 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     double acc64[2][2][16];
     zero(acc_e);
     zero(acc_o);
-    const bool pp = !FOLD && g.nq > 1;
+    constexpr bool pp = !FOLD && PP;  // per-patch method: g.nq moment sets
     if (FOLD) {
         const int ne = ne_p / TK, no = (np - ne_p) / TK;
-        run_ring<2, 1, false>(S0, S1, L, ne - 1, -1, ne, wm, wn, lane, acc_e, acc64);
+        run_ring<2, 1, false>(S0, S1, L, ne - 1, -1, ne, three_slabs(ne, g.six_e / TK), wm, wn, lane, acc_e, acc64);
         // the odd block refills buffers the even block's last slabs were read from
         __syncthreads();
-        run_ring<2, 1, false>(S0, S1, L, ne + no - 1, -1, no, wm, wn, lane, acc_o, acc64);
+        run_ring<2, 1, false>(S0, S1, L, ne + no - 1, -1, no, three_slabs(no, g.six_o / TK), wm, wn, lane, acc_o,
+                              acc64);
     } else if (!pp) {
         const int ns = g.ks2;
-        run_ring<2, 1, false>(S0, S1, L, ns - 1, -1, ns, wm, wn, lane, acc_e, acc64);
+        run_ring<2, 1, false>(S0, S1, L, ns - 1, -1, ns, three_slabs(ns, g.six_e / TK), wm, wn, lane, acc_e, acc64);
     } else {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -408,7 +444,17 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
         const int nsb = np / TK;
         for (int gq = 0; gq < g.nq; ++gq) {
             if (gq) __syncthreads();
-            run_ring<2, 1, true>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, wm, wn, lane, acc_e, acc64);
+            run_ring<2, 1, false>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, three_slabs(nsb, g.six_e / TK), wm, wn,
+                                  lane, acc_e, acc64);
+            // each patch's moment set is summed in FP32 (as the single set
+            // of the other forms) and added in FP64
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc64[a][b][r] += (double)acc_e[a][b][r];
+            zero(acc_e);
         }
     }
 
@@ -439,18 +485,36 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 }
 
 // ---------------------------------------------------------------------------
-// Grid launches for one plan: GEMM1 grid x = column pair, y = row tile,
-// z = K split; GEMM2 grid x = row pair, y = angular tile.
+// Grid launches for one plan: GEMM1 grid x = (column pair, row tile), z =
+// K split; GEMM2 grid x = row pair, y = angular tile.
+// GEMM1's blocks in x run over (column pair, row tile), the pairs that take
+// six products first (they take about twice as long as the others), so the
+// long blocks are dispatched before the short ones.
 template <bool FOLD>
 __global__ __launch_bounds__(kThreads) void k_gemm1(SplitArgs g) {
     __shared__ Slab1 s0, s1;
-    gemm1_tile<FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, s0, s1);
+    const int pe = (g.tiles_e + 1) / 2, po = (g.tiles_o + 1) / 2;
+    const int he = six_pairs(g.six_e, pe), ho = FOLD ? six_pairs(g.six_o, po) : 0;
+    const int nh = he + ho, nl = pe + po - nh;
+    const int rt = gridDim.x / (pe + po);
+    int b = blockIdx.x, tn, tm;
+    if (b < nh * rt) {
+        const int i = b % nh;
+        tm = b / nh;
+        tn = i < he ? i : pe + (i - he);
+    } else {
+        b -= nh * rt;
+        const int i = b % nl;
+        tm = b / nl;
+        tn = i < pe - he ? he + i : pe + ho + (i - (pe - he));
+    }
+    gemm1_tile<FOLD>(g, tn, tm, blockIdx.z, s0, s1);
 }
 
-template <typename T, bool FOLD>
+template <typename T, bool FOLD, bool PP>
 __global__ __launch_bounds__(kThreads) void k_gemm2(SplitArgs g) {
     __shared__ Slab2 s0, s1;
-    gemm2_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, s0, s1);
+    gemm2_tile<T, FOLD, PP>(g, blockIdx.x, blockIdx.y, s0, s1);
 }
 
 // Persistent batch kernels: every block takes work items from a queue
@@ -492,8 +556,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_gemm2(const SplitArgs *__res
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const SplitArgs g = args[w.f];
-        if (g.fold) gemm2_tile<T, true>(g, w.a, w.b, s0, s1);
-        else gemm2_tile<T, false>(g, w.a, w.b, s0, s1);
+        // (batches hold no per-patch plans)
+        if (g.fold) gemm2_tile<T, true, false>(g, w.a, w.b, s0, s1);
+        else gemm2_tile<T, false, false>(g, w.a, w.b, s0, s1);
     }
 }
 
@@ -530,6 +595,8 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.row_tiles = p.row_tiles();
     g.ks1 = p.kang() / TK;
     g.ks2 = p.kq() / TK;
+    g.six_e = p.six_e;
+    g.six_o = p.six_o;
     return g;
 }
 
@@ -554,7 +621,7 @@ hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rh
 
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
     SplitArgs g = split_args(p, n_fields, rho, nullptr, rho_dtype);
-    dim3 grid((g.tiles_e + 1) / 2 + (g.tiles_o + 1) / 2, (g.rows + TB - 1) / TB, p.splitk);
+    dim3 grid(((g.tiles_e + 1) / 2 + (g.tiles_o + 1) / 2) * ((g.rows + TB - 1) / TB), 1, p.splitk);
     if (p.fold) hipLaunchKernelGGL((k_gemm1<true>), grid, dim3(kThreads), 0, p.stream, g);
     else hipLaunchKernelGGL((k_gemm1<false>), grid, dim3(kThreads), 0, p.stream, g);
     return hipGetLastError();
@@ -564,11 +631,13 @@ hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     SplitArgs g = split_args(p, n_fields, nullptr, phi, phi_dtype, true);
     dim3 grid((g.rows + 2 * TB - 1) / (2 * TB), g.kang / TB);
     if (phi_dtype == MPG_F64) {
-        if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(kThreads), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(kThreads), 0, p.stream, g);
+        if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true, false>), grid, dim3(kThreads), 0, p.stream, g);
+        else if (g.nq > 1) hipLaunchKernelGGL((k_gemm2<double, false, true>), grid, dim3(kThreads), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm2<double, false, false>), grid, dim3(kThreads), 0, p.stream, g);
     } else {
-        if (p.fold) hipLaunchKernelGGL((k_gemm2<float, true>), grid, dim3(kThreads), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm2<float, false>), grid, dim3(kThreads), 0, p.stream, g);
+        if (p.fold) hipLaunchKernelGGL((k_gemm2<float, true, false>), grid, dim3(kThreads), 0, p.stream, g);
+        else if (g.nq > 1) hipLaunchKernelGGL((k_gemm2<float, false, true>), grid, dim3(kThreads), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm2<float, false, false>), grid, dim3(kThreads), 0, p.stream, g);
     }
     return hipGetLastError();
 }

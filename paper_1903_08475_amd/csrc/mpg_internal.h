@@ -36,6 +36,13 @@ constexpr int kSlabK = 32;
 constexpr int kBlk = kSplitTile * kSlabK;
 __host__ __device__ inline int blk_pos(int r, int k) { return (4 * r + ((k >> 3) ^ ((r >> 2) & 3))) * 8 + (k & 7); }
 
+// Column pairs (GEMM1 blocks of 2*kSplitTile columns) of a block of
+// `pairs` pairs whose leading six_cols columns take six products.
+__host__ __device__ inline int six_pairs(int six_cols, int pairs) {
+    const int n = (six_cols + 2 * kSplitTile - 1) / (2 * kSplitTile);
+    return n < pairs ? n : pairs;
+}
+
 // Table layout of a plan (all device arrays are owned by the plan).
 //
 // Columns are the real moment indices permuted so that even-m columns come
@@ -47,6 +54,7 @@ struct Plan {
     int n_patches = 0, n_r = 0, n_theta = 0, n_phi = 0, n_ang = 0;
     double theta0 = 0, phi0 = 0, dtheta = 0, dphi = 0;
     int lmax = 0, n_lm = 0, precision = MPG_FP64, max_fields = 1;
+    bool split() const { return precision != MPG_FP64; }
     // overlap geometry of a symmetric Yin-Yang pair (used when no w is given)
     double ovl_sc = 0, ovl_kap = 0;
     int ovl_kap_inf = 0;
@@ -58,6 +66,10 @@ struct Plan {
     // column layout
     int n_e = 0, n_o = 0, ne_p = 0, no_p = 0, np = 0, np_alloc = 0;
     int n_angp = 0;            // n_ang padded to kAngPad
+    // split forms: leading columns of the even / odd block (multiples of
+    // kSlabK) whose products take all six bf16 piece products; the other
+    // columns take three (all columns for MPG_SPLIT_BF16)
+    int six_e = 0, six_o = 0;
     // patch blocks of the contractions: 1 under the fold (and for one
     // patch), n_patches on the general path, whose GEMM1 K and GEMM2 N run
     // over the cells of every patch, patch after patch (kang = npat*n_angp)
@@ -131,6 +143,7 @@ struct SplitArgs {
     bf16 *A;                // split input (tile-slab blocks, one plane per parity)
     int row_tiles;          // row tiles of a plane of A (and of M)
     int ks1, ks2;           // slabs of GEMM1 (kang/32) and GEMM2 (np/32)
+    int six_e, six_o;       // leading columns of each block with six products (see Plan)
 };
 
 // Arguments of one field's FP64 contractions.

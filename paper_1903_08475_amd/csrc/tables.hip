@@ -596,7 +596,7 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
         }
 
     // split-BF16 copies
-    if (p.precision == MPG_SPLIT_BF16) {
+    if (p.split()) {
         // U: GEMM1 column tiles over the K = n_angp slabs
         const int ks1 = (int)(kang / kSlabK), ks2 = p.kq() / kSlabK;
         const size_t tU = (size_t)(p.tiles_e() + p.tiles_o()) * ks1 * 512;

@@ -10,7 +10,7 @@ from gpu_util import oracle_tables, rel_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "split_bf16": 1e-6}
+TOL = {"fp64": 1e-12, "split_bf16": 1e-6, "split_bf16_tiered": 1e-6}
 
 
 def fields():
@@ -30,7 +30,7 @@ def oracle_phi(g, rho):
     return phi
 
 
-@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16", "split_bf16_tiered"])
 def test_batch_matches_oracle_over_replays(precision):
     import torch
     import paper_1903_08475_amd as mpg

@@ -14,7 +14,7 @@ from gpu_util import rel_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "split_bf16": 1e-6}
+TOL = {"fp64": 1e-12, "split_bf16": 1e-6, "split_bf16_tiered": 1e-6}
 
 
 def euler_of(R):
@@ -59,12 +59,24 @@ def two_free():
     return g, w, w
 
 
+def yy_rotated_high_degree():
+    """The turned Yin-Yang grid at lmax 30: the tiered split form takes
+    three products on the degrees above its six-product tier."""
+    base = W.yinyang(16, W.geometric_edges(6, 1.3), 30)
+    X = O.rotation(-0.3, 2.0, 0.8)
+    eul = [euler_of(X @ O.rotation(*e)) for e in base.euler]
+    g = W.patches(eul, base.n_theta, base.n_phi, base.theta0, base.phi0, base.dtheta, base.dphi, base.r_edges,
+                  base.lmax, name="yy_rot_hi")
+    return g, O.overlap_weights(base), None
+
+
 def polar_turned():
     g = W.polar(8, 16, W.uniform_edges(9), 7, euler=(0.4, 0.9, -1.3), name="polar_turned")
     return g, None, None
 
 
-CASES = {"yy_rot": yy_rotated, "three": three_patches, "two_free": two_free, "polar_turned": polar_turned}
+CASES = {"yy_rot": yy_rotated, "three": three_patches, "two_free": two_free, "polar_turned": polar_turned,
+         "yy_rot_hi": yy_rotated_high_degree}
 
 
 @functools.lru_cache(maxsize=8)
@@ -75,7 +87,7 @@ def case(key):
     return g, w_plan, rho, phi, B
 
 
-@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16", "split_bf16_tiered"])
 @pytest.mark.parametrize("key", list(CASES))
 def test_general_path_matches_oracle(key, precision):
     import torch
@@ -116,7 +128,7 @@ def test_identical_per_patch_weights_keep_the_fold():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16", "split_bf16_tiered"])
 def test_batch_mixes_general_and_folded_plans(precision):
     import torch
     import paper_1903_08475_amd as mpg

@@ -24,7 +24,7 @@ def big():
     return g, w, U
 
 
-@functools.lru_cache(maxsize=2)
+@functools.lru_cache(maxsize=3)
 def plan(precision, method="global"):
     import paper_1903_08475_amd as mpg
     return mpg.Plan(W.config5(), precision=precision, max_fields=N_FIELDS, method=method)
@@ -52,6 +52,7 @@ def sample_points(g, seed, n):
 
 
 @pytest.mark.parametrize("precision,tol,method", [("split_bf16", 1e-6, "global"), ("fp64", 1e-12, "global"),
+                                                  ("split_bf16_tiered", 1e-6, "global"),
                                                   ("split_bf16", 1e-6, "per_patch")])
 def test_potential_at_sampled_vertices(precision, tol, method):
     import torch

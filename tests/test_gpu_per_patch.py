@@ -12,11 +12,11 @@ import pytest
 import oracle as O
 import workloads as W
 from gpu_util import rel_err
-from test_gpu_general import yy_rotated
+from test_gpu_general import yy_rotated, yy_rotated_high_degree
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "split_bf16": 1e-6}
+TOL = {"fp64": 1e-12, "split_bf16": 1e-6, "split_bf16_tiered": 1e-6}
 
 
 def three_shared():
@@ -43,7 +43,8 @@ def polar():
     return g, None, None
 
 
-CASES = {"c1": yinyang_c1, "ragged": ragged, "polar": polar, "yy_rot": yy_rotated, "three_shared": three_shared}
+CASES = {"c1": yinyang_c1, "ragged": ragged, "polar": polar, "yy_rot": yy_rotated, "three_shared": three_shared,
+         "yy_rot_hi": yy_rotated_high_degree}
 
 
 @functools.lru_cache(maxsize=8)
@@ -54,7 +55,7 @@ def case(key):
     return g, w_oracle, w_plan, rho, phi
 
 
-@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16", "split_bf16_tiered"])
 @pytest.mark.parametrize("key", list(CASES))
 def test_per_patch_method_matches_oracle(key, precision):
     import torch

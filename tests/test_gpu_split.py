@@ -1,6 +1,9 @@
-"""Parity of the split-BF16 GPU path (six-product three-piece bf16 MFMA
-contractions, FP32 accumulation, FP64 scans) with the CPU oracle and with
-the FP64 GPU path.  Bar: 1e-6 max-norm relative error of Phi."""
+"""Parity of the split-BF16 GPU path (three-piece bf16 MFMA contractions
+with six products, or three above the low-degree tier; FP32 accumulation,
+FP64 scans) with the CPU oracle and with the FP64 GPU path.  Bar: 1e-6
+max-norm relative error of Phi.  Moments: 1e-6 for the six-product form;
+the tiered form's moments of degree above the tier carry the three-product
+rounding (each product within 3*2^-16 of |a||b|), checked at 1e-5."""
 import numpy as np
 import pytest
 
@@ -11,6 +14,8 @@ from gpu_util import oracle_tables, rel_err
 pytestmark = pytest.mark.gpu
 
 TOL_SPLIT = 1e-6
+TOL_MOMENTS = {"split_bf16": 1e-6, "split_bf16_tiered": 1e-5}
+SPLITS = ["split_bf16", "split_bf16_tiered"]
 
 
 def torch_mods():
@@ -27,37 +32,75 @@ def density(key, g):
     return W.random_rho(g, 21)
 
 
+@pytest.mark.parametrize("precision", SPLITS)
 @pytest.mark.parametrize("key", ["c3", "c1", "ragged", "polar", "medium", "tiny"])
-def test_split_potential_matches_oracle_and_fp64_path(key):
+def test_split_potential_matches_oracle_and_fp64_path(key, precision):
     torch, mpg = torch_mods()
     g, w, U, Q = oracle_tables(key)
     rho = density(key, g)
     M = O.radial(g, g.lmax, O.moments(g, g.lmax, U, rho))
     phi = O.expand(g, g.lmax, Q, M)
     t = torch.tensor(rho, device="cuda")
-    out = mpg.Plan(g, precision="split_bf16").potential(t).cpu().numpy()
+    out = mpg.Plan(g, precision=precision).potential(t).cpu().numpy()
     ref64 = mpg.Plan(g, precision="fp64").potential(t).cpu().numpy()
     e_orc, e_64 = rel_err(out, phi), rel_err(out, ref64)
-    print(f"{key}: split-BF16 vs oracle {e_orc:.3e}, vs FP64 GPU {e_64:.3e}")
+    print(f"{key} {precision}: vs oracle {e_orc:.3e}, vs FP64 GPU {e_64:.3e}")
     assert e_orc < TOL_SPLIT and e_64 < TOL_SPLIT
 
 
-def test_split_moments_match_oracle():
+@pytest.mark.parametrize("precision", SPLITS)
+def test_split_moments_match_oracle(precision):
     torch, mpg = torch_mods()
     g, w, U, Q = oracle_tables("c3")
     rho = density("c3", g)
     B = O.moments(g, g.lmax, U, rho)
     M = O.radial(g, g.lmax, B)
-    Bg, Mg = mpg.Plan(g, precision="split_bf16").moments(torch.tensor(rho, device="cuda"))
-    assert rel_err(Bg[0].cpu().numpy(), B) < TOL_SPLIT
-    assert rel_err(Mg[0].cpu().numpy(), M) < TOL_SPLIT
+    Bg, Mg = mpg.Plan(g, precision=precision).moments(torch.tensor(rho, device="cuda"))
+    eb, em = rel_err(Bg[0].cpu().numpy(), B), rel_err(Mg[0].cpu().numpy(), M)
+    print(f"{precision}: B vs oracle {eb:.3e}, M vs oracle {em:.3e}")
+    assert eb < TOL_MOMENTS[precision] and em < TOL_MOMENTS[precision]
 
 
-def test_split_float32_fields_batched():
+def test_tiered_form_changes_only_the_degrees_above_its_tier():
+    """Moments of degree <= 21 come out of the tiered form's six-product
+    blocks and equal the six-product form's bit for bit; above the tier the
+    three-product rounding shows, and stays within its bound: each product
+    a*b is formed to within 3.02*2^-16 |a||b| (the dropped piece products),
+    plus the FP32 accumulation of at most 512 terms between FP64 flushes."""
+    torch, mpg = torch_mods()
+    g, w, U, Q = oracle_tables("c3")
+    rho = density("c3", g)
+    t = torch.tensor(rho, device="cuda")
+    B6, _ = mpg.Plan(g, precision="split_bf16").moments(t)
+    BT, _ = mpg.Plan(g, precision="split_bf16_tiered").moments(t)
+    B6, BT = B6[0].cpu().numpy(), BT[0].cpu().numpy()
+    low = 22 * 22  # real columns of degree <= 21
+    assert np.array_equal(B6[:, :low], BT[:, :low])
+    assert np.abs(B6[:, low:] - BT[:, low:]).max() > 0.0
+    # bound per entry: sum over cells of |rho_fold| |U| times the per-product
+    # bound, the FP32 accumulation bound (512 * 2^-24 per flush run) and the
+    # FP32 rounding of the folded density and of U, and subnormal densities
+    # (below 2^-126) that the MFMAs may flush; against the oracle's moments
+    # of the FP32-rounded density the split path reads
+    n_ang = g.n_theta * g.n_phi
+    r32 = rho.astype(np.float32).astype(np.float64)
+    a = np.abs(r32.reshape(2, g.n_r, n_ang))
+    S = (a[0] + a[1]) @ np.abs(U[0])  # U_Yang = +-U_Yin column by column
+    B = O.moments(g, g.lmax, U, r32)
+    bound = (3.02 * 2.0 ** -16 + 512 * 2.0 ** -24 + 2.0 ** -23) * S + 2.0 ** -125 * np.abs(U[0]).sum(axis=0)
+    err = np.abs(BT - B)
+    excess = err - bound
+    hi = bound[:, low:] > 0
+    print(f"tiered moments: worst error / bound {np.max(err[:, low:][hi] / bound[:, low:][hi]):.3e}")
+    assert excess.max() <= 0.0
+
+
+@pytest.mark.parametrize("precision", SPLITS)
+def test_split_float32_fields_batched(precision):
     torch, mpg = torch_mods()
     g, w, U, Q = oracle_tables("ragged")
     rhos = np.stack([W.random_rho(g, 300 + f) for f in range(3)]).astype(np.float32)
-    plan = mpg.Plan(g, precision="split_bf16", max_fields=3)
+    plan = mpg.Plan(g, precision=precision, max_fields=3)
     out = plan.potential(torch.tensor(rhos, device="cuda"), out_dtype=torch.float64).cpu().numpy()
     for f in range(3):
         M = O.radial(g, g.lmax, O.moments(g, g.lmax, U, rhos[f].astype(np.float64)))
