@@ -168,6 +168,16 @@ int mpg_potential(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
 int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho,
                         void *const *phi, int dtype);
 
+/* Completion times of the fields of the last mpg_potential_batch call with
+ * these plans (same list and order) and dtype, for measuring per-field
+ * latency inside one batched solve: ms[f] (host, n entries) receives the
+ * time from the start of the batched solve on the device to the moment the
+ * last expansion tile of field f finished, read from the device wall
+ * clock.  Waits for plans[0]'s stream.
+ * Errors: MPG_EINVAL (bad arguments, or no batched solve of these plans
+ * and dtype), MPG_EDEVICE. */
+int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms);
+
 /* Autotune the plan for n_fields fields: time the moment contraction for
  * every K split the work space allows (powers of two and the default
  * choice) and the radial scan for 4, 8 and 16 shell chunks per column, on

@@ -26,8 +26,9 @@ PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16, "split_bf16_tiered
 METHODS = {"global": 0, "per_patch": 1}
 
 # Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
-EXPORTS = ("mpg_plan", "mpg_plan_method", "mpg_moments", "mpg_potential", "mpg_potential_batch", "mpg_autotune", "mpg_tables",
-           "mpg_plan_info", "mpg_timing", "mpg_stage_times", "mpg_sync", "mpg_destroy", "mpg_last_error")
+EXPORTS = ("mpg_plan", "mpg_plan_method", "mpg_moments", "mpg_potential", "mpg_potential_batch",
+           "mpg_batch_field_times", "mpg_autotune", "mpg_tables", "mpg_plan_info", "mpg_timing", "mpg_stage_times",
+           "mpg_sync", "mpg_destroy", "mpg_last_error")
 STAGES = ("input_split", "moments", "radial_scan", "expansion")
 
 
@@ -65,6 +66,7 @@ def lib():
         L.mpg_moments.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp]
         L.mpg_potential.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int]
         L.mpg_potential_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
+        L.mpg_batch_field_times.argtypes = [C.c_int, C.POINTER(vp), C.c_int, dp]
         L.mpg_autotune.argtypes = [vp, C.c_int, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.mpg_tables.argtypes = [vp, vp, vp, vp]
         L.mpg_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]
@@ -234,3 +236,17 @@ def potential_batch(plans, rhos, phis):
     P = (C.c_void_p * n)(*[p.data_ptr() for p in phis])
     _check(lib().mpg_potential_batch(n, H, R, P, dt))
     return phis
+
+
+def batch_field_times(plans, dtype):
+    """Per-field completion times (ms from the start of the batched solve,
+    device wall clock) of the last potential_batch call with these plans
+    and element type (torch.float32 or torch.float64)."""
+    import numpy as np
+    import torch
+    n = len(plans)
+    dt = MPG_F64 if dtype == torch.float64 else MPG_F32
+    H = (C.c_void_p * n)(*[p.handle for p in plans])
+    ms = np.zeros(n, dtype=np.float64)
+    _check(lib().mpg_batch_field_times(n, H, dt, ms.ctypes.data_as(C.POINTER(C.c_double))))
+    return ms

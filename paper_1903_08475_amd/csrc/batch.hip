@@ -5,7 +5,9 @@
 // pull tiles until the queue is empty.  The three launches and the counter
 // reset are captured once in a hipGraph and replayed; a call only refreshes
 // the fields' rho/phi pointers (kept in device memory, read by the kernels)
-// and launches the graph on the caller's stream.
+// and launches the graph on the caller's stream.  The expansion kernels also
+// stamp the device wall clock when the last tile of a field is done, so the
+// per-field completion times inside one batched call can be read back.
 #include <algorithm>
 #include <mutex>
 #include <new>
@@ -17,9 +19,14 @@
 namespace mpg {
 namespace {
 
-__global__ void k_zero_ints(int *p, int n) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) p[t] = 0;
+// Start of a batched solve: clears the queue heads and the per-field
+// completion stamps and stamps the start time (stamps[n]).
+__global__ void k_batch_start(int *heads, int n_heads, unsigned long long *stamps, int n) {
+    for (int t = threadIdx.x; t < n_heads || t < n + 2; t += blockDim.x) {
+        if (t < n_heads) heads[t] = 0;
+        if (t < n + 2 && t != n) stamps[t] = 0;
+    }
+    if (threadIdx.x == 0) stamps[n] = wall_clock64();
 }
 
 struct Batch {
@@ -33,6 +40,7 @@ struct Batch {
     ScanArgs *scan_dev = nullptr;
     BatchItem *items_dev = nullptr;
     int *heads = nullptr;
+    unsigned long long *stamps = nullptr;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -45,6 +53,7 @@ struct Batch {
         if (scan_dev) (void)hipFree(scan_dev);
         if (items_dev) (void)hipFree(items_dev);
         if (heads) (void)hipFree(heads);
+        if (stamps) (void)hipFree(stamps);
     }
 };
 
@@ -149,14 +158,17 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     CHECK(hipMalloc(&b.scan_dev, sizeof(ScanArgs) * n));
     CHECK(hipMalloc(&b.items_dev, sizeof(BatchItem) * all.size()));
     CHECK(hipMalloc(&b.heads, sizeof(int) * 4));
+    CHECK(hipMalloc(&b.stamps, sizeof(unsigned long long) * (n + 2)));
+    CHECK(hipMemset(b.stamps, 0, sizeof(unsigned long long) * (n + 2)));
+    const BatchTrack track{b.stamps, n};
     CHECK(hipMemcpy(b.scan_dev, b.sc.data(), sizeof(ScanArgs) * n, hipMemcpyHostToDevice));
     CHECK(hipMemcpy(b.items_dev, all.data(), sizeof(BatchItem) * all.size(), hipMemcpyHostToDevice));
 
-    // capture: counter reset (a kernel, not a memset) and the three stages
+    // capture: counter reset and start stamp (a kernel, not a memset) and the three stages
     CHECK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
     CHECK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
     const int cus = cu_count();
-    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, b.cap, b.heads, 4);
+    hipLaunchKernelGGL(k_batch_start, dim3(1), dim3(256), 0, b.cap, b.heads, 4, b.stamps, n);
     const BatchItem *it1 = b.items_dev, *its = b.items_dev + b.n1, *it2 = b.items_dev + b.n1 + b.ns;
     hipError_t e;
     e = hipSuccess;
@@ -166,11 +178,13 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
         if (e == hipSuccess)
             e = batch_gemm1_bf16((const SplitArgs *)b.args_dev, it1, b.n1, b.heads + 0, dtype, cus, b.cap);
         if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);
-        if (e == hipSuccess) e = batch_gemm2_bf16((const SplitArgs *)b.args_dev, it2, b.n2, b.heads + 2, dtype, cus, b.cap);
+        if (e == hipSuccess)
+            e = batch_gemm2_bf16((const SplitArgs *)b.args_dev, it2, b.n2, b.heads + 2, dtype, cus, track, b.cap);
     } else {
         e = batch_gemm1_f64((const F64Args *)b.args_dev, it1, b.n1, b.heads + 0, dtype, 4 * cus, b.cap);
         if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);
-        if (e == hipSuccess) e = batch_gemm2_f64((const F64Args *)b.args_dev, it2, b.n2, b.heads + 2, dtype, 4 * cus, b.cap);
+        if (e == hipSuccess)
+            e = batch_gemm2_f64((const F64Args *)b.args_dev, it2, b.n2, b.heads + 2, dtype, 4 * cus, track, b.cap);
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b.cap, &g);
@@ -221,6 +235,21 @@ hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *c
         CHECK(hipMemcpyAsync(b->args_dev, b->fa.data(), sizeof(F64Args) * n, hipMemcpyHostToDevice, stream));
     }
     return hipGraphLaunch(b->exec, stream);
+}
+
+hipError_t batch_field_times(const std::vector<const Plan *> &plans, int dtype, double *ms) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    Batch *b = find(plans, dtype);
+    if (!b) return hipErrorNotFound;
+    const int n = (int)plans.size();
+    CHECK(hipStreamSynchronize(plans[0]->stream));
+    std::vector<unsigned long long> st(n + 2);
+    CHECK(hipMemcpy(st.data(), b->stamps, sizeof(unsigned long long) * (n + 2), hipMemcpyDeviceToHost));
+    int khz = 0;
+    CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, plans[0]->device));
+    if (khz <= 0) return hipErrorInvalidValue;
+    for (int f = 0; f < n; ++f) ms[f] = st[f] > st[n] ? (double)(st[f] - st[n]) / khz : -1.0;
+    return hipSuccess;
 }
 
 void forget_plan(const Plan *p) {

@@ -379,6 +379,19 @@ int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho, 
     return MPG_OK;
 }
 
+int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms) {
+    if (n < 1 || !plans || !ms) return fail(MPG_EINVAL, "mpg_batch_field_times: bad arguments");
+    std::vector<const Plan *> ps(n);
+    for (int f = 0; f < n; ++f) {
+        if (!plans[f]) return fail(MPG_EINVAL, "mpg_batch_field_times: NULL plan");
+        ps[f] = plans[f];
+    }
+    hipError_t e = batch_field_times(ps, dtype, ms);
+    if (e == hipErrorNotFound) return fail(MPG_EINVAL, "mpg_batch_field_times: no batched solve of these plans");
+    if (e != hipSuccess) return hip_fail(e, "mpg_batch_field_times");
+    return MPG_OK;
+}
+
 int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, int *splitk, int *chunks) {
     int rc = check_call(p, n_fields_in, rho, rho_dtype, "mpg_autotune");
     if (rc) return rc;

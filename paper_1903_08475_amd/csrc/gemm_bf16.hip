@@ -548,17 +548,18 @@ __global__ __launch_bounds__(kThreads) void k_batch_gemm1(const SplitArgs *__res
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_batch_gemm2(const SplitArgs *__restrict__ args,
                                                           const BatchItem *__restrict__ items, int n_items,
-                                                          int *head) {
+                                                          int *head, BatchTrack track) {
     __shared__ Slab2 s0, s1;
     __shared__ int slot;
-    for (;;) {
-        const int it = next_item(head, &slot);
+    for (int prev = -1;;) {
+        const int it = next_item_tracked(head, &slot, track, prev);
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const SplitArgs g = args[w.f];
         // (batches hold no per-patch plans)
         if (g.fold) gemm2_tile<T, true, false>(g, w.a, w.b, s0, s1);
         else gemm2_tile<T, false, false>(g, w.a, w.b, s0, s1);
+        prev = w.f;
     }
 }
 
@@ -659,11 +660,13 @@ hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n
 }
 
 hipError_t batch_gemm2_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
-                            int blocks, hipStream_t s) {
+                            int blocks, BatchTrack track, hipStream_t s) {
     if (io_dtype == MPG_F64)
-        hipLaunchKernelGGL((k_batch_gemm2<double>), dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head);
+        hipLaunchKernelGGL((k_batch_gemm2<double>), dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head,
+                           track);
     else
-        hipLaunchKernelGGL((k_batch_gemm2<float>), dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head);
+        hipLaunchKernelGGL((k_batch_gemm2<float>), dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head,
+                           track);
     return hipGetLastError();
 }
 

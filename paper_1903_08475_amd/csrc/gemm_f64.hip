@@ -275,16 +275,18 @@ __global__ __launch_bounds__(256) void k_batch_gemm1(const F64Args *__restrict__
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_gemm2(const F64Args *__restrict__ args,
-                                                     const BatchItem *__restrict__ items, int n_items, int *head) {
+                                                     const BatchItem *__restrict__ items, int n_items, int *head,
+                                                     BatchTrack track) {
     __shared__ Smem sm;
     __shared__ int slot;
-    for (;;) {
-        const int it = next_item(head, &slot);
+    for (int prev = -1;;) {
+        const int it = next_item_tracked(head, &slot, track, prev);
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const F64Args g = args[w.f];
         if (g.fold) gemm2_tile<T, true>(g, w.a, w.b, sm);
         else gemm2_tile<T, false>(g, w.a, w.b, sm);
+        prev = w.f;
     }
 }
 
@@ -356,11 +358,11 @@ hipError_t batch_gemm1_f64(const F64Args *args, const BatchItem *items, int n_it
 }
 
 hipError_t batch_gemm2_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
-                           int blocks, hipStream_t s) {
+                           int blocks, BatchTrack track, hipStream_t s) {
     if (io_dtype == MPG_F64)
-        hipLaunchKernelGGL((k_batch_gemm2<double>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+        hipLaunchKernelGGL((k_batch_gemm2<double>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head, track);
     else
-        hipLaunchKernelGGL((k_batch_gemm2<float>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head);
+        hipLaunchKernelGGL((k_batch_gemm2<float>), dim3(blocks), dim3(256), 0, s, args, items, n_items, head, track);
     return hipGetLastError();
 }
 

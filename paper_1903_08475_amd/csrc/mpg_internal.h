@@ -128,6 +128,31 @@ struct BatchItem {
     int f, a, b, c;
 };
 
+// Per-field completion tracking of a batched solve: when a block of an
+// expansion kernel has finished an item of field f (every wave past the
+// item-queue barrier), its first thread raises stamps[f] to the device
+// wall clock, so stamps[f] ends as the time the field's last item was done.
+// stamps[n] is the batch's start; stamps[n + 1] takes the stamp of "no
+// item yet" (the first fetch of a block).
+struct BatchTrack {
+    unsigned long long *stamps;  // [n + 2]
+    int n;
+};
+
+// Item queue of the persistent batch kernels: a block's next item index
+// (all threads get the same), after stamping the previous item's field
+// (prev_f, or -1 before the first).  The stamp and the fetch share one
+// first-thread section, so the loop around it keeps a single structure.
+__device__ __forceinline__ int next_item_tracked(int *head, int *slot, const BatchTrack &t, int prev_f) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(t.stamps + (prev_f >= 0 ? prev_f : t.n + 1), (unsigned long long)wall_clock64());
+        *slot = atomicAdd(head, 1);
+    }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*slot);
+}
+
 // Arguments of one field's split-BF16 contractions.
 struct SplitArgs {
     const void *rho;
@@ -194,7 +219,7 @@ F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io
 hipError_t batch_gemm1_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                            int blocks, hipStream_t s);
 hipError_t batch_gemm2_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
-                           int blocks, hipStream_t s);
+                           int blocks, BatchTrack track, hipStream_t s);
 
 // radial scans (scan.hip): Bpart -> Bred, M (and the split copies of M)
 hipError_t radial_scan(const Plan &p, int n_fields, bool split_out);
@@ -213,12 +238,15 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
 hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                             int blocks, hipStream_t s);
 hipError_t batch_gemm2_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
-                            int blocks, hipStream_t s);
+                            int blocks, BatchTrack track, hipStream_t s);
 
 // batched solve (batch.hip)
 hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *const *rho, void *const *phi,
                            int dtype, hipStream_t stream);
 void forget_plan(const Plan *p);
+// per-field completion times (ms from the batch's start) of the last
+// batched solve of these plans with this dtype; hipErrorNotFound if none
+hipError_t batch_field_times(const std::vector<const Plan *> &plans, int dtype, double *ms);
 // K splits used for n_fields fields of a plan (autotuned or heuristic)
 int choose_splitk(const Plan &p, int n_fields);
 

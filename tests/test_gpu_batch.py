@@ -70,6 +70,34 @@ def test_batch_float32_and_reuse_of_graph():
         assert rel_err(a[k].cpu().numpy(), ref) < 1e-6
 
 
+@pytest.mark.parametrize("precision", ["split_bf16_tiered", "fp64"])
+def test_batch_field_completion_times(precision):
+    """Per-field completion times inside one batched solve: positive, no
+    later than the batch's end seen by events on its stream, and the last
+    one close to it; unknown plan lists are rejected."""
+    import torch
+    import paper_1903_08475_amd as mpg
+    gs = fields()
+    plans = [mpg.Plan(g, precision=precision) for g in gs]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    rhos = [torch.tensor(W.random_rho(g, 8100 + k), dtype=dt, device="cuda") for k, g in enumerate(gs)]
+    outs = [torch.empty_like(r) for r in rhos]
+    mpg.potential_batch(plans, rhos, outs)  # builds the graph
+    stream = plans[0].stream
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    mpg.potential_batch(plans, rhos, outs)
+    b.record(stream)
+    ms = mpg.batch_field_times(plans, dt)
+    total = a.elapsed_time(b)
+    print(f"{precision}: field completion ms {np.round(ms, 3).tolist()}, batch {total:.3f} ms")
+    assert (ms > 0).all() and ms.max() <= total * 1.05 + 0.05
+    assert ms.max() >= 0.5 * total
+    with pytest.raises(mpg.MpgError):
+        mpg.batch_field_times(plans[:2], dt)
+
+
 def test_batch_rejects_duplicate_plans_and_mixed_precision():
     import torch
     import paper_1903_08475_amd as mpg
