@@ -92,14 +92,20 @@ __device__ inline void zero(v16f (&acc)[2][2]) {
 // (odd-m block) under the fold (U_Yang = (-1)^m U_Yin, Sec. 4.2), else A =
 // rho, rounded once to FP32 and written as three bf16 pieces in tile-slab
 // blocks (one plane per parity; zero past n_ang and past the last row).
-// Thread = one 16-byte chunk (8 consecutive K of one row) of one block, so
-// consecutive threads write consecutive chunks.
+// Thread = one 16-byte chunk (8 consecutive K of one row) of one block.
 template <typename T, bool FOLD>
 __device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
-    const size_t blk = t / 512;
-    const int c = (int)(t - blk * 512);
-    const int tile = (int)(blk / g.ks1), slab = (int)(blk - (size_t)tile * g.ks1);
-    const int r = c >> 2, kc = (c & 3) ^ ((r >> 2) & 3);
+    // a wave covers 4 rows x 4 slabs: 512 consecutive bytes of each row
+    // read (FP32), 256 consecutive bytes of each piece of each slab written
+    const size_t unit = t / 2048;  // (row tile, group of 4 slabs)
+    const int rem = (int)(t - unit * 2048);
+    const int ng = (g.ks1 + 3) / 4;
+    const int tile = (int)(unit / ng), sg = (int)(unit - (size_t)tile * ng);
+    const int lane = rem & 63, r = 4 * (rem >> 6) + (lane >> 4), qq = lane & 15;
+    const int slab = 4 * sg + (qq >> 2), kc = qq & 3;
+    if (slab >= g.ks1) return;
+    const size_t blk = (size_t)tile * g.ks1 + slab;
+    const int c = 4 * r + (kc ^ ((r >> 2) & 3));  // stored chunk position
     const int row = tile * TB + r;
     int k0 = slab * TK + kc * 8;
     const int n_r = g.n_r, n_ang = g.n_ang;
@@ -602,8 +608,9 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
 }
 
 // one thread per 16-byte chunk of the row tiles holding the fields' rows
+// (slabs in groups of four)
 size_t split_input_threads(const Plan &p, int n_fields) {
-    return (size_t)((n_fields * p.n_r + TB - 1) / TB) * (p.kang() / TK) * 512;
+    return (size_t)((n_fields * p.n_r + TB - 1) / TB) * ((p.kang() / TK + 3) / 4) * 2048;
 }
 
 hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
