@@ -84,7 +84,8 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     b.precision = plans[0]->precision;
     const int n = (int)plans.size();
     const bool split = b.precision != MPG_FP64;
-    const int T1 = split ? kSplitTile : kF64Tile;
+    // tile sides of the moment contraction (rows) and the expansion
+    const int T1 = split ? kSplitTile : kF64Tile1, T2 = split ? kSplitTile : kF64Tile2;
 
     // work items per stage, longest first
     std::vector<int> order(n);
@@ -139,8 +140,8 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     for (int f : order) {
         const Plan &p = q[f];
         // the split GEMM2 takes row tiles in pairs
-        const int rt = split ? (p.n_r + 2 * T1 - 1) / (2 * T1) : (p.n_r + T1 - 1) / T1;
-        const int at = p.n2() / T1;
+        const int rt = split ? (p.n_r + 2 * T2 - 1) / (2 * T2) : (p.n_r + T2 - 1) / T2;
+        const int at = p.n2() / T2;
         for (int a = 0; a < at; ++a)
             for (int m = 0; m < rt; ++m) i2.push_back({f, m, a, 0});
     }

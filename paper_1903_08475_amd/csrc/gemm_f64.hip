@@ -12,9 +12,12 @@
 //   Phi_Yin = E + O and Phi_Yang = E - O under the fold; otherwise k runs
 //   over the cells of every patch as in GEMM1.
 //
-// Rows are (field, shell) pairs; tiles are 64x64x16 on 256 threads (four
-// waves of 32x32, v_mfma_f64_16x16x4f64), with the next K slab loaded into
-// registers while the current one is multiplied from LDS.
+// Rows are (field, shell) pairs; 256 threads (four waves) per tile on
+// v_mfma_f64_16x16x4f64, with the next K slab (16 deep) loaded into
+// registers while the current one is multiplied from LDS.  GEMM1 tiles are
+// 128x128 (waves of 64x64: 16 MFMAs per 4-deep step); GEMM2, which keeps
+// the even- and odd-m sums of its tile apart, uses 64x64 tiles (waves of
+// 32x32) so that both sets of accumulators fit two waves per SIMD.
 #include "mpg_internal.h"
 
 namespace mpg {
@@ -22,7 +25,8 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int BM = kF64Tile, BN = kF64Tile, BK = 16, LDP = BM + 2;
+constexpr int BK = 16;
+constexpr int T1 = kF64Tile1, T2 = kF64Tile2;  // GEMM1 / GEMM2 tile sides
 
 // Lane layout of v_mfma_f64_16x16x4f64 on gfx950 (measured): lane l
 // supplies A[l%16][l/16] and B[l/16][l%16]; result register r of lane l is
@@ -33,17 +37,37 @@ __device__ inline int out_col(int l, int r) { return l & 15; }
 template <typename T>
 __device__ inline double ld(const T *p) { return (double)*p; }
 
-// one 64x16 slab of a K-contiguous operand: thread t covers row t/4,
-// k = 4*(t%4) .. +3
+// one TxBK slab of a K-contiguous operand: thread t covers row
+// t / (256/T), kPer consecutive K from (t % (256/T)) * kPer
+template <int T>
 struct Slab {
-    double v[4];
+    static constexpr int kPer = T * BK / 256;  // elements per thread
+    double v[kPer];
 };
 
-// four consecutive K of one row of A; k = patch*n_angp + cell (the four
-// never straddle a patch), r0/r1 the row in patch 0 and 1, pstride the
-// distance between patches of a field
-template <typename T, bool FOLD>
-__device__ inline void load_rho(Slab &s, const T *r0, const T *r1, int k, int n_ang, int n_angp, size_t pstride,
+template <int T>
+__device__ inline int slab_row(int t) { return t / (256 / T); }
+template <int T>
+__device__ inline int slab_k(int t) { return (t % (256 / T)) * Slab<T>::kPer; }
+
+// LDS row pitch of a slab (doubles), chosen by measurement: 144 for the
+// 128-wide tiles (rows k and k+1, read by the two halves of a wave's 64-bit
+// fragment reads, fall in disjoint bank halves), 66 for the 64-wide ones
+// (whose stores of four rows at once conflict less)
+template <int T>
+constexpr int ldp() { return T == 64 ? T + 2 : T + 16; }
+
+template <int T>
+struct Smem {
+    double As[BK][ldp<T>()];
+    double Bs[BK][ldp<T>()];
+};
+
+// kPer consecutive K of one row of A; k = patch*n_angp + cell (they never
+// straddle a patch: n_angp is a multiple of 128), r0/r1 the row in patch 0
+// and 1, pstride the distance between patches of a field
+template <typename T, bool FOLD, int TS>
+__device__ inline void load_rho(Slab<TS> &s, const T *r0, const T *r1, int k, int n_ang, int n_angp, size_t pstride,
                                 bool row_ok, bool odd) {
     if (!FOLD) {
         const int gp = k / n_angp;
@@ -51,7 +75,7 @@ __device__ inline void load_rho(Slab &s, const T *r0, const T *r1, int k, int n_
         k -= gp * n_angp;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < Slab<TS>::kPer; ++q) {
         double a = 0.0;
         if (row_ok && k + q < n_ang) {
             a = ld(r0 + k + q);
@@ -64,45 +88,47 @@ __device__ inline void load_rho(Slab &s, const T *r0, const T *r1, int k, int n_
     }
 }
 
-__device__ inline void load_rowk(Slab &s, const double *row, int k, bool ok) {
+template <int TS>
+__device__ inline void load_rowk(Slab<TS> &s, const double *row, int k, bool ok) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s.v[q] = ok ? row[k + q] : 0.0;
+    for (int q = 0; q < Slab<TS>::kPer; ++q) s.v[q] = ok ? row[k + q] : 0.0;
 }
 
-__device__ inline void store_slab(double (*S)[LDP], const Slab &s, int lr, int lk) {
+template <int TS>
+__device__ inline void store_slab(double (*S)[ldp<TS>()], const Slab<TS> &s, int lr, int lk) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) S[lk + q][lr] = s.v[q];
+    for (int q = 0; q < Slab<TS>::kPer; ++q) S[lk + q][lr] = s.v[q];
 }
 
-__device__ inline void mma_slab(const double (*As)[LDP], const double (*Bs)[LDP], int wm, int wn, int lane,
-                                v4d (&acc)[2][2]) {
+// a wave's WT x WT tiles of 16x16 (TS/2 x TS/2 per wave, four waves)
+template <int TS, int WT = TS / 32>
+__device__ inline void mma_slab(const double (*As)[ldp<TS>()], const double (*Bs)[ldp<TS>()], int wm, int wn,
+                                int lane, v4d (&acc)[WT][WT]) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-        double a[2], b[2];
+        double a[WT], b[WT];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = As[kk * 4 + (lane >> 4)][wm + i * 16 + (lane & 15)];
+        for (int i = 0; i < WT; ++i) a[i] = As[kk * 4 + (lane >> 4)][wm + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = Bs[kk * 4 + (lane >> 4)][wn + j * 16 + (lane & 15)];
+        for (int j = 0; j < WT; ++j) b[j] = Bs[kk * 4 + (lane >> 4)][wn + j * 16 + (lane & 15)];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < WT; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < WT; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
 }
 
-struct Smem {
-    double As[BK][LDP];
-    double Bs[BK][LDP];
-};
 
 // One output tile of GEMM1 (column tile tn: even-m tiles first, then
 // odd-m tiles; row tile tm; K split tz).
 template <typename T, bool FOLD>
-__device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int tz, Smem &sm) {
+__device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int tz, Smem<T1> &sm) {
+    constexpr int BM = T1, BN = T1, WT = T1 / 32;
     const T *rho = (const T *)g.rho;
     const int rows = g.rows, n_r = g.n_r, n_ang = g.n_ang, n_angp = g.n_angp, np = g.np, ne_p = g.ne_p;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
     const bool odd = FOLD && tn >= g.tiles_e;
     const int c0 = odd ? ne_p + (tn - g.tiles_e) * BN : tn * BN;
     const int cend = odd ? np : (FOLD ? ne_p : np);
@@ -110,7 +136,7 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
     const int kbeg = tz * g.kchunk;
     const int kend = min(g.kang, kbeg + g.kchunk);
 
-    const int lr = t >> 2, lk = (t & 3) * 4;
+    const int lr = slab_row<T1>(t), lk = slab_k<T1>(t);
     const int row = m0 + lr;
     const bool row_ok = row < rows;
     const int f = row_ok ? row / n_r : 0, i = row_ok ? row - f * n_r : 0;
@@ -119,15 +145,15 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
     const T *r1 = r0 + pstride;
     const double *urow = g.Ut + (size_t)(c0 + lr) * g.kang;
 
-    v4d acc[2][2];
+    v4d acc[WT][WT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < WT; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < WT; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    Slab sa, sb;
+    Slab<T1> sa, sb;
     if (kbeg < kend) {
-        load_rho<T, FOLD>(sa, r0, r1, kbeg + lk, n_ang, n_angp, pstride, row_ok, odd);
+        load_rho<T, FOLD, T1>(sa, r0, r1, kbeg + lk, n_ang, n_angp, pstride, row_ok, odd);
         load_rowk(sb, urow, kbeg + lk, true);
     }
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
@@ -136,17 +162,17 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
         store_slab(sm.Bs, sb, lr, lk);
         __syncthreads();
         if (k0 + BK < kend) {
-            load_rho<T, FOLD>(sa, r0, r1, k0 + BK + lk, n_ang, n_angp, pstride, row_ok, odd);
+            load_rho<T, FOLD, T1>(sa, r0, r1, k0 + BK + lk, n_ang, n_angp, pstride, row_ok, odd);
             load_rowk(sb, urow, k0 + BK + lk, true);
         }
-        mma_slab(sm.As, sm.Bs, wm, wn, lane, acc);
+        mma_slab<T1>(sm.As, sm.Bs, wm, wn, lane, acc);
     }
     __syncthreads();
     double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < WT; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < WT; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int rr = m0 + wm + a * 16 + out_row(lane, r);
@@ -157,28 +183,29 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
 
 // One output tile of GEMM2 (row tile tm, angular tile tn).
 template <typename T, bool FOLD>
-__device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Smem &sm) {
+__device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Smem<T2> &sm) {
+    constexpr int BM = T2, BN = T2, WT = T2 / 32;
     T *phi = (T *)g.phi;
     const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
     const int m0 = tm * BM, n0 = tn * BN;
-    const int lr = t >> 2, lk = (t & 3) * 4;
+    const int lr = slab_row<T2>(t), lk = slab_k<T2>(t);
     const bool row_ok = m0 + lr < rows;
     const int arw = row_ok ? m0 + lr : 0;
     const double *brow = g.Qt + (size_t)(n0 + lr) * g.kq;
 
-    v4d acc[2][2][2];
+    v4d acc[2][WT][WT];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < WT; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[p][a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < WT; ++b) acc[p][a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
 
     // one K block [kb, ke) of A row `arow` against Q row `brow`, into acc[blk]
-    auto kblock = [&](const double *arow, const double *bq, int kb, int ke, v4d(&ac)[2][2]) {
-        Slab sa, sb;
+    auto kblock = [&](const double *arow, const double *bq, int kb, int ke, v4d(&ac)[WT][WT]) {
+        Slab<T2> sa, sb;
         if (kb < ke) {
             load_rowk(sa, arow, kb + lk, row_ok);
             load_rowk(sb, bq, kb + lk, true);
@@ -192,7 +219,7 @@ __device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Sme
                 load_rowk(sa, arow, k0 + BK + lk, row_ok);
                 load_rowk(sb, bq, k0 + BK + lk, true);
             }
-            mma_slab(sm.As, sm.Bs, wm, wn, lane, ac);
+            mma_slab<T2>(sm.As, sm.Bs, wm, wn, lane, ac);
         }
     };
     if (FOLD) {
@@ -212,9 +239,9 @@ __device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Sme
     const size_t pstride = (size_t)n_r * n_ang, fld = (size_t)g.n_patches * pstride;
     const int n_angp = g.n_angp;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < WT; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < WT; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int rr = m0 + wm + a * 16 + out_row(lane, r);
@@ -237,14 +264,14 @@ __device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Sme
 // grid: x = column tile (E tiles then O tiles), y = row tile, z = K split
 template <typename T, bool FOLD>
 __global__ __launch_bounds__(256) void k_gemm1(F64Args g) {
-    __shared__ Smem sm;
+    __shared__ Smem<T1> sm;
     gemm1_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, sm);
 }
 
 // grid: x = row tile, y = angular tile
 template <typename T, bool FOLD>
 __global__ __launch_bounds__(256) void k_gemm2(F64Args g) {
-    __shared__ Smem sm;
+    __shared__ Smem<T2> sm;
     gemm2_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, sm);
 }
 
@@ -261,7 +288,7 @@ __device__ __forceinline__ int next_item(int *head, int *slot) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_gemm1(const F64Args *__restrict__ args,
                                                      const BatchItem *__restrict__ items, int n_items, int *head) {
-    __shared__ Smem sm;
+    __shared__ Smem<T1> sm;
     __shared__ int slot;
     for (;;) {
         const int it = next_item(head, &slot);
@@ -277,7 +304,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_batch_gemm2(const F64Args *__restrict__ args,
                                                      const BatchItem *__restrict__ items, int n_items, int *head,
                                                      BatchTrack track) {
-    __shared__ Smem sm;
+    __shared__ Smem<T2> sm;
     __shared__ int slot;
     for (int prev = -1;;) {
         const int it = next_item_tracked(head, &slot, track, prev);
@@ -311,8 +338,8 @@ F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io
     g.kang = pp2 ? p.n2() : p.kang();
     g.nq = pp2 ? p.nq() : 1;
     g.kq = pp2 ? p.kq() : p.np;
-    g.tiles_e = p.fold ? (p.ne_p + BN - 1) / BN : (p.np + BN - 1) / BN;
-    g.tiles_o = p.fold ? (p.no_p + BN - 1) / BN : 0;
+    g.tiles_e = p.fold ? (p.ne_p + T1 - 1) / T1 : (p.np + T1 - 1) / T1;
+    g.tiles_o = p.fold ? (p.no_p + T1 - 1) / T1 : 0;
     g.kchunk = ((p.kang() / p.splitk + BK - 1) / BK) * BK;
     g.splitk = p.splitk;
     g.Ut = p.Ut;
@@ -324,7 +351,7 @@ F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io
 
 hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
     F64Args g = f64_args(p, n_fields, rho, nullptr, rho_dtype);
-    dim3 grid(g.tiles_e + g.tiles_o, (g.rows + BM - 1) / BM, p.splitk);
+    dim3 grid(g.tiles_e + g.tiles_o, (g.rows + T1 - 1) / T1, p.splitk);
     if (rho_dtype == MPG_F64) {
         if (p.fold) hipLaunchKernelGGL((k_gemm1<double, true>), grid, dim3(256), 0, p.stream, g);
         else hipLaunchKernelGGL((k_gemm1<double, false>), grid, dim3(256), 0, p.stream, g);
@@ -337,7 +364,7 @@ hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype
 
 hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     F64Args g = f64_args(p, n_fields, nullptr, phi, phi_dtype, true);
-    dim3 grid((g.rows + BM - 1) / BM, g.kang / BN);
+    dim3 grid((g.rows + T2 - 1) / T2, g.kang / T2);
     if (phi_dtype == MPG_F64) {
         if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true>), grid, dim3(256), 0, p.stream, g);
         else hipLaunchKernelGGL((k_gemm2<double, false>), grid, dim3(256), 0, p.stream, g);

@@ -19,7 +19,8 @@ void set_error(const std::string &msg);
 
 // Tile constants shared by the plan layout and the kernels.
 constexpr int kSplitTile = 128;  // split-BF16 GEMM tiles are kSplitTile x kSplitTile
-constexpr int kF64Tile = 64;     // FP64 GEMM tiles are kF64Tile x kF64Tile
+constexpr int kF64Tile1 = 128;   // FP64 GEMM1 tiles are kF64Tile1 x kF64Tile1
+constexpr int kF64Tile2 = 64;    // FP64 GEMM2 tiles are kF64Tile2 x kF64Tile2
 constexpr int kColPad = 32;    // each m-parity column block is padded to this
 constexpr int kColSlack = 128; // zero rows after the last column block
 constexpr int kAngPad = 128;   // angular dimension padded to this
