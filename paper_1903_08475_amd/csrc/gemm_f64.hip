@@ -24,6 +24,7 @@ namespace mpg {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 16;
 constexpr int T1 = kF64Tile1, T2 = kF64Tile2;  // GEMM1 / GEMM2 tile sides
@@ -73,6 +74,22 @@ __device__ inline void load_rho(Slab<TS> &s, const T *r0, const T *r1, int k, in
         const int gp = k / n_angp;
         r0 += gp * pstride;
         k -= gp * n_angp;
+    }
+    if (sizeof(T) == 4 && (n_ang & 3) == 0) {
+        // FP32 rows whose length is a multiple of 4: groups of four K (16-byte
+        // aligned; k is a multiple of 4) lie wholly inside or outside the row
+#pragma unroll
+        for (int q = 0; q < Slab<TS>::kPer; q += 4) {
+            f32x4 a = {0.f, 0.f, 0.f, 0.f}, b = a;
+            if (row_ok && k + q < n_ang) {
+                a = *(const f32x4 *)(r0 + k + q);
+                if (FOLD) b = *(const f32x4 *)(r1 + k + q);
+            }
+            const double av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s.v[q + u] = FOLD ? (odd ? av[u] - bv[u] : av[u] + bv[u]) : av[u];
+        }
+        return;
     }
 #pragma unroll
     for (int q = 0; q < Slab<TS>::kPer; ++q) {
