@@ -602,8 +602,8 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.row_tiles = p.row_tiles();
     g.ks1 = p.kang() / TK;
     g.ks2 = p.kq() / TK;
-    g.six_e = p.six_e;
-    g.six_o = p.six_o;
+    g.six_e = expansion ? p.six2_e : p.six_e;
+    g.six_o = expansion ? p.six2_o : p.six_o;
     return g;
 }
 
