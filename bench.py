@@ -4,8 +4,7 @@ A step is one pass of the whole hot path (moment contraction, radial scans,
 expansion) over one batch of 8 snapshots of the large workload: Yin-Yang grid
 at pi/256 (128x384 cells per patch), 1200 log-spaced shells, lmax 48,
 float32 densities, split-BF16 contractions in the tiered form (three bf16
-products per product, six on the moments of degree <= 21 in the moment
-contraction and <= 15 in the expansion).  Inputs are
+products per product, six on the moments of degree <= 15).  Inputs are
 resident in HBM before the timed region starts.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -63,15 +62,15 @@ def traffic_record(stage, precision):
     return r.get("bytes_per_launch")
 
 
-TIER_LMAX = {"moments": 21, "expansion": 15}  # MPG_TIER_LMAX, MPG_TIER_LMAX_EXPANSION
+TIER_LMAX = {"moments": 15, "expansion": 15}  # MPG_TIER_LMAX
 
 
-def products_per_term(lmax, precision, blk=256, slab=32):
+def products_per_term(lmax, precision, blk=64, slab=32):
     """bf16 MFMA products per algorithmic product, averaged over the moment
     columns of the folded contractions (even and odd m blocks): six for the
     six-product form; for the tiered form six on the columns of a moment
-    contraction block of 256 columns (or an expansion K slab of 32) that
-    reaches into the stage's low-degree tier, else three."""
+    contraction wave tile of 64 columns (or an expansion K slab of 32) that
+    reaches into the low-degree tier, else three."""
     if precision != "split_bf16_tiered":
         return {"moments": 6.0, "expansion": 6.0}
     res = {}
@@ -288,9 +287,8 @@ def main():
     prods = products_per_term(grid.lmax, prec)
     desc = {"split_bf16": "six MFMA products per product",
             "split_bf16_tiered": (f"three MFMA products per product (h*h + h*m + m*h), six on the moments of "
-                                  f"degree <= {TIER_LMAX['moments']} in the moment contraction and <= "
-                                  f"{TIER_LMAX['expansion']} in the expansion ({prods['moments']:.2f} and "
-                                  f"{prods['expansion']:.2f} per product on average)")}
+                                  f"degree <= {TIER_LMAX['moments']} ({prods['moments']:.2f} per product on "
+                                  f"average)")}
 
     out = {
         "metric": METRIC,

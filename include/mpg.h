@@ -56,11 +56,8 @@ extern "C" {
                                  six bf16 products per product          */
 #define MPG_SPLIT_BF16_TIERED 2 /* as MPG_SPLIT_BF16 with three products
                                  (h*h, h*m, m*h) per product, six on the
-                                 moments of low degree (below)           */
-#define MPG_TIER_LMAX   21    /* six products up to this degree in the
-                                 moment contraction                      */
-#define MPG_TIER_LMAX_EXPANSION 15 /* ... and up to this degree in the
-                                 expansion                               */
+                                 moments of degree <= MPG_TIER_LMAX      */
+#define MPG_TIER_LMAX   15
 
 /* element types of rho / Phi */
 #define MPG_F64 0
@@ -98,12 +95,11 @@ typedef struct mpg_plan_s *mpg_plan_t;
  *                h + m + l (exact).  MPG_SPLIT_BF16 forms every product
  *                from the six piece products of weight >= 2^-18 of h*h.
  *                MPG_SPLIT_BF16_TIERED keeps those six for the moments of
- *                degree l <= MPG_TIER_LMAX in the moment contraction (and
- *                the others that share their 256-column moment tile) and
- *                l <= MPG_TIER_LMAX_EXPANSION in the expansion (and the
- *                others that share their 32-moment K slab), and uses the
- *                three products h*h + h*m + m*h (16-bit operands) for the
- *                rest: about 43% less MFMA work at lmax 48.  Its potential stays
+ *                degree l <= MPG_TIER_LMAX (and the others that share their
+ *                64-column wave tile in the moment contraction or their
+ *                32-moment K slab in the expansion) and uses the three
+ *                products h*h + h*m + m*h (16-bit operands) for the rest:
+ *                about 45% less MFMA work at lmax 48.  Its potential stays
  *                within 1e-6 (max-norm relative) of the FP64 result on the
  *                test workloads; its moments B and M of high degree carry
  *                errors of a few 1e-6 of max|B|.

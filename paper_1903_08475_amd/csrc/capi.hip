@@ -253,24 +253,20 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
         return rc;
     }
     if (precision == MPG_SPLIT_BF16_TIERED) {
-        // leading columns of each block up to degree lt (columns keep the
-        // order of the real index inside a block), rounded up to K slabs
-        auto tier = [&](int lt, int &se, int &so) {
-            int ce = 0, co = 0;
-            for (int l = 0; l <= lmax && l <= lt; ++l)
-                for (int m = 0; m <= l; ++m) {
-                    const int c = m == 0 ? 1 : 2;
-                    if (!p->fold || m % 2 == 0) ce += c;
-                    else co += c;
-                }
-            se = std::min(roundup(ce, kSlabK), p->ne_p);
-            so = std::min(roundup(co, kSlabK), p->no_p);
-        };
-        tier(MPG_TIER_LMAX, p->six_e, p->six_o);
-        tier(MPG_TIER_LMAX_EXPANSION, p->six2_e, p->six2_o);
+        // leading columns of each block up to degree MPG_TIER_LMAX (columns
+        // keep the order of the real index inside a block), rounded up to K slabs
+        int ce = 0, co = 0;
+        for (int l = 0; l <= lmax && l <= MPG_TIER_LMAX; ++l)
+            for (int m = 0; m <= l; ++m) {
+                const int c = m == 0 ? 1 : 2;
+                if (!p->fold || m % 2 == 0) ce += c;
+                else co += c;
+            }
+        p->six_e = std::min(roundup(ce, kSlabK), p->ne_p);
+        p->six_o = std::min(roundup(co, kSlabK), p->no_p);
     } else {
-        p->six_e = p->six2_e = p->ne_p;
-        p->six_o = p->six2_o = p->no_p;
+        p->six_e = p->ne_p;
+        p->six_o = p->no_p;
     }
     if (p->split()) {
         // tile-slab blocks; rows past the last field stay zero (finite)

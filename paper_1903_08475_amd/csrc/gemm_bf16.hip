@@ -9,8 +9,8 @@
 // tiered form keeps the six for the leading (low-degree) columns of each
 // m-parity block (six_e, six_o) and forms the others from the three
 // products of weight >= 2^-9, ah*bh + ah*bm + am*bh, i.e. with 16-bit
-// operands h + m: whole GEMM1 blocks of 256 moment columns, and whole K
-// slabs of GEMM2, take one form or the other.  GEMM1's
+// operands h + m: whole GEMM1 wave tiles of 64 moment columns, and whole
+// K slabs of GEMM2, take one form or the other.  GEMM1's
 // FP32 accumulators are flushed into FP64 registers every kFlushSlabs K
 // slabs, so no FP32 sum runs over more than kFlushSlabs*32 terms (GEMM2's K
 // is the moment count, short enough for FP32 sums).
@@ -278,11 +278,11 @@ __device__ __forceinline__ void ring_barrier() {
 // all with three.
 template <int NA, int NB, bool FLUSH, bool SIX>
 __device__ __forceinline__ void ring_phase(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
-                                           int dk, int t0, int t1, int last, int n3, int wm, int wn, int lane,
+                                           int dk, int t0, int t1, int last, int n3_load, int wm, int wn, int lane,
                                            v16f (&acc)[2][2], double (&acc64)[2][2][16]) {
 #define RING_STEP(CUR, NXT, O)                                       \
     ring_barrier<0>();                                               \
-    load_slab(NXT, L, k0 + min(t + O + 1, last) * dk, t + O + 1 >= n3); \
+    load_slab(NXT, L, k0 + min(t + O + 1, last) * dk, t + O + 1 >= n3_load); \
     if (t + O < t1) mma_slab<NA, NB, SIX>(CUR, wm, wn, lane, acc);
     for (int s = t0; s < t1; s += kFlushSlabs) {
 #pragma unroll
@@ -308,8 +308,9 @@ __device__ __forceinline__ void ring_phase(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1,
 
 // Multiplies nsl consecutive K slabs of the block into acc through the two
 // buffers S0, S1.  Slab t is block k0 + t*dk of the tiles (dk = +-1); slabs
-// t < n3 take three products (their copies skip the l pieces), the others
-// six; n3 is even or nsl, so slab n3 always lands in S0.  Each step waits
+// t < n3 take three products, the others six; the copies of slabs
+// t < n3_load skip the l pieces (n3_load <= n3).  n3 is even or nsl, so
+// slab n3 always lands in S0.  Each step waits
 // for the one copy in flight (its slab), then, once every wave is past the
 // barrier, copies the next slab into the buffer the previous step read;
 // past the end it copies the last slab again (same addresses, cache hits),
@@ -317,17 +318,19 @@ __device__ __forceinline__ void ring_phase(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1,
 // after every kFlushSlabs slabs of a phase and at the end.  A group of
 // kFlushSlabs slabs is unrolled in full so the compiler can tell which
 // buffer every LDS read and copy touches (and adds no wait of its own).
-// Every wave must call it with the same arguments; on return all copies
-// have landed, and the buffers may be refilled after a barrier.
+// Every wave must call it with the same k0, dk, nsl and n3_load; n3 may
+// differ between waves when it is 0 or nsl (each wave then runs nsl steps,
+// rounded up to even, and as many barriers).  On return all copies have
+// landed, and the buffers may be refilled after a barrier.
 template <int NA, int NB, bool FLUSH>
 __device__ __forceinline__ void run_ring(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
-                                         int dk, int nsl, int n3, int wm, int wn, int lane, v16f (&acc)[2][2],
-                                         double (&acc64)[2][2][16]) {
+                                         int dk, int nsl, int n3, int n3_load, int wm, int wn, int lane,
+                                         v16f (&acc)[2][2], double (&acc64)[2][2][16]) {
     if (nsl <= 0) return;
     const int last = nsl - 1;
-    load_slab(S0, L, k0, n3 == 0);
-    ring_phase<NA, NB, FLUSH, false>(S0, S1, L, k0, dk, 0, n3, last, n3, wm, wn, lane, acc, acc64);
-    ring_phase<NA, NB, FLUSH, true>(S0, S1, L, k0, dk, n3, nsl, last, n3, wm, wn, lane, acc, acc64);
+    load_slab(S0, L, k0, n3_load == 0);
+    ring_phase<NA, NB, FLUSH, false>(S0, S1, L, k0, dk, 0, n3, last, n3_load, wm, wn, lane, acc, acc64);
+    ring_phase<NA, NB, FLUSH, true>(S0, S1, L, k0, dk, n3, nsl, last, n3_load, wm, wn, lane, acc, acc64);
     // the trailing copy lands before anyone may reuse or free the LDS
     asm volatile("" ::: "memory");
     MPG_WAIT_VM(0);
@@ -385,10 +388,12 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
-    // six products when the block's first column lies in its parity block's tier
+    // six products for a wave whose first column lies in its parity block's
+    // tier; the block copies the l pieces when any of its waves needs them
     const int cl = odd ? 2 * (tn - pe) * TB : 2 * tn * TB;
-    const bool six = cl < (odd ? g.six_o : g.six_e);
-    run_ring<1, 2, true>(S0, S1, L, kbeg / TK, 1, nsl, six ? 0 : nsl, wm, wn, lane, acc, acc64);
+    const int six_par = odd ? g.six_o : g.six_e;
+    const bool six_b = cl < six_par, six_w = cl + wn < six_par;
+    run_ring<1, 2, true>(S0, S1, L, kbeg / TK, 1, nsl, six_w ? 0 : nsl, six_b ? 0 : nsl, wm, wn, lane, acc, acc64);
 
     double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
@@ -432,14 +437,14 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     constexpr bool pp = !FOLD && PP;  // per-patch method: g.nq moment sets
     if (FOLD) {
         const int ne = ne_p / TK, no = (np - ne_p) / TK;
-        run_ring<2, 1, false>(S0, S1, L, ne - 1, -1, ne, three_slabs(ne, g.six_e / TK), wm, wn, lane, acc_e, acc64);
+        const int e3 = three_slabs(ne, g.six_e / TK), o3 = three_slabs(no, g.six_o / TK);
+        run_ring<2, 1, false>(S0, S1, L, ne - 1, -1, ne, e3, e3, wm, wn, lane, acc_e, acc64);
         // the odd block refills buffers the even block's last slabs were read from
         __syncthreads();
-        run_ring<2, 1, false>(S0, S1, L, ne + no - 1, -1, no, three_slabs(no, g.six_o / TK), wm, wn, lane, acc_o,
-                              acc64);
+        run_ring<2, 1, false>(S0, S1, L, ne + no - 1, -1, no, o3, o3, wm, wn, lane, acc_o, acc64);
     } else if (!pp) {
-        const int ns = g.ks2;
-        run_ring<2, 1, false>(S0, S1, L, ns - 1, -1, ns, three_slabs(ns, g.six_e / TK), wm, wn, lane, acc_e, acc64);
+        const int ns = g.ks2, n3 = three_slabs(ns, g.six_e / TK);
+        run_ring<2, 1, false>(S0, S1, L, ns - 1, -1, ns, n3, n3, wm, wn, lane, acc_e, acc64);
     } else {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -447,11 +452,10 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
-        const int nsb = np / TK;
+        const int nsb = np / TK, n3 = three_slabs(nsb, g.six_e / TK);
         for (int gq = 0; gq < g.nq; ++gq) {
             if (gq) __syncthreads();
-            run_ring<2, 1, false>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, three_slabs(nsb, g.six_e / TK), wm, wn,
-                                  lane, acc_e, acc64);
+            run_ring<2, 1, false>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, n3, n3, wm, wn, lane, acc_e, acc64);
             // each patch's moment set is summed in FP32 (as the single set
             // of the other forms) and added in FP64
 #pragma unroll
@@ -602,8 +606,8 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.row_tiles = p.row_tiles();
     g.ks1 = p.kang() / TK;
     g.ks2 = p.kq() / TK;
-    g.six_e = expansion ? p.six2_e : p.six_e;
-    g.six_o = expansion ? p.six2_o : p.six_o;
+    g.six_e = p.six_e;
+    g.six_o = p.six_o;
     return g;
 }
 

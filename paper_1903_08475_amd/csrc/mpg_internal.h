@@ -68,10 +68,9 @@ struct Plan {
     int n_e = 0, n_o = 0, ne_p = 0, no_p = 0, np = 0, np_alloc = 0;
     int n_angp = 0;            // n_ang padded to kAngPad
     // split forms: leading columns of the even / odd block (multiples of
-    // kSlabK) whose products take all six bf16 piece products in the moment
-    // contraction (six_*) and in the expansion (six2_*); the other columns
-    // take three (all columns for MPG_SPLIT_BF16)
-    int six_e = 0, six_o = 0, six2_e = 0, six2_o = 0;
+    // kSlabK) whose products take all six bf16 piece products; the other
+    // columns take three (all columns for MPG_SPLIT_BF16)
+    int six_e = 0, six_o = 0;
     // patch blocks of the contractions: 1 under the fold (and for one
     // patch), n_patches on the general path, whose GEMM1 K and GEMM2 N run
     // over the cells of every patch, patch after patch (kang = npat*n_angp)

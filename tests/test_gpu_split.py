@@ -62,8 +62,8 @@ def test_split_moments_match_oracle(precision):
 
 
 def test_tiered_form_changes_only_the_degrees_above_its_tier():
-    """Moments of degree <= 21 come out of the tiered form's six-product
-    blocks and equal the six-product form's bit for bit; above the tier the
+    """Moments of degree <= 15 come out of the tiered form's six-product
+    wave tiles and equal the six-product form's bit for bit; above the tier the
     three-product rounding shows, and stays within its bound: each product
     a*b is formed to within 3.02*2^-16 |a||b| (the dropped piece products),
     plus the FP32 accumulation of at most 512 terms between FP64 flushes."""
@@ -74,7 +74,7 @@ def test_tiered_form_changes_only_the_degrees_above_its_tier():
     B6, _ = mpg.Plan(g, precision="split_bf16").moments(t)
     BT, _ = mpg.Plan(g, precision="split_bf16_tiered").moments(t)
     B6, BT = B6[0].cpu().numpy(), BT[0].cpu().numpy()
-    low = 22 * 22  # real columns of degree <= 21
+    low = 16 * 16  # real columns of degree <= 15
     assert np.array_equal(B6[:, :low], BT[:, :low])
     assert np.abs(B6[:, low:] - BT[:, low:]).max() > 0.0
     # bound per entry: sum over cells of |rho_fold| |U| times the per-product
