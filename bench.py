@@ -247,6 +247,8 @@ def main():
     ap.add_argument("--precision", default="split_bf16_tiered", choices=["split_bf16_tiered", "split_bf16"],
                     help="split form of the timed step (the other one is timed beside it)")
     ap.add_argument("--no-other-split", action="store_true", help="skip timing the other split form")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the plans' default K split and scan schedule instead of autotuning them")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-patch comparison method")
     ap.add_argument("--batch", action="store_true",
                     help="also time the 64-field uneven batch (one batched call per precision)")
@@ -282,6 +284,11 @@ def main():
     other = "split_bf16" if prec == "split_bf16_tiered" else "split_bf16_tiered"
     log(f"[bench] building {prec} plan")
     plan = mpg.Plan(grid, precision=prec, max_fields=n)
+    tuned = None
+    if not args.no_autotune:
+        sk, ch = plan.autotune(rho)
+        tuned = {"gemm1_splitk": sk, "scan_chunks": ch}
+        log(f"[bench] autotuned: K split {sk}, scan chunks {ch}")
     ms, wall, stages, pct = time_path(plan, rho, phi, args.steps, args.warmup)
     log(f"[bench] {prec}: {ms:.3f} ms/step ({pct}); stages {stages}")
     prods = products_per_term(grid.lmax, prec)
@@ -315,6 +322,7 @@ def main():
             "precision": (f"{prec}: three bf16 pieces per operand, {desc[prec]}, FP32 accumulate, "
                           "FP64 flush, FP64 tables and scans"),
             "parallelism": "single GPU",
+            "autotuned": tuned,
         },
     }
 
@@ -341,6 +349,8 @@ def main():
     if not args.no_other_split:
         log(f"[bench] {other} on the same workload")
         po = mpg.Plan(grid, precision=other, max_fields=n)
+        if not args.no_autotune:
+            po.autotune(rho)
         phi_other = torch.empty_like(rho)
         ms_o, _, st_o, _ = time_path(po, rho, phi_other, args.steps, 1)
         out["other_split_form"] = {
@@ -357,6 +367,8 @@ def main():
         log("[bench] FP64 path on the same workload")
         ref = torch.empty_like(rho, dtype=torch.float64)
         plan64 = mpg.Plan(grid, precision="fp64", max_fields=n)
+        if not args.no_autotune:
+            plan64.autotune(rho)
         ms64, _, st64, _ = time_path(plan64, rho, ref, args.fp64_steps, 1)
         plan.potential(rho, out=phi)
         torch.cuda.synchronize()
@@ -379,6 +391,8 @@ def main():
         # frame, potentials of the patches added (same result up to rounding)
         log(f"[bench] per-patch comparison method ({prec})")
         pp = mpg.Plan(grid, precision=prec, max_fields=n, method="per_patch")
+        if not args.no_autotune:
+            pp.autotune(rho)
         phi_pp = torch.empty_like(rho)
         ms_pp, _, st_pp, _ = time_path(pp, rho, phi_pp, args.fp64_steps, 1)
         plan.potential(rho, out=phi)
