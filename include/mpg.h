@@ -88,7 +88,7 @@ typedef struct mpg_plan_s *mpg_plan_t;
 /* Build a plan: validate the grid, upload its geometry and build the FP64
  * tables U, Q, the overlap weights (Sec. 4.2, w_jk = 1 - alpha_jk/2, when
  * overlap_w is NULL) and the radial recurrence coefficients on the device
- * (Sec. 4.3 step 1), plus their split-BF16 copies for MPG_SPLIT_BF16.
+ * (Sec. 4.3 step 1), plus their split-BF16 copies for the split forms.
  *   lmax       : truncation degree, 0 <= lmax <= 64
  *   precision  : MPG_FP64, MPG_SPLIT_BF16 or MPG_SPLIT_BF16_TIERED.  The
  *                split forms write each FP32 operand as three bf16 pieces
