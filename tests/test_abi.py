@@ -51,6 +51,8 @@ def test_plan_rejects_bad_grids_on_host():
     assert L.mpg_plan(ctypes.byref(s), -1, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
     assert L.mpg_plan(ctypes.byref(s), 8, 7, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
     assert L.mpg_plan(ctypes.byref(s), 8, 0, 0, None, ctypes.byref(h)) == mpg.MPG_EINVAL
+    assert L.mpg_plan(ctypes.byref(s), 65, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL  # lmax above 64
+    assert L.mpg_plan_method(ctypes.byref(s), 8, 0, 1, 2, None, ctypes.byref(h)) == mpg.MPG_EINVAL  # method
     bad = r.copy()
     bad[5] = bad[4]
     s.r_edges = bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

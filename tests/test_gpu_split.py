@@ -4,6 +4,8 @@ FP64 scans) with the CPU oracle and with the FP64 GPU path.  Bar: 1e-6
 max-norm relative error of Phi.  Moments: 1e-6 for the six-product form;
 the tiered form's moments of degree above the tier carry the three-product
 rounding (each product within 3*2^-16 of |a||b|), checked at 1e-5."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -106,6 +108,26 @@ def test_split_float32_fields_batched(precision):
         M = O.radial(g, g.lmax, O.moments(g, g.lmax, U, rhos[f].astype(np.float64)))
         phi = O.expand(g, g.lmax, Q, M)
         assert rel_err(out[f], phi) < TOL_SPLIT
+
+
+@functools.lru_cache(maxsize=1)
+def largest_degree_case():
+    g = W.yinyang(16, W.geometric_edges(5, 1.3), 64, name="lmax64")
+    rho = W.random_rho(g, 64)
+    phi, *_ = O.potential(g, g.lmax, rho, O.overlap_weights(g))
+    return g, rho, phi
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("split_bf16_tiered", TOL_SPLIT)])
+def test_largest_degree(precision, tol):
+    """lmax 64, the largest the plan accepts (4225 moments, ragged column
+    blocks), on config 1's angular grid with a few shells."""
+    torch, mpg = torch_mods()
+    g, rho, phi = largest_degree_case()
+    out = mpg.Plan(g, precision=precision).potential(torch.tensor(rho, device="cuda")).cpu().numpy()
+    err = rel_err(out, phi)
+    print(f"lmax 64 {precision}: vs oracle {err:.3e}")
+    assert err < tol
 
 
 def test_split_zero_density():
