@@ -178,11 +178,12 @@ int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho,
  * and dtype), MPG_EDEVICE. */
 int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms);
 
-/* Autotune the plan for n_fields fields: time the moment contraction for
- * every K split the work space allows (powers of two and the default
- * choice) and the radial scan for 4, 8 and 16 shell chunks per column, on
- * the given device input, and keep the fastest for later calls (including
- * mpg_potential_batch).  Blocks until done; overwrites the plan's work
+/* Autotune the plan for n_fields fields: time the moment contraction and
+ * the radial scan that reduces its partial sums for every K split the work
+ * space allows (the default choice first, then powers of two; another
+ * split is kept only when it is at least 1% faster), then the radial scan
+ * for 4, 8 and 16 shell chunks per column, on the given device input, and
+ * keep the choices for later calls (including mpg_potential_batch).  Blocks until done; overwrites the plan's work
  * space.  splitk and chunks (may be NULL) receive the choices.
  * Errors: as mpg_moments. */
 int mpg_autotune(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,

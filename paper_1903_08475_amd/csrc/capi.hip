@@ -409,7 +409,7 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
         q.splitk = sk;
         q.scan_chunks = ch;
         float best = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {  // first run is a warm-up
+        for (int rep = 0; rep < 4; ++rep) {  // first run is a warm-up
             hipError_t err;
             if ((err = hipEventRecord(a, q.stream)) != hipSuccess) return err;
             if (scan) err = radial_scan(q, n_fields, split);
@@ -429,18 +429,22 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
         (void)hipEventDestroy(b);
         return hip_fail(e, "mpg_autotune");
     }
-    // K splits: powers of two up to the work space, plus the heuristic choice
+    // K splits: the heuristic choice, then powers of two up to the work
+    // space; each timed as the moment contraction plus the scan that reduces
+    // its partial sums, and kept only when it beats the best so far by 1%
     std::vector<int> cands;
     p->splitk_sel = 0;
     int heur = choose_splitk(*p, n_fields);
-    for (int s = 1; s <= p->splitk; s *= 2) cands.push_back(s);
-    if (std::find(cands.begin(), cands.end(), heur) == cands.end()) cands.push_back(heur);
+    cands.push_back(heur);
+    for (int s = 1; s <= p->splitk; s *= 2)
+        if (s != heur) cands.push_back(s);
     int best_s = heur;
     float best_t = 1e30f;
     for (int s : cands) {
-        float t;
+        float t, ts;
         if ((e = time_stage(s, p->scan_chunks, false, &t)) != hipSuccess) break;
-        if (t < best_t) { best_t = t; best_s = s; }
+        if ((e = time_stage(s, p->scan_chunks, true, &ts)) != hipSuccess) break;
+        if (t + ts < 0.99f * best_t) { best_t = t + ts; best_s = s; }
     }
     int best_c = p->scan_chunks;
     if (e == hipSuccess) {
