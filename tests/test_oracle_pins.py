@@ -368,3 +368,62 @@ def test_per_patch_overlap_weights_scale_each_patch_own_rows():
     Us, _ = O.tables(g, 6, w[0])
     Ue, _ = O.tables(g, 6, np.stack([w[0], w[0]]))
     assert np.array_equal(Us, Ue)
+
+
+# --- convergence of the Yin-Yang discretisation (Sec. 4.2, Sec. 5) --------------
+
+def _global_harmonic(l, m, kind, R):
+    """s_lm P_l^m(cos theta) {cos, sin}(m phi) in global angles, for a density
+    given in the Yin frame (x_global = R x_Yin); P_l^m from scipy, with the
+    Condon-Shortley phase."""
+    s = math.sqrt(math.factorial(l - m) / math.factorial(l + m))
+
+    def f(x, y, z, xp):
+        import torch
+        X = R[0, 0] * x + R[0, 1] * y + R[0, 2] * z
+        Y = R[1, 0] * x + R[1, 1] * y + R[1, 2] * z
+        Z = R[2, 0] * x + R[2, 1] * y + R[2, 2] * z
+        ct = (Z / torch.sqrt(X * X + Y * Y + Z * Z)).numpy()
+        ph = torch.atan2(Y, X).numpy()
+        return torch.from_numpy(s * lpmv(m, l, ct) * (np.cos(m * ph) if kind == "c" else np.sin(m * ph)))
+    return f
+
+
+def test_yinyang_weights_converge_to_orthogonality():
+    """Moments of a cell-averaged real harmonic on the Yin-Yang grid tend to
+    4 pi/(2l+1) in its own column and zero elsewhere (orthogonality of the
+    Y_lm, Eqs. A_lm_mult/B_lm_mult with the overlap weights); the error falls
+    about four-fold per halving of the cell size."""
+    L = 5
+    cases = [(0, 0, "c"), (1, 0, "c"), (2, 1, "c"), (3, 2, "s"), (4, 3, "c"), (5, 1, "s")]
+    errs = []
+    for k in (8, 16):
+        g = W.yinyang(k, W.uniform_edges(1), L)
+        R = O.rotation(*g.euler[0])
+        U, _ = O.tables(g, L, O.overlap_weights(g), want_Q=False)
+        err = 0.0
+        for l, m, kind in cases:
+            B = O.moments(g, L, U, W.cell_average(g, _global_harmonic(l, m, kind, R), sub=4))[0]
+            ref = np.zeros_like(B)
+            ref[l * l if m == 0 else l * l + 2 * m - (kind == "c")] = 4 * math.pi / (2 * l + 1)
+            err = max(err, np.abs(B - ref).max())
+        errs.append(err)
+    assert errs[0] < 0.15 and errs[1] < 0.04 and errs[0] / errs[1] > 3.0, errs
+
+
+def test_one_patch_and_yinyang_agree_for_smooth_density():
+    """The same smooth density on a one-patch polar grid and on the Yin-Yang
+    grid at the same cell size gives radial sums M that agree to O(Delta^2)."""
+    L = 8
+    blobs = W.Blobs(np.array([[0.3, -0.2, 0.25], [-0.35, 0.1, -0.3]]), np.array([0.25, 0.3]), np.array([1.0, 0.7]))
+    edges = W.uniform_edges(6)
+    diffs = []
+    for k in (8, 16):
+        yy = W.yinyang(k, edges, L)
+        po = W.polar(2 * k, 4 * k, edges, L, frame=O.rotation(*yy.euler[0]).T)
+        M = []
+        for g, w in ((yy, O.overlap_weights(yy)), (po, None)):
+            U, _ = O.tables(g, L, w, want_Q=False)
+            M.append(O.radial(g, L, O.moments(g, L, U, W.cell_average(g, blobs, sub=4))))
+        diffs.append(np.abs(M[0] - M[1]).max() / np.abs(M[1]).max())
+    assert diffs[0] < 1e-3 and diffs[1] < 2.5e-4 and diffs[0] / diffs[1] > 3.0, diffs
