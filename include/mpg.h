@@ -182,7 +182,7 @@ int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms)
  * the radial scan that reduces its partial sums for every K split the work
  * space allows (the default choice first, then powers of two; another
  * split is kept only when it is at least 1% faster), then the radial scan
- * for 4, 8 and 16 shell chunks per column, on the given device input, and
+ * for 4, 8, 12 and 16 shell chunks per column, on the given device input, and
  * keep the choices for later calls (including mpg_potential_batch).  Blocks until done; overwrites the plan's work
  * space.  splitk and chunks (may be NULL) receive the choices.
  * Errors: as mpg_moments. */

@@ -139,9 +139,9 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return q[a].np > q[c].np; });
     for (int f : order) {
         const Plan &p = q[f];
-        // the split GEMM2 takes row tiles in pairs
-        const int rt = split ? (p.n_r + 2 * T2 - 1) / (2 * T2) : (p.n_r + T2 - 1) / T2;
-        const int at = p.n2() / T2;
+        // the split GEMM2 takes angular tiles in pairs
+        const int rt = (p.n_r + T2 - 1) / T2;
+        const int at = split ? (p.n2() / T2 + 1) / 2 : p.n2() / T2;
         for (int a = 0; a < at; ++a)
             for (int m = 0; m < rt; ++m) i2.push_back({f, m, a, 0});
     }

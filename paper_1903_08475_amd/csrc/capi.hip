@@ -452,7 +452,7 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
         float tc = 1e30f;
         if ((e = time_stage(best_s, 16, false, &tc)) == hipSuccess) {  // leave matching partials in place
             tc = 1e30f;
-            for (int ch : {4, 8, 16}) {
+            for (int ch : {4, 8, 12, 16}) {
                 if (ch > p->n_r && ch != 4) continue;
                 float t;
                 if ((e = time_stage(best_s, ch, true, &t)) != hipSuccess) break;

@@ -25,8 +25,9 @@
 // to the smallest partial sums last.
 //
 // Tiles: GEMM1 128x256 (rows x moment columns: two column tiles, so every
-// rho+- slab serves 256 columns), GEMM2 256x128 (two row tiles x one
-// angular tile); 512 threads = 8 waves of 64x64 (2x2 MFMA blocks of 32x32,
+// rho+- slab serves 256 columns), GEMM2 128x256 (one row tile x two
+// angular tiles: consecutive blocks share the Q tiles, and each M row tile
+// is read once per 256 angular cells); 512 threads = 8 waves of 64x64 (2x2 MFMA blocks of 32x32,
 // two waves per SIMD); K slabs of 32.  A slab of a block (both operands,
 // three pieces, 72 KB) is copied from global memory straight into LDS by
 // global_load_lds_dwordx4 (no staging registers) into two slab buffers
@@ -345,8 +346,9 @@ __device__ __forceinline__ int three_slabs(int nsl, int six_sl) {
     return n3 == nsl ? n3 : (n3 & ~1);
 }
 
-typedef SlabT<1, 2> Slab1;  // GEMM1: 128 rows of rho+-, 256 columns of U
-typedef SlabT<2, 1> Slab2;  // GEMM2: 256 rows of M, 128 angular cells of Q
+// 128 rows of rho+- and 256 columns of U (GEMM1), or 128 rows of M and 256
+// angular cells of Q (GEMM2)
+typedef SlabT<1, 2> Slab1;
 
 // ---------------------------------------------------------------------------
 // One output block of GEMM1: column pair tn (two 128-column tiles; pairs of
@@ -408,25 +410,25 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
             }
 }
 
-// One output block of GEMM2 (row pair tm: two 128-row tiles; angular tile
-// tn): the even-m K block into acc_e, then the odd-m block into acc_o, each
+// One output block of GEMM2 (row tile tm; angular tile pair tn: two
+// 128-cell tiles): the even-m K block into acc_e, then the odd-m block into acc_o, each
 // walked from its top slab down; per-patch method: the moment sets of the
 // patches one after the other, each flushed into FP64.
 template <typename T, bool FOLD, bool PP>
-__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Slab2 &S0, Slab2 &S1) {
+__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Slab1 &S0, Slab1 &S1) {
     T *phi = (T *)g.phi;
     const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = (wave & 3) * 64, wn = (wave >> 2) * 64;
-    const int m0 = tm * 2 * TB, n0 = tn * TB;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const int m0 = tm * TB, n0 = tn * 2 * TB;
+    const int n_cols = g.kang;  // angular cells of all output patches (tiles of TB)
 
-    LoaderT<2, 1> L;
+    LoaderT<1, 2> L;
     const size_t tstride = (size_t)g.ks2 * 3 * kBlk;
-    const int rt_used = (rows + TB - 1) / TB;  // row tiles holding this call's rows
-    L.a[0] = g.M + (size_t)(2 * tm) * tstride;
-    L.a[1] = g.M + (size_t)min(2 * tm + 1, rt_used - 1) * tstride;  // past the end: rows never stored
-    L.b[0] = g.Q + (size_t)tn * tstride;
+    L.a[0] = g.M + (size_t)tm * tstride;
+    L.b[0] = g.Q + (size_t)(2 * tn) * tstride;
+    L.b[1] = g.Q + (size_t)min(2 * tn + 1, n_cols / TB - 1) * tstride;  // past the end: columns never stored
     L.part = wave * 512;
     L.lo = L.part + lane * 8;
 
@@ -438,13 +440,13 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     if (FOLD) {
         const int ne = ne_p / TK, no = (np - ne_p) / TK;
         const int e3 = three_slabs(ne, g.six_e / TK), o3 = three_slabs(no, g.six_o / TK);
-        run_ring<2, 1, false>(S0, S1, L, ne - 1, -1, ne, e3, e3, wm, wn, lane, acc_e, acc64);
+        run_ring<1, 2, false>(S0, S1, L, ne - 1, -1, ne, e3, e3, wm, wn, lane, acc_e, acc64);
         // the odd block refills buffers the even block's last slabs were read from
         __syncthreads();
-        run_ring<2, 1, false>(S0, S1, L, ne + no - 1, -1, no, o3, o3, wm, wn, lane, acc_o, acc64);
+        run_ring<1, 2, false>(S0, S1, L, ne + no - 1, -1, no, o3, o3, wm, wn, lane, acc_o, acc64);
     } else if (!pp) {
         const int ns = g.ks2, n3 = three_slabs(ns, g.six_e / TK);
-        run_ring<2, 1, false>(S0, S1, L, ns - 1, -1, ns, n3, n3, wm, wn, lane, acc_e, acc64);
+        run_ring<1, 2, false>(S0, S1, L, ns - 1, -1, ns, n3, n3, wm, wn, lane, acc_e, acc64);
     } else {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -455,7 +457,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
         const int nsb = np / TK, n3 = three_slabs(nsb, g.six_e / TK);
         for (int gq = 0; gq < g.nq; ++gq) {
             if (gq) __syncthreads();
-            run_ring<2, 1, false>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, n3, n3, wm, wn, lane, acc_e, acc64);
+            run_ring<1, 2, false>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, n3, n3, wm, wn, lane, acc_e, acc64);
             // each patch's moment set is summed in FP32 (as the single set
             // of the other forms) and added in FP64
 #pragma unroll
@@ -479,7 +481,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
                 int rr = m0 + wm + 32 * a + d_row(lane, r);
                 int kk = n0 + wn + 32 * b + (lane & 31);
                 const int gp = kk / n_angp, jk = kk - gp * n_angp;
-                if (rr >= rows || jk >= n_ang) continue;
+                if (rr >= rows || kk >= n_cols || jk >= n_ang) continue;
                 int f = rr / n_r, i = rr - f * n_r;
                 T *o = phi + f * fld + gp * pstride + (size_t)i * n_ang + jk;
                 double e = (double)acc_e[a][b][r];
@@ -496,7 +498,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 
 // ---------------------------------------------------------------------------
 // Grid launches for one plan: GEMM1 grid x = (column pair, row tile), z =
-// K split; GEMM2 grid x = row pair, y = angular tile.
+// K split; GEMM2 grid x = row tile, y = angular tile pair.
 // GEMM1's blocks in x run over (column pair, row tile), the pairs that take
 // six products first (they take about twice as long as the others), so the
 // long blocks are dispatched before the short ones.
@@ -523,7 +525,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm1(SplitArgs g) {
 
 template <typename T, bool FOLD, bool PP>
 __global__ __launch_bounds__(kThreads) void k_gemm2(SplitArgs g) {
-    __shared__ Slab2 s0, s1;
+    __shared__ Slab1 s0, s1;
     gemm2_tile<T, FOLD, PP>(g, blockIdx.x, blockIdx.y, s0, s1);
 }
 
@@ -559,7 +561,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_batch_gemm2(const SplitArgs *__restrict__ args,
                                                           const BatchItem *__restrict__ items, int n_items,
                                                           int *head, BatchTrack track) {
-    __shared__ Slab2 s0, s1;
+    __shared__ Slab1 s0, s1;
     __shared__ int slot;
     for (int prev = -1;;) {
         const int it = next_item_tracked(head, &slot, track, prev);
@@ -641,7 +643,7 @@ hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtyp
 
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     SplitArgs g = split_args(p, n_fields, nullptr, phi, phi_dtype, true);
-    dim3 grid((g.rows + 2 * TB - 1) / (2 * TB), g.kang / TB);
+    dim3 grid((g.rows + TB - 1) / TB, (g.kang / TB + 1) / 2);
     if (phi_dtype == MPG_F64) {
         if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true, false>), grid, dim3(kThreads), 0, p.stream, g);
         else if (g.nq > 1) hipLaunchKernelGGL((k_gemm2<double, false, true>), grid, dim3(kThreads), 0, p.stream, g);

@@ -17,6 +17,7 @@ namespace mpg {
 namespace {
 
 constexpr int kLanes = 64, kMaxChunks = 16;
+constexpr int kGroup = 4;  // shells per group of loads in each sweep
 
 // element (row, col) of piece 0 of the tile-slab split copy of M
 __device__ inline size_t split_offset(int row, int col, int ks2) {
@@ -40,7 +41,11 @@ __device__ inline double reduce_parts(const double *Bpart, size_t stride, int sp
 }
 
 // One block of 64 columns.  Threads with lane >= the column count, and
-// chunks past the last shell, hold identity maps and write nothing.
+// chunks past the last shell, hold identity maps and write nothing.  Each
+// sweep takes kGroup shells at a time: the loads of a group are issued
+// together before the recurrence consumes them, so a wave waits for one
+// memory latency per group rather than per shell (the loads of a short
+// last group repeat an in-range shell; their values are not used).
 __device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
     const double *__restrict__ Bpart = g.Bpart;
     const int splitk = g.splitk, n_fields = g.n_fields, n_r = g.n_r, np = g.np, L = g.L;
@@ -57,32 +62,53 @@ __device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
     const int f = active ? cidx / np : 0, q = active ? cidx - f * np : 0;
     const int l = active ? col_l[q] : -1;
     const int len = (n_r + T - 1) / T;
-    const int lo = min(n_r, ch * len), hi = min(n_r, lo + len);
+    // a chunk is one wave (64 lanes): its shell range is wave-uniform
+    const int lo = __builtin_amdgcn_readfirstlane(min(n_r, ch * len));
+    const int hi = __builtin_amdgcn_readfirstlane(min(n_r, lo + len));
     const size_t stride = (size_t)n_fields * n_r * np;
     const size_t base = (size_t)f * n_r * np + q;
     const int cl = l < 0 ? 0 : l;
     const double *cf = coef + 4 * (size_t)cl;
     const size_t cstep = 4 * (size_t)(L + 1);
 
+    // first sweep: reduce the partial sums, compose the chunk's maps; the
+    // outer sum over shells n > lo uses the coefficients (c, e) of shell n - 1
     double A = 1.0, y = 0.0, P = 1.0, zl = 0.0;
     if (l >= 0) {
-        for (int n = lo; n < hi; ++n) {
-            double Bn = reduce_parts(Bpart, stride, splitk, base + (size_t)n * np);
-            Bred[base + (size_t)n * np] = Bn;
-            const double *c = cf + n * cstep;
-            y = c[0] * y + c[1] * Bn;
-            A *= c[0];
-            if (n > lo) {
-                const double *cp = cf + (n - 1) * cstep;
-                zl += P * cp[3] * Bn;
-                P *= cp[2];
+        double pc = 0.0, pe = 0.0;
+        for (int n0 = lo; n0 < hi; n0 += kGroup) {
+            const int cnt = min(kGroup, hi - n0);
+            double Bv[kGroup], c[kGroup][4];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                Bv[u] = 0.0;
+                const double *cn = cf + min(n0 + u, hi - 1) * cstep;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) c[u][k] = cn[k];
+            }
+            for (int k = 0; k < splitk; ++k)
+#pragma unroll
+                for (int u = 0; u < kGroup; ++u)
+                    Bv[u] += Bpart[k * stride + base + (size_t)min(n0 + u, hi - 1) * np];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                if (u >= cnt) break;
+                const int n = n0 + u;
+                Bred[base + (size_t)n * np] = Bv[u];
+                y = c[u][0] * y + c[u][1] * Bv[u];
+                A *= c[u][0];
+                if (n > lo) {
+                    zl += P * pe * Bv[u];
+                    P *= pc;
+                }
+                pc = c[u][2];
+                pe = c[u][3];
             }
         }
         if (hi > lo && hi < n_r) {
             double Bh = reduce_parts(Bpart, stride, splitk, base + (size_t)hi * np);
-            const double *cp = cf + (hi - 1) * cstep;
-            zl += P * cp[3] * Bh;
-            P *= cp[2];
+            zl += P * pe * Bh;
+            P *= pc;
         }
     }
     sA[ch][lane] = A;
@@ -105,29 +131,59 @@ __device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
         }
         return;
     }
+    // inner sums, upwards
     y = Yin;
-    for (int n = lo; n < hi; ++n) {
-        const double *c = cf + n * cstep;
-        y = c[0] * y + c[1] * Bred[base + (size_t)n * np];
-        M[base + (size_t)n * np] = y;
+    for (int n0 = lo; n0 < hi; n0 += kGroup) {
+        const int cnt = min(kGroup, hi - n0);
+        double Bv[kGroup], a[kGroup], b[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int n = min(n0 + u, hi - 1);
+            const double *cn = cf + n * cstep;
+            a[u] = cn[0];
+            b[u] = cn[1];
+            Bv[u] = Bred[base + (size_t)n * np];
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            if (u >= cnt) break;
+            y = a[u] * y + b[u] * Bv[u];
+            M[base + (size_t)(n0 + u) * np] = y;
+        }
     }
+    // outer sums, downwards; M = inner + outer
     double z = Zin;
-    for (int n = hi - 1; n >= lo; --n) {
-        const double *c = cf + n * cstep;
-        double Bn1 = (n + 1 < n_r) ? Bred[base + (size_t)(n + 1) * np] : 0.0;
-        z = c[2] * z + c[3] * Bn1;
-        double m = M[base + (size_t)n * np] + z;
-        M[base + (size_t)n * np] = m;
-        if (Ms) {
-            // three-piece bf16 copy for the split contraction
-            bf16 h = (bf16)(float)m;
-            double r = m - (double)(float)h;
-            bf16 md = (bf16)(float)r;
-            double r2 = r - (double)(float)md;
-            bf16 *o = Ms + split_offset_of(f, n, q, n_r, np, g.pp, g.ks2);
-            o[0] = h;
-            o[kBlk] = md;
-            o[2 * kBlk] = (bf16)(float)r2;
+    for (int n1 = hi; n1 > lo; n1 -= kGroup) {
+        const int cnt = min(kGroup, n1 - lo);
+        double Bv[kGroup], Mv[kGroup], cc[kGroup], e[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int n = max(n1 - 1 - u, lo);
+            const double *cn = cf + n * cstep;
+            cc[u] = cn[2];
+            e[u] = cn[3];
+            const double b1 = Bred[base + (size_t)min(n + 1, n_r - 1) * np];
+            Bv[u] = n + 1 < n_r ? b1 : 0.0;
+            Mv[u] = M[base + (size_t)n * np];
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            if (u >= cnt) break;
+            const int n = n1 - 1 - u;
+            z = cc[u] * z + e[u] * Bv[u];
+            double m = Mv[u] + z;
+            M[base + (size_t)n * np] = m;
+            if (Ms) {
+                // three-piece bf16 copy for the split contraction
+                bf16 h = (bf16)(float)m;
+                double r = m - (double)(float)h;
+                bf16 md = (bf16)(float)r;
+                double r2 = r - (double)(float)md;
+                bf16 *o = Ms + split_offset_of(f, n, q, n_r, np, g.pp, g.ks2);
+                o[0] = h;
+                o[kBlk] = md;
+                o[2 * kBlk] = (bf16)(float)r2;
+            }
         }
     }
 }
