@@ -2,8 +2,9 @@
 // sizes, lmax) through persistent work-queue kernels, one per stage
 // (moment contraction, radial scans, expansion).  Each stage's queue holds
 // the tiles of every field, ordered longest first; the persistent blocks
-// pull tiles until the queue is empty.  The three launches and the counter
-// reset are captured once in a hipGraph and replayed; a call only refreshes
+// pull tiles until the queue is empty.  The three launches, the counter
+// reset and (split forms) one launch that splits the inputs of every field
+// are captured once in a hipGraph and replayed; a call only refreshes
 // the fields' rho/phi pointers (kept in device memory, read by the kernels)
 // and launches the graph on the caller's stream.  The expansion kernels also
 // stamp the device wall clock when the last tile of a field is done, so the
@@ -39,6 +40,7 @@ struct Batch {
     void *args_dev = nullptr;
     ScanArgs *scan_dev = nullptr;
     BatchItem *items_dev = nullptr;
+    size_t *split_offs = nullptr;  // input split: first thread of each field, and the total
     int *heads = nullptr;
     unsigned long long *stamps = nullptr;
     hipStream_t cap = nullptr;
@@ -52,6 +54,7 @@ struct Batch {
         if (args_dev) (void)hipFree(args_dev);
         if (scan_dev) (void)hipFree(scan_dev);
         if (items_dev) (void)hipFree(items_dev);
+        if (split_offs) (void)hipFree(split_offs);
         if (heads) (void)hipFree(heads);
         if (stamps) (void)hipFree(stamps);
     }
@@ -164,8 +167,15 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     const BatchTrack track{b.stamps, n};
     CHECK(hipMemcpy(b.scan_dev, b.sc.data(), sizeof(ScanArgs) * n, hipMemcpyHostToDevice));
     CHECK(hipMemcpy(b.items_dev, all.data(), sizeof(BatchItem) * all.size(), hipMemcpyHostToDevice));
+    std::vector<size_t> offs(n + 1, 0);
+    for (int f = 0; f < n; ++f) offs[f + 1] = offs[f] + (split ? split_input_threads(q[f], 1) : 0);
+    if (split) {
+        CHECK(hipMalloc(&b.split_offs, sizeof(size_t) * (n + 1)));
+        CHECK(hipMemcpy(b.split_offs, offs.data(), sizeof(size_t) * (n + 1), hipMemcpyHostToDevice));
+    }
 
-    // capture: counter reset and start stamp (a kernel, not a memset) and the three stages
+    // capture: counter reset and start stamp (a kernel, not a memset), the input
+    // split of every field (split forms) and the three stages
     CHECK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
     CHECK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
     const int cus = cu_count();
@@ -174,8 +184,7 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     hipError_t e;
     e = hipSuccess;
     if (split) {
-        for (int f = 0; f < n && e == hipSuccess; ++f)
-            e = batch_split_input_bf16((const SplitArgs *)b.args_dev, f, split_input_threads(q[f], 1), dtype, b.cap);
+        e = batch_split_input_bf16((const SplitArgs *)b.args_dev, b.split_offs, n, offs[n], dtype, b.cap);
         if (e == hipSuccess)
             e = batch_gemm1_bf16((const SplitArgs *)b.args_dev, it1, b.n1, b.heads + 0, dtype, cus, b.cap);
         if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);

@@ -171,12 +171,22 @@ __global__ __launch_bounds__(256) void k_fold_split(SplitArgs g, size_t n_thread
     if (t < n_threads) fold_split_chunk<T, FOLD>(g, t);
 }
 
-// batch version: the field's arguments come from device memory
+// batch version: one launch over the chunks of every field.  Field f owns
+// threads offs[f] .. offs[f+1]-1; every field's count is a multiple of 2048,
+// so a block of 256 threads lies inside one field.
 template <typename T>
-__global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *args, int f, size_t n_threads) {
-    const SplitArgs g = args[f];
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_threads) return;
+__global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *__restrict__ args,
+                                                          const size_t *__restrict__ offs, int n) {
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x;
+    // the last field f with offs[f] <= t0 (offs[0] = 0 <= t0 < offs[n])
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (offs[mid] <= t0) lo = mid;
+        else hi = mid;
+    }
+    const SplitArgs g = args[lo];
+    const size_t t = t0 + threadIdx.x - offs[lo];
     if (g.fold) fold_split_chunk<T, true>(g, t);
     else fold_split_chunk<T, false>(g, t);
 }
@@ -656,12 +666,12 @@ hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     return hipGetLastError();
 }
 
-hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t n_threads, int io_dtype, hipStream_t s) {
-    dim3 grid((unsigned)((n_threads + 255) / 256));
-    if (io_dtype == MPG_F64)
-        hipLaunchKernelGGL((k_batch_fold_split<double>), grid, dim3(256), 0, s, args, f, n_threads);
-    else
-        hipLaunchKernelGGL((k_batch_fold_split<float>), grid, dim3(256), 0, s, args, f, n_threads);
+hipError_t batch_split_input_bf16(const SplitArgs *args, const size_t *offs, int n, size_t n_threads, int io_dtype,
+                                  hipStream_t s) {
+    if (n_threads % 256 || n_threads / 256 > 0x7fffffff) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)(n_threads / 256));
+    if (io_dtype == MPG_F64) hipLaunchKernelGGL((k_batch_fold_split<double>), grid, dim3(256), 0, s, args, offs, n);
+    else hipLaunchKernelGGL((k_batch_fold_split<float>), grid, dim3(256), 0, s, args, offs, n);
     return hipGetLastError();
 }
 

@@ -232,7 +232,11 @@ hipError_t batch_scan(const ScanArgs *args, const BatchItem *items, int n_items,
 hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype);
-hipError_t batch_split_input_bf16(const SplitArgs *args, int f, size_t n_threads, int io_dtype, hipStream_t s);
+// input split of every field of a batch in one launch: field f takes threads
+// offs[f] .. offs[f+1]-1 (device array of n+1 entries, each count a multiple
+// of 2048); n_threads = offs[n]
+hipError_t batch_split_input_bf16(const SplitArgs *args, const size_t *offs, int n, size_t n_threads, int io_dtype,
+                                  hipStream_t s);
 // threads of the input split of n_fields fields of a plan
 size_t split_input_threads(const Plan &p, int n_fields);
 SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype, bool expansion = false);
