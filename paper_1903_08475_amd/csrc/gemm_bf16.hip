@@ -286,15 +286,15 @@ __device__ __forceinline__ void ring_barrier() {
 }
 
 // Steps t0 <= t < t1 of run_ring (below), all with six products (SIX) or
-// all with three.
-template <int NA, int NB, bool FLUSH, bool SIX>
+// all with three; without MMA only the copies and barriers.
+template <int NA, int NB, bool FLUSH, bool SIX, bool MMA>
 __device__ __forceinline__ void ring_phase(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
                                            int dk, int t0, int t1, int last, int n3_load, int wm, int wn, int lane,
                                            v16f (&acc)[2][2], double (&acc64)[2][2][16]) {
 #define RING_STEP(CUR, NXT, O)                                       \
     ring_barrier<0>();                                               \
     load_slab(NXT, L, k0 + min(t + O + 1, last) * dk, t + O + 1 >= n3_load); \
-    if (t + O < t1) mma_slab<NA, NB, SIX>(CUR, wm, wn, lane, acc);
+    if (MMA && t + O < t1) mma_slab<NA, NB, SIX>(CUR, wm, wn, lane, acc);
     for (int s = t0; s < t1; s += kFlushSlabs) {
 #pragma unroll
         for (int j = 0; j < kFlushSlabs / 2; ++j) {
@@ -304,7 +304,7 @@ __device__ __forceinline__ void ring_phase(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1,
                 RING_STEP(S1, S0, 1)
             }
         }
-        if (FLUSH) {
+        if (FLUSH && MMA) {
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -333,15 +333,15 @@ __device__ __forceinline__ void ring_phase(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1,
 // differ between waves when it is 0 or nsl (each wave then runs nsl steps,
 // rounded up to even, and as many barriers).  On return all copies have
 // landed, and the buffers may be refilled after a barrier.
-template <int NA, int NB, bool FLUSH>
+template <int NA, int NB, bool FLUSH, bool MMA = true>
 __device__ __forceinline__ void run_ring(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
                                          int dk, int nsl, int n3, int n3_load, int wm, int wn, int lane,
                                          v16f (&acc)[2][2], double (&acc64)[2][2][16]) {
     if (nsl <= 0) return;
     const int last = nsl - 1;
     load_slab(S0, L, k0, n3_load == 0);
-    ring_phase<NA, NB, FLUSH, false>(S0, S1, L, k0, dk, 0, n3, last, n3_load, wm, wn, lane, acc, acc64);
-    ring_phase<NA, NB, FLUSH, true>(S0, S1, L, k0, dk, n3, nsl, last, n3_load, wm, wn, lane, acc, acc64);
+    ring_phase<NA, NB, FLUSH, false, MMA>(S0, S1, L, k0, dk, 0, n3, last, n3_load, wm, wn, lane, acc, acc64);
+    ring_phase<NA, NB, FLUSH, true, MMA>(S0, S1, L, k0, dk, n3, nsl, last, n3_load, wm, wn, lane, acc, acc64);
     // the trailing copy lands before anyone may reuse or free the LDS
     asm volatile("" ::: "memory");
     MPG_WAIT_VM(0);
@@ -402,10 +402,17 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
     // six products for a wave whose first column lies in its parity block's
     // tier; the block copies the l pieces when any of its waves needs them
-    const int cl = odd ? 2 * (tn - pe) * TB : 2 * tn * TB;
+    const int pair = odd ? tn - pe : tn;  // column pair within the parity block
+    const int cl = 2 * pair * TB;
     const int six_par = odd ? g.six_o : g.six_e;
     const bool six_b = cl < six_par, six_w = cl + wn < six_par;
-    run_ring<1, 2, true>(S0, S1, L, kbeg / TK, 1, nsl, six_w ? 0 : nsl, six_b ? 0 : nsl, wm, wn, lane, acc, acc64);
+    // the waves on a second tile past the parity block's last only copy
+    // and wait (the same steps and barriers); the SIMD they share goes to
+    // the wave on the first tile
+    const bool idle = wn >= TB && 2 * pair + 1 >= (odd ? g.tiles_o : g.tiles_e);
+    const int n3 = six_w ? 0 : nsl, n3_load = six_b ? 0 : nsl;
+    if (idle) run_ring<1, 2, true, false>(S0, S1, L, kbeg / TK, 1, nsl, n3, n3_load, wm, wn, lane, acc, acc64);
+    else run_ring<1, 2, true, true>(S0, S1, L, kbeg / TK, 1, nsl, n3, n3_load, wm, wn, lane, acc, acc64);
 
     double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
