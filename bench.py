@@ -286,9 +286,10 @@ def main():
     plan = mpg.Plan(grid, precision=prec, max_fields=n)
     tuned = None
     if not args.no_autotune:
-        sk, ch = plan.autotune(rho)
-        tuned = {"gemm1_splitk": sk, "scan_chunks": ch}
-        log(f"[bench] autotuned: K split {sk}, scan chunks {ch}")
+        sk, ch, rows = plan.autotune(rho)
+        tuned = {"gemm1_splitk": sk, "scan_chunks": ch,
+                 "expansion_block": "128x256" if rows == 1 else "256x128"}
+        log(f"[bench] autotuned: K split {sk}, scan chunks {ch}, expansion block {tuned['expansion_block']}")
     ms, wall, stages, pct = time_path(plan, rho, phi, args.steps, args.warmup)
     log(f"[bench] {prec}: {ms:.3f} ms/step ({pct}); stages {stages}")
     prods = products_per_term(grid.lmax, prec)

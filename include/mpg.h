@@ -178,16 +178,34 @@ int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho,
  * and dtype), MPG_EDEVICE. */
 int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms);
 
-/* Autotune the plan for n_fields fields: time the moment contraction and
- * the radial scan that reduces its partial sums for every K split the work
- * space allows (the default choice first, then powers of two; another
- * split is kept only when it is at least 1% faster), then the radial scan
- * for 4, 8, 12 and 16 shell chunks per column, on the given device input, and
- * keep the choices for later calls (including mpg_potential_batch).  Blocks until done; overwrites the plan's work
- * space.  splitk and chunks (may be NULL) receive the choices.
+/* Autotune the plan for n_fields fields on the given device input, and keep
+ * the choices for later calls:
+ *  - the K split of the moment contraction, timed together with the radial
+ *    scan that reduces its partial sums, for every split the work space
+ *    allows (the default choice first, then powers of two; another split is
+ *    kept only when it is at least 1% faster);
+ *  - the radial scan's shell chunks per column: 4, 8, 12 or 16;
+ *  - split forms: the expansion's block shape, 128 rows x 256 angular cells
+ *    (gemm2_rows = 1, the default) or 256 x 128 (gemm2_rows = 2, kept only
+ *    when at least 1% faster).  Its timing writes a temporary output of one
+ *    call's size, allocated and freed here; if it cannot be allocated, the
+ *    shape is left as it is.
+ * Batched calls (mpg_potential_batch) use the K split; their scan and
+ * expansion kernels keep fixed shapes.  Blocks until done; overwrites the
+ * plan's work space.  splitk, chunks and gemm2_rows (each may be NULL)
+ * receive the choices (gemm2_rows: 1 for the FP64 form).
  * Errors: as mpg_moments. */
 int mpg_autotune(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
-                 int *splitk, int *chunks);
+                 int *splitk, int *chunks, int *gemm2_rows);
+
+/* Set the choices mpg_autotune makes, e.g. ones it made earlier for the same
+ * grid and lmax: the K split of the moment contraction (at most the plan's
+ * work space allows), the radial scan's shell chunks per column (1..16) and
+ * the split expansion's block shape (gemm2_rows 1: 128 rows x 256 angular
+ * cells, 2: 256 x 128).  A value <= 0 leaves that choice as it is.  Results
+ * do not depend on the shape; they may differ in rounding with the K split.
+ * Errors: MPG_EINVAL (NULL plan, a value out of range; nothing is changed). */
+int mpg_set_tuning(mpg_plan_t plan, int splitk, int chunks, int gemm2_rows);
 
 /* Copy the plan's FP64 tables to device buffers, in the real index:
  *   U : [n_patches][n_theta*n_phi][n_lm]   (Eqs. U_C/U_S), or NULL

@@ -27,8 +27,8 @@ METHODS = {"global": 0, "per_patch": 1}
 
 # Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
 EXPORTS = ("mpg_plan", "mpg_plan_method", "mpg_moments", "mpg_potential", "mpg_potential_batch",
-           "mpg_batch_field_times", "mpg_autotune", "mpg_tables", "mpg_plan_info", "mpg_timing", "mpg_stage_times",
-           "mpg_sync", "mpg_destroy", "mpg_last_error")
+           "mpg_batch_field_times", "mpg_autotune", "mpg_set_tuning", "mpg_tables", "mpg_plan_info",
+           "mpg_timing", "mpg_stage_times", "mpg_sync", "mpg_destroy", "mpg_last_error")
 STAGES = ("input_split", "moments", "radial_scan", "expansion")
 
 
@@ -67,7 +67,9 @@ def lib():
         L.mpg_potential.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int]
         L.mpg_potential_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
         L.mpg_batch_field_times.argtypes = [C.c_int, C.POINTER(vp), C.c_int, dp]
-        L.mpg_autotune.argtypes = [vp, C.c_int, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.mpg_autotune.argtypes = [vp, C.c_int, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_int)]
+        L.mpg_set_tuning.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.mpg_tables.argtypes = [vp, vp, vp, vp]
         L.mpg_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]
         L.mpg_timing.argtypes = [vp, C.c_int]
@@ -185,13 +187,18 @@ class Plan:
         return B, M
 
     def autotune(self, rho):
-        """Time the K split of the moment contraction and the scan schedule
-        on this input and keep the fastest; returns (splitk, chunks)."""
+        """Time the K split of the moment contraction, the scan schedule and
+        (split forms) the expansion's block shape on this input and keep the
+        fastest; returns (splitk, chunks, gemm2_rows)."""
         n = self._fields(rho)
-        sk, ch = C.c_int(), C.c_int()
+        sk, ch, gr = C.c_int(), C.c_int(), C.c_int()
         _check(lib().mpg_autotune(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
-                                  C.byref(sk), C.byref(ch)))
-        return sk.value, ch.value
+                                  C.byref(sk), C.byref(ch), C.byref(gr)))
+        return sk.value, ch.value, gr.value
+
+    def set_tuning(self, splitk=0, chunks=0, gemm2_rows=0):
+        """Set the autotuner's choices (0 leaves one as it is)."""
+        _check(lib().mpg_set_tuning(self._h, splitk, chunks, gemm2_rows))
 
     def tables(self):
         """(U, Q, w) as float64 device tensors [n_patches, n_ang, n_lm] (twice)

@@ -392,7 +392,8 @@ int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms)
     return MPG_OK;
 }
 
-int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, int *splitk, int *chunks) {
+int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, int *splitk, int *chunks,
+                 int *gemm2_rows) {
     int rc = check_call(p, n_fields_in, rho, rho_dtype, "mpg_autotune");
     if (rc) return rc;
     const int n_fields = p->vfields(n_fields_in);
@@ -460,13 +461,53 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
             }
         }
     }
+    int best_r = p->gemm2_rows;
+    if (e == hipSuccess && split) {
+        // block shape of the expansion, timed on the moments of this input
+        // (GEMM1 and the scan with the choices above write M's split copy);
+        // Phi goes to a temporary buffer of one call's size (if that cannot
+        // be allocated, the shape stays as it is)
+        const size_t cells = (size_t)n_fields_in * p->n_patches * p->n_r * p->n_ang;
+        void *phi = nullptr;
+        if (hipMalloc(&phi, cells * (rho_dtype == MPG_F64 ? sizeof(double) : sizeof(float))) != hipSuccess) {
+            (void)hipGetLastError();
+            phi = nullptr;
+        }
+        if (phi) {
+            Plan q = *p;
+            q.splitk = best_s;
+            q.scan_chunks = best_c;
+            e = gemm1_bf16(q, n_fields, rho, rho_dtype);
+            if (e == hipSuccess) e = radial_scan(q, n_fields, true);
+            float tr[3] = {0.0f, 1e30f, 1e30f};
+            for (int r = 1; r <= 2 && e == hipSuccess; ++r) {
+                q.gemm2_rows = r;
+                for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {  // first run is a warm-up
+                    float t = 0.0f;
+                    if ((e = hipEventRecord(a, q.stream)) != hipSuccess) break;
+                    if ((e = gemm2_bf16(q, n_fields_in, phi, rho_dtype)) != hipSuccess) break;
+                    if ((e = hipEventRecord(b, q.stream)) != hipSuccess) break;
+                    if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+                    if ((e = hipEventElapsedTime(&t, a, b)) != hipSuccess) break;
+                    if (rep > 0 && t < tr[r]) tr[r] = t;
+                }
+            }
+            // the default shape, unless the other is at least 1% faster
+            if (e == hipSuccess) best_r = tr[2] < 0.99f * tr[1] ? 2 : 1;
+            hipError_t es = hipStreamSynchronize(p->stream);
+            hipError_t ef = hipFree(phi);
+            if (e == hipSuccess) e = es != hipSuccess ? es : ef;
+        }
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (e != hipSuccess) return hip_fail(e, "mpg_autotune");
     p->splitk_sel = best_s;
     p->scan_chunks = best_c;
+    p->gemm2_rows = best_r;
     if (splitk) *splitk = best_s;
     if (chunks) *chunks = best_c;
+    if (gemm2_rows) *gemm2_rows = best_r;
     return MPG_OK;
 }
 
@@ -474,6 +515,17 @@ int mpg_tables(mpg_plan_t p, double *U, double *Q, double *w) {
     if (!p) return fail(MPG_EINVAL, "mpg_tables: plan is NULL");
     hipError_t e = export_tables(*p, U, Q, w);
     if (e != hipSuccess) return hip_fail(e, "mpg_tables");
+    return MPG_OK;
+}
+
+int mpg_set_tuning(mpg_plan_t p, int splitk, int chunks, int gemm2_rows) {
+    if (!p) return fail(MPG_EINVAL, "mpg_set_tuning: plan is NULL");
+    if (splitk > p->splitk) return fail(MPG_EINVAL, "mpg_set_tuning: K split exceeds the plan's work space");
+    if (chunks > 16) return fail(MPG_EINVAL, "mpg_set_tuning: more than 16 shell chunks");
+    if (gemm2_rows > 2) return fail(MPG_EINVAL, "mpg_set_tuning: gemm2_rows must be 1 or 2");
+    if (splitk > 0) p->splitk_sel = splitk;
+    if (chunks > 0) p->scan_chunks = chunks;
+    if (gemm2_rows > 0) p->gemm2_rows = gemm2_rows;
     return MPG_OK;
 }
 

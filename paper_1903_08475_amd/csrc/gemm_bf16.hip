@@ -25,9 +25,10 @@
 // to the smallest partial sums last.
 //
 // Tiles: GEMM1 128x256 (rows x moment columns: two column tiles, so every
-// rho+- slab serves 256 columns), GEMM2 128x256 (one row tile x two
-// angular tiles: consecutive blocks share the Q tiles, and each M row tile
-// is read once per 256 angular cells); 512 threads = 8 waves of 64x64 (2x2 MFMA blocks of 32x32,
+// rho+- slab serves 256 columns), GEMM2 128x256 by default (one row tile x
+// two angular tiles: consecutive blocks share the Q tiles, and each M row
+// tile is read once per 256 angular cells) or 256x128 (the autotuner's
+// other choice); 512 threads = 8 waves of 64x64 (2x2 MFMA blocks of 32x32,
 // two waves per SIMD); K slabs of 32.  A slab of a block (both operands,
 // three pieces, 72 KB) is copied from global memory straight into LDS by
 // global_load_lds_dwordx4 (no staging registers) into two slab buffers
@@ -357,7 +358,7 @@ __device__ __forceinline__ int three_slabs(int nsl, int six_sl) {
 }
 
 // 128 rows of rho+- and 256 columns of U (GEMM1), or 128 rows of M and 256
-// angular cells of Q (GEMM2)
+// angular cells of Q (GEMM2's default block)
 typedef SlabT<1, 2> Slab1;
 
 // ---------------------------------------------------------------------------
@@ -427,25 +428,32 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
             }
 }
 
-// One output block of GEMM2 (row tile tm; angular tile pair tn: two
-// 128-cell tiles): the even-m K block into acc_e, then the odd-m block into acc_o, each
-// walked from its top slab down; per-patch method: the moment sets of the
-// patches one after the other, each flushed into FP64.
-template <typename T, bool FOLD, bool PP>
-__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, Slab1 &S0, Slab1 &S1) {
+// One output block of GEMM2, NA row tiles x (3 - NA) angular tiles of 128:
+// NA = 1 is 128 x 256 (row tile tm, angular tile pair tn), NA = 2 is
+// 256 x 128 (row tile pair tm, angular tile tn).  The even-m K block goes
+// into acc_e, then the odd-m block into acc_o, each walked from its top slab
+// down; per-patch method: the moment sets of the patches one after the
+// other, each flushed into FP64.
+template <typename T, bool FOLD, bool PP, int NA>
+__device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, SlabT<NA, 3 - NA> &S0,
+                                           SlabT<NA, 3 - NA> &S1) {
+    constexpr int NB = 3 - NA;
     T *phi = (T *)g.phi;
     const int rows = g.rows, np = g.np, ne_p = g.ne_p, n_ang = g.n_ang, n_r = g.n_r;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-    const int m0 = tm * TB, n0 = tn * 2 * TB;
-    const int n_cols = g.kang;  // angular cells of all output patches (tiles of TB)
+    const int wm = (wave % (2 * NA)) * 64, wn = (wave / (2 * NA)) * 64;
+    const int m0 = tm * NA * TB, n0 = tn * NB * TB;
+    const int n_cols = g.kang;                  // angular cells of all output patches (tiles of TB)
+    const int rt_used = (rows + TB - 1) / TB;   // row tiles holding this call's rows
 
-    LoaderT<1, 2> L;
+    // a second tile past the end is read in bounds and never stored
+    LoaderT<NA, NB> L;
     const size_t tstride = (size_t)g.ks2 * 3 * kBlk;
-    L.a[0] = g.M + (size_t)tm * tstride;
-    L.b[0] = g.Q + (size_t)(2 * tn) * tstride;
-    L.b[1] = g.Q + (size_t)min(2 * tn + 1, n_cols / TB - 1) * tstride;  // past the end: columns never stored
+    L.a[0] = g.M + (size_t)(NA * tm) * tstride;
+    if constexpr (NA == 2) L.a[1] = g.M + (size_t)min(2 * tm + 1, rt_used - 1) * tstride;
+    L.b[0] = g.Q + (size_t)(NB * tn) * tstride;
+    if constexpr (NB == 2) L.b[1] = g.Q + (size_t)min(2 * tn + 1, n_cols / TB - 1) * tstride;
     L.part = wave * 512;
     L.lo = L.part + lane * 8;
 
@@ -457,13 +465,13 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     if (FOLD) {
         const int ne = ne_p / TK, no = (np - ne_p) / TK;
         const int e3 = three_slabs(ne, g.six_e / TK), o3 = three_slabs(no, g.six_o / TK);
-        run_ring<1, 2, false>(S0, S1, L, ne - 1, -1, ne, e3, e3, wm, wn, lane, acc_e, acc64);
+        run_ring<NA, NB, false>(S0, S1, L, ne - 1, -1, ne, e3, e3, wm, wn, lane, acc_e, acc64);
         // the odd block refills buffers the even block's last slabs were read from
         __syncthreads();
-        run_ring<1, 2, false>(S0, S1, L, ne + no - 1, -1, no, o3, o3, wm, wn, lane, acc_o, acc64);
+        run_ring<NA, NB, false>(S0, S1, L, ne + no - 1, -1, no, o3, o3, wm, wn, lane, acc_o, acc64);
     } else if (!pp) {
         const int ns = g.ks2, n3 = three_slabs(ns, g.six_e / TK);
-        run_ring<1, 2, false>(S0, S1, L, ns - 1, -1, ns, n3, n3, wm, wn, lane, acc_e, acc64);
+        run_ring<NA, NB, false>(S0, S1, L, ns - 1, -1, ns, n3, n3, wm, wn, lane, acc_e, acc64);
     } else {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -474,7 +482,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
         const int nsb = np / TK, n3 = three_slabs(nsb, g.six_e / TK);
         for (int gq = 0; gq < g.nq; ++gq) {
             if (gq) __syncthreads();
-            run_ring<1, 2, false>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, n3, n3, wm, wn, lane, acc_e, acc64);
+            run_ring<NA, NB, false>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, n3, n3, wm, wn, lane, acc_e, acc64);
             // each patch's moment set is summed in FP32 (as the single set
             // of the other forms) and added in FP64
 #pragma unroll
@@ -515,7 +523,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 
 // ---------------------------------------------------------------------------
 // Grid launches for one plan: GEMM1 grid x = (column pair, row tile), z =
-// K split; GEMM2 grid x = row tile, y = angular tile pair.
+// K split; GEMM2 grid x = row tile (pair), y = angular tile pair (tile).
 // GEMM1's blocks in x run over (column pair, row tile), the pairs that take
 // six products first (they take about twice as long as the others), so the
 // long blocks are dispatched before the short ones.
@@ -540,10 +548,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm1(SplitArgs g) {
     gemm1_tile<FOLD>(g, tn, tm, blockIdx.z, s0, s1);
 }
 
-template <typename T, bool FOLD, bool PP>
+template <typename T, bool FOLD, bool PP, int NA>
 __global__ __launch_bounds__(kThreads) void k_gemm2(SplitArgs g) {
-    __shared__ Slab1 s0, s1;
-    gemm2_tile<T, FOLD, PP>(g, blockIdx.x, blockIdx.y, s0, s1);
+    __shared__ SlabT<NA, 3 - NA> s0, s1;
+    gemm2_tile<T, FOLD, PP, NA>(g, blockIdx.x, blockIdx.y, s0, s1);
 }
 
 // Persistent batch kernels: every block takes work items from a queue
@@ -586,8 +594,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_gemm2(const SplitArgs *__res
         const BatchItem w = items[it];
         const SplitArgs g = args[w.f];
         // (batches hold no per-patch plans)
-        if (g.fold) gemm2_tile<T, true, false>(g, w.a, w.b, s0, s1);
-        else gemm2_tile<T, false, false>(g, w.a, w.b, s0, s1);
+        if (g.fold) gemm2_tile<T, true, false, 1>(g, w.a, w.b, s0, s1);
+        else gemm2_tile<T, false, false, 1>(g, w.a, w.b, s0, s1);
         prev = w.f;
     }
 }
@@ -658,17 +666,24 @@ hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtyp
     return hipGetLastError();
 }
 
+template <typename T, int NA>
+void launch_gemm2(const Plan &p, const SplitArgs &g, dim3 grid) {
+    if (p.fold) hipLaunchKernelGGL((k_gemm2<T, true, false, NA>), grid, dim3(kThreads), 0, p.stream, g);
+    else if (g.nq > 1) hipLaunchKernelGGL((k_gemm2<T, false, true, NA>), grid, dim3(kThreads), 0, p.stream, g);
+    else hipLaunchKernelGGL((k_gemm2<T, false, false, NA>), grid, dim3(kThreads), 0, p.stream, g);
+}
+
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     SplitArgs g = split_args(p, n_fields, nullptr, phi, phi_dtype, true);
-    dim3 grid((g.rows + TB - 1) / TB, (g.kang / TB + 1) / 2);
-    if (phi_dtype == MPG_F64) {
-        if (p.fold) hipLaunchKernelGGL((k_gemm2<double, true, false>), grid, dim3(kThreads), 0, p.stream, g);
-        else if (g.nq > 1) hipLaunchKernelGGL((k_gemm2<double, false, true>), grid, dim3(kThreads), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm2<double, false, false>), grid, dim3(kThreads), 0, p.stream, g);
+    const int rt = (g.rows + TB - 1) / TB, at = g.kang / TB;
+    if (p.gemm2_rows == 2) {
+        dim3 grid((rt + 1) / 2, at);
+        if (phi_dtype == MPG_F64) launch_gemm2<double, 2>(p, g, grid);
+        else launch_gemm2<float, 2>(p, g, grid);
     } else {
-        if (p.fold) hipLaunchKernelGGL((k_gemm2<float, true, false>), grid, dim3(kThreads), 0, p.stream, g);
-        else if (g.nq > 1) hipLaunchKernelGGL((k_gemm2<float, false, true>), grid, dim3(kThreads), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm2<float, false, false>), grid, dim3(kThreads), 0, p.stream, g);
+        dim3 grid(rt, (at + 1) / 2);
+        if (phi_dtype == MPG_F64) launch_gemm2<double, 1>(p, g, grid);
+        else launch_gemm2<float, 1>(p, g, grid);
     }
     return hipGetLastError();
 }

@@ -102,6 +102,7 @@ struct Plan {
     int splitk = 1;            // K splits of the moment contraction (work space holds this many)
     int splitk_sel = 0;        // chosen by mpg_autotune (0: heuristic)
     int scan_chunks = 16;      // shell chunks per column in the radial scan
+    int gemm2_rows = 1;        // split expansion blocks: 1 = 128 rows x 256 cells, 2 = 256 x 128
     double *Bpart = nullptr;   // [splitk][rows][np]
     double *Bred = nullptr;    // [rows][np]
     double *M = nullptr;       // [rows][np]

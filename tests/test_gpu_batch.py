@@ -119,10 +119,10 @@ def test_autotune_keeps_parity(precision):
     rho = W.random_rho(g, 31)
     t = torch.tensor(rho, device="cuda")
     plan = mpg.Plan(g, precision=precision)
-    sk, ch = plan.autotune(t)
-    assert sk >= 1 and ch in (4, 8, 16)
+    sk, ch, rows = plan.autotune(t)
+    assert sk >= 1 and ch in (4, 8, 12, 16) and rows in (1, 2)
     M = O.radial(g, g.lmax, O.moments(g, g.lmax, U, rho))
     phi = O.expand(g, g.lmax, Q, M)
     out = plan.potential(t).cpu().numpy()
-    print(f"{precision}: autotuned splitk {sk}, scan chunks {ch}, err {rel_err(out, phi):.3e}")
+    print(f"{precision}: autotuned splitk {sk}, scan chunks {ch}, expansion rows {rows}, err {rel_err(out, phi):.3e}")
     assert rel_err(out, phi) < TOL[precision]

@@ -148,3 +148,31 @@ def test_stage_timing_counts_launches():
     st = plan.stage_times()
     assert all(st[k][1] == 3 for k in st) and all(st[k][0] > 0 for k in st)
     assert all(v[1] == 0 for v in plan.stage_times().values())
+
+
+@pytest.mark.parametrize("key,method", [("c1", "global"), ("ragged", "global"), ("polar", "global"),
+                                        ("medium", "global"), ("tiny", "global"), ("ragged", "per_patch")])
+def test_expansion_block_shapes_agree(key, method):
+    """The expansion's two block shapes (128 x 256 and 256 x 128) give the
+    same potential; the shape set back gives the first result again."""
+    torch, mpg = torch_mods()
+    g, w, U, Q = oracle_tables(key)
+    t = torch.tensor(density(key, g).astype(np.float32), device="cuda")
+    plan = mpg.Plan(g, precision="split_bf16_tiered", method=method)
+    wide = plan.potential(t).cpu().numpy()
+    plan.set_tuning(gemm2_rows=2)
+    tall = plan.potential(t).cpu().numpy()
+    plan.set_tuning(gemm2_rows=1)
+    again = plan.potential(t).cpu().numpy()
+    print(f"{key} {method}: 256x128 vs 128x256 blocks, max abs diff {np.abs(tall - wide).max():.3e}")
+    assert np.array_equal(wide, again)
+    assert rel_err(tall, wide) <= 1e-12
+
+
+def test_set_tuning_rejects_out_of_range_values():
+    torch, mpg = torch_mods()
+    g, w, U, Q = oracle_tables("tiny")
+    plan = mpg.Plan(g, precision="split_bf16")
+    for kw in ({"gemm2_rows": 3}, {"chunks": 17}, {"splitk": 10 ** 6}):
+        with pytest.raises(mpg.MpgError):
+            plan.set_tuning(**kw)
