@@ -176,3 +176,25 @@ def test_set_tuning_rejects_out_of_range_values():
     for kw in ({"gemm2_rows": 3}, {"chunks": 17}, {"splitk": 10 ** 6}):
         with pytest.raises(mpg.MpgError):
             plan.set_tuning(**kw)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16", "split_bf16_tiered"])
+def test_solves_are_bitwise_reproducible(precision):
+    """Every reduction runs in a fixed order (K splits summed in order in the
+    scan, no atomics in the arithmetic), so repeated solves, with other work
+    in between and with a K split of 2, give the same bits."""
+    torch, mpg = torch_mods()
+    g, w, U, Q = oracle_tables("medium")
+    t = torch.tensor(density("medium", g), device="cuda")
+    if precision != "fp64":
+        t = t.float()
+    plan = mpg.Plan(g, precision=precision)
+    other = mpg.Plan(*oracle_tables("ragged")[:1], precision=precision)
+    first = plan.potential(t).cpu().numpy()
+    for splitk in (0, 2):
+        if splitk:
+            plan.set_tuning(splitk=splitk)
+            first = plan.potential(t).cpu().numpy()
+        for _ in range(2):
+            other.potential(torch.rand(other.shape, device="cuda", dtype=t.dtype))
+            assert np.array_equal(plan.potential(t).cpu().numpy(), first)
