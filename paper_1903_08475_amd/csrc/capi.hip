@@ -25,8 +25,12 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
+// Reports a failed HIP call and clears the thread's last HIP error, which
+// would otherwise be returned by later error checks (this library's after
+// its launches, or the caller's) although those calls succeeded.
 int hip_fail(hipError_t e, const char *where) {
     set_error(std::string(where) + ": " + hipGetErrorString(e));
+    (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? MPG_ENOMEM : MPG_EDEVICE;
 }
 

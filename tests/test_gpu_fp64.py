@@ -125,3 +125,20 @@ def test_bad_calls_raise():
         plan.potential(rho)  # two fields > max_fields
     with pytest.raises(ValueError):
         plan.potential(torch.zeros(7, dtype=torch.float64, device="cuda"))
+
+
+def test_plan_whose_work_space_does_not_fit_fails_cleanly():
+    """A plan whose FP64 work space exceeds the GPU's memory (4096 fields of
+    2000 shells at lmax 48: about 160 GB per work array) is refused with
+    MPG_ENOMEM, frees what it had allocated, and later plans solve correctly."""
+    torch, mpg = torch_mods()
+    big = W.yinyang(4, W.uniform_edges(2000), 48)
+    with pytest.raises(mpg.MpgError) as err:
+        mpg.Plan(big, max_fields=4096)
+    assert err.value.code == mpg.MPG_ENOMEM
+    assert "work space" in str(err.value)
+    g, w, U, Q = oracle_tables("ragged")
+    rho = W.random_rho(g, 41)
+    phi = O.expand(g, g.lmax, Q, O.radial(g, g.lmax, O.moments(g, g.lmax, U, rho)))
+    out = mpg.Plan(g).potential(torch.tensor(rho, device="cuda")).cpu().numpy()
+    assert rel_err(out, phi) < TOL64
