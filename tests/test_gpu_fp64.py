@@ -125,6 +125,10 @@ def test_bad_calls_raise():
         plan.potential(rho)  # two fields > max_fields
     with pytest.raises(ValueError):
         plan.potential(torch.zeros(7, dtype=torch.float64, device="cuda"))
+    plan.close()  # a destroyed plan is refused, not used
+    with pytest.raises(mpg.MpgError) as err:
+        plan.potential(rho[:1])
+    assert err.value.code == mpg.MPG_EINVAL
 
 
 def test_plan_whose_work_space_does_not_fit_fails_cleanly():
