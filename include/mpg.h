@@ -79,7 +79,14 @@ typedef struct mpg_grid {
     int w_per_patch;            /* 0: overlap_w holds n_theta*n_phi weights
                                    shared by every patch; 1: it holds
                                    n_patches*n_theta*n_phi, patch-major      */
+    int eval_point;             /* where Phi is evaluated in each cell, on the
+                                   outer radius of its shell:
+                                   MPG_EVAL_UPPER_VERTEX (0, Eq. gravpotmult)
+                                   or MPG_EVAL_ANGULAR_CENTRE (1)            */
 } mpg_grid;
+
+#define MPG_EVAL_UPPER_VERTEX 0
+#define MPG_EVAL_ANGULAR_CENTRE 1
 
 #define MPG_MAX_PATCHES 16
 

@@ -41,6 +41,7 @@ class _OrcGrid(C.Structure):
         ("euler", C.POINTER(C.c_double)),
         ("G", C.c_double),
         ("w_stride", C.c_int),
+        ("eval_centre", C.c_int),
     ]
 
 
@@ -100,6 +101,7 @@ class _G:
         s.r_edges, s.euler = _dp(self.r), _dp(self.e)
         s.theta0, s.phi0, s.dtheta, s.dphi = grid.theta0, grid.phi0, grid.dtheta, grid.dphi
         s.G = grid.G
+        s.eval_centre = int(getattr(grid, "eval_point", "vertex") == "centre")
         self.s = s
 
     def set_w_stride(self, w, n_ang):

@@ -306,7 +306,8 @@ int orc_tables_range(const orc_grid *g, int lmax, const double *w,
             }
             if (Q) {
                 double cth, phg;
-                global_angles(R, t1 + g->dtheta, f1 + g->dphi, &cth, &phg);
+                const double ev = g->eval_centre ? 0.5 : 1.0;  /* evaluation point in the cell */
+                global_angles(R, t1 + ev * g->dtheta, f1 + ev * g->dphi, &cth, &phg);
                 orc_legendre(lmax, cth, P);
                 double *row = Q + ((size_t)p * n_ang + c) * nlm;
                 for (int l = 0; l <= lmax; ++l) {
@@ -487,8 +488,9 @@ int orc_brute_phi(const orc_grid *g, int lmax, const double *w,
         for (int l = 0; l <= lmax; ++l)
             for (int i = 0; i < nr; ++i) K[l * nr + i] = orc_radial_factor(g->r_edges, nt, i, l);
         double tv[3];
-        local_dir(g->theta0 + (ct / g->n_phi + 1) * g->dtheta,
-                  g->phi0 + (ct % g->n_phi + 1) * g->dphi, pt, tv);
+        const double ev = g->eval_centre ? 0.5 : 1.0;  /* evaluation point in the cell */
+        local_dir(g->theta0 + (ct / g->n_phi + ev) * g->dtheta,
+                  g->phi0 + (ct % g->n_phi + ev) * g->dphi, pt, tv);
         double s = 0.0, cp = 0.0;
         for (int p = 0; p < g->n_patches; ++p)
             for (int c = 0; c < n_ang; ++c) {

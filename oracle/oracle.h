@@ -22,7 +22,8 @@
  * phase, (th, ph) the global angles of a point of patch g under
  * x = R^(g) xi (Eq. rottransmatrix), the cell integral taken in the
  * patch's local (theta, phi) by tensor Gauss-Legendre quadrature, and Q
- * the prefactors of Eqs. Q_C/Q_S at the upper cell vertex.  No Wigner d,
+ * the prefactors of Eqs. Q_C/Q_S at the upper cell vertex (or, with
+ * eval_centre, at the cell's angular centre on the same outer radius).  No Wigner d,
  * no T/C/S integrals, no (-1)^m sharing between patches and no radial
  * recurrence is used.
  *
@@ -53,6 +54,9 @@ typedef struct {
     double G;               /* gravitational constant                       */
     int w_stride;           /* overlap weights of patch p start at
                                w + p*w_stride (0: one set for all patches) */
+    int eval_centre;        /* 0: Phi at the upper cell vertex (Eq.
+                               gravpotmult); 1: at the cell's angular centre,
+                               still at the outer radius of its shell      */
 } orc_grid;
 
 /* Eq. rottransmatrix: R = R_z''(gamma) R_y'(beta) R_z(alpha), x = R xi. */

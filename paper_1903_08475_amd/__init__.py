@@ -24,6 +24,8 @@ PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16, "split_bf16_tiered
 # "global": the paper's method; "per_patch": the comparison method (moments
 # of every patch in its own frame, potentials of the patches added)
 METHODS = {"global": 0, "per_patch": 1}
+# where Phi is evaluated in each cell (on the shell's outer radius)
+EVAL_POINTS = {"vertex": 0, "centre": 1}
 
 # Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
 EXPORTS = ("mpg_plan", "mpg_plan_method", "mpg_moments", "mpg_potential", "mpg_potential_batch",
@@ -47,6 +49,7 @@ class _Grid(C.Structure):
         ("overlap_w", C.POINTER(C.c_double)),
         ("G", C.c_double),
         ("w_per_patch", C.c_int),
+        ("eval_point", C.c_int),
     ]
 
 
@@ -106,7 +109,8 @@ class Plan:
     """A solver plan for one grid and lmax (tables built once on the device).
 
     grid: any object with n_patches, n_r, n_theta, n_phi, r_edges, theta0,
-    phi0, dtheta, dphi, euler, G (e.g. ``workloads.Grid``).
+    phi0, dtheta, dphi, euler, G and optionally eval_point ("vertex", the
+    default, or "centre") (e.g. ``workloads.Grid``).
     """
 
     def __init__(self, grid, lmax=None, precision="fp64", max_fields=1, stream=None, overlap_w=None,
@@ -134,6 +138,10 @@ class Plan:
         g.overlap_w = None if self._w is None else self._w.ctypes.data_as(C.POINTER(C.c_double))
         g.G = grid.G
         g.w_per_patch = int(self._w is not None and self._w.size != n_ang)
+        ev = getattr(grid, "eval_point", "vertex")
+        if ev not in EVAL_POINTS:
+            raise ValueError(f"eval_point must be one of {sorted(EVAL_POINTS)}")
+        g.eval_point = EVAL_POINTS[ev]
         h = C.c_void_p()
         _check(lib().mpg_plan_method(C.byref(g), self.lmax, PRECISIONS[precision], max_fields, METHODS[method],
                                      _stream_handle(self.stream), C.byref(h)))

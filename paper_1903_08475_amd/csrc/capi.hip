@@ -139,6 +139,8 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
     if (precision != MPG_FP64 && precision != MPG_SPLIT_BF16 && precision != MPG_SPLIT_BF16_TIERED)
         return fail(MPG_EINVAL, "mpg_plan: bad precision");
     if (max_fields < 1 || max_fields > 4096) return fail(MPG_EINVAL, "mpg_plan: max_fields outside [1, 4096]");
+    if (g->eval_point != MPG_EVAL_UPPER_VERTEX && g->eval_point != MPG_EVAL_ANGULAR_CENTRE)
+        return fail(MPG_EINVAL, "mpg_plan: bad eval_point");
     for (int i = 0; i < 3 * g->n_patches; ++i)
         if (!std::isfinite(g->euler[i])) return fail(MPG_EINVAL, "mpg_plan: non-finite Euler angle");
 
@@ -158,6 +160,7 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
     p->precision = precision;
     p->max_fields = max_fields;
     p->G = g->G;
+    p->eval_centre = g->eval_point == MPG_EVAL_ANGULAR_CENTRE;
     p->stream = (hipStream_t)stream;
     p->per_patch = method == MPG_METHOD_PER_PATCH;
     (void)hipGetDevice(&p->device);

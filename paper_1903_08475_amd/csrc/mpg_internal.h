@@ -61,6 +61,7 @@ struct Plan {
     int ovl_kap_inf = 0;
     bool fold = false;
     double G = 1.0;
+    bool eval_centre = false;  // Phi at the cells' angular centres instead of their upper vertices
     hipStream_t stream = nullptr;
     int device = 0;
 

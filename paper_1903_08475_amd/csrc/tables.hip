@@ -208,13 +208,15 @@ struct Rot {
     double r[9];
 };
 
-// Eqs. Q_C/Q_S at the upper vertex of every cell of patch 0:
+// Eqs. Q_C/Q_S at the upper vertex of every cell of patch 0 (ev = 1), or at
+// its angular centre (ev = 1/2):
 //   Q = -G s_lm P_l^m(cos theta) {cos, sin}(m phi)
 // with (theta, phi) the global angles of x = R xi.  The normalised
 // functions s_lm P_l^m come from the recurrences of the normalised
 // associated Legendre functions (Condon-Shortley phase).  Qt[jk][perm].
 __global__ void k_Q(int L, int np, int n_angp, int n_ang, int n_phi, double theta0, double phi0,
-                    double dtheta, double dphi, Rot R, double G, const int *perm_of, size_t ld, double *Qt) {
+                    double dtheta, double dphi, double ev, Rot R, double G, const int *perm_of, size_t ld,
+                    double *Qt) {
     int jk = blockIdx.x * blockDim.x + threadIdx.x;
     if (jk >= n_angp) return;
     double *row = Qt + (size_t)jk * ld;
@@ -224,8 +226,8 @@ __global__ void k_Q(int L, int np, int n_angp, int n_ang, int n_phi, double thet
     }
     int j = jk / n_phi, k = jk - j * n_phi;
     double st, ct, sp, cp;
-    sincos(theta0 + (j + 1) * dtheta, &st, &ct);
-    sincos(phi0 + (k + 1) * dphi, &sp, &cp);
+    sincos(theta0 + (j + ev) * dtheta, &st, &ct);
+    sincos(phi0 + (k + ev) * dphi, &sp, &cp);
     double xi = st * cp, et = st * sp, ze = ct;
     double x = R.r[0] * xi + R.r[1] * et + R.r[2] * ze;
     double y = R.r[3] * xi + R.r[4] * et + R.r[5] * ze;
@@ -590,7 +592,7 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
             }
             const size_t ldq = (size_t)p.kq();
             hipLaunchKernelGGL(k_Q, dim3(blocks(p.n_angp, 64)), dim3(64), 0, s, L, p.np, p.n_angp, p.n_ang, p.n_phi,
-                               p.theta0, p.phi0, p.dtheta, p.dphi, R, p.G, d_perm, ldq,
+                               p.theta0, p.phi0, p.dtheta, p.dphi, p.eval_centre ? 0.5 : 1.0, R, p.G, d_perm, ldq,
                                p.Qt + (size_t)b * p.n_angp * ldq + (size_t)c * p.np);
             STEP(hipGetLastError());
         }

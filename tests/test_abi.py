@@ -51,6 +51,10 @@ def test_plan_rejects_bad_grids_on_host():
     assert L.mpg_plan(ctypes.byref(s), -1, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
     assert L.mpg_plan(ctypes.byref(s), 8, 7, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
     assert L.mpg_plan(ctypes.byref(s), 8, 0, 0, None, ctypes.byref(h)) == mpg.MPG_EINVAL
+    s.eval_point = 2
+    assert L.mpg_plan(ctypes.byref(s), 8, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL
+    assert b"eval_point" in L.mpg_last_error()
+    s.eval_point = mpg.EVAL_POINTS["centre"]
     assert L.mpg_plan(ctypes.byref(s), 65, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL  # lmax above 64
     assert L.mpg_plan_method(ctypes.byref(s), 8, 0, 1, 2, None, ctypes.byref(h)) == mpg.MPG_EINVAL  # method
     bad = r.copy()

@@ -427,3 +427,34 @@ def test_one_patch_and_yinyang_agree_for_smooth_density():
             M.append(O.radial(g, L, O.moments(g, L, U, W.cell_average(g, blobs, sub=4))))
         diffs.append(np.abs(M[0] - M[1]).max() / np.abs(M[1]).max())
     assert diffs[0] < 1e-3 and diffs[1] < 2.5e-4 and diffs[0] / diffs[1] > 3.0, diffs
+
+
+# --- evaluation at the angular cell centres ---------------------------------------
+
+def test_centre_evaluation_matches_brute_force():
+    """Phi at the cells' angular centres (outer shell radius) from the oracle's
+    tables agrees with the addition-theorem brute force at the same points."""
+    g = W.yinyang(4, W.geometric_edges(6, 1.5), 8)
+    g.eval_point = "centre"
+    w = O.overlap_weights(g)
+    rho = W.random_rho(g, 9)
+    phi, *_ = O.potential(g, 8, rho, w)
+    pts = [(p, i, c) for p in range(2) for i in (0, 3, 5) for c in (0, 9, 47)]
+    p, i, c = map(np.array, zip(*pts))
+    bf = O.brute_phi(g, 8, w, rho, p, i, c, nq=12)
+    got = phi.reshape(2, g.n_r, -1)[p, i, c]
+    assert np.abs(got - bf).max() <= 1e-13 * np.abs(bf).max()
+    gv = W.yinyang(4, W.geometric_edges(6, 1.5), 8)
+    phv, *_ = O.potential(gv, 8, rho, w)
+    assert np.abs(phv - phi).max() > 1e-6 * np.abs(phi).max()  # a different point set
+
+
+def test_centre_evaluation_of_homogeneous_sphere():
+    g = W.yinyang(8, W.uniform_edges(10), 0)
+    g.eval_point = "centre"
+    w = O.overlap_weights(g)
+    R = g.r_edges[6]
+    phi, *_ = O.potential(g, 0, _sphere_rho(g, 6), w)
+    r = g.r_edges[1:]
+    exact = np.where(r >= R, -4 * math.pi / 3 * R ** 3 / r, -2 * math.pi * (R * R - r * r / 3))
+    assert np.abs(phi.reshape(2, g.n_r, -1) - exact[None, :, None]).max() < 1e-13

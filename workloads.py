@@ -45,6 +45,9 @@ class Grid:
     # matrices mapping each patch's local Cartesian frame to the density frame
     frames: list = field(default_factory=list)
     name: str = ""
+    # where Phi is evaluated in each cell, on the shell's outer radius:
+    # "vertex" (the upper vertex, Eq. gravpotmult) or "centre" (angular centre)
+    eval_point: str = "vertex"
 
     @property
     def n_ang(self):
