@@ -155,10 +155,17 @@ def cpu_baseline(lmax):
     O.expand(g, lmax, Q, M)
     dt = time.perf_counter() - t0
     terms = g.n_cells * g.n_lm
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {
         "value": terms / dt,
         "unit": "terms/s",
         "cores": 1,
+        "cpu": cpu,
         "kind": "oracle",
         "sample": (f"lmax {lmax}, Yin-Yang pi/128 (2x64x192 cells), 144 log-spaced shells, "
                    f"{terms:.3e} terms; moments + radial sums + expansion in {dt:.1f} s, "
