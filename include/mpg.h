@@ -6,7 +6,8 @@
  *
  * The library computes, for cell-averaged densities rho on every patch of a
  * grid, the potential Phi at the upper vertex (r_i^+, theta_j^+, phi_k^+) of
- * every cell (Eq. gravpotmult), in three device steps:
+ * every cell (Eq. gravpotmult; or at the angular centre on the same outer
+ * radius, see mpg_grid.eval_point), in three device steps:
  *   1. moments   B_{i,lm} = sum_g sum_jk rho_{g,i,jk} U_{g,jk,lm}      (Eq. B_CS, Sec. 4.3 step 2)
  *   2. radial sums M_{i,lm} of Eq. M_C (Sec. 4.3 step 4)
  *   3. expansion Phi_{g,i,jk} = sum_lm Q_{g,jk,lm} M_{i,lm}            (Sec. 4.3 step 5)
@@ -166,12 +167,14 @@ int mpg_potential(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
 /* Solve n independent fields with different plans (grid sizes and lmax)
  * together: one persistent work-queue kernel per stage (moments, radial
  * scans, expansion) holds the tiles of every field, longest first, and the
- * three launches are captured once in a hipGraph (per set of plans and
- * dtype) and replayed.  rho[f] and phi[f] are device pointers of field f
+ * three launches (after one launch that splits every field's input, in the
+ * split forms) are captured once in a hipGraph (per set of plans and dtype)
+ * and replayed.  rho[f] and phi[f] are device pointers of field f
  * (one field each), of element type dtype.  The plans must be distinct and
  * share precision; the work runs on plans[0]'s stream.  Not for concurrent
  * use from several host threads with the same plans.
- * Errors: MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE. */
+ * Errors: MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE, MPG_EUNSUPPORTED (a plan of
+ * the per-patch method). */
 int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho,
                         void *const *phi, int dtype);
 
