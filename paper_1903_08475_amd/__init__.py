@@ -194,15 +194,41 @@ class Plan:
                                  C.c_void_p(B.data_ptr()), C.c_void_p(M.data_ptr())))
         return B, M
 
-    def autotune(self, rho):
+    def tuning_key(self, n_fields, dtype):
+        """Key of this plan's tuning in a cache file: precision, method, grid
+        size, lmax, the number of fields and the input dtype."""
+        g = self.grid
+        return (f"{self.precision}/{self.method}/patches{g.n_patches}/shells{g.n_r}/"
+                f"cells{g.n_theta}x{g.n_phi}/lmax{self.lmax}/fields{n_fields}/{dtype}")
+
+    def autotune(self, rho, cache=None):
         """Time the K split of the moment contraction, the scan schedule and
         (split forms) the expansion's block shape on this input and keep the
-        fastest; returns (splitk, chunks, gemm2_rows)."""
+        fastest; returns (splitk, chunks, gemm2_rows).  With cache (a JSON
+        file path), choices stored there for the same key are applied
+        without timing, and new ones are added to it."""
+        import json
         n = self._fields(rho)
+        key = self.tuning_key(n, str(rho.dtype).replace("torch.", ""))
+        table = {}
+        if cache is not None and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                sk, ch, gr = (int(v) for v in table[key])
+                self.set_tuning(sk, ch, gr)
+                return sk, ch, gr
         sk, ch, gr = C.c_int(), C.c_int(), C.c_int()
         _check(lib().mpg_autotune(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
                                   C.byref(sk), C.byref(ch), C.byref(gr)))
-        return sk.value, ch.value, gr.value
+        res = (sk.value, ch.value, gr.value)
+        if cache is not None:
+            table[key] = list(res)
+            tmp = f"{cache}.tmp{os.getpid()}"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return res
 
     def set_tuning(self, splitk=0, chunks=0, gemm2_rows=0):
         """Set the autotuner's choices (0 leaves one as it is)."""

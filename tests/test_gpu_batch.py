@@ -126,3 +126,21 @@ def test_autotune_keeps_parity(precision):
     out = plan.potential(t).cpu().numpy()
     print(f"{precision}: autotuned splitk {sk}, scan chunks {ch}, expansion rows {rows}, err {rel_err(out, phi):.3e}")
     assert rel_err(out, phi) < TOL[precision]
+
+
+def test_autotune_cache_file(tmp_path):
+    """Choices stored in a cache file are applied to a new plan of the same
+    grid without timing, and the solve equals the first plan's bit for bit."""
+    import json
+    import torch
+    import paper_1903_08475_amd as mpg
+    g, w, U, Q = oracle_tables("medium")
+    t = torch.tensor(W.random_rho(g, 33), device="cuda").float()
+    cache = str(tmp_path / "tuning.json")
+    p1 = mpg.Plan(g, precision="split_bf16_tiered")
+    first = p1.autotune(t, cache=cache)
+    table = json.load(open(cache))
+    assert table == {p1.tuning_key(1, "float32"): list(first)}
+    p2 = mpg.Plan(g, precision="split_bf16_tiered")
+    assert p2.autotune(t, cache=cache) == first
+    assert np.array_equal(p1.potential(t).cpu().numpy(), p2.potential(t).cpu().numpy())
