@@ -59,7 +59,9 @@ def test_potential_at_sampled_vertices(precision, tol, method):
     g, w, U = big()
     rhos = np.stack([sparse_rho(g, 700 + f, SHELLS) for f in range(N_FIELDS)])
     pl = plan(precision, method)
-    out = pl.potential(torch.tensor(rhos, device="cuda"), out_dtype=torch.float64)
+    t = torch.tensor(rhos, device="cuda")
+    tuned = pl.autotune(t)  # as the benchmark does before it times
+    out = pl.potential(t, out_dtype=torch.float64)
     if method != "global":
         pl.close()
         plan.cache_clear()
@@ -73,7 +75,8 @@ def test_potential_at_sampled_vertices(precision, tol, method):
         ref = O.phi_points(g, g.lmax, M, p, i, c)
         err = rel_err(out[f][p, i, c], ref)
         worst = max(worst, err)
-    print(f"{precision} {method}: max rel err at sampled vertices {worst:.3e}")
+    print(f"{precision} {method} (K split, scan chunks, expansion rows {tuned}): "
+          f"max rel err at sampled vertices {worst:.3e}")
     assert worst < tol
 
 
