@@ -173,7 +173,7 @@ def cpu_baseline(lmax):
     }
 
 
-def batch_workload(dev, reps):
+def batch_workload(dev, reps, autotune=True):
     """The batching workload: 64 seeded fields of uneven sizes (shells
     U{100..800}, Delta in {pi/64, pi/128, pi/256}, lmax U{12..32}; ellipsoid
     with random semi-axes plus 4-32 blobs), solved in one batched call (one
@@ -192,7 +192,7 @@ def batch_workload(dev, reps):
         if k % 16 == 15:
             log(f"[bench] batch: {k + 1} fields generated")
     terms = sum(g.n_cells * g.n_lm for g, _ in fields)
-    res = {"fields": len(fields), "terms_per_batch": terms,
+    res = {"fields": len(fields), "terms_per_batch": terms, "plans_autotuned": autotune,
            "cells_per_batch": sum(g.n_cells for g, _ in fields)}
     phis = {}
     for prec, dtype in (("split_bf16_tiered", torch.float32), ("split_bf16", torch.float32),
@@ -200,6 +200,10 @@ def batch_workload(dev, reps):
         plans = [mpg.Plan(g, precision=prec) for g, _ in fields]
         rhos = [r.to(dtype) for r in rho64]
         out = [torch.empty_like(r) for r in rhos]
+        if autotune:  # each field's plan on its own input (the batch takes their K splits)
+            for p, r in zip(plans, rhos):
+                p.autotune(r)
+            log(f"[bench] batch {prec}: {len(plans)} plans autotuned")
         mpg.potential_batch(plans, rhos, out)  # builds and captures the graph
         torch.cuda.synchronize()
         stream = plans[0].stream
@@ -420,7 +424,7 @@ def main():
         log("[bench] 64-field batch")
         del rho, phi
         torch.cuda.empty_cache()
-        out["batch"] = batch_workload(dev, args.batch_reps)
+        out["batch"] = batch_workload(dev, args.batch_reps, autotune=not args.no_autotune)
 
     if cpu is not None:
         out["cpu_baseline"] = cpu
