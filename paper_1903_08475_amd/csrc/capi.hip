@@ -247,6 +247,10 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
         int tiles = col_tiles * ((p->n_r + 63) / 64);
         int s = (1024 + tiles - 1) / tiles;
         int kmax = p->kang() / 64;
+        // room for at least four splits for the autotuner to try, while the
+        // partial sums stay within 2 GiB
+        const double plane = 8.0 * p->np * (double)p->vfields(max_fields) * p->n_r;
+        while (s < 4 && (s + 1) * plane <= 2147483648.0) ++s;
         p->splitk = s < 1 ? 1 : (s > kmax ? kmax : s);
         if (p->splitk < 1) p->splitk = 1;
     }
@@ -444,7 +448,7 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
     p->splitk_sel = 0;
     int heur = choose_splitk(*p, n_fields);
     cands.push_back(heur);
-    for (int s = 1; s <= p->splitk; s *= 2)
+    for (int s = 1; s <= p->splitk; s = s < 4 ? s + 1 : 2 * s)  // 1, 2, 3, 4, 8, 16, ...
         if (s != heur) cands.push_back(s);
     int best_s = heur;
     float best_t = 1e30f;
