@@ -260,6 +260,9 @@ def main():
     ap.add_argument("--no-other-split", action="store_true", help="skip timing the other split form")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plans' default K split and scan schedule instead of autotuning them")
+    ap.add_argument("--tuning", default=None,
+                    help="SPLITK,CHUNKS,ROWS: apply these choices to the timed plan instead of autotuning it "
+                         "(e.g. to profile the configuration an autotuned run chose, without its timing launches)")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-patch comparison method")
     ap.add_argument("--batch", action="store_true",
                     help="also time the 64-field uneven batch (one batched call per precision)")
@@ -296,7 +299,13 @@ def main():
     log(f"[bench] building {prec} plan")
     plan = mpg.Plan(grid, precision=prec, max_fields=n)
     tuned = None
-    if not args.no_autotune:
+    if args.tuning:
+        sk, ch, rows = (int(v) for v in args.tuning.split(","))
+        plan.set_tuning(sk, ch, rows)
+        tuned = {"gemm1_splitk": sk, "scan_chunks": ch, "expansion_block": "128x256" if rows == 1 else "256x128",
+                 "given": True}
+        log(f"[bench] tuning given: K split {sk}, scan chunks {ch}, expansion block {tuned['expansion_block']}")
+    elif not args.no_autotune:
         sk, ch, rows = plan.autotune(rho)
         tuned = {"gemm1_splitk": sk, "scan_chunks": ch,
                  "expansion_block": "128x256" if rows == 1 else "256x128"}
