@@ -109,8 +109,11 @@ typedef struct mpg_plan_s *mpg_plan_t;
  *                products h*h + h*m + m*h (16-bit operands) for the rest:
  *                about 45% less MFMA work at lmax 48.  Its potential stays
  *                within 1e-6 (max-norm relative) of the FP64 result on the
- *                test workloads; its moments B and M of high degree carry
- *                errors of a few 1e-6 of max|B|.
+ *                test workloads.  The moments B and M that mpg_moments
+ *                returns are formed with six products on every column in
+ *                both split forms (within 1e-6 of max|B|); the tiered
+ *                three-product moments only feed the expansion inside
+ *                mpg_potential.
  *   max_fields : largest n_fields later passed to the compute calls (>= 1);
  *                sizes the work space
  *   stream     : hipStream_t on which the plan runs (NULL: default stream)
@@ -153,6 +156,8 @@ int mpg_plan_method(const mpg_grid *grid, int lmax, int precision, int max_field
 /* Moments only (Eq. B_CS and Eq. M_C).
  *   rho   : device, n_fields fields of rho_dtype
  *   B, M  : device FP64 [n_fields][n_r][n_lm] in the real index, or NULL
+ * The split forms contract with six bf16 products on every column here
+ * (the tiered form included).  Any number of (field, shell) rows.
  * Errors: MPG_EINVAL (n_fields out of [1, max_fields], bad dtype, null
  * rho), MPG_EDEVICE. */
 int mpg_moments(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
@@ -169,8 +174,10 @@ int mpg_potential(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
  * scans, expansion) holds the tiles of every field, longest first, and the
  * three launches (after one launch that splits every field's input, in the
  * split forms) are captured once in a hipGraph (per set of plans and dtype)
- * and replayed.  rho[f] and phi[f] are device pointers of field f
- * (one field each), of element type dtype.  The plans must be distinct and
+ * and replayed; a later mpg_autotune or mpg_set_tuning of one of the plans
+ * makes the next call capture afresh.  rho[f] and phi[f] are device
+ * pointers of field f, each holding exactly one field of plans[f]'s grid
+ * (the library cannot check their sizes), of element type dtype.  The plans must be distinct and
  * share precision; the work runs on plans[0]'s stream.  Not for concurrent
  * use from several host threads with the same plans.
  * Errors: MPG_EINVAL, MPG_ENOMEM, MPG_EDEVICE, MPG_EUNSUPPORTED (a plan of

@@ -199,7 +199,7 @@ class Plan:
         size, lmax, the number of fields and the input dtype."""
         g = self.grid
         return (f"{self.precision}/{self.method}/patches{g.n_patches}/shells{g.n_r}/"
-                f"cells{g.n_theta}x{g.n_phi}/lmax{self.lmax}/fields{n_fields}/{dtype}")
+                f"cells{g.n_theta}x{g.n_phi}/lmax{self.lmax}/fields{n_fields}/max{self.max_fields}/{dtype}")
 
     def autotune(self, rho, cache=None):
         """Time the K split of the moment contraction, the scan schedule and
@@ -216,8 +216,11 @@ class Plan:
                 table = json.load(f)
             if key in table:
                 sk, ch, gr = (int(v) for v in table[key])
-                self.set_tuning(sk, ch, gr)
-                return sk, ch, gr
+                try:
+                    self.set_tuning(sk, ch, gr)
+                    return sk, ch, gr
+                except MpgError:
+                    pass  # not applicable to this plan (e.g. its work space): time afresh
         sk, ch, gr = C.c_int(), C.c_int(), C.c_int()
         _check(lib().mpg_autotune(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
                                   C.byref(sk), C.byref(ch), C.byref(gr)))
@@ -264,14 +267,24 @@ class Plan:
 
 
 def potential_batch(plans, rhos, phis):
-    """Solve independent fields with their own plans in one call."""
+    """Solve independent fields with their own plans in one call: field k
+    is one field of plans[k]'s grid (rhos[k] and phis[k] contiguous device
+    tensors of that size and one shared dtype)."""
     n = len(plans)
+    if n == 0:
+        raise ValueError("no fields")
     if not (len(rhos) == len(phis) == n):
         raise ValueError("plans, rhos and phis differ in length")
-    dt = _dtype_code(rhos[0]) if n else MPG_F64
-    for r, p in zip(rhos, phis):
+    dt = _dtype_code(rhos[0])
+    for k, (pl, r, p) in enumerate(zip(plans, rhos, phis)):
         if _dtype_code(r) != dt or _dtype_code(p) != dt:
             raise TypeError("all rho and phi must share one dtype")
+        per = int(np.prod(pl.shape))
+        for name, t in (("rho", r), ("phi", p)):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name}[{k}] must be a contiguous device tensor")
+            if t.numel() != per:
+                raise ValueError(f"{name}[{k}] has {t.numel()} elements; one field of its plan has {per}")
     H = (C.c_void_p * n)(*[p.handle for p in plans])
     R = (C.c_void_p * n)(*[r.data_ptr() for r in rhos])
     P = (C.c_void_p * n)(*[p.data_ptr() for p in phis])

@@ -32,6 +32,7 @@ __global__ void k_batch_start(int *heads, int n_heads, unsigned long long *stamp
 
 struct Batch {
     std::vector<const Plan *> plans;
+    std::vector<int> epochs;  // the plans' tuning epochs when the batch was built
     int dtype = MPG_F64, precision = MPG_FP64;
     int n1 = 0, ns = 0, n2 = 0;
     std::vector<SplitArgs> sa;
@@ -83,6 +84,7 @@ int cu_count() {
 
 hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     b.plans = plans;
+    for (const Plan *p : plans) b.epochs.push_back(p->tune_epoch);
     b.dtype = dtype;
     b.precision = plans[0]->precision;
     const int n = (int)plans.size();
@@ -214,12 +216,26 @@ Batch *find(const std::vector<const Plan *> &plans, int dtype) {
     return nullptr;
 }
 
+// whether a plan's tuning changed since the batch captured its launches
+bool stale(const Batch &b) {
+    for (size_t f = 0; f < b.plans.size(); ++f)
+        if (b.plans[f]->tune_epoch != b.epochs[f]) return true;
+    return false;
+}
+
 }  // namespace
 
 hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *const *rho, void *const *phi,
                            int dtype, hipStream_t stream) {
     std::lock_guard<std::mutex> lock(g_mu);
     Batch *b = find(plans, dtype);
+    if (b && stale(*b)) {
+        // captured with older tuning choices: rebuild (after its last replay)
+        CHECK(hipStreamSynchronize(stream));
+        g_batches.erase(std::find(g_batches.begin(), g_batches.end(), b));
+        delete b;
+        b = nullptr;
+    }
     if (!b) {
         b = new (std::nothrow) Batch();
         if (!b) return hipErrorOutOfMemory;

@@ -311,13 +311,22 @@ static int check_call(mpg_plan_t p, int n_fields, const void *rho, int dt, const
 }
 
 // GEMM1 and the scans of n_fields fields (for the per-patch method:
-// n_patches single-patch fields per field, each patch in its own frame)
-static int run_moments(const Plan *p, int n_fields_in, const void *rho, int rho_dtype, bool split_out) {
+// n_patches single-patch fields per field, each patch in its own frame).
+// all_six: the split forms take six products on every moment column (the
+// moments a caller reads back meet the six-product error bound in either
+// split form; the tiered form's three-product columns only feed the
+// expansion).
+static int run_moments(const Plan *p, int n_fields_in, const void *rho, int rho_dtype, bool split_out,
+                       bool all_six = false) {
     hipError_t e;
     const int n_fields = p->vfields(n_fields_in);
     int sk = choose_splitk(*p, n_fields);
     Plan q = *p;
     q.splitk = sk;
+    if (all_six) {
+        q.six_e = q.ne_p;
+        q.six_o = q.no_p;
+    }
     hipEvent_t ev;
     if (p->split()) {
         ev = stage_begin(q, 0);
@@ -342,7 +351,7 @@ static int run_moments(const Plan *p, int n_fields_in, const void *rho, int rho_
 int mpg_moments(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, double *B, double *M) {
     int rc = check_call(p, n_fields, rho, rho_dtype, "mpg_moments");
     if (rc) return rc;
-    if ((rc = run_moments(p, n_fields, rho, rho_dtype, false))) return rc;
+    if ((rc = run_moments(p, n_fields, rho, rho_dtype, false, true))) return rc;
     hipError_t e;
     const int vf = p->vfields(n_fields);
     if (B && (e = unpermute(*p, vf, p->Bred, B)) != hipSuccess) return hip_fail(e, "mpg_moments: B");
@@ -516,6 +525,7 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
     p->splitk_sel = best_s;
     p->scan_chunks = best_c;
     p->gemm2_rows = best_r;
+    ++p->tune_epoch;
     if (splitk) *splitk = best_s;
     if (chunks) *chunks = best_c;
     if (gemm2_rows) *gemm2_rows = best_r;
@@ -537,6 +547,7 @@ int mpg_set_tuning(mpg_plan_t p, int splitk, int chunks, int gemm2_rows) {
     if (splitk > 0) p->splitk_sel = splitk;
     if (chunks > 0) p->scan_chunks = chunks;
     if (gemm2_rows > 0) p->gemm2_rows = gemm2_rows;
+    ++p->tune_epoch;
     return MPG_OK;
 }
 

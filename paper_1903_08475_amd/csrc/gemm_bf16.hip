@@ -623,7 +623,7 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.kq = pp2 ? p.kq() : p.np;
     g.tiles_e = p.tiles_e();
     g.tiles_o = p.tiles_o();
-    g.kchunk = ((p.kang() / p.splitk + TK - 1) / TK) * TK;
+    g.kchunk = ksplit_chunk(p.kang(), p.splitk, TK);
     g.splitk = p.splitk;
     g.U = p.Us;
     g.Q = p.Qs;

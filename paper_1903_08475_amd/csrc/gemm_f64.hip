@@ -357,7 +357,7 @@ F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io
     g.kq = pp2 ? p.kq() : p.np;
     g.tiles_e = p.fold ? (p.ne_p + T1 - 1) / T1 : (p.np + T1 - 1) / T1;
     g.tiles_o = p.fold ? (p.no_p + T1 - 1) / T1 : 0;
-    g.kchunk = ((p.kang() / p.splitk + BK - 1) / BK) * BK;
+    g.kchunk = ksplit_chunk(p.kang(), p.splitk, BK);
     g.splitk = p.splitk;
     g.Ut = p.Ut;
     g.Qt = p.Qt;

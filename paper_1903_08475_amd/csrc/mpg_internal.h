@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/mpg.h"
+#include "ksplit.h"
 
 namespace mpg {
 
@@ -104,6 +105,7 @@ struct Plan {
     int splitk_sel = 0;        // chosen by mpg_autotune (0: heuristic)
     int scan_chunks = 16;      // shell chunks per column in the radial scan
     int gemm2_rows = 1;        // split expansion blocks: 1 = 128 rows x 256 cells, 2 = 256 x 128
+    int tune_epoch = 0;        // raised whenever the choices above change (batched solves rebuild)
     double *Bpart = nullptr;   // [splitk][rows][np]
     double *Bred = nullptr;    // [rows][np]
     double *M = nullptr;       // [rows][np]

@@ -210,12 +210,14 @@ __global__ __launch_bounds__(1024) void k_batch_scan(const ScanArgs *__restrict_
     }
 }
 
+// one thread per (row, permuted column), flat over rows * np
 __global__ void k_unpermute(const double *src, int rows, int np, int n_lm, const int *col_src, double *dst) {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    int row = blockIdx.y;
-    if (q >= np || row >= rows) return;
-    int s = col_src[q];
-    if (s >= 0) dst[(size_t)row * n_lm + s] = src[(size_t)row * np + q];
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)rows * np) return;
+    const size_t row = t / np;
+    const int q = (int)(t - row * np);
+    const int s = col_src[q];
+    if (s >= 0) dst[row * n_lm + s] = src[t];
 }
 
 }  // namespace
@@ -256,9 +258,9 @@ hipError_t batch_scan(const ScanArgs *args, const BatchItem *items, int n_items,
 }
 
 hipError_t unpermute(const Plan &p, int n_fields, const double *src, double *dst) {
-    if (n_fields * p.n_r > 65535) return hipErrorInvalidConfiguration;
-    dim3 grid((p.np + 127) / 128, n_fields * p.n_r);
-    hipLaunchKernelGGL(k_unpermute, grid, dim3(128), 0, p.stream, src, n_fields * p.n_r, p.np, p.n_lm, p.col_src, dst);
+    const size_t n = (size_t)n_fields * p.n_r * p.np;
+    dim3 grid((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(k_unpermute, grid, dim3(256), 0, p.stream, src, n_fields * p.n_r, p.np, p.n_lm, p.col_src, dst);
     return hipGetLastError();
 }
 

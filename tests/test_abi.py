@@ -82,3 +82,44 @@ def test_plan_rejects_bad_grids_on_host():
     assert L.mpg_potential(None, 1, None, 0, None, 0) == mpg.MPG_EINVAL
     assert L.mpg_set_tuning(None, 1, 16, 1) == mpg.MPG_EINVAL
     assert L.mpg_autotune(None, 1, None, 0, None, None, None) == mpg.MPG_EINVAL
+
+
+class _FakeTensor:
+    """Stands in for a device tensor in the host-side argument checks."""
+
+    def __init__(self, n, dtype):
+        self.n, self.dtype, self.is_cuda = n, dtype, True
+
+    def numel(self):
+        return self.n
+
+    def is_contiguous(self):
+        return True
+
+    def data_ptr(self):
+        raise AssertionError("the library must not be called")
+
+
+class _FakePlan:
+    def __init__(self, shape):
+        self.shape = shape
+
+    @property
+    def handle(self):
+        raise AssertionError("the library must not be called")
+
+
+def test_batch_refuses_wrong_size_fields_before_the_library():
+    import torch
+    plans = [_FakePlan((2, 4, 3, 5)), _FakePlan((1, 2, 2, 2))]
+    good = [_FakeTensor(120, torch.float32), _FakeTensor(8, torch.float32)]
+    short = [_FakeTensor(120, torch.float32), _FakeTensor(7, torch.float32)]
+    two = [_FakeTensor(240, torch.float32), _FakeTensor(8, torch.float32)]
+    with pytest.raises(ValueError, match="rho\\[1\\] has 7 elements"):
+        mpg.potential_batch(plans, short, good)
+    with pytest.raises(ValueError, match="phi\\[0\\] has 240 elements"):
+        mpg.potential_batch(plans, good, two)
+    with pytest.raises(TypeError):
+        mpg.potential_batch(plans, good, [_FakeTensor(120, torch.float64), _FakeTensor(8, torch.float32)])
+    with pytest.raises(ValueError):
+        mpg.potential_batch(plans[:1], good, good)

@@ -99,6 +99,59 @@ def test_moments_on_sampled_shells_of_the_benchmark_field():
             assert rel_err(B[f, i], Bo[i]) < 1e-6, (f, i)
 
 
+_SHARED = {}
+
+
+def _moments_worker(shells):
+    g, U, rho = _SHARED["g"], _SHARED["U"], _SHARED["rho"]
+    B = np.zeros((g.n_r, g.n_lm))
+    O.moments(g, g.lmax, U, rho, shells=list(shells), B=B)
+    return list(shells), B[list(shells)]
+
+
+def oracle_moments_all_shells(g, U, rho, workers=16):
+    """The oracle's moments of every shell of one field, shells dealt to
+    forked worker processes (each runs the single-threaded oracle)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    _SHARED.update(g=g, U=U, rho=rho)
+    chunks = [range(k, g.n_r, 4 * workers) for k in range(4 * workers)]
+    B = np.zeros((g.n_r, g.n_lm))
+    try:
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+            for sh, rows in ex.map(_moments_worker, chunks):
+                B[sh] = rows
+    finally:
+        _SHARED.clear()
+    return B
+
+
+def test_tiered_potential_of_the_benchmark_field():
+    """The benchmark's own density, all 1200 shells of 8 snapshots, solved in
+    the benchmarked form (tiered split-BF16, autotuned as the benchmark
+    does): Phi of snapshots 0 and 7 against the oracle at sampled vertices
+    (the oracle's moments cover every shell, as every radius needs them)."""
+    import torch
+    g, w, U = big()
+    dev = torch.device("cuda")
+    rho = torch.empty((N_FIELDS,) + g.shape, dtype=torch.float32, device=dev)
+    for t in range(N_FIELDS):
+        rho[t] = W.cell_average(g, W.density5(t), sub=2, device=dev, as_tensor=True, out_dtype=torch.float32)
+    pl = plan("split_bf16_tiered")
+    tuned = pl.autotune(rho)
+    out = pl.potential(rho).cpu().numpy().reshape(N_FIELDS, 2, g.n_r, -1)
+    worst = 0.0
+    for f in (0, 7):
+        B = oracle_moments_all_shells(g, U, rho[f].double().cpu().numpy())
+        p, i, c = sample_points(g, 1300 + f, 64)
+        M = O.radial(g, g.lmax, B, shells=sorted(set(i.tolist())))
+        ref = O.phi_points(g, g.lmax, M, p, i, c)
+        err = rel_err(out[f][p, i, c], ref)
+        print(f"benchmark field, snapshot {f}, tiered (tuning {tuned}): max rel err at sampled vertices {err:.3e}")
+        worst = max(worst, err)
+    assert worst < 1e-6
+
+
 def test_symmetries_at_full_size():
     """Scaling the density by 2 scales the potential by 2 bit for bit (binary
     scaling commutes with every rounding step).  Swapping the patches swaps
