@@ -286,6 +286,115 @@ __device__ __forceinline__ void ring_barrier() {
     asm volatile("" ::: "memory");
 }
 
+// ---------------------------------------------------------------------------
+// Software-pipelined ring.  The fragments of one 16-deep step of a wave's
+// 64x64 tile (h and m pieces of its two A row blocks and two B column
+// blocks, plus the l pieces with six products) are read from LDS while the
+// MFMAs of the previous step run, so LDS latency hides behind MFMA work.
+// The workgroup barrier of a slab sits between its two steps: the second
+// step's fragments are already in registers, and the first step of the
+// next slab is read right after it, while the second step's MFMAs run.
+template <bool SIX>
+struct Frags {
+    v8bf a[SIX ? 3 : 2][2], b[SIX ? 3 : 2][2];  // [piece][block]
+};
+
+template <int NA, int NB, bool SIX>
+__device__ __forceinline__ void read_frags(Frags<SIX> &F, const SlabT<NA, NB> &S, int ks, int wm, int wn,
+                                           int lane) {
+    const int r = lane & 31, kc = 2 * ks + (lane >> 5);
+    const int ao = (wm >> 7) * kPiece, ar = wm & 127, bo = (wn >> 7) * kPiece, br = wn & 127;
+#pragma unroll
+    for (int q = 0; q < (SIX ? 3 : 2); ++q)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            F.a[q][i] = frag(S.a[q] + ao, ar + 32 * i + r, kc);
+            F.b[q][i] = frag(S.b[q] + bo, br + 32 * i + r, kc);
+        }
+}
+
+// the partial products of one step, in the order of mma_slab (smallest
+// weight first, product by product over the four accumulators)
+template <bool SIX>
+__device__ __forceinline__ void mma_frags(const Frags<SIX> &F, v16f (&acc)[2][2]) {
+#define MMQ(X, Y)                                                                              \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) \
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.a[X][i], F.b[Y][j], acc[i][j], 0, 0, 0);
+    if constexpr (SIX) {
+        MMQ(2, 0)
+        MMQ(1, 1)
+        MMQ(0, 2)
+    }
+    MMQ(1, 0)
+    MMQ(0, 1)
+    MMQ(0, 0)
+#undef MMQ
+}
+
+// Barrier of the pipelined ring: this wave's fragment reads and slab copies
+// are complete, then every wave joins.  The scheduling barriers keep the
+// compiler from moving MFMAs or LDS reads across it.
+__device__ __forceinline__ void pipe_barrier() {
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Multiplies nsl consecutive K slabs (slab t is block k0 + t*dk of the
+// tiles), all with six products (SIX) or all with three, into acc through
+// the two buffers S0, S1.  Step t: read the second step's fragments of slab
+// t, multiply the first step's, barrier (slab t+1 has landed, and no wave
+// reads slab t's buffer any more), copy slab t+2 into that buffer, read the
+// first step's fragments of slab t+1, multiply the second step's.  With
+// FLUSH, acc is added into acc64 and cleared after every kFlushSlabs slabs
+// and at the end.  Every wave calls it with the same k0, dk, nsl; both
+// buffers must be free on entry (no wave reading them, no copy in flight),
+// and are free again on return.  Without MMA only the copies, reads and
+// barriers (waves whose tile lies past the end of the block).
+template <int NA, int NB, bool SIX, bool FLUSH, bool MMA = true>
+__device__ __forceinline__ void run_pipe(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
+                                         int dk, int nsl, int wm, int wn, int lane, v16f (&acc)[2][2],
+                                         double (&acc64)[2][2][16]) {
+    if (nsl <= 0) return;
+    Frags<SIX> F0, F1;
+    load_slab(S0, L, k0, SIX);
+    pipe_barrier();
+    if (nsl > 1) load_slab(S1, L, k0 + dk, SIX);
+    read_frags<NA, NB, SIX>(F0, S0, 0, wm, wn, lane);
+#define PIPE_STEP(CUR, NXT, O)                                               \
+    {                                                                        \
+        const int t = s + O;                                                 \
+        read_frags<NA, NB, SIX>(F1, CUR, 1, wm, wn, lane);                   \
+        if (MMA) mma_frags<SIX>(F0, acc);                                    \
+        pipe_barrier();                                                      \
+        if (t + 2 < nsl) load_slab(CUR, L, k0 + (t + 2) * dk, SIX);          \
+        if (t + 1 < nsl) read_frags<NA, NB, SIX>(F0, NXT, 0, wm, wn, lane);  \
+        if (MMA) mma_frags<SIX>(F1, acc);                                    \
+    }
+    for (int s0 = 0; s0 < nsl; s0 += kFlushSlabs) {
+#pragma unroll
+        for (int j = 0; j < kFlushSlabs / 2; ++j) {
+            const int s = s0 + 2 * j;
+            if (s < nsl) PIPE_STEP(S0, S1, 0)
+            if (s + 1 < nsl) PIPE_STEP(S1, S0, 1)
+        }
+        if (FLUSH && MMA) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc64[a][b][r] += (double)acc[a][b][r];
+            zero(acc);
+        }
+    }
+#undef PIPE_STEP
+}
+
+
 // Steps t0 <= t < t1 of run_ring (below), all with six products (SIX) or
 // all with three; without MMA only the copies and barriers.
 template <int NA, int NB, bool FLUSH, bool SIX, bool MMA>
@@ -347,6 +456,28 @@ __device__ __forceinline__ void run_ring(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, c
     asm volatile("" ::: "memory");
     MPG_WAIT_VM(0);
     asm volatile("" ::: "memory");
+}
+
+// nsl slabs whose first n3 take three products (pipelined ring) and the
+// rest six (the plain ring, which keeps one step's fragments in registers:
+// the expansion's two accumulator sets leave no room for two six-product
+// fragment sets); the second run starts with its own first copy
+// (PIPE false: the plain ring for both, for kernels with no registers to
+// spare for a second fragment set)
+template <int NA, int NB, bool PIPE = true>
+__device__ __forceinline__ void run_tiered(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
+                                           int dk, int nsl, int n3, int wm, int wn, int lane, v16f (&acc)[2][2],
+                                           double (&acc64)[2][2][16]) {
+    if constexpr (!PIPE) {
+        run_ring<NA, NB, false>(S0, S1, L, k0, dk, nsl, n3, n3, wm, wn, lane, acc, acc64);
+        __syncthreads();
+        return;
+    }
+    run_pipe<NA, NB, false, false>(S0, S1, L, k0, dk, n3, wm, wn, lane, acc, acc64);
+    if (nsl > n3) {
+        run_ring<NA, NB, false>(S0, S1, L, k0 + n3 * dk, dk, nsl - n3, 0, 0, wm, wn, lane, acc, acc64);
+        __syncthreads();  // no wave still reads the buffers the next run refills
+    }
 }
 
 // Leading three-product slabs of a K walk of nsl slabs that runs from the
@@ -465,13 +596,11 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     if (FOLD) {
         const int ne = ne_p / TK, no = (np - ne_p) / TK;
         const int e3 = three_slabs(ne, g.six_e / TK), o3 = three_slabs(no, g.six_o / TK);
-        run_ring<NA, NB, false>(S0, S1, L, ne - 1, -1, ne, e3, e3, wm, wn, lane, acc_e, acc64);
-        // the odd block refills buffers the even block's last slabs were read from
-        __syncthreads();
-        run_ring<NA, NB, false>(S0, S1, L, ne + no - 1, -1, no, o3, o3, wm, wn, lane, acc_o, acc64);
+        run_tiered<NA, NB>(S0, S1, L, ne - 1, -1, ne, e3, wm, wn, lane, acc_e, acc64);
+        run_tiered<NA, NB>(S0, S1, L, ne + no - 1, -1, no, o3, wm, wn, lane, acc_o, acc64);
     } else if (!pp) {
         const int ns = g.ks2, n3 = three_slabs(ns, g.six_e / TK);
-        run_ring<NA, NB, false>(S0, S1, L, ns - 1, -1, ns, n3, n3, wm, wn, lane, acc_e, acc64);
+        run_tiered<NA, NB>(S0, S1, L, ns - 1, -1, ns, n3, wm, wn, lane, acc_e, acc64);
     } else {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -481,8 +610,7 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
                 for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
         const int nsb = np / TK, n3 = three_slabs(nsb, g.six_e / TK);
         for (int gq = 0; gq < g.nq; ++gq) {
-            if (gq) __syncthreads();
-            run_ring<NA, NB, false>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, n3, n3, wm, wn, lane, acc_e, acc64);
+            run_tiered<NA, NB, false>(S0, S1, L, (gq + 1) * nsb - 1, -1, nsb, n3, wm, wn, lane, acc_e, acc64);
             // each patch's moment set is summed in FP32 (as the single set
             // of the other forms) and added in FP64
 #pragma unroll
