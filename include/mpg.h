@@ -169,6 +169,25 @@ int mpg_moments(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
 int mpg_potential(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
                   void *phi, int phi_dtype);
 
+/* The whole solve as mpg_potential, allocating nothing: for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  The work arrays of the call
+ * (K-split partial moments, B, M and, in the split forms, the bf16 pieces
+ * of the input and of M) live in one static device array of
+ * MPG_STATIC_WORKSPACE_MB MiB per GPU, part of the library's code object
+ * and held until the process ends, instead of the plan's work space; the
+ * plan supplies only its tables.  The plan's K split choice is reduced
+ * until the call's arrays fit; a call that does not fit even with one
+ * split fails with MPG_EINVAL and a message stating the size it needs.
+ * Nothing in the array needs clearing between calls: every entry a call
+ * reads it writes first.  Calls that overlap on one GPU (on different
+ * streams or host threads) race on the array and must be serialized by the
+ * caller.  The plan's device must be current.  No stage timing.
+ * Arguments, layout and errors as mpg_potential. */
+#define MPG_STATIC_WORKSPACE_MB 64
+int mpg_potential_static(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
+                         void *phi, int phi_dtype);
+
 /* Solve n independent fields with different plans (grid sizes and lmax)
  * together: one persistent work-queue kernel per stage (moments, radial
  * scans, expansion) holds the tiles of every field, longest first, and the

@@ -28,7 +28,8 @@ METHODS = {"global": 0, "per_patch": 1}
 EVAL_POINTS = {"vertex": 0, "centre": 1}
 
 # Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
-EXPORTS = ("mpg_plan", "mpg_plan_method", "mpg_moments", "mpg_potential", "mpg_potential_batch",
+EXPORTS = ("mpg_plan", "mpg_plan_method", "mpg_moments", "mpg_potential", "mpg_potential_static",
+           "mpg_potential_batch",
            "mpg_batch_field_times", "mpg_autotune", "mpg_set_tuning", "mpg_tables", "mpg_plan_info",
            "mpg_timing", "mpg_stage_times", "mpg_sync", "mpg_destroy", "mpg_last_error")
 STAGES = ("input_split", "moments", "radial_scan", "expansion")
@@ -68,6 +69,7 @@ def lib():
         L.mpg_plan_method.argtypes = [C.POINTER(_Grid), C.c_int, C.c_int, C.c_int, C.c_int, vp, C.POINTER(vp)]
         L.mpg_moments.argtypes = [vp, C.c_int, vp, C.c_int, vp, vp]
         L.mpg_potential.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int]
+        L.mpg_potential_static.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int]
         L.mpg_potential_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
         L.mpg_batch_field_times.argtypes = [C.c_int, C.POINTER(vp), C.c_int, dp]
         L.mpg_autotune.argtypes = [vp, C.c_int, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
@@ -180,6 +182,16 @@ class Plan:
             raise ValueError("out must be contiguous with rho's size")
         _check(lib().mpg_potential(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
                                    C.c_void_p(out.data_ptr()), _dtype_code(out)))
+        return out
+
+    def potential_static(self, rho, out):
+        """As potential(), through mpg_potential_static: nothing is allocated,
+        so the caller passes the output tensor (same size as rho)."""
+        n = self._fields(rho)
+        if not out.is_cuda or not out.is_contiguous() or out.numel() != rho.numel():
+            raise ValueError("out must be a contiguous device tensor of rho's size")
+        _check(lib().mpg_potential_static(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
+                                          C.c_void_p(out.data_ptr()), _dtype_code(out)))
         return out
 
     def moments(self, rho):

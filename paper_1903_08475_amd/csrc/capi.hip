@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "mpg_internal.h"
 
@@ -376,6 +377,103 @@ int mpg_potential(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, vo
     if (!phi) return fail(MPG_EINVAL, "mpg_potential: phi is NULL");
     if (phi_dtype != MPG_F64 && phi_dtype != MPG_F32) return fail(MPG_EINVAL, "mpg_potential: bad phi dtype");
     return solve(p, n_fields, rho, rho_dtype, phi, phi_dtype);
+}
+
+// ---- the solve without allocation (mpg_potential_static) -----------------
+//
+// Work space of mpg_potential_static: one file-scope device array per GPU
+// the library runs on, held until the process ends.  In host code its name
+// is a stand-in, not a device address: the address is taken per device
+// with hipGetSymbolAddress (with that device current) on the first call on
+// the device, and only that address is handed to kernels.
+}  // extern "C"
+
+namespace mpg {
+namespace {
+
+constexpr size_t kStaticBytes = size_t(MPG_STATIC_WORKSPACE_MB) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of this device's scratch array (taken once per device)
+hipError_t scratch_address(int dev, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Byte offsets of the work arrays of one call (q sized for this call's
+// fields: q.max_fields = n_fields) with `splitk` K splits: Bpart, Bred, M,
+// and for the split forms Ms and A_split; returns the total.
+size_t static_layout(const Plan &q, int splitk, size_t off[5]) {
+    const size_t rows = (size_t)q.rows_alloc(), np = (size_t)q.np;
+    size_t o = 0;
+    off[0] = o;
+    o += align256(sizeof(double) * splitk * rows * np);
+    off[1] = o;
+    o += align256(sizeof(double) * rows * np);
+    off[2] = o;
+    o += align256(sizeof(double) * rows * np);
+    off[3] = off[4] = o;
+    if (q.split()) {
+        o += align256(sizeof(bf16) * (size_t)q.out_row_tiles() * (q.kq() / kSlabK) * 3 * kBlk);
+        off[4] = o;
+        o += align256(sizeof(bf16) * (size_t)(q.fold ? 2 : 1) * q.row_tiles() * (q.kang() / kSlabK) * 3 * kBlk);
+    }
+    return o;
+}
+
+}  // namespace
+}  // namespace mpg
+
+extern "C" {
+
+int mpg_potential_static(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, void *phi, int phi_dtype) {
+    int rc = check_call(p, n_fields, rho, rho_dtype, "mpg_potential_static");
+    if (rc) return rc;
+    if (!phi) return fail(MPG_EINVAL, "mpg_potential_static: phi is NULL");
+    if (phi_dtype != MPG_F64 && phi_dtype != MPG_F32)
+        return fail(MPG_EINVAL, "mpg_potential_static: bad phi dtype");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "mpg_potential_static");
+    if (dev != p->device) return fail(MPG_EINVAL, "mpg_potential_static: the plan's device must be current");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MPG_EUNSUPPORTED, "mpg_potential_static: device index too large");
+    // this call's arrays, with the plan's K split choice reduced until they fit
+    Plan q = *p;
+    q.max_fields = n_fields;
+    q.timing = false;  // stage events would be created (allocated) per call
+    int sk = choose_splitk(q, q.vfields(n_fields));
+    size_t off[5];
+    while (sk > 1 && static_layout(q, sk, off) > kStaticBytes) --sk;
+    const size_t need = static_layout(q, sk, off);
+    if (need > kStaticBytes)
+        return fail(MPG_EINVAL, "mpg_potential_static: the call needs " + std::to_string(need >> 20) +
+                                    " MiB of work space, more than the " +
+                                    std::to_string(MPG_STATIC_WORKSPACE_MB) + " MiB static work space");
+    void *base = nullptr;
+    if ((e = scratch_address(dev, &base)) != hipSuccess) return hip_fail(e, "mpg_potential_static: work space");
+    unsigned char *b = (unsigned char *)base;
+    q.splitk = sk;
+    q.splitk_sel = sk;
+    q.Bpart = (double *)(b + off[0]);
+    q.Bred = (double *)(b + off[1]);
+    q.M = (double *)(b + off[2]);
+    q.Ms = q.split() ? (bf16 *)(b + off[3]) : nullptr;
+    q.A_split = q.split() ? (bf16 *)(b + off[4]) : nullptr;
+    return solve(&q, n_fields, rho, rho_dtype, phi, phi_dtype);
 }
 
 int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho, void *const *phi, int dtype) {
