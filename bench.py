@@ -173,7 +173,57 @@ def cpu_baseline(lmax):
     }
 
 
-def batch_workload(dev, reps, autotune=True):
+def fp64_workload(dev, steps):
+    """The FP64 workload (Yin-Yang pi/128, 400 shells of ratio 1.02, lmax 25,
+    ellipsoid + 16 blobs, float64 density): ms per solve on the FP64 path
+    (plan autotuned), throughput, and the FP64 MFMA fraction of its moment
+    contraction (2 flops per folded term against 78.6 TFLOP/s)."""
+    import torch
+    import paper_1903_08475_amd as mpg
+    import workloads as W
+    g = W.config2()
+    rho = W.cell_average(g, W.density2(), sub=4, device=dev, as_tensor=True)
+    phi = torch.empty_like(rho)
+    plan = mpg.Plan(g, precision="fp64")
+    tuned = plan.autotune(rho)
+    ms, _, st, pct = time_path(plan, rho, phi, steps, 2)
+    per = {k: v[0] / max(1, v[1]) for k, v in st.items()}
+    flops = 2.0 * g.n_r * g.n_ang * g.n_lm
+    out = {"workload": "Yin-Yang pi/128 (2x64x192 cells), 400 shells of ratio 1.02, lmax 25, float64",
+           "precision": "fp64", "ms_per_solve": ms, "ms_percentiles": pct,
+           "value": g.n_cells * g.n_lm / (ms * 1e-3), "unit": "terms/s", "stage_ms": per,
+           "moments_fp64_mfma_frac": flops / (per["moments"] * 1e-3) / PEAK_FP64,
+           "expansion_fp64_mfma_frac": flops / (per["expansion"] * 1e-3) / PEAK_FP64,
+           "autotuned": {"gemm1_splitk": tuned[0], "scan_chunks": tuned[1]}}
+    log(f"[bench] FP64 workload: {ms:.3f} ms per solve")
+    return out
+
+
+def precision_workload(dev):
+    """The precision workload (Yin-Yang pi/32, 32 shells, lmax 40; ellipsoid +
+    a point-like Gaussian mass): max-norm relative error of Phi against the
+    oracle for both split forms and the FP64 path, and split vs FP64."""
+    import torch
+    import oracle as O
+    import paper_1903_08475_amd as mpg
+    import workloads as W
+    g = W.config3()
+    rho = W.cell_average(g, W.density3(), sub=4)
+    phi_ref, *_ = O.potential(g, g.lmax, rho, O.overlap_weights(g))
+    t = torch.tensor(rho, device=dev)
+    res = {"workload": "Yin-Yang pi/32 (2x16x48 cells), 32 shells, lmax 40, ellipsoid + Gaussian mass"}
+    phis = {}
+    for prec in ("fp64", "split_bf16_tiered", "split_bf16"):
+        phis[prec] = mpg.Plan(g, precision=prec).potential(t).cpu().numpy()
+        res[f"{prec}_vs_oracle_max_rel_err"] = float(np.abs(phis[prec] - phi_ref).max() / np.abs(phi_ref).max())
+    for prec in ("split_bf16_tiered", "split_bf16"):
+        res[f"{prec}_vs_fp64_max_rel_err"] = float(np.abs(phis[prec] - phis["fp64"]).max()
+                                                   / np.abs(phis["fp64"]).max())
+    log(f"[bench] precision workload: tiered vs oracle {res['split_bf16_tiered_vs_oracle_max_rel_err']:.3e}")
+    return res
+
+
+def batch_workload(dev, reps, autotune=True, precisions=("split_bf16_tiered", "split_bf16", "fp64")):
     """The batching workload: 64 seeded fields of uneven sizes (shells
     U{100..800}, Delta in {pi/64, pi/128, pi/256}, lmax U{12..32}; ellipsoid
     with random semi-axes plus 4-32 blobs), solved in one batched call (one
@@ -195,8 +245,8 @@ def batch_workload(dev, reps, autotune=True):
     res = {"fields": len(fields), "terms_per_batch": terms, "plans_autotuned": autotune,
            "cells_per_batch": sum(g.n_cells for g, _ in fields)}
     phis = {}
-    for prec, dtype in (("split_bf16_tiered", torch.float32), ("split_bf16", torch.float32),
-                        ("fp64", torch.float64)):
+    for prec in precisions:
+        dtype = torch.float64 if prec == "fp64" else torch.float32
         plans = [mpg.Plan(g, precision=prec) for g, _ in fields]
         rhos = [r.to(dtype) for r in rho64]
         out = [torch.empty_like(r) for r in rhos]
@@ -238,7 +288,9 @@ def batch_workload(dev, reps, autotune=True):
         torch.cuda.synchronize()
         phis[prec] = out
         del plans
-    for prec in ("split_bf16_tiered", "split_bf16"):
+    for prec in precisions:
+        if prec == "fp64" or "fp64" not in phis:
+            continue
         err = 0.0
         for x, y in zip(phis[prec], phis["fp64"]):
             err = max(err, float((x.double() - y).abs().max() / y.abs().max()))
@@ -264,9 +316,13 @@ def main():
                     help="SPLITK,CHUNKS,ROWS: apply these choices to the timed plan instead of autotuning it "
                          "(e.g. to profile the configuration an autotuned run chose, without its timing launches)")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-patch comparison method")
-    ap.add_argument("--batch", action="store_true",
-                    help="also time the 64-field uneven batch (one batched call per precision)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-field uneven batch (one batched call per precision)")
+    ap.add_argument("--batch-all", action="store_true",
+                    help="time the batch in the six-product split form too")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the FP64 workload and the precision workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -429,11 +485,19 @@ def main():
         log(f"[bench] per-patch method: {ms_pp:.2f} ms/step ({ms_pp / ms:.2f}x the paper's method)")
         del pp, phi_pp
 
-    if args.batch:
-        log("[bench] 64-field batch")
+    if not args.no_workloads or not args.no_batch:
         del rho, phi
         torch.cuda.empty_cache()
-        out["batch"] = batch_workload(dev, args.batch_reps, autotune=not args.no_autotune)
+    if not args.no_workloads:
+        log("[bench] FP64 workload")
+        out["fp64_workload"] = fp64_workload(dev, 10)
+        log("[bench] precision workload")
+        out["precision_workload"] = precision_workload(dev)
+    if not args.no_batch:
+        log("[bench] 64-field batch")
+        torch.cuda.empty_cache()
+        precs = ("split_bf16_tiered", "split_bf16", "fp64") if args.batch_all else ("split_bf16_tiered", "fp64")
+        out["batch"] = batch_workload(dev, args.batch_reps, autotune=not args.no_autotune, precisions=precs)
 
     if cpu is not None:
         out["cpu_baseline"] = cpu

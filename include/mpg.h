@@ -221,7 +221,7 @@ int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms)
  *    allows (the default choice first, then 1, 2, 3, 4 and the powers of
  *    two beyond; another split is kept only when it is at least 1% faster;
  *    the work space holds at least four splits when their partial sums fit
- *    in 2 GiB);
+ *    in 2 GiB, and up to 32 while they fit in 512 MiB);
  *  - the radial scan's shell chunks per column: 4, 8, 12 or 16;
  *  - split forms: the expansion's block shape, 128 rows x 256 angular cells
  *    (gemm2_rows = 1, the default) or 256 x 128 (gemm2_rows = 2, kept only

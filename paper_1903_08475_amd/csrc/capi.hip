@@ -249,9 +249,12 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
         int s = (1024 + tiles - 1) / tiles;
         int kmax = p->kang() / 64;
         // room for at least four splits for the autotuner to try, while the
-        // partial sums stay within 2 GiB
+        // partial sums stay within 2 GiB, and up to 32 (small grids, whose
+        // moment contraction fills the chip only when split finely) while
+        // they stay within 512 MiB
         const double plane = 8.0 * p->np * (double)p->vfields(max_fields) * p->n_r;
         while (s < 4 && (s + 1) * plane <= 2147483648.0) ++s;
+        while (s < 32 && (s + 1) * plane <= 536870912.0) ++s;
         p->splitk = s < 1 ? 1 : (s > kmax ? kmax : s);
         if (p->splitk < 1) p->splitk = 1;
     }
