@@ -189,12 +189,21 @@ int mpg_potential_static(mpg_plan_t plan, int n_fields, const void *rho, int rho
                          void *phi, int phi_dtype);
 
 /* Solve n independent fields with different plans (grid sizes and lmax)
- * together: one persistent work-queue kernel per stage (moments, radial
- * scans, expansion) holds the tiles of every field, longest first, and the
- * three launches (after one launch that splits every field's input, in the
- * split forms) are captured once in a hipGraph (per set of plans and dtype)
- * and replayed; a later mpg_autotune or mpg_set_tuning of one of the plans
- * makes the next call capture afresh.  rho[f] and phi[f] are device
+ * together.  Split forms: one persistent kernel (one block per CU) takes
+ * the tiles of every stage of every field (input split, moments, radial
+ * scans, expansion) from one queue, whose order (fixed on the host by a
+ * list-scheduling simulation) puts every tile after the tiles of its
+ * field's previous stage; a tile waits on device counters until that stage
+ * has finished (a bounded wait: past about 4 s it gives up, every block
+ * drains, and mpg_batch_field_times reports it), so small fields complete
+ * early.  Each field's moment contraction is split along K only as far as
+ * needed for tiles of at most about 0.5 ms (a single solve's autotuned K
+ * split is not used: the other fields fill the chip).  FP64: one persistent work-queue
+ * kernel per stage (moments, radial scans, expansion), each holding the
+ * tiles of every field, longest first.  The launches are captured once in
+ * a hipGraph (per set of plans and dtype) and replayed; a later
+ * mpg_autotune or mpg_set_tuning of one of the plans makes the next call
+ * capture afresh.  rho[f] and phi[f] are device
  * pointers of field f, each holding exactly one field of plans[f]'s grid
  * (the library cannot check their sizes), of element type dtype.  The plans must be distinct and
  * share precision; the work runs on plans[0]'s stream.  Not for concurrent
@@ -211,11 +220,12 @@ int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho,
  * last expansion tile of field f finished, read from the device wall
  * clock.  Waits for plans[0]'s stream.
  * Errors: MPG_EINVAL (bad arguments, or no batched solve of these plans
- * and dtype), MPG_EDEVICE. */
+ * and dtype), MPG_EDEVICE (also when a stage wait of that solve gave up:
+ * its results are then incomplete). */
 int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms);
 
 /* Autotune the plan for n_fields fields on the given device input, and keep
- * the choices for later calls:
+ * the choices for later single-plan calls:
  *  - the K split of the moment contraction, timed together with the radial
  *    scan that reduces its partial sums, for every split the work space
  *    allows (the default choice first, then 1, 2, 3, 4 and the powers of
@@ -228,8 +238,8 @@ int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms)
  *    when at least 1% faster).  Its timing writes a temporary output of one
  *    call's size, allocated and freed here; if it cannot be allocated, the
  *    shape is left as it is.
- * Batched calls (mpg_potential_batch) use the K split; their scan and
- * expansion kernels keep fixed shapes.  Blocks until done; overwrites the
+ * Batched calls (mpg_potential_batch) keep fixed scan and expansion
+ * shapes.  Blocks until done; overwrites the
  * plan's work space.  splitk, chunks and gemm2_rows (each may be NULL)
  * receive the choices (gemm2_rows: 1 for the FP64 form).
  * Errors: as mpg_moments. */

@@ -1,15 +1,18 @@
 // Batched solve of many independent fields with different plans (grid
-// sizes, lmax) through persistent work-queue kernels, one per stage
-// (moment contraction, radial scans, expansion).  Each stage's queue holds
-// the tiles of every field, ordered longest first; the persistent blocks
-// pull tiles until the queue is empty.  The three launches, the counter
-// reset and (split forms) one launch that splits the inputs of every field
-// are captured once in a hipGraph and replayed; a call only refreshes
-// the fields' rho/phi pointers (kept in device memory, read by the kernels)
-// and launches the graph on the caller's stream.  The expansion kernels also
-// stamp the device wall clock when the last tile of a field is done, so the
-// per-field completion times inside one batched call can be read back.
+// sizes, lmax).  Split forms: one persistent kernel takes the items of
+// every stage (input split, moment contraction, radial scans, expansion)
+// of every field from one queue, in an order fixed on the host
+// (batch_order.h) so that each item's producers come before it; per-field
+// counters make an item wait for its field's previous stage, so fields
+// finish one after another instead of all at the end.  FP64: one persistent
+// work-queue kernel per stage, each queue holding the tiles of every field,
+// longest first.  The launches and a counter reset are captured once in a
+// hipGraph per plan list and dtype and replayed; a call only refreshes the
+// fields' rho/phi pointers (kept in device memory, read by the kernels) and
+// launches the graph on the caller's stream.  Per-field completion times
+// inside one batched call are stamped on the device and can be read back.
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <new>
 #include <utility>
@@ -20,8 +23,9 @@
 namespace mpg {
 namespace {
 
-// Start of a batched solve: clears the queue heads and the per-field
-// completion stamps and stamps the start time (stamps[n]).
+// Start of a batched solve: clears the queue heads (and the fused
+// kernel's counters and status word, n_heads of them in all) and the
+// per-field completion stamps, and stamps the start time (stamps[n]).
 __global__ void k_batch_start(int *heads, int n_heads, unsigned long long *stamps, int n) {
     for (int t = threadIdx.x; t < n_heads || t < n + 2; t += blockDim.x) {
         if (t < n_heads) heads[t] = 0;
@@ -41,8 +45,9 @@ struct Batch {
     void *args_dev = nullptr;
     ScanArgs *scan_dev = nullptr;
     BatchItem *items_dev = nullptr;
-    size_t *split_offs = nullptr;  // input split: first thread of each field, and the total
-    int *heads = nullptr;
+    int *heads = nullptr;        // fused: [0] queue head, [1] status, [2 ..] finished items per field and stage
+    int *need = nullptr;         // fused: items per field and stage
+    FusedItem *fitems = nullptr;
     unsigned long long *stamps = nullptr;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -55,8 +60,9 @@ struct Batch {
         if (args_dev) (void)hipFree(args_dev);
         if (scan_dev) (void)hipFree(scan_dev);
         if (items_dev) (void)hipFree(items_dev);
-        if (split_offs) (void)hipFree(split_offs);
         if (heads) (void)hipFree(heads);
+        if (need) (void)hipFree(need);
+        if (fitems) (void)hipFree(fitems);
         if (stamps) (void)hipFree(stamps);
     }
 };
@@ -82,57 +88,128 @@ int cu_count() {
         if (e_ != hipSuccess) return e_;          \
     } while (0)
 
-hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
+// Work of one field (one field of the plan) in the fused kernel's units.
+FieldShape field_shape(const Plan &p) {
+    FieldShape sh;
+    sh.split_units = (int)(split_input_threads(p, 1) / 2048);
+    sh.row_tiles1 = (p.n_r + kSplitTile - 1) / kSplitTile;
+    sh.pairs_e = (p.tiles_e() + 1) / 2;
+    sh.pairs_o = (p.tiles_o() + 1) / 2;
+    sh.six_e = six_pairs(p.six_e, sh.pairs_e);
+    sh.six_o = p.fold ? six_pairs(p.six_o, sh.pairs_o) : 0;
+    sh.kang = p.kang();
+    sh.splitk_max = p.splitk;
+    // a single solve's K split choice fills the chip with one field's tiles;
+    // in a batch the other fields fill it, so only the item length counts
+    sh.splitk_min = 1;
+    sh.scan_blocks = (p.np + 63) / 64;
+    sh.n_r = p.n_r;
+    sh.row_tiles2 = (p.n_r + kSplitTile - 1) / kSplitTile;
+    sh.ang_pairs = (p.n2() / kSplitTile + 1) / 2;
+    if (p.fold) {
+        const int ne = p.ne_p / kSlabK, no = p.no_p / kSlabK;
+        const int e3 = three_slabs(ne, p.six_e / kSlabK), o3 = three_slabs(no, p.six_o / kSlabK);
+        sh.k2_three = e3 + o3;
+        sh.k2_six = (ne - e3) + (no - o3);
+    } else {
+        const int ns = p.kq() / kSlabK, n3 = three_slabs(ns, p.six_e / kSlabK);
+        sh.k2_three = n3;
+        sh.k2_six = ns - n3;
+    }
+    return sh;
+}
+
+// polls of a stage wait before it gives up (about 4 s; MPG_BATCH_SPIN_LIMIT
+// overrides it when the batch is built, to exercise the give-up path)
+int spin_limit() {
+    const char *v = getenv("MPG_BATCH_SPIN_LIMIT");
+    const long x = v ? strtol(v, nullptr, 10) : 0;
+    return x > 0 && x < (1L << 30) ? (int)x : (1 << 24);
+}
+
+// Split forms: every stage of every field in one persistent kernel (one
+// block per CU), items in the order of batch_order.h; each field's K split
+// as fused_splitk chooses.
+hipError_t build_fused(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     b.plans = plans;
     for (const Plan *p : plans) b.epochs.push_back(p->tune_epoch);
     b.dtype = dtype;
     b.precision = plans[0]->precision;
     const int n = (int)plans.size();
-    const bool split = b.precision != MPG_FP64;
-    // tile sides of the moment contraction (rows) and the expansion
-    const int T1 = split ? kSplitTile : kF64Tile1, T2 = split ? kSplitTile : kF64Tile2;
+    const int cus = cu_count();
+    std::vector<FieldShape> shapes(n);
+    for (int f = 0; f < n; ++f) shapes[f] = field_shape(*plans[f]);
+    const std::vector<FusedItem> items = fused_items(shapes, cus);
+    std::vector<int> need(n * kFusedStages, 0);
+    for (const FusedItem &it : items) ++need[it.f * kFusedStages + it.st];
+    for (int f = 0; f < n; ++f) {
+        Plan q = *plans[f];
+        q.splitk = fused_splitk(shapes[f]);
+        b.sa.push_back(split_args(q, 1, nullptr, nullptr, dtype));
+        b.sc.push_back(scan_args(q, 1, true));
+    }
+    b.n1 = (int)items.size();
+    const int n_counters = 2 + n * kFusedStages;
+    CHECK(hipMalloc(&b.args_dev, sizeof(SplitArgs) * n));
+    CHECK(hipMalloc(&b.scan_dev, sizeof(ScanArgs) * n));
+    CHECK(hipMalloc(&b.fitems, sizeof(FusedItem) * items.size()));
+    CHECK(hipMalloc(&b.heads, sizeof(int) * n_counters));
+    CHECK(hipMalloc(&b.need, sizeof(int) * n * kFusedStages));
+    CHECK(hipMalloc(&b.stamps, sizeof(unsigned long long) * (n + 2)));
+    CHECK(hipMemset(b.stamps, 0, sizeof(unsigned long long) * (n + 2)));
+    CHECK(hipMemset(b.heads, 0, sizeof(int) * n_counters));
+    CHECK(hipMemcpy(b.scan_dev, b.sc.data(), sizeof(ScanArgs) * n, hipMemcpyHostToDevice));
+    CHECK(hipMemcpy(b.fitems, items.data(), sizeof(FusedItem) * items.size(), hipMemcpyHostToDevice));
+    CHECK(hipMemcpy(b.need, need.data(), sizeof(int) * n * kFusedStages, hipMemcpyHostToDevice));
+    FusedCtl ctl{b.heads, b.heads + 2, b.need, b.heads + 1, b.stamps, n, spin_limit()};
+
+    // capture: counter reset and start stamp (a kernel, not a memset), then
+    // the fused kernel
+    CHECK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+    CHECK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(k_batch_start, dim3(1), dim3(256), 0, b.cap, b.heads, n_counters, b.stamps, n);
+    hipError_t e = batch_fused_bf16((const SplitArgs *)b.args_dev, b.scan_dev, b.fitems, b.n1, ctl, dtype, cus, b.cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b.cap, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    CHECK(e2);
+    b.graph = g;
+    CHECK(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+    return hipSuccess;
+}
+
+// FP64: one persistent work-queue kernel per stage (moments, radial scans,
+// expansion), each queue holding the tiles of every field, longest first.
+hipError_t build_staged(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
+    b.plans = plans;
+    for (const Plan *p : plans) b.epochs.push_back(p->tune_epoch);
+    b.dtype = dtype;
+    b.precision = plans[0]->precision;
+    const int n = (int)plans.size();
+    const int T1 = kF64Tile1, T2 = kF64Tile2;  // tile sides of the moment contraction (rows) and the expansion
 
     // work items per stage, longest first
     std::vector<int> order(n);
     for (int f = 0; f < n; ++f) order[f] = f;
     std::vector<BatchItem> i1, is, i2;
-    std::vector<int> kchunk(n), tiles_e(n), tiles_o(n);
     std::vector<Plan> q(n);
     for (int f = 0; f < n; ++f) {
         q[f] = *plans[f];
         q[f].splitk = choose_splitk(q[f], 1);
-        const Plan &p = q[f];
-        if (split) {
-            SplitArgs g = split_args(p, 1, nullptr, nullptr, dtype);
-            b.sa.push_back(g);
-            kchunk[f] = g.kchunk;
-            tiles_e[f] = g.tiles_e;
-            tiles_o[f] = g.tiles_o;
-        } else {
-            F64Args g = f64_args(p, 1, nullptr, nullptr, dtype);
-            b.fa.push_back(g);
-            kchunk[f] = g.kchunk;
-            tiles_e[f] = g.tiles_e;
-            tiles_o[f] = g.tiles_o;
-        }
-        b.sc.push_back(scan_args(p, 1, split));
+        b.fa.push_back(f64_args(q[f], 1, nullptr, nullptr, dtype));
+        b.sc.push_back(scan_args(q[f], 1, false));
     }
-    // GEMM1 items, longest first: K per item, times the products per
-    // product of the split forms (six, or three off the tier's column pairs)
+    // moment items, longest K first
     std::vector<std::pair<long long, BatchItem>> c1;
     for (int f = 0; f < n; ++f) {
         const Plan &p = q[f];
-        const int rt = (p.n_r + T1 - 1) / T1;
-        // the split GEMM1 takes column tiles in pairs (per parity block)
-        const int pe = (tiles_e[f] + 1) / 2, po = (tiles_o[f] + 1) / 2;
-        const int ct = split ? pe + po : tiles_e[f] + tiles_o[f];
+        const int rt = (p.n_r + T1 - 1) / T1, ct = b.fa[f].tiles_e + b.fa[f].tiles_o;
         for (int z = 0; z < p.splitk; ++z)
             for (int m = 0; m < rt; ++m)
-                for (int c = 0; c < ct; ++c) {
-                    bool six = true;
-                    if (split) six = c < pe ? c < six_pairs(p.six_e, pe) : c - pe < six_pairs(p.six_o, po);
-                    c1.push_back({(long long)kchunk[f] * (six ? 6 : 3), BatchItem{f, c, m, z}});
-                }
+                for (int c = 0; c < ct; ++c) c1.push_back({(long long)b.fa[f].kchunk, BatchItem{f, c, m, z}});
     }
     std::stable_sort(c1.begin(), c1.end(), [](const std::pair<long long, BatchItem> &a,
                                               const std::pair<long long, BatchItem> &b) { return a.first > b.first; });
@@ -144,9 +221,7 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return q[a].np > q[c].np; });
     for (int f : order) {
         const Plan &p = q[f];
-        // the split GEMM2 takes angular tiles in pairs
-        const int rt = (p.n_r + T2 - 1) / T2;
-        const int at = split ? (p.n2() / T2 + 1) / 2 : p.n2() / T2;
+        const int rt = (p.n_r + T2 - 1) / T2, at = p.n2() / T2;
         for (int a = 0; a < at; ++a)
             for (int m = 0; m < rt; ++m) i2.push_back({f, m, a, 0});
     }
@@ -159,8 +234,7 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     all.insert(all.end(), is.begin(), is.end());
     all.insert(all.end(), i2.begin(), i2.end());
 
-    const size_t asz = split ? sizeof(SplitArgs) * n : sizeof(F64Args) * n;
-    CHECK(hipMalloc(&b.args_dev, asz));
+    CHECK(hipMalloc(&b.args_dev, sizeof(F64Args) * n));
     CHECK(hipMalloc(&b.scan_dev, sizeof(ScanArgs) * n));
     CHECK(hipMalloc(&b.items_dev, sizeof(BatchItem) * all.size()));
     CHECK(hipMalloc(&b.heads, sizeof(int) * 4));
@@ -169,35 +243,18 @@ hipError_t build(Batch &b, const std::vector<const Plan *> &plans, int dtype) {
     const BatchTrack track{b.stamps, n};
     CHECK(hipMemcpy(b.scan_dev, b.sc.data(), sizeof(ScanArgs) * n, hipMemcpyHostToDevice));
     CHECK(hipMemcpy(b.items_dev, all.data(), sizeof(BatchItem) * all.size(), hipMemcpyHostToDevice));
-    std::vector<size_t> offs(n + 1, 0);
-    for (int f = 0; f < n; ++f) offs[f + 1] = offs[f] + (split ? split_input_threads(q[f], 1) : 0);
-    if (split) {
-        CHECK(hipMalloc(&b.split_offs, sizeof(size_t) * (n + 1)));
-        CHECK(hipMemcpy(b.split_offs, offs.data(), sizeof(size_t) * (n + 1), hipMemcpyHostToDevice));
-    }
 
-    // capture: counter reset and start stamp (a kernel, not a memset), the input
-    // split of every field (split forms) and the three stages
+    // capture: counter reset and start stamp (a kernel, not a memset) and the
+    // three stages
     CHECK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
     CHECK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
     const int cus = cu_count();
     hipLaunchKernelGGL(k_batch_start, dim3(1), dim3(256), 0, b.cap, b.heads, 4, b.stamps, n);
     const BatchItem *it1 = b.items_dev, *its = b.items_dev + b.n1, *it2 = b.items_dev + b.n1 + b.ns;
-    hipError_t e;
-    e = hipSuccess;
-    if (split) {
-        e = batch_split_input_bf16((const SplitArgs *)b.args_dev, b.split_offs, n, offs[n], dtype, b.cap);
-        if (e == hipSuccess)
-            e = batch_gemm1_bf16((const SplitArgs *)b.args_dev, it1, b.n1, b.heads + 0, dtype, cus, b.cap);
-        if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);
-        if (e == hipSuccess)
-            e = batch_gemm2_bf16((const SplitArgs *)b.args_dev, it2, b.n2, b.heads + 2, dtype, cus, track, b.cap);
-    } else {
-        e = batch_gemm1_f64((const F64Args *)b.args_dev, it1, b.n1, b.heads + 0, dtype, 4 * cus, b.cap);
-        if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);
-        if (e == hipSuccess)
-            e = batch_gemm2_f64((const F64Args *)b.args_dev, it2, b.n2, b.heads + 2, dtype, 4 * cus, track, b.cap);
-    }
+    hipError_t e = batch_gemm1_f64((const F64Args *)b.args_dev, it1, b.n1, b.heads + 0, dtype, 4 * cus, b.cap);
+    if (e == hipSuccess) e = batch_scan(b.scan_dev, its, b.ns, b.heads + 1, 2 * cus, b.cap);
+    if (e == hipSuccess)
+        e = batch_gemm2_f64((const F64Args *)b.args_dev, it2, b.n2, b.heads + 2, dtype, 4 * cus, track, b.cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b.cap, &g);
     if (e != hipSuccess) {
@@ -239,7 +296,7 @@ hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *c
     if (!b) {
         b = new (std::nothrow) Batch();
         if (!b) return hipErrorOutOfMemory;
-        hipError_t e = build(*b, plans, dtype);
+        hipError_t e = plans[0]->split() ? build_fused(*b, plans, dtype) : build_staged(*b, plans, dtype);
         if (e != hipSuccess) {
             delete b;
             return e;
@@ -271,6 +328,11 @@ hipError_t batch_field_times(const std::vector<const Plan *> &plans, int dtype, 
     CHECK(hipStreamSynchronize(plans[0]->stream));
     std::vector<unsigned long long> st(n + 2);
     CHECK(hipMemcpy(st.data(), b->stamps, sizeof(unsigned long long) * (n + 2), hipMemcpyDeviceToHost));
+    if (b->fitems) {
+        int status = 0;
+        CHECK(hipMemcpy(&status, b->heads + 1, sizeof(int), hipMemcpyDeviceToHost));
+        if (status) return hipErrorLaunchTimeOut;  // a stage wait gave up: the results are incomplete
+    }
     int khz = 0;
     CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, plans[0]->device));
     if (khz <= 0) return hipErrorInvalidValue;

@@ -509,6 +509,9 @@ int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms)
     }
     hipError_t e = batch_field_times(ps, dtype, ms);
     if (e == hipErrorNotFound) return fail(MPG_EINVAL, "mpg_batch_field_times: no batched solve of these plans");
+    if (e == hipErrorLaunchTimeOut)
+        return fail(MPG_EDEVICE, "mpg_batch_field_times: a stage wait of the last batched solve gave up; its "
+                                 "results are incomplete");
     if (e != hipSuccess) return hip_fail(e, "mpg_batch_field_times");
     return MPG_OK;
 }

@@ -41,6 +41,7 @@
 // modulo 16); the lanes of a fragment read cover 16 consecutive rows at one
 // kchunk, whose positions modulo 16 are then all distinct.
 #include "mpg_internal.h"
+#include "scan_core.h"
 
 namespace mpg {
 namespace {
@@ -94,9 +95,18 @@ __device__ inline void zero(v16f (&acc)[2][2]) {
 // (odd-m block) under the fold (U_Yang = (-1)^m U_Yin, Sec. 4.2), else A =
 // rho, rounded once to FP32 and written as three bf16 pieces in tile-slab
 // blocks (one plane per parity; zero past n_ang and past the last row).
-// Thread = one 16-byte chunk (8 consecutive K of one row) of one block.
+// Thread = one 16-byte chunk (8 consecutive K of one row) of one block:
+// the loads of a chunk (widened to FP64) and its destination, then the
+// pieces and their stores, so a thread can hold several chunks' loads in
+// flight before it stores any.
+struct ChunkIn {
+    double d0[8], d1[8];
+    size_t dst;  // piece-0 element offset of the chunk in its parity plane
+    bool live;   // the chunk lies in the plane (slabs past the last do not)
+};
+
 template <typename T, bool FOLD>
-__device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
+__device__ __forceinline__ void fold_split_load(const SplitArgs &g, size_t t, ChunkIn &in) {
     // a wave covers 4 rows x 4 slabs: 512 consecutive bytes of each row
     // read (FP32), 256 consecutive bytes of each piece of each slab written
     const size_t unit = t / 2048;  // (row tile, group of 4 slabs)
@@ -105,13 +115,14 @@ __device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
     const int tile = (int)(unit / ng), sg = (int)(unit - (size_t)tile * ng);
     const int lane = rem & 63, r = 4 * (rem >> 6) + (lane >> 4), qq = lane & 15;
     const int slab = 4 * sg + (qq >> 2), kc = qq & 3;
-    if (slab >= g.ks1) return;
+    in.live = slab < g.ks1;
     const size_t blk = (size_t)tile * g.ks1 + slab;
     const int c = 4 * r + (kc ^ ((r >> 2) & 3));  // stored chunk position
+    in.dst = blk * 3 * kBlk + (size_t)c * 8;
     const int row = tile * TB + r;
     int k0 = slab * TK + kc * 8;
     const int n_r = g.n_r, n_ang = g.n_ang;
-    const bool row_ok = row < g.rows;
+    const bool row_ok = in.live && row < g.rows;
     const int f = row_ok ? row / n_r : 0, i = row_ok ? row - f * n_r : 0;
     const size_t pstride = (size_t)n_r * n_ang, fld = (size_t)g.n_patches * pstride;
     // without the fold K runs over every patch's cells (k = patch*n_angp + cell)
@@ -119,7 +130,6 @@ __device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
     k0 -= gp * g.n_angp;
     const T *r0 = (const T *)g.rho + f * fld + gp * pstride + (size_t)i * n_ang;
     const T *r1 = r0 + pstride;
-    double d0[8], d1[8];
     if (sizeof(T) == 4 && (n_ang & 7) == 0) {
         // whole chunk inside or outside the row; 32-byte aligned
         f32x4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, b0 = a0, b1 = a0;
@@ -131,27 +141,32 @@ __device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
                 b1 = *(const f32x4 *)(r1 + k0 + 4);
             }
         }
-        d0[0] = a0.x; d0[1] = a0.y; d0[2] = a0.z; d0[3] = a0.w;
-        d0[4] = a1.x; d0[5] = a1.y; d0[6] = a1.z; d0[7] = a1.w;
-        d1[0] = b0.x; d1[1] = b0.y; d1[2] = b0.z; d1[3] = b0.w;
-        d1[4] = b1.x; d1[5] = b1.y; d1[6] = b1.z; d1[7] = b1.w;
+        in.d0[0] = a0.x; in.d0[1] = a0.y; in.d0[2] = a0.z; in.d0[3] = a0.w;
+        in.d0[4] = a1.x; in.d0[5] = a1.y; in.d0[6] = a1.z; in.d0[7] = a1.w;
+        in.d1[0] = b0.x; in.d1[1] = b0.y; in.d1[2] = b0.z; in.d1[3] = b0.w;
+        in.d1[4] = b1.x; in.d1[5] = b1.y; in.d1[6] = b1.z; in.d1[7] = b1.w;
     } else {
         // FP64 input (or rows not a multiple of 8): element by element
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const bool in = row_ok && k0 + q < n_ang;
-            d0[q] = in ? (double)r0[k0 + q] : 0.0;
-            d1[q] = in && FOLD ? (double)r1[k0 + q] : 0.0;
+            const bool on = row_ok && k0 + q < n_ang;
+            in.d0[q] = on ? (double)r0[k0 + q] : 0.0;
+            in.d1[q] = on && FOLD ? (double)r1[k0 + q] : 0.0;
         }
     }
+}
+
+template <bool FOLD>
+__device__ __forceinline__ void fold_split_store(const SplitArgs &g, const ChunkIn &in) {
+    if (!in.live) return;
     const size_t plane = (size_t)g.row_tiles * g.ks1 * 3 * kBlk;
 #pragma unroll
     for (int par = 0; par < (FOLD ? 2 : 1); ++par) {
         uint32_t h[4], m[4], l[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            float x0 = (float)(par ? d0[2 * q] - d1[2 * q] : d0[2 * q] + d1[2 * q]);
-            float x1 = (float)(par ? d0[2 * q + 1] - d1[2 * q + 1] : d0[2 * q + 1] + d1[2 * q + 1]);
+            float x0 = (float)(par ? in.d0[2 * q] - in.d1[2 * q] : in.d0[2 * q] + in.d1[2 * q]);
+            float x1 = (float)(par ? in.d0[2 * q + 1] - in.d1[2 * q + 1] : in.d0[2 * q + 1] + in.d1[2 * q + 1]);
             bf16 h0, m0, l0, h1, m1, l1;
             split3f(x0, h0, m0, l0);
             split3f(x1, h1, m1, l1);
@@ -159,7 +174,7 @@ __device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
             m[q] = pack2(m0, m1);
             l[q] = pack2(l0, l1);
         }
-        bf16 *o = g.A + par * plane + blk * 3 * kBlk + (size_t)c * 8;
+        bf16 *o = g.A + par * plane + in.dst;
         *(u32x4 *)(o) = (u32x4){h[0], h[1], h[2], h[3]};
         *(u32x4 *)(o + kBlk) = (u32x4){m[0], m[1], m[2], m[3]};
         *(u32x4 *)(o + 2 * kBlk) = (u32x4){l[0], l[1], l[2], l[3]};
@@ -167,29 +182,28 @@ __device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
 }
 
 template <typename T, bool FOLD>
+__device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
+    ChunkIn in;
+    fold_split_load<T, FOLD>(g, t, in);
+    fold_split_store<FOLD>(g, in);
+}
+
+// the 2048 chunks of one split unit by a block of kThreads threads: every
+// thread's loads first, then its stores
+template <typename T, bool FOLD>
+__device__ __forceinline__ void fold_split_unit(const SplitArgs &g, size_t u, int tid) {
+    constexpr int kPer = 2048 / kThreads;
+    ChunkIn in[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) fold_split_load<T, FOLD>(g, u * 2048 + k * kThreads + tid, in[k]);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) fold_split_store<FOLD>(g, in[k]);
+}
+
+template <typename T, bool FOLD>
 __global__ __launch_bounds__(256) void k_fold_split(SplitArgs g, size_t n_threads) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_threads) fold_split_chunk<T, FOLD>(g, t);
-}
-
-// batch version: one launch over the chunks of every field.  Field f owns
-// threads offs[f] .. offs[f+1]-1; every field's count is a multiple of 2048,
-// so a block of 256 threads lies inside one field.
-template <typename T>
-__global__ __launch_bounds__(256) void k_batch_fold_split(const SplitArgs *__restrict__ args,
-                                                          const size_t *__restrict__ offs, int n) {
-    const size_t t0 = (size_t)blockIdx.x * blockDim.x;
-    // the last field f with offs[f] <= t0 (offs[0] = 0 <= t0 < offs[n])
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) / 2;
-        if (offs[mid] <= t0) lo = mid;
-        else hi = mid;
-    }
-    const SplitArgs g = args[lo];
-    const size_t t = t0 + threadIdx.x - offs[lo];
-    if (g.fold) fold_split_chunk<T, true>(g, t);
-    else fold_split_chunk<T, false>(g, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -480,13 +494,6 @@ __device__ __forceinline__ void run_tiered(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1,
     }
 }
 
-// Leading three-product slabs of a K walk of nsl slabs that runs from the
-// top of a column block down, whose lowest six_sl slabs take six products:
-// rounded down to an even count (so one more slab may take six).
-__device__ __forceinline__ int three_slabs(int nsl, int six_sl) {
-    const int n3 = max(nsl - six_sl, 0);
-    return n3 == nsl ? n3 : (n3 & ~1);
-}
 
 // 128 rows of rho+- and 256 columns of U (GEMM1), or 128 rows of M and 256
 // angular cells of Q (GEMM2's default block)
@@ -565,7 +572,9 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
 // into acc_e, then the odd-m block into acc_o, each walked from its top slab
 // down; per-patch method: the moment sets of the patches one after the
 // other, each flushed into FP64.
-template <typename T, bool FOLD, bool PP, int NA>
+// NT: Phi is stored non-temporally (the fused batch kernel, whose L2
+// write-backs should not carry it).
+template <typename T, bool FOLD, bool PP, int NA, bool NT = false>
 __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, SlabT<NA, 3 - NA> &S0,
                                            SlabT<NA, 3 - NA> &S1) {
     constexpr int NB = 3 - NA;
@@ -641,8 +650,15 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
                 if (!FOLD && pp) e = acc64[a][b][r];
                 if (FOLD) {
                     double od = (double)acc_o[a][b][r];
-                    o[0] = (T)(e + od);
-                    o[pstride] = (T)(e - od);
+                    if (NT) {
+                        __builtin_nontemporal_store((T)(e + od), o);
+                        __builtin_nontemporal_store((T)(e - od), o + pstride);
+                    } else {
+                        o[0] = (T)(e + od);
+                        o[pstride] = (T)(e - od);
+                    }
+                } else if (NT) {
+                    __builtin_nontemporal_store((T)e, o);
                 } else {
                     o[0] = (T)e;
                 }
@@ -682,53 +698,99 @@ __global__ __launch_bounds__(kThreads) void k_gemm2(SplitArgs g) {
     gemm2_tile<T, FOLD, PP, NA>(g, blockIdx.x, blockIdx.y, s0, s1);
 }
 
-// Persistent batch kernels: every block takes work items from a queue
-// (items[], ordered longest first) through an atomic head until the queue
-// is empty.  Item = (field, tile coordinates); args[] holds each field's
-// arguments.  No item waits on another, so every block exits.  The barrier
-// in next_item also keeps the next tile's first copies from overwriting
-// slabs other waves are still reading.
-__device__ __forceinline__ int next_item(int *head, int *slot) {
-    __syncthreads();
-    if (threadIdx.x == 0) *slot = atomicAdd(head, 1);
-    __syncthreads();
-    return __builtin_amdgcn_readfirstlane(*slot);
-}
-
-__global__ __launch_bounds__(kThreads) void k_batch_gemm1(const SplitArgs *__restrict__ args,
-                                                          const BatchItem *__restrict__ items, int n_items,
-                                                          int *head) {
-    __shared__ Slab1 s0, s1;
-    __shared__ int slot;
-    for (;;) {
-        const int it = next_item(head, &slot);
-        if (it >= n_items) break;
-        const BatchItem w = items[it];
-        const SplitArgs g = args[w.f];
-        if (g.fold) gemm1_tile<true>(g, w.a, w.b, w.c, s0, s1);
-        else gemm1_tile<false>(g, w.a, w.b, w.c, s0, s1);
-    }
-}
-
+// The fused batch kernel: one persistent block per CU takes items of every
+// stage of every field from one queue (ordered by batch_order.h, so an
+// item's producers were taken before it).  Before an item of stage s of
+// field f, the first thread waits until every item of stage s-1 of f has
+// finished (a bounded poll; on giving up it sets the status word and every
+// block drains).  After an item, once every thread's stores are complete,
+// the first thread makes them visible device-wide (release fence: this
+// XCD's L2 written back) and counts the item; the item that completes a
+// field's expansion stamps the field's completion time (the expansion's
+// output is read by no item, needs no write-back and is stored
+// non-temporally).  Scans run with 8 shell
+// chunks of 64 lanes on the slab buffers' LDS; expansions in 128 x 256
+// blocks.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_batch_gemm2(const SplitArgs *__restrict__ args,
-                                                          const BatchItem *__restrict__ items, int n_items,
-                                                          int *head, BatchTrack track) {
-    __shared__ Slab1 s0, s1;
-    __shared__ int slot;
-    for (int prev = -1;;) {
-        const int it = next_item_tracked(head, &slot, track, prev);
+__global__ __launch_bounds__(kThreads) void k_batch_fused(const SplitArgs *__restrict__ args,
+                                                          const ScanArgs *__restrict__ sargs,
+                                                          const FusedItem *__restrict__ items, int n_items,
+                                                          FusedCtl c) {
+    __shared__ Slab1 sl[2];
+    __shared__ int slot, go;
+    Slab1 &s0 = sl[0], &s1 = sl[1];
+    const int tid = threadIdx.x;
+    for (;;) {
+        __syncthreads();  // every thread is done with the previous item and the shared slots
+        if (tid == 0) slot = atomicAdd(c.head, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(slot);
         if (it >= n_items) break;
-        const BatchItem w = items[it];
+        const FusedItem w = items[it];
+        if (tid == 0) {
+            int ok = 1;
+            if (w.st > 0) {
+                const int *cnt = c.done + w.f * kFusedStages + w.st - 1;
+                const int need = c.need[w.f * kFusedStages + w.st - 1];
+                for (int spins = 0; __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need;
+                     ++spins) {
+                    if (spins >= c.spin_limit ||
+                        __hip_atomic_load(c.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        ok = 0;
+                        __hip_atomic_store(c.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+            }
+            go = ok;
+        }
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(go)) break;
         const SplitArgs g = args[w.f];
-        // (batches hold no per-patch plans)
-        if (g.fold) gemm2_tile<T, true, false, 1>(g, w.a, w.b, s0, s1);
-        else gemm2_tile<T, false, false, 1>(g, w.a, w.b, s0, s1);
-        prev = w.f;
+        if (w.st == 0) {
+            // input split: units of 2048 chunks
+            for (int u = w.a; u < w.a + w.b; ++u) {
+                if (g.fold) fold_split_unit<T, true>(g, u, tid);
+                else fold_split_unit<T, false>(g, u, tid);
+            }
+        } else if (w.st == 1) {
+            if (g.fold) gemm1_tile<true>(g, w.a, w.b, w.c, s0, s1);
+            else gemm1_tile<false>(g, w.a, w.b, w.c, s0, s1);
+        } else if (w.st == 2) {
+            double *lds = reinterpret_cast<double *>(&s0);
+            constexpr int kCh = kThreads / 64;
+            scan_detail::scan_block_core(sargs[w.f], w.a, tid & 63, tid >> 6, kCh, lds, lds + kCh * 64,
+                                         lds + 2 * kCh * 64, lds + 3 * kCh * 64);
+        } else {
+            if (g.fold) gemm2_tile<T, true, false, 1, true>(g, w.a, w.b, s0, s1);
+            else gemm2_tile<T, false, false, 1, true>(g, w.a, w.b, s0, s1);
+        }
+        // this block's stores are complete; then (but after the expansion,
+        // whose output no item reads) one wave writes this XCD's L2 back
+        __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) lgkmcnt(0)
+        __syncthreads();
+        if (tid == 0 && w.st < kFusedStages - 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (tid == 0) {
+            const int old = atomicAdd(c.done + w.f * kFusedStages + w.st, 1);
+            if (w.st == kFusedStages - 1 && old + 1 == c.need[w.f * kFusedStages + w.st])
+                c.stamps[w.f] = wall_clock64();
+        }
     }
 }
 
 }  // namespace
+
+hipError_t batch_fused_bf16(const SplitArgs *args, const ScanArgs *sargs, const FusedItem *items, int n_items,
+                            FusedCtl ctl, int io_dtype, int blocks, hipStream_t s) {
+    if (io_dtype == MPG_F64)
+        hipLaunchKernelGGL((k_batch_fused<double>), dim3(blocks), dim3(kThreads), 0, s, args, sargs, items, n_items,
+                           ctl);
+    else
+        hipLaunchKernelGGL((k_batch_fused<float>), dim3(blocks), dim3(kThreads), 0, s, args, sargs, items, n_items,
+                           ctl);
+    return hipGetLastError();
+}
 
 SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype, bool expansion) {
     SplitArgs g;
@@ -813,33 +875,6 @@ hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype) {
         if (phi_dtype == MPG_F64) launch_gemm2<double, 1>(p, g, grid);
         else launch_gemm2<float, 1>(p, g, grid);
     }
-    return hipGetLastError();
-}
-
-hipError_t batch_split_input_bf16(const SplitArgs *args, const size_t *offs, int n, size_t n_threads, int io_dtype,
-                                  hipStream_t s) {
-    if (n_threads % 256 || n_threads / 256 > 0x7fffffff) return hipErrorInvalidConfiguration;
-    dim3 grid((unsigned)(n_threads / 256));
-    if (io_dtype == MPG_F64) hipLaunchKernelGGL((k_batch_fold_split<double>), grid, dim3(256), 0, s, args, offs, n);
-    else hipLaunchKernelGGL((k_batch_fold_split<float>), grid, dim3(256), 0, s, args, offs, n);
-    return hipGetLastError();
-}
-
-hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
-                            int blocks, hipStream_t s) {
-    (void)io_dtype;
-    hipLaunchKernelGGL(k_batch_gemm1, dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head);
-    return hipGetLastError();
-}
-
-hipError_t batch_gemm2_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
-                            int blocks, BatchTrack track, hipStream_t s) {
-    if (io_dtype == MPG_F64)
-        hipLaunchKernelGGL((k_batch_gemm2<double>), dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head,
-                           track);
-    else
-        hipLaunchKernelGGL((k_batch_gemm2<float>), dim3(blocks), dim3(kThreads), 0, s, args, items, n_items, head,
-                           track);
     return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/mpg.h"
+#include "batch_order.h"
 #include "ksplit.h"
 
 namespace mpg {
@@ -43,6 +44,14 @@ __host__ __device__ inline int blk_pos(int r, int k) { return (4 * r + ((k >> 3)
 __host__ __device__ inline int six_pairs(int six_cols, int pairs) {
     const int n = (six_cols + 2 * kSplitTile - 1) / (2 * kSplitTile);
     return n < pairs ? n : pairs;
+}
+
+// Leading three-product slabs of a K walk of nsl slabs that runs from the
+// top of a column block down, whose lowest six_sl slabs take six products:
+// rounded down to an even count (so one more slab may take six).
+__host__ __device__ inline int three_slabs(int nsl, int six_sl) {
+    const int n3 = nsl - six_sl > 0 ? nsl - six_sl : 0;
+    return n3 == nsl ? n3 : (n3 & ~1);
 }
 
 // Table layout of a plan (all device arrays are owned by the plan).
@@ -158,6 +167,20 @@ __device__ __forceinline__ int next_item_tracked(int *head, int *slot, const Bat
     return __builtin_amdgcn_readfirstlane(*slot);
 }
 
+// Control block of the fused batch kernel (device pointers): the queue
+// head, per field and stage the items finished and the items in all
+// ([n][kFusedStages] each), a status word that a wait sets to 1 when it
+// gives up (the kernel then drains; the host reads it back), and the
+// per-field completion stamps ([n + 2]: stamps[n] is the start).  A wait
+// for a stage gives up after spin_limit polls (about 0.25 us each).
+struct FusedCtl {
+    int *head, *done;
+    const int *need;
+    int *status;
+    unsigned long long *stamps;
+    int n, spin_limit;
+};
+
 // Arguments of one field's split-BF16 contractions.
 struct SplitArgs {
     const void *rho;
@@ -236,18 +259,13 @@ hipError_t batch_scan(const ScanArgs *args, const BatchItem *items, int n_items,
 hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm2_bf16(const Plan &p, int n_fields, void *phi, int phi_dtype);
-// input split of every field of a batch in one launch: field f takes threads
-// offs[f] .. offs[f+1]-1 (device array of n+1 entries, each count a multiple
-// of 2048); n_threads = offs[n]
-hipError_t batch_split_input_bf16(const SplitArgs *args, const size_t *offs, int n, size_t n_threads, int io_dtype,
-                                  hipStream_t s);
 // threads of the input split of n_fields fields of a plan
 size_t split_input_threads(const Plan &p, int n_fields);
 SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype, bool expansion = false);
-hipError_t batch_gemm1_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
-                            int blocks, hipStream_t s);
-hipError_t batch_gemm2_bf16(const SplitArgs *args, const BatchItem *items, int n_items, int *head, int io_dtype,
-                            int blocks, BatchTrack track, hipStream_t s);
+// the whole split-form batch in one persistent kernel (items of every stage
+// of every field in one queue; see batch_order.h)
+hipError_t batch_fused_bf16(const SplitArgs *args, const ScanArgs *sargs, const FusedItem *items, int n_items,
+                            FusedCtl ctl, int io_dtype, int blocks, hipStream_t s);
 
 // batched solve (batch.hip)
 hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *const *rho, void *const *phi,

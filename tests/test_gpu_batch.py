@@ -147,3 +147,55 @@ def test_autotune_cache_file(tmp_path):
     p2 = mpg.Plan(g, precision="split_bf16_tiered")
     assert p2.autotune(t, cache=cache) == first
     assert np.array_equal(p1.potential(t).cpu().numpy(), p2.potential(t).cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", ["split_bf16_tiered", "split_bf16"])
+def test_batch_matches_single_solves_over_replays(precision):
+    """The fused batch kernel runs the single-plan kernels' tiles per item
+    (its K splits may differ): every field matches a single solve of its
+    plan to the split tolerance, over replays with new inputs."""
+    import torch
+    import paper_1903_08475_amd as mpg
+    gs = fields()
+    plans = [mpg.Plan(g, precision=precision) for g in gs]
+    singles = [mpg.Plan(g, precision=precision) for g in gs]
+    for rep in range(2):
+        rhos = [torch.tensor(W.random_rho(g, 7000 + 10 * rep + k), dtype=torch.float32, device="cuda")
+                for k, g in enumerate(gs)]
+        outs = [torch.full_like(r, float("nan")) for r in rhos]
+        mpg.potential_batch(plans, rhos, outs)
+        for k, (s, r, o) in enumerate(zip(singles, rhos, outs)):
+            ref = s.potential(r)
+            e = rel_err(o.cpu().numpy(), ref.cpu().numpy())
+            print(f"{precision} rep {rep} field {k}: batch vs single {e:.3e}")
+            assert e < TOL[precision]
+
+
+def test_batch_wait_give_up_path_exits(monkeypatch):
+    """A batch built with a wait limit of one poll: the persistent kernel
+    still exits (blocks whose producers are not done give up and every block
+    drains); the give-up, if one happened, is reported, and a batch built
+    afterwards with the default limit solves correctly."""
+    import torch
+    import paper_1903_08475_amd as mpg
+    gs = fields()
+    rhos = [torch.tensor(W.random_rho(g, 7100 + k), dtype=torch.float32, device="cuda") for k, g in enumerate(gs)]
+    monkeypatch.setenv("MPG_BATCH_SPIN_LIMIT", "1")
+    plans = [mpg.Plan(g, precision="split_bf16_tiered") for g in gs]
+    outs = [torch.zeros_like(r) for r in rhos]
+    mpg.potential_batch(plans, rhos, outs)
+    torch.cuda.synchronize()
+    try:
+        mpg.batch_field_times(plans, torch.float32)
+        gave_up = False
+    except mpg.MpgError as err:
+        assert "gave up" in str(err)
+        gave_up = True
+    print(f"wait limit 1: a wait gave up: {gave_up}")
+    monkeypatch.delenv("MPG_BATCH_SPIN_LIMIT")
+    plans2 = [mpg.Plan(g, precision="split_bf16_tiered") for g in gs]
+    outs2 = [torch.full_like(r, float("nan")) for r in rhos]
+    mpg.potential_batch(plans2, rhos, outs2)
+    mpg.batch_field_times(plans2, torch.float32)
+    for p, r, o in zip(plans2, rhos, outs2):
+        assert rel_err(o.cpu().numpy(), p.potential(r).cpu().numpy()) < 1e-6
