@@ -323,11 +323,27 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the FP64 workload and the precision workload")
+    ap.add_argument("--only", choices=["fp64", "precision", "batch"], default=None,
+                    help="run only this workload (no headline line; e.g. to profile its kernels) and print its "
+                         "JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               "(the solver has no multi-GPU path)", file=sys.stderr)
         return 2
+    if args.only:
+        import torch
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        if args.only == "fp64":
+            res = fp64_workload(dev, 10)
+        elif args.only == "precision":
+            res = precision_workload(dev)
+        else:
+            precs = ("split_bf16_tiered", "split_bf16", "fp64") if args.batch_all else ("split_bf16_tiered", "fp64")
+            res = batch_workload(dev, args.batch_reps, autotune=not args.no_autotune, precisions=precs)
+        print(json.dumps({args.only: res}), flush=True)
+        return 0
 
     import workloads as W
     cpu = None
