@@ -250,10 +250,14 @@ def batch_workload(dev, reps, autotune=True, precisions=("split_bf16_tiered", "s
         plans = [mpg.Plan(g, precision=prec) for g, _ in fields]
         rhos = [r.to(dtype) for r in rho64]
         out = [torch.empty_like(r) for r in rhos]
-        if autotune:  # each field's plan on its own input (the batch takes their K splits)
+        if autotune:  # each field's plan on its own input (the batch takes its shapes and scan chunks)
             for p, r in zip(plans, rhos):
                 p.autotune(r)
             log(f"[bench] batch {prec}: {len(plans)} plans autotuned")
+        ch = mpg.batch_choices(plans, dtype)
+        res.setdefault("choices", {})[prec] = {
+            "gemm1_256x128": sum(c[2] == 2 for c in ch), "gemm2_256x128": sum(c[3] == 2 for c in ch),
+            "scan_chunks": {str(k): sum(c[1] == k for c in ch) for k in sorted({c[1] for c in ch})}}
         mpg.potential_batch(plans, rhos, out)  # builds and captures the graph
         torch.cuda.synchronize()
         stream = plans[0].stream
@@ -313,8 +317,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plans' default K split and scan schedule instead of autotuning them")
     ap.add_argument("--tuning", default=None,
-                    help="SPLITK,CHUNKS,ROWS: apply these choices to the timed plan instead of autotuning it "
-                         "(e.g. to profile the configuration an autotuned run chose, without its timing launches)")
+                    help="SPLITK,CHUNKS,GEMM1_ROWS,GEMM2_ROWS (or SPLITK,CHUNKS,GEMM2_ROWS with 128x256 moment "
+                         "blocks): apply these choices to the timed plan instead of autotuning it (e.g. to "
+                         "profile the configuration an autotuned run chose, without its timing launches)")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-patch comparison method")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-field uneven batch (one batched call per precision)")
@@ -371,17 +376,19 @@ def main():
     log(f"[bench] building {prec} plan")
     plan = mpg.Plan(grid, precision=prec, max_fields=n)
     tuned = None
+    def shape(r):
+        return "128x256" if r == 1 else "256x128"
     if args.tuning:
-        sk, ch, rows = (int(v) for v in args.tuning.split(","))
-        plan.set_tuning(sk, ch, rows)
-        tuned = {"gemm1_splitk": sk, "scan_chunks": ch, "expansion_block": "128x256" if rows == 1 else "256x128",
+        vals = [int(v) for v in args.tuning.split(",")]
+        sk, ch, g1, g2 = vals if len(vals) == 4 else (vals[0], vals[1], 1, vals[2])
+        plan.set_tuning(sk, ch, g1, g2)
+        tuned = {"gemm1_splitk": sk, "scan_chunks": ch, "moment_block": shape(g1), "expansion_block": shape(g2),
                  "given": True}
-        log(f"[bench] tuning given: K split {sk}, scan chunks {ch}, expansion block {tuned['expansion_block']}")
+        log(f"[bench] tuning given: {tuned}")
     elif not args.no_autotune:
-        sk, ch, rows = plan.autotune(rho)
-        tuned = {"gemm1_splitk": sk, "scan_chunks": ch,
-                 "expansion_block": "128x256" if rows == 1 else "256x128"}
-        log(f"[bench] autotuned: K split {sk}, scan chunks {ch}, expansion block {tuned['expansion_block']}")
+        sk, ch, g1, g2 = plan.autotune(rho)
+        tuned = {"gemm1_splitk": sk, "scan_chunks": ch, "moment_block": shape(g1), "expansion_block": shape(g2)}
+        log(f"[bench] autotuned: {tuned}")
     ms, wall, stages, pct = time_path(plan, rho, phi, args.steps, args.warmup)
     log(f"[bench] {prec}: {ms:.3f} ms/step ({pct}); stages {stages}")
     prods = products_per_term(grid.lmax, prec)

@@ -196,11 +196,14 @@ int mpg_potential_static(mpg_plan_t plan, int n_fields, const void *rho, int rho
  * field's previous stage; a tile waits on device counters until that stage
  * has finished (a bounded wait: past about 4 s it gives up, every block
  * drains, and mpg_batch_field_times reports it), so small fields complete
- * early.  Each field's moment contraction is split along K only as far as
- * needed for tiles of at most about 0.5 ms (a single solve's autotuned K
- * split is not used: the other fields fill the chip).  FP64: one persistent work-queue
+ * early.  Each field takes its plan's block shapes of both contractions
+ * and its scan chunks (autotuned or set); its moment contraction is split
+ * along K only as far as needed for tiles of at most about 0.5 ms (a single
+ * solve's autotuned K split is not used: the other fields fill the chip;
+ * mpg_batch_choices reports the split).  FP64: one persistent work-queue
  * kernel per stage (moments, radial scans, expansion), each holding the
- * tiles of every field, longest first.  The launches are captured once in
+ * tiles of every field, longest first, with each plan's K split and scan
+ * chunks.  The launches are captured once in
  * a hipGraph (per set of plans and dtype) and replayed; a later
  * mpg_autotune or mpg_set_tuning of one of the plans makes the next call
  * capture afresh.  rho[f] and phi[f] are device
@@ -224,36 +227,56 @@ int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho,
  * its results are then incomplete). */
 int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms);
 
+/* The choices each field takes in a batched solve (mpg_potential_batch)
+ * of these plans in this dtype: per field f, splitk[f] the K split of its
+ * moment contraction, chunks[f] its scan's shell chunks per column, and
+ * gemm1_rows[f], gemm2_rows[f] the block shapes of its contractions (as in
+ * mpg_set_tuning; 1 for the FP64 form).  Each pointer is a host array of n
+ * entries, or NULL.  A single solve with these choices set
+ * (mpg_set_tuning) gives the batched field's results bit for bit.
+ * Errors: MPG_EINVAL (bad arguments). */
+int mpg_batch_choices(int n, const mpg_plan_t *plans, int dtype, int *splitk, int *chunks,
+                      int *gemm1_rows, int *gemm2_rows);
+
 /* Autotune the plan for n_fields fields on the given device input, and keep
- * the choices for later single-plan calls:
+ * the choices for later calls (batched calls take all but the K split):
  *  - the K split of the moment contraction, timed together with the radial
  *    scan that reduces its partial sums, for every split the work space
  *    allows (the default choice first, then 1, 2, 3, 4 and the powers of
  *    two beyond; another split is kept only when it is at least 1% faster;
  *    the work space holds at least four splits when their partial sums fit
  *    in 2 GiB, and up to 32 while they fit in 512 MiB);
+ *  - split forms: the moment contraction's block shape, 128 rows x 256
+ *    columns (gemm1_rows = 1, the default) or 256 x 128 (gemm1_rows = 2),
+ *    each timed without a K split;
  *  - the radial scan's shell chunks per column: 4, 8, 12 or 16;
  *  - split forms: the expansion's block shape, 128 rows x 256 angular cells
- *    (gemm2_rows = 1, the default) or 256 x 128 (gemm2_rows = 2, kept only
- *    when at least 1% faster).  Its timing writes a temporary output of one
- *    call's size, allocated and freed here; if it cannot be allocated, the
- *    shape is left as it is.
- * Batched calls (mpg_potential_batch) keep fixed scan and expansion
- * shapes.  Blocks until done; overwrites the
- * plan's work space.  splitk, chunks and gemm2_rows (each may be NULL)
- * receive the choices (gemm2_rows: 1 for the FP64 form).
+ *    (gemm2_rows = 1, the default) or 256 x 128 (gemm2_rows = 2).  Its
+ *    timing writes a temporary output of one call's size, allocated and
+ *    freed here; if it cannot be allocated, the shape is left as it is.
+ * Of two block shapes the one with less chip work is kept when it is at
+ * least 1% less: the time of one of its blocks (its time over its waves of
+ * one block per CU) times its blocks, over the CUs; that is its time when
+ * its blocks fill whole waves, and otherwise leaves out the CUs a partial
+ * wave leaves idle, which the other fields of a batch use.  Otherwise the
+ * one with fewer blocks (padding included), and the default when those are
+ * equal too.
+ * Blocks until done; overwrites the plan's work space.  splitk, chunks,
+ * gemm1_rows and gemm2_rows (each may be NULL) receive the choices (the
+ * shapes: 1 for the FP64 form).
  * Errors: as mpg_moments. */
 int mpg_autotune(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
-                 int *splitk, int *chunks, int *gemm2_rows);
+                 int *splitk, int *chunks, int *gemm1_rows, int *gemm2_rows);
 
 /* Set the choices mpg_autotune makes, e.g. ones it made earlier for the same
  * grid and lmax: the K split of the moment contraction (at most the plan's
- * work space allows), the radial scan's shell chunks per column (1..16) and
- * the split expansion's block shape (gemm2_rows 1: 128 rows x 256 angular
- * cells, 2: 256 x 128).  A value <= 0 leaves that choice as it is.  Results
- * do not depend on the shape; they may differ in rounding with the K split.
+ * work space allows), the radial scan's shell chunks per column (1..16),
+ * and the split contractions' block shapes (gemm1_rows, gemm2_rows 1: 128
+ * rows x 256 columns or angular cells, 2: 256 x 128).  A value <= 0 leaves
+ * that choice as it is.  Results do not depend on the shapes; they may
+ * differ in rounding with the K split and the chunks.
  * Errors: MPG_EINVAL (NULL plan, a value out of range; nothing is changed). */
-int mpg_set_tuning(mpg_plan_t plan, int splitk, int chunks, int gemm2_rows);
+int mpg_set_tuning(mpg_plan_t plan, int splitk, int chunks, int gemm1_rows, int gemm2_rows);
 
 /* Copy the plan's FP64 tables to device buffers, in the real index:
  *   U : [n_patches][n_theta*n_phi][n_lm]   (Eqs. U_C/U_S), or NULL

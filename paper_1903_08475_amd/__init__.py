@@ -30,7 +30,8 @@ EVAL_POINTS = {"vertex": 0, "centre": 1}
 # Every symbol the C ABI exports (kept equal to include/mpg.h by a test).
 EXPORTS = ("mpg_plan", "mpg_plan_method", "mpg_moments", "mpg_potential", "mpg_potential_static",
            "mpg_potential_batch",
-           "mpg_batch_field_times", "mpg_autotune", "mpg_set_tuning", "mpg_tables", "mpg_plan_info",
+           "mpg_batch_field_times", "mpg_batch_choices", "mpg_autotune", "mpg_set_tuning", "mpg_tables",
+           "mpg_plan_info",
            "mpg_timing", "mpg_stage_times", "mpg_sync", "mpg_destroy", "mpg_last_error")
 STAGES = ("input_split", "moments", "radial_scan", "expansion")
 
@@ -72,9 +73,10 @@ def lib():
         L.mpg_potential_static.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int]
         L.mpg_potential_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
         L.mpg_batch_field_times.argtypes = [C.c_int, C.POINTER(vp), C.c_int, dp]
-        L.mpg_autotune.argtypes = [vp, C.c_int, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                   C.POINTER(C.c_int)]
-        L.mpg_set_tuning.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        ip = C.POINTER(C.c_int)
+        L.mpg_batch_choices.argtypes = [C.c_int, C.POINTER(vp), C.c_int, ip, ip, ip, ip]
+        L.mpg_autotune.argtypes = [vp, C.c_int, vp, C.c_int, ip, ip, ip, ip]
+        L.mpg_set_tuning.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.mpg_tables.argtypes = [vp, vp, vp, vp]
         L.mpg_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]
         L.mpg_timing.argtypes = [vp, C.c_int]
@@ -214,11 +216,12 @@ class Plan:
                 f"cells{g.n_theta}x{g.n_phi}/lmax{self.lmax}/fields{n_fields}/max{self.max_fields}/{dtype}")
 
     def autotune(self, rho, cache=None):
-        """Time the K split of the moment contraction, the scan schedule and
-        (split forms) the expansion's block shape on this input and keep the
-        fastest; returns (splitk, chunks, gemm2_rows).  With cache (a JSON
-        file path), choices stored there for the same key are applied
-        without timing, and new ones are added to it."""
+        """Time the K split of the moment contraction, (split forms) its block
+        shape, the scan schedule and (split forms) the expansion's block
+        shape on this input and keep the fastest; returns (splitk, chunks,
+        gemm1_rows, gemm2_rows).  With cache (a JSON file path), choices
+        stored there for the same key are applied without timing, and new
+        ones are added to it."""
         import json
         n = self._fields(rho)
         key = self.tuning_key(n, str(rho.dtype).replace("torch.", ""))
@@ -226,17 +229,17 @@ class Plan:
         if cache is not None and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
-            if key in table:
-                sk, ch, gr = (int(v) for v in table[key])
+            if key in table and len(table[key]) == 4:
+                res = tuple(int(v) for v in table[key])
                 try:
-                    self.set_tuning(sk, ch, gr)
-                    return sk, ch, gr
+                    self.set_tuning(*res)
+                    return res
                 except MpgError:
                     pass  # not applicable to this plan (e.g. its work space): time afresh
-        sk, ch, gr = C.c_int(), C.c_int(), C.c_int()
+        out = [C.c_int() for _ in range(4)]
         _check(lib().mpg_autotune(self._h, n, C.c_void_p(rho.data_ptr()), _dtype_code(rho),
-                                  C.byref(sk), C.byref(ch), C.byref(gr)))
-        res = (sk.value, ch.value, gr.value)
+                                  *(C.byref(v) for v in out)))
+        res = tuple(v.value for v in out)
         if cache is not None:
             table[key] = list(res)
             tmp = f"{cache}.tmp{os.getpid()}"
@@ -245,9 +248,9 @@ class Plan:
             os.replace(tmp, cache)
         return res
 
-    def set_tuning(self, splitk=0, chunks=0, gemm2_rows=0):
+    def set_tuning(self, splitk=0, chunks=0, gemm1_rows=0, gemm2_rows=0):
         """Set the autotuner's choices (0 leaves one as it is)."""
-        _check(lib().mpg_set_tuning(self._h, splitk, chunks, gemm2_rows))
+        _check(lib().mpg_set_tuning(self._h, splitk, chunks, gemm1_rows, gemm2_rows))
 
     def tables(self):
         """(U, Q, w) as float64 device tensors [n_patches, n_ang, n_lm] (twice)
@@ -302,6 +305,20 @@ def potential_batch(plans, rhos, phis):
     P = (C.c_void_p * n)(*[p.data_ptr() for p in phis])
     _check(lib().mpg_potential_batch(n, H, R, P, dt))
     return phis
+
+
+def batch_choices(plans, dtype):
+    """The choices each field takes in a batched solve of these plans in this
+    element type (torch.float32 or torch.float64): a list of (splitk,
+    chunks, gemm1_rows, gemm2_rows), one per field, in set_tuning's order."""
+    import numpy as np
+    import torch
+    n = len(plans)
+    dt = MPG_F64 if dtype == torch.float64 else MPG_F32
+    H = (C.c_void_p * n)(*[p.handle for p in plans])
+    out = [np.zeros(n, dtype=np.int32) for _ in range(4)]
+    _check(lib().mpg_batch_choices(n, H, dt, *(a.ctypes.data_as(C.POINTER(C.c_int)) for a in out)))
+    return [tuple(int(a[f]) for a in out) for f in range(n)]
 
 
 def batch_field_times(plans, dtype):

@@ -88,15 +88,18 @@ int cu_count() {
         if (e_ != hipSuccess) return e_;          \
     } while (0)
 
-// Work of one field (one field of the plan) in the fused kernel's units.
+// Work of one field (one field of the plan) in the fused kernel's units,
+// with the plan's block shapes and scan chunks.
 FieldShape field_shape(const Plan &p) {
     FieldShape sh;
+    const int rt = (p.n_r + kSplitTile - 1) / kSplitTile;
+    const int nb1 = p.gemm1_rows == 2 ? 1 : 2;  // column tiles per moment block
     sh.split_units = (int)(split_input_threads(p, 1) / 2048);
-    sh.row_tiles1 = (p.n_r + kSplitTile - 1) / kSplitTile;
-    sh.pairs_e = (p.tiles_e() + 1) / 2;
-    sh.pairs_o = (p.tiles_o() + 1) / 2;
-    sh.six_e = six_pairs(p.six_e, sh.pairs_e);
-    sh.six_o = p.fold ? six_pairs(p.six_o, sh.pairs_o) : 0;
+    sh.rows1 = p.gemm1_rows == 2 ? (rt + 1) / 2 : rt;
+    sh.units_e = (p.tiles_e() + nb1 - 1) / nb1;
+    sh.units_o = (p.tiles_o() + nb1 - 1) / nb1;
+    sh.six_e = six_units(p.six_e, sh.units_e, nb1);
+    sh.six_o = p.fold ? six_units(p.six_o, sh.units_o, nb1) : 0;
     sh.kang = p.kang();
     sh.splitk_max = p.splitk;
     // a single solve's K split choice fills the chip with one field's tiles;
@@ -104,8 +107,10 @@ FieldShape field_shape(const Plan &p) {
     sh.splitk_min = 1;
     sh.scan_blocks = (p.np + 63) / 64;
     sh.n_r = p.n_r;
-    sh.row_tiles2 = (p.n_r + kSplitTile - 1) / kSplitTile;
-    sh.ang_pairs = (p.n2() / kSplitTile + 1) / 2;
+    sh.chunks = scan_args(p, 1, true).chunks;
+    const int at = p.n2() / kSplitTile;
+    sh.rows2 = p.gemm2_rows == 2 ? (rt + 1) / 2 : rt;
+    sh.cols2 = p.gemm2_rows == 2 ? at : (at + 1) / 2;
     if (p.fold) {
         const int ne = p.ne_p / kSlabK, no = p.no_p / kSlabK;
         const int e3 = three_slabs(ne, p.six_e / kSlabK), o3 = three_slabs(no, p.six_o / kSlabK);
@@ -318,6 +323,20 @@ hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *c
         CHECK(hipMemcpyAsync(b->args_dev, b->fa.data(), sizeof(F64Args) * n, hipMemcpyHostToDevice, stream));
     }
     return hipGraphLaunch(b->exec, stream);
+}
+
+BatchChoice batch_choice(const Plan &p) {
+    BatchChoice c;
+    c.chunks = scan_args(p, 1, true).chunks;
+    if (p.split()) {
+        c.splitk = fused_splitk(field_shape(p));
+        c.gemm1_rows = p.gemm1_rows;
+        c.gemm2_rows = p.gemm2_rows;
+    } else {
+        c.splitk = choose_splitk(p, 1);
+        c.gemm1_rows = c.gemm2_rows = 1;
+    }
+    return c;
 }
 
 hipError_t batch_field_times(const std::vector<const Plan *> &plans, int dtype, double *ms) {

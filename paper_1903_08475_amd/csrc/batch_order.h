@@ -120,23 +120,27 @@ inline std::vector<int> order_items(const std::vector<OrderItem> &items, int n_f
 namespace mpg {
 
 // Work of one field of a split-form batch, in the units of the fused
-// persistent kernel (tiles of 128, K slabs of 32 cells or moments).
+// persistent kernel (tiles of 128, K slabs of 32 cells or moments).  A
+// contraction block is 128 rows x 256 columns (two column tiles, one row
+// tile) or 256 x 128 (one column tile, two row tiles), as the field's plan
+// chose; its row and column units count blocks of that shape.
 struct FieldShape {
-    int split_units;           // input split: units of 2048 16-byte chunks
-    int row_tiles1;            // moment contraction: row tiles
-    int pairs_e, pairs_o;      // column-tile pairs of the even / odd block
-    int six_e, six_o;          // leading pairs of each block with six products
-    int kang;                  // moment contraction: K (angular cells, a multiple of 128)
-    int splitk_min, splitk_max; // K splits: at least (the plan's choice), at most (its work space)
-    int scan_blocks, n_r;      // radial scans: column blocks of 64, shells
-    int row_tiles2, ang_pairs; // expansion: row tiles and angular tile pairs
-    int k2_three, k2_six;      // expansion: K slabs with three / six products
+    int split_units;            // input split: units of 2048 16-byte chunks
+    int rows1;                  // moment contraction: row units
+    int units_e, units_o;       // column units of the even / odd block
+    int six_e, six_o;           // leading column units of each block with six products
+    int kang;                   // moment contraction: K (angular cells, a multiple of 128)
+    int splitk_min, splitk_max; // K splits: at least, at most (its work space)
+    int scan_blocks, n_r;       // radial scans: column blocks of 64, shells
+    int chunks;                 // radial scans: shell chunks per column
+    int rows2, cols2;           // expansion: row units and angular units
+    int k2_three, k2_six;       // expansion: K slabs with three / six products
 };
 
 // A queue entry of the fused kernel: field f, stage st (0 input split,
-// 1 moments, 2 radial scans, 3 expansion) and the stage's tile coordinates:
-// split (first unit, units), moments (column pair, row tile, K split),
-// scans (column block), expansion (row tile, angular pair).
+// 1 moments, 2 radial scans, 3 expansion) and the stage's block
+// coordinates: split (first unit, units), moments (column unit, row unit,
+// K split), scans (column block), expansion (row unit, angular unit).
 struct FusedItem {
     int f, st, a, b, c;
 };
@@ -145,15 +149,19 @@ constexpr int kFusedStages = 4;
 constexpr int kSplitUnitsPerItem = 8;
 
 // Estimated item costs (microseconds on one CU of the target): measured
-// rates of the stage kernels on the benchmark workload.  sk: K splits.
+// rates of the stage kernels on the benchmark workload.  sk: K splits.  A
+// scan item's eight thread rows take the chunks in turns.
 inline double fused_cost(const FieldShape &s, int sk, int st, int a, int b) {
     switch (st) {
         case 0: return 14.0 * b;
         case 1: {
-            const bool six = a < s.pairs_e ? a < s.six_e : a - s.pairs_e < s.six_o;
+            const bool six = a < s.units_e ? a < s.six_e : a - s.units_e < s.six_o;
             return ksplit_chunk(s.kang, sk, 32) / 32 * (six ? 2.4 : 1.6);
         }
-        case 2: return s.n_r * (0.15 + 0.05 * sk);
+        case 2: {
+            const int ch = std::max(s.chunks, 1);
+            return 1.2 * ((ch + 7) / 8) * ((s.n_r + ch - 1) / ch) * (1.0 + sk / 3.0);
+        }
         default: return 1.66 * s.k2_three + 2.5 * s.k2_six;
     }
 }
@@ -186,11 +194,11 @@ inline std::vector<FusedItem> fused_items(const std::vector<FieldShape> &shapes,
         for (int u = 0; u < s.split_units; u += kSplitUnitsPerItem)
             add(0, u, std::min(kSplitUnitsPerItem, s.split_units - u), 0);
         for (int z = 0; z < sk; ++z)
-            for (int m = 0; m < s.row_tiles1; ++m)
-                for (int c = 0; c < s.pairs_e + s.pairs_o; ++c) add(1, c, m, z);
+            for (int m = 0; m < s.rows1; ++m)
+                for (int c = 0; c < s.units_e + s.units_o; ++c) add(1, c, m, z);
         for (int x = 0; x < s.scan_blocks; ++x) add(2, x, 0, 0);
-        for (int a = 0; a < s.ang_pairs; ++a)
-            for (int m = 0; m < s.row_tiles2; ++m) add(3, m, a, 0);
+        for (int a = 0; a < s.cols2; ++a)
+            for (int m = 0; m < s.rows2; ++m) add(3, m, a, 0);
     }
     for (int i = 0; i < (int)ord.size(); ++i) ord[i].idx = i;
     const std::vector<int> q = order_items(ord, (int)shapes.size(), kFusedStages, workers);

@@ -90,6 +90,28 @@ void free_plan(mpg_plan_s *p) {
 // K splits of the moment contraction for n_fields fields: the autotuned
 // choice if there is one, else enough blocks to cover the chip; never more
 // than the plan's work space holds.
+// Block shape of a contraction from the timings of its two shapes (t1:
+// 128 x 256, t2: 256 x 128) and their block counts b1, b2 (padding
+// included), on a chip of `cus` CUs (one block each at a time).  Each
+// shape's cost is its chip work: the time of one of its blocks (its time
+// over its waves of blocks) times its blocks, over the CUs.  For a solve
+// that fills the chip in whole waves that is its time; otherwise it leaves
+// out the CUs a partial wave leaves idle, which the other work beside it
+// (the fields of a batch) can use.  The cheaper shape is kept when it is
+// at least 1% cheaper; else the one with fewer blocks, and the first when
+// those are equal too.
+static double chip_work(float t, long blocks, int cus) {
+    const long waves = (blocks + cus - 1) / cus;
+    return waves > 0 ? (double)t * blocks / ((double)waves * cus) : 0.0;
+}
+
+static int pick_shape(float t1, float t2, long b1, long b2, int cus) {
+    const double c1 = chip_work(t1, b1, cus), c2 = chip_work(t2, b2, cus);
+    if (c2 < 0.99 * c1) return 2;
+    if (c1 < 0.99 * c2) return 1;
+    return b2 < b1 ? 2 : 1;
+}
+
 int choose_splitk(const Plan &p, int n_fields) {
     int s;
     if (p.splitk_sel > 0) {
@@ -516,8 +538,23 @@ int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms)
     return MPG_OK;
 }
 
+int mpg_batch_choices(int n, const mpg_plan_t *plans, int dtype, int *splitk, int *chunks, int *gemm1_rows,
+                      int *gemm2_rows) {
+    if (n < 1 || !plans) return fail(MPG_EINVAL, "mpg_batch_choices: bad arguments");
+    if (dtype != MPG_F64 && dtype != MPG_F32) return fail(MPG_EINVAL, "mpg_batch_choices: bad dtype");
+    for (int f = 0; f < n; ++f) {
+        if (!plans[f]) return fail(MPG_EINVAL, "mpg_batch_choices: NULL plan");
+        BatchChoice c = batch_choice(*plans[f]);
+        if (splitk) splitk[f] = c.splitk;
+        if (chunks) chunks[f] = c.chunks;
+        if (gemm1_rows) gemm1_rows[f] = c.gemm1_rows;
+        if (gemm2_rows) gemm2_rows[f] = c.gemm2_rows;
+    }
+    return MPG_OK;
+}
+
 int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, int *splitk, int *chunks,
-                 int *gemm2_rows) {
+                 int *gemm1_rows, int *gemm2_rows) {
     int rc = check_call(p, n_fields_in, rho, rho_dtype, "mpg_autotune");
     if (rc) return rc;
     const int n_fields = p->vfields(n_fields_in);
@@ -529,10 +566,12 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
         return hip_fail(e, "mpg_autotune");
     }
     const bool split = p->split();
+    int best_g1 = p->gemm1_rows;
     auto time_stage = [&](int sk, int ch, bool scan, float *ms) -> hipError_t {
         Plan q = *p;
         q.splitk = sk;
         q.scan_chunks = ch;
+        q.gemm1_rows = best_g1;
         float best = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {  // first run is a warm-up
             hipError_t err;
@@ -571,6 +610,25 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
         if ((e = time_stage(s, p->scan_chunks, true, &ts)) != hipSuccess) break;
         if (t + ts < 0.99f * best_t) { best_t = t + ts; best_s = s; }
     }
+    // rows of the contractions (GEMM1's per-patch rows included)
+    const int rt1 = (n_fields * p->n_r + kSplitTile - 1) / kSplitTile;
+    const int rt2 = (n_fields_in * p->n_r + kSplitTile - 1) / kSplitTile;
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (cus < 1) cus = 1;
+    if (e == hipSuccess && split) {
+        // block shape of the moment contraction: 128 x 256 (the default) or
+        // 256 x 128, each timed without a K split
+        float tg[3] = {0.0f, 1e30f, 1e30f};
+        const int g1_was = best_g1;
+        for (int r = 1; r <= 2 && e == hipSuccess; ++r) {
+            best_g1 = r;
+            e = time_stage(1, p->scan_chunks, false, &tg[r]);
+        }
+        const int ct_e = p->tiles_e(), ct_o = p->tiles_o();
+        const long b1 = (long)((ct_e + 1) / 2 + (ct_o + 1) / 2) * rt1, b2 = (long)(ct_e + ct_o) * ((rt1 + 1) / 2);
+        best_g1 = e == hipSuccess ? pick_shape(tg[1], tg[2], b1, b2, cus) : g1_was;
+    }
     int best_c = p->scan_chunks;
     if (e == hipSuccess) {
         // scan schedule: shell chunks per column (the scan reads best_s partial sums)
@@ -601,6 +659,7 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
             Plan q = *p;
             q.splitk = best_s;
             q.scan_chunks = best_c;
+            q.gemm1_rows = best_g1;
             e = gemm1_bf16(q, n_fields, rho, rho_dtype);
             if (e == hipSuccess) e = radial_scan(q, n_fields, true);
             float tr[3] = {0.0f, 1e30f, 1e30f};
@@ -616,8 +675,10 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
                     if (rep > 0 && t < tr[r]) tr[r] = t;
                 }
             }
-            // the default shape, unless the other is at least 1% faster
-            if (e == hipSuccess) best_r = tr[2] < 0.99f * tr[1] ? 2 : 1;
+            if (e == hipSuccess) {
+                const int at = p->n2() / kSplitTile;
+                best_r = pick_shape(tr[1], tr[2], (long)rt2 * ((at + 1) / 2), (long)((rt2 + 1) / 2) * at, cus);
+            }
             hipError_t es = hipStreamSynchronize(p->stream);
             hipError_t ef = hipFree(phi);
             if (e == hipSuccess) e = es != hipSuccess ? es : ef;
@@ -628,11 +689,13 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
     if (e != hipSuccess) return hip_fail(e, "mpg_autotune");
     p->splitk_sel = best_s;
     p->scan_chunks = best_c;
+    p->gemm1_rows = best_g1;
     p->gemm2_rows = best_r;
     ++p->tune_epoch;
     if (splitk) *splitk = best_s;
     if (chunks) *chunks = best_c;
-    if (gemm2_rows) *gemm2_rows = best_r;
+    if (gemm1_rows) *gemm1_rows = split ? best_g1 : 1;
+    if (gemm2_rows) *gemm2_rows = split ? best_r : 1;
     return MPG_OK;
 }
 
@@ -643,13 +706,15 @@ int mpg_tables(mpg_plan_t p, double *U, double *Q, double *w) {
     return MPG_OK;
 }
 
-int mpg_set_tuning(mpg_plan_t p, int splitk, int chunks, int gemm2_rows) {
+int mpg_set_tuning(mpg_plan_t p, int splitk, int chunks, int gemm1_rows, int gemm2_rows) {
     if (!p) return fail(MPG_EINVAL, "mpg_set_tuning: plan is NULL");
     if (splitk > p->splitk) return fail(MPG_EINVAL, "mpg_set_tuning: K split exceeds the plan's work space");
     if (chunks > 16) return fail(MPG_EINVAL, "mpg_set_tuning: more than 16 shell chunks");
+    if (gemm1_rows > 2) return fail(MPG_EINVAL, "mpg_set_tuning: gemm1_rows must be 1 or 2");
     if (gemm2_rows > 2) return fail(MPG_EINVAL, "mpg_set_tuning: gemm2_rows must be 1 or 2");
     if (splitk > 0) p->splitk_sel = splitk;
     if (chunks > 0) p->scan_chunks = chunks;
+    if (gemm1_rows > 0) p->gemm1_rows = gemm1_rows;
     if (gemm2_rows > 0) p->gemm2_rows = gemm2_rows;
     ++p->tune_epoch;
     return MPG_OK;

@@ -495,38 +495,46 @@ __device__ __forceinline__ void run_tiered(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1,
 }
 
 
-// 128 rows of rho+- and 256 columns of U (GEMM1), or 128 rows of M and 256
-// angular cells of Q (GEMM2's default block)
-typedef SlabT<1, 2> Slab1;
-
 // ---------------------------------------------------------------------------
-// One output block of GEMM1: column pair tn (two 128-column tiles; pairs of
-// the even-m block first, then of the odd-m block), row tile tm, K split
-// tz.  Writes Bpart[tz][row][col] in FP64.
-template <bool FOLD>
-__device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, Slab1 &S0, Slab1 &S1) {
+// One output block of GEMM1, NA row tiles x (3 - NA) column tiles of 128:
+// NA = 1 is 128 x 256 (column pair tn: two 128-column tiles, pairs of the
+// even-m block first, then of the odd-m block; row tile tm), NA = 2 is
+// 256 x 128 (column tile tn, tiles of the even-m block first; row tile pair
+// tm); K split tz.  Writes Bpart[tz][row][col] in FP64.  Each output takes
+// the same products in the same order in both shapes.
+template <bool FOLD, int NA>
+__device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, SlabT<NA, 3 - NA> &S0,
+                                           SlabT<NA, 3 - NA> &S1) {
+    constexpr int NB = 3 - NA;
     const int rows = g.rows, np = g.np, ne_p = g.ne_p;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-    const int pe = (g.tiles_e + 1) / 2;  // column pairs of the even block
-    const bool odd = FOLD && tn >= pe;
-    const int ct0 = odd ? g.tiles_e + 2 * (tn - pe) : 2 * tn;
+    const int wm = (wave % (2 * NA)) * 64, wn = (wave / (2 * NA)) * 64;
+    // column units (pairs or tiles) of the even block
+    const int ue = NA == 1 ? (g.tiles_e + 1) / 2 : g.tiles_e;
+    const bool odd = FOLD && tn >= ue;
+    const int u = odd ? tn - ue : tn;  // column unit within the parity block
+    const int ct0 = (odd ? g.tiles_e : 0) + NB * u;
     // a second tile past the block's end: in bounds, and its columns are never stored
     const int ct1 = min(ct0 + 1, g.tiles_e + g.tiles_o - 1);
-    const int c0 = odd ? ne_p + 2 * (tn - pe) * TB : 2 * tn * TB;
+    const int cl = NB * u * TB;  // first column within the parity block
+    const int c0 = (odd ? ne_p : 0) + cl;
     const int cend = odd ? np : (FOLD ? ne_p : np);
-    const int m0 = tm * TB;
+    const int m0 = tm * NA * TB;
+    const int rt_used = (rows + TB - 1) / TB;  // row tiles holding this call's rows
     const int kbeg = tz * g.kchunk;
     const int kend = min(g.kang, kbeg + g.kchunk);
     const int nsl = kend > kbeg ? (kend - kbeg) / TK : 0;
 
     // A: the pre-split rho (+-) of this block's column parity; B: split U
-    LoaderT<1, 2> L;
+    // (a second row tile past the rows in use is read in bounds and never stored)
+    LoaderT<NA, NB> L;
     const size_t tstride = (size_t)g.ks1 * 3 * kBlk;
-    L.a[0] = g.A + (odd ? (size_t)g.row_tiles * tstride : 0) + (size_t)tm * tstride;
+    const bf16 *A = g.A + (odd ? (size_t)g.row_tiles * tstride : 0);
+    L.a[0] = A + (size_t)(NA * tm) * tstride;
+    if constexpr (NA == 2) L.a[1] = A + (size_t)min(2 * tm + 1, rt_used - 1) * tstride;
     L.b[0] = g.U + (size_t)ct0 * tstride;
-    L.b[1] = g.U + (size_t)ct1 * tstride;
+    if constexpr (NB == 2) L.b[1] = g.U + (size_t)ct1 * tstride;
     L.part = wave * 512;
     L.lo = L.part + lane * 8;
 
@@ -541,17 +549,16 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
             for (int r = 0; r < 16; ++r) acc64[a][b][r] = 0.0;
     // six products for a wave whose first column lies in its parity block's
     // tier; the block copies the l pieces when any of its waves needs them
-    const int pair = odd ? tn - pe : tn;  // column pair within the parity block
-    const int cl = 2 * pair * TB;
     const int six_par = odd ? g.six_o : g.six_e;
     const bool six_b = cl < six_par, six_w = cl + wn < six_par;
-    // the waves on a second tile past the parity block's last only copy
-    // and wait (the same steps and barriers); the SIMD they share goes to
-    // the wave on the first tile
-    const bool idle = wn >= TB && 2 * pair + 1 >= (odd ? g.tiles_o : g.tiles_e);
+    // the waves on a second tile past the parity block's last, or on a
+    // second row tile past the rows in use, only copy and wait (the same
+    // steps and barriers); the SIMD they share goes to the other wave
+    const bool idle = NA == 1 ? wn >= TB && 2 * u + 1 >= (odd ? g.tiles_o : g.tiles_e)
+                              : wm >= TB && 2 * tm + 1 >= rt_used;
     const int n3 = six_w ? 0 : nsl, n3_load = six_b ? 0 : nsl;
-    if (idle) run_ring<1, 2, true, false>(S0, S1, L, kbeg / TK, 1, nsl, n3, n3_load, wm, wn, lane, acc, acc64);
-    else run_ring<1, 2, true, true>(S0, S1, L, kbeg / TK, 1, nsl, n3, n3_load, wm, wn, lane, acc, acc64);
+    if (idle) run_ring<NA, NB, true, false>(S0, S1, L, kbeg / TK, 1, nsl, n3, n3_load, wm, wn, lane, acc, acc64);
+    else run_ring<NA, NB, true, true>(S0, S1, L, kbeg / TK, 1, nsl, n3, n3_load, wm, wn, lane, acc, acc64);
 
     double *out = g.Bpart + (size_t)tz * rows * np;
 #pragma unroll
@@ -565,6 +572,11 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
                 if (rr < rows && cc < cend) out[(size_t)rr * np + cc] = acc64[a][b][r];
             }
 }
+
+// 128 rows x 256 columns (GEMM1) or angular cells (GEMM2), and 256 x 128
+typedef SlabT<1, 2> Slab1;
+typedef SlabT<2, 1> Slab2;
+static_assert(sizeof(Slab1) == sizeof(Slab2), "both block shapes use the same LDS");
 
 // One output block of GEMM2, NA row tiles x (3 - NA) angular tiles of 128:
 // NA = 1 is 128 x 256 (row tile tm, angular tile pair tn), NA = 2 is
@@ -666,30 +678,39 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
 }
 
 // ---------------------------------------------------------------------------
-// Grid launches for one plan: GEMM1 grid x = (column pair, row tile), z =
+// Grid launches for one plan: GEMM1 grid x = (column unit, row unit), z =
 // K split; GEMM2 grid x = row tile (pair), y = angular tile pair (tile).
-// GEMM1's blocks in x run over (column pair, row tile), the pairs that take
-// six products first (they take about twice as long as the others), so the
-// long blocks are dispatched before the short ones.
-template <bool FOLD>
+// A GEMM1 column unit is a pair of 128-column tiles (NA = 1) or one tile
+// (NA = 2), a row unit one row tile or a pair.  GEMM1's blocks in x run
+// over (column unit, row unit), the units that take six products first
+// (they take about twice as long as the others), so the long blocks are
+// dispatched before the short ones.
+template <int NA>
+__host__ __device__ inline void gemm1_units(int tiles_e, int tiles_o, int &ue, int &uo) {
+    ue = NA == 1 ? (tiles_e + 1) / 2 : tiles_e;
+    uo = NA == 1 ? (tiles_o + 1) / 2 : tiles_o;
+}
+
+template <bool FOLD, int NA>
 __global__ __launch_bounds__(kThreads) void k_gemm1(SplitArgs g) {
-    __shared__ Slab1 s0, s1;
-    const int pe = (g.tiles_e + 1) / 2, po = (g.tiles_o + 1) / 2;
-    const int he = six_pairs(g.six_e, pe), ho = FOLD ? six_pairs(g.six_o, po) : 0;
-    const int nh = he + ho, nl = pe + po - nh;
-    const int rt = gridDim.x / (pe + po);
+    __shared__ SlabT<NA, 3 - NA> s0, s1;
+    int ue, uo;
+    gemm1_units<NA>(g.tiles_e, g.tiles_o, ue, uo);
+    const int he = six_units(g.six_e, ue, 3 - NA), ho = FOLD ? six_units(g.six_o, uo, 3 - NA) : 0;
+    const int nh = he + ho, nl = ue + uo - nh;
+    const int rt = gridDim.x / (ue + uo);
     int b = blockIdx.x, tn, tm;
     if (b < nh * rt) {
         const int i = b % nh;
         tm = b / nh;
-        tn = i < he ? i : pe + (i - he);
+        tn = i < he ? i : ue + (i - he);
     } else {
         b -= nh * rt;
         const int i = b % nl;
         tm = b / nl;
-        tn = i < pe - he ? he + i : pe + ho + (i - (pe - he));
+        tn = i < ue - he ? he + i : ue + ho + (i - (ue - he));
     }
-    gemm1_tile<FOLD>(g, tn, tm, blockIdx.z, s0, s1);
+    gemm1_tile<FOLD, NA>(g, tn, tm, blockIdx.z, s0, s1);
 }
 
 template <typename T, bool FOLD, bool PP, int NA>
@@ -708,9 +729,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm2(SplitArgs g) {
 // XCD's L2 written back) and counts the item; the item that completes a
 // field's expansion stamps the field's completion time (the expansion's
 // output is read by no item, needs no write-back and is stored
-// non-temporally).  Scans run with 8 shell
-// chunks of 64 lanes on the slab buffers' LDS; expansions in 128 x 256
-// blocks.
+// non-temporally).  Each field's items take its plan's choices: the block
+// shapes of both contractions and the scans' chunk count (eight thread
+// rows of 64 lanes, on the slab buffers' LDS).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_batch_fused(const SplitArgs *__restrict__ args,
                                                           const ScanArgs *__restrict__ sargs,
@@ -719,6 +740,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const SplitArgs *__res
     __shared__ Slab1 sl[2];
     __shared__ int slot, go;
     Slab1 &s0 = sl[0], &s1 = sl[1];
+    // the same two buffers in the 256 x 128 block shape
+    Slab2 &t0 = *reinterpret_cast<Slab2 *>(&sl[0]), &t1 = *reinterpret_cast<Slab2 *>(&sl[1]);
     const int tid = threadIdx.x;
     for (;;) {
         __syncthreads();  // every thread is done with the previous item and the shared slots
@@ -755,16 +778,28 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const SplitArgs *__res
                 else fold_split_unit<T, false>(g, u, tid);
             }
         } else if (w.st == 1) {
-            if (g.fold) gemm1_tile<true>(g, w.a, w.b, w.c, s0, s1);
-            else gemm1_tile<false>(g, w.a, w.b, w.c, s0, s1);
+            if (g.g1_rows == 2) {
+                if (g.fold) gemm1_tile<true, 2>(g, w.a, w.b, w.c, t0, t1);
+                else gemm1_tile<false, 2>(g, w.a, w.b, w.c, t0, t1);
+            } else {
+                if (g.fold) gemm1_tile<true, 1>(g, w.a, w.b, w.c, s0, s1);
+                else gemm1_tile<false, 1>(g, w.a, w.b, w.c, s0, s1);
+            }
         } else if (w.st == 2) {
+            // the field's own chunk count, eight thread rows
+            constexpr int kMC = scan_detail::kMaxChunks * scan_detail::kLanes;
+            static_assert(4 * kMC * sizeof(double) <= sizeof(Slab1), "scan carries fit in one slab buffer");
             double *lds = reinterpret_cast<double *>(&s0);
-            constexpr int kCh = kThreads / 64;
-            scan_detail::scan_block_core(sargs[w.f], w.a, tid & 63, tid >> 6, kCh, lds, lds + kCh * 64,
-                                         lds + 2 * kCh * 64, lds + 3 * kCh * 64);
+            scan_detail::scan_block_core(sargs[w.f], w.a, tid & 63, tid >> 6, kThreads / 64, lds, lds + kMC,
+                                         lds + 2 * kMC, lds + 3 * kMC);
         } else {
-            if (g.fold) gemm2_tile<T, true, false, 1, true>(g, w.a, w.b, s0, s1);
-            else gemm2_tile<T, false, false, 1, true>(g, w.a, w.b, s0, s1);
+            if (g.g2_rows == 2) {
+                if (g.fold) gemm2_tile<T, true, false, 2, true>(g, w.a, w.b, t0, t1);
+                else gemm2_tile<T, false, false, 2, true>(g, w.a, w.b, t0, t1);
+            } else {
+                if (g.fold) gemm2_tile<T, true, false, 1, true>(g, w.a, w.b, s0, s1);
+                else gemm2_tile<T, false, false, 1, true>(g, w.a, w.b, s0, s1);
+            }
         }
         // this block's stores are complete; then (but after the expansion,
         // whose output no item reads) one wave writes this XCD's L2 back
@@ -825,6 +860,8 @@ SplitArgs split_args(const Plan &p, int n_fields, const void *rho, void *phi, in
     g.ks2 = p.kq() / TK;
     g.six_e = p.six_e;
     g.six_o = p.six_o;
+    g.g1_rows = p.gemm1_rows;
+    g.g2_rows = p.gemm2_rows;
     return g;
 }
 
@@ -850,9 +887,19 @@ hipError_t split_input_bf16(const Plan &p, int n_fields, const void *rho, int rh
 
 hipError_t gemm1_bf16(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
     SplitArgs g = split_args(p, n_fields, rho, nullptr, rho_dtype);
-    dim3 grid(((g.tiles_e + 1) / 2 + (g.tiles_o + 1) / 2) * ((g.rows + TB - 1) / TB), 1, p.splitk);
-    if (p.fold) hipLaunchKernelGGL((k_gemm1<true>), grid, dim3(kThreads), 0, p.stream, g);
-    else hipLaunchKernelGGL((k_gemm1<false>), grid, dim3(kThreads), 0, p.stream, g);
+    const int rt = (g.rows + TB - 1) / TB;
+    int ue, uo;
+    if (g.g1_rows == 2) {
+        gemm1_units<2>(g.tiles_e, g.tiles_o, ue, uo);
+        dim3 grid((ue + uo) * ((rt + 1) / 2), 1, p.splitk);
+        if (p.fold) hipLaunchKernelGGL((k_gemm1<true, 2>), grid, dim3(kThreads), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm1<false, 2>), grid, dim3(kThreads), 0, p.stream, g);
+    } else {
+        gemm1_units<1>(g.tiles_e, g.tiles_o, ue, uo);
+        dim3 grid((ue + uo) * rt, 1, p.splitk);
+        if (p.fold) hipLaunchKernelGGL((k_gemm1<true, 1>), grid, dim3(kThreads), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm1<false, 1>), grid, dim3(kThreads), 0, p.stream, g);
+    }
     return hipGetLastError();
 }
 

@@ -39,11 +39,12 @@ constexpr int kSlabK = 32;
 constexpr int kBlk = kSplitTile * kSlabK;
 __host__ __device__ inline int blk_pos(int r, int k) { return (4 * r + ((k >> 3) ^ ((r >> 2) & 3))) * 8 + (k & 7); }
 
-// Column pairs (GEMM1 blocks of 2*kSplitTile columns) of a block of
-// `pairs` pairs whose leading six_cols columns take six products.
-__host__ __device__ inline int six_pairs(int six_cols, int pairs) {
-    const int n = (six_cols + 2 * kSplitTile - 1) / (2 * kSplitTile);
-    return n < pairs ? n : pairs;
+// Column units of GEMM1 blocks (nb = 2: pairs of kSplitTile-column tiles;
+// nb = 1: single tiles) among the `units` units of a parity block, whose
+// leading six_cols columns take six products: the units holding any of them.
+__host__ __device__ inline int six_units(int six_cols, int units, int nb) {
+    const int n = (six_cols + nb * kSplitTile - 1) / (nb * kSplitTile);
+    return n < units ? n : units;
 }
 
 // Leading three-product slabs of a K walk of nsl slabs that runs from the
@@ -113,6 +114,7 @@ struct Plan {
     int splitk = 1;            // K splits of the moment contraction (work space holds this many)
     int splitk_sel = 0;        // chosen by mpg_autotune (0: heuristic)
     int scan_chunks = 16;      // shell chunks per column in the radial scan
+    int gemm1_rows = 1;        // split moment blocks: 1 = 128 rows x 256 columns, 2 = 256 x 128
     int gemm2_rows = 1;        // split expansion blocks: 1 = 128 rows x 256 cells, 2 = 256 x 128
     int tune_epoch = 0;        // raised whenever the choices above change (batched solves rebuild)
     double *Bpart = nullptr;   // [splitk][rows][np]
@@ -197,6 +199,7 @@ struct SplitArgs {
     int row_tiles;          // row tiles of a plane of A (and of M)
     int ks1, ks2;           // slabs of GEMM1 (kang/32) and GEMM2 (np/32)
     int six_e, six_o;       // leading columns of each block with six products (see Plan)
+    int g1_rows, g2_rows;   // block shapes: 1 = 128 rows x 256 columns, 2 = 256 x 128 (see Plan)
 };
 
 // Arguments of one field's FP64 contractions.
@@ -225,6 +228,7 @@ struct ScanArgs {
     int pp;          // per-patch method: single-patch fields per field (its row (f, shell), column
                      // (patch, q) in Ms), else 0
     int col_blocks;  // blocks of 64 columns
+    int chunks;      // shell chunks per column (1..16, at most n_r)
 };
 
 // ---- kernels launchers (each returns hipError_t of the launch) ----------
@@ -248,6 +252,12 @@ hipError_t batch_gemm1_f64(const F64Args *args, const BatchItem *items, int n_it
                            int blocks, hipStream_t s);
 hipError_t batch_gemm2_f64(const F64Args *args, const BatchItem *items, int n_items, int *head, int io_dtype,
                            int blocks, BatchTrack track, hipStream_t s);
+
+// the choices one field of a plan takes in a batched solve (batch.hip)
+struct BatchChoice {
+    int splitk, chunks, gemm1_rows, gemm2_rows;
+};
+BatchChoice batch_choice(const Plan &p);
 
 // radial scans (scan.hip): Bpart -> Bred, M (and the split copies of M)
 hipError_t radial_scan(const Plan &p, int n_fields, bool split_out);

@@ -6,18 +6,18 @@
 // All coefficients are ratios <= 1 (no r^l, r^-(l+1) overflow at any radius).
 //
 // A block owns 64 consecutive columns (one lane each) and splits the shells
-// into T chunks (one wave-row of threads each).  Every chunk first composes
-// its affine maps (product of a or c, local sums), the chunk carries are
-// chained through LDS, and a second sweep writes M.  The first sweep also
-// reduces the split-K partial sums of the moments in a fixed order, so the
-// result does not depend on scheduling.
+// into T chunks (the plan's choice; one wave-row of threads each here).
+// Every chunk first composes its affine maps (product of a or c, local
+// sums), the chunk carries are chained through LDS, and a second sweep
+// writes M.  The first sweep also reduces the split-K partial sums of the
+// moments in a fixed order, so the result does not depend on scheduling.
 #include "scan_core.h"
 
 namespace mpg {
 namespace {
 
 using scan_detail::kLanes;
-constexpr int kMaxChunks = 16;
+using scan_detail::kMaxChunks;
 
 // one block of the scan kernel: lanes in x, shell chunks in y
 __device__ __forceinline__ void scan_block(const ScanArgs &g, int bx) {
@@ -30,7 +30,8 @@ __global__ __launch_bounds__(1024) void k_scan(ScanArgs g) {
     scan_block(g, blockIdx.x);
 }
 
-// persistent batch version: items (field, column block) from a queue
+// persistent batch version: items (field, column block) from a queue; each
+// field's scan takes its own chunk count (16 thread rows, one chunk each)
 __global__ __launch_bounds__(1024) void k_batch_scan(const ScanArgs *__restrict__ args,
                                                      const BatchItem *__restrict__ items, int n_items, int *head) {
     __shared__ int slot;
@@ -76,16 +77,17 @@ ScanArgs scan_args(const Plan &p, int n_fields, bool split_out) {
     g.ks2 = p.kq() / kSlabK;
     g.pp = p.per_patch ? p.n_patches : 0;
     g.col_blocks = (n_fields * p.np + kLanes - 1) / kLanes;
+    int T = p.scan_chunks;
+    if (T > p.n_r) T = p.n_r;
+    if (T < 1) T = 1;
+    if (T > kMaxChunks) T = kMaxChunks;
+    g.chunks = T;
     return g;
 }
 
 hipError_t radial_scan(const Plan &p, int n_fields, bool split_out) {
     ScanArgs g = scan_args(p, n_fields, split_out);
-    int T = p.scan_chunks;
-    if (T > p.n_r) T = p.n_r;
-    if (T < 1) T = 1;
-    if (T > kMaxChunks) T = kMaxChunks;
-    hipLaunchKernelGGL(k_scan, dim3(g.col_blocks), dim3(kLanes, T), 0, p.stream, g);
+    hipLaunchKernelGGL(k_scan, dim3(g.col_blocks), dim3(kLanes, g.chunks), 0, p.stream, g);
     return hipGetLastError();
 }
 

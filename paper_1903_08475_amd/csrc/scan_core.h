@@ -9,6 +9,7 @@ namespace scan_detail {
 
 constexpr int kLanes = 64;
 constexpr int kGroup = 4;  // shells per group of loads in each sweep
+constexpr int kMaxChunks = 16;  // shell chunks per column, at most
 
 // element (row, col) of piece 0 of the tile-slab split copy of M
 __device__ inline size_t split_offset(int row, int col, int ks2) {
@@ -31,100 +32,73 @@ __device__ inline double reduce_parts(const double *Bpart, size_t stride, int sp
     return s;
 }
 
-// One block of 64 columns: lane (0..63) is the thread's column, ch (0..T-1)
-// its shell chunk (a wave's worth of lanes each); the block's threads must
-// all call it (it holds one workgroup barrier).  sA, sY, sC, sZ: T x 64
-// doubles of LDS each.  Threads with lane >= the column count, and
-// chunks past the last shell, hold identity maps and write nothing.  Each
-// sweep takes kGroup shells at a time: the loads of a group are issued
-// together before the recurrence consumes them, so a wave waits for one
-// memory latency per group rather than per shell (the loads of a short
-// last group repeat an in-range shell; their values are not used).
-__device__ __forceinline__ void scan_block_core(const ScanArgs &g, int bx, int lane, int ch, int T, double *sA,
-                                                double *sY, double *sC, double *sZ) {
+// First sweep over chunk [lo, hi) of one column: reduces the partial sums
+// into Bred and composes the chunk's maps (inner: y -> A y + y0; outer:
+// z -> P z + zl).  The outer sum over shells n > lo uses the coefficients
+// (c, e) of shell n - 1.  Each sweep takes kGroup shells at a time: the
+// loads of a group are issued together before the recurrence consumes
+// them, so a wave waits for one memory latency per group rather than per
+// shell (the loads of a short last group repeat an in-range shell; their
+// values are not used).
+struct ChunkMap {
+    double A, y, P, zl;
+};
+
+__device__ __forceinline__ ChunkMap compose_chunk(const ScanArgs &g, size_t base, const double *cf, size_t cstep,
+                                                  int lo, int hi) {
     const double *__restrict__ Bpart = g.Bpart;
-    const int splitk = g.splitk, n_fields = g.n_fields, n_r = g.n_r, np = g.np, L = g.L;
-    const int *__restrict__ col_l = g.col_l;
-    const double *__restrict__ coef = g.coef;
+    const int splitk = g.splitk, n_r = g.n_r, np = g.np;
+    const size_t stride = (size_t)g.n_fields * n_r * np;
     double *__restrict__ Bred = g.Bred;
+    ChunkMap m{1.0, 0.0, 1.0, 0.0};
+    double pc = 0.0, pe = 0.0;
+    for (int n0 = lo; n0 < hi; n0 += kGroup) {
+        const int cnt = min(kGroup, hi - n0);
+        double Bv[kGroup], c[kGroup][4];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            Bv[u] = 0.0;
+            const double *cn = cf + min(n0 + u, hi - 1) * cstep;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[u][k] = cn[k];
+        }
+        for (int k = 0; k < splitk; ++k)
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) Bv[u] += Bpart[k * stride + base + (size_t)min(n0 + u, hi - 1) * np];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            if (u >= cnt) break;
+            const int n = n0 + u;
+            Bred[base + (size_t)n * np] = Bv[u];
+            m.y = c[u][0] * m.y + c[u][1] * Bv[u];
+            m.A *= c[u][0];
+            if (n > lo) {
+                m.zl += m.P * pe * Bv[u];
+                m.P *= pc;
+            }
+            pc = c[u][2];
+            pe = c[u][3];
+        }
+    }
+    if (hi > lo && hi < n_r) {
+        const double Bh = reduce_parts(Bpart, stride, splitk, base + (size_t)hi * np);
+        m.zl += m.P * pe * Bh;
+        m.P *= pc;
+    }
+    return m;
+}
+
+// Second sweep over chunk [lo, hi) of one column, entered with the inner
+// sum of the shells below the chunk (Yin) and the outer sum of the shells
+// above it (Zin): writes M (and its split copy).
+__device__ __forceinline__ void finish_chunk(const ScanArgs &g, size_t base, const double *cf, size_t cstep, int f,
+                                             int q, int lo, int hi, double Yin, double Zin) {
+    const int n_r = g.n_r, np = g.np;
+    const double *__restrict__ Bred = g.Bred;
     double *__restrict__ M = g.M;
     bf16 *__restrict__ Ms = g.Ms;
-    const int cidx = bx * kLanes + lane;
-    const bool active = cidx < n_fields * np;
-    const int f = active ? cidx / np : 0, q = active ? cidx - f * np : 0;
-    const int l = active ? col_l[q] : -1;
-    const int len = (n_r + T - 1) / T;
-    // a chunk is one wave (64 lanes): its shell range is wave-uniform
-    const int lo = __builtin_amdgcn_readfirstlane(min(n_r, ch * len));
-    const int hi = __builtin_amdgcn_readfirstlane(min(n_r, lo + len));
-    const size_t stride = (size_t)n_fields * n_r * np;
-    const size_t base = (size_t)f * n_r * np + q;
-    const int cl = l < 0 ? 0 : l;
-    const double *cf = coef + 4 * (size_t)cl;
-    const size_t cstep = 4 * (size_t)(L + 1);
-
-    // first sweep: reduce the partial sums, compose the chunk's maps; the
-    // outer sum over shells n > lo uses the coefficients (c, e) of shell n - 1
-    double A = 1.0, y = 0.0, P = 1.0, zl = 0.0;
-    if (l >= 0) {
-        double pc = 0.0, pe = 0.0;
-        for (int n0 = lo; n0 < hi; n0 += kGroup) {
-            const int cnt = min(kGroup, hi - n0);
-            double Bv[kGroup], c[kGroup][4];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-                Bv[u] = 0.0;
-                const double *cn = cf + min(n0 + u, hi - 1) * cstep;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) c[u][k] = cn[k];
-            }
-            for (int k = 0; k < splitk; ++k)
-#pragma unroll
-                for (int u = 0; u < kGroup; ++u)
-                    Bv[u] += Bpart[k * stride + base + (size_t)min(n0 + u, hi - 1) * np];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-                if (u >= cnt) break;
-                const int n = n0 + u;
-                Bred[base + (size_t)n * np] = Bv[u];
-                y = c[u][0] * y + c[u][1] * Bv[u];
-                A *= c[u][0];
-                if (n > lo) {
-                    zl += P * pe * Bv[u];
-                    P *= pc;
-                }
-                pc = c[u][2];
-                pe = c[u][3];
-            }
-        }
-        if (hi > lo && hi < n_r) {
-            double Bh = reduce_parts(Bpart, stride, splitk, base + (size_t)hi * np);
-            zl += P * pe * Bh;
-            P *= pc;
-        }
-    }
-    sA[ch * kLanes + lane] = A;
-    sY[ch * kLanes + lane] = y;
-    sC[ch * kLanes + lane] = P;
-    sZ[ch * kLanes + lane] = zl;
-    __syncthreads();
-    if (!active) return;  // after the barrier: every thread must reach it
-    double Yin = 0.0, Zin = 0.0;
-    for (int c = 0; c < ch; ++c) Yin = sA[c * kLanes + lane] * Yin + sY[c * kLanes + lane];
-    for (int c = T - 1; c > ch; --c) Zin = sZ[c * kLanes + lane] + sC[c * kLanes + lane] * Zin;
-    if (l < 0) {
-        for (int n = lo; n < hi; ++n) {
-            M[base + (size_t)n * np] = 0.0;
-            Bred[base + (size_t)n * np] = 0.0;
-            if (Ms) {
-                bf16 *o = Ms + split_offset_of(f, n, q, n_r, np, g.pp, g.ks2);
-                o[0] = o[kBlk] = o[2 * kBlk] = (bf16)0.0f;
-            }
-        }
-        return;
-    }
     // inner sums, upwards
-    y = Yin;
+    double y = Yin;
     for (int n0 = lo; n0 < hi; n0 += kGroup) {
         const int cnt = min(kGroup, hi - n0);
         double Bv[kGroup], a[kGroup], b[kGroup];
@@ -177,6 +151,62 @@ __device__ __forceinline__ void scan_block_core(const ScanArgs &g, int bx, int l
                 o[2 * kBlk] = (bf16)(float)r2;
             }
         }
+    }
+}
+
+// One block of 64 columns, its shells in g.chunks chunks of equal length:
+// lane (0..63) is the thread's column, and thread row `row` (0..W-1, a wave
+// of lanes each) takes chunks row, row + W, ...; the block's threads must
+// all call it (it holds one workgroup barrier).  Every chunk first composes
+// its affine maps, the chunk carries are chained through LDS, and a second
+// sweep writes M; the result depends on g.chunks only, not on W.  sA, sY,
+// sC, sZ: g.chunks x 64 doubles of LDS each.  Threads with lane >= the
+// column count, and chunks past the last shell, hold identity maps and
+// write nothing.
+__device__ __forceinline__ void scan_block_core(const ScanArgs &g, int bx, int lane, int row, int W, double *sA,
+                                                double *sY, double *sC, double *sZ) {
+    const int n_r = g.n_r, np = g.np, L = g.L, T = g.chunks;
+    const int cidx = bx * kLanes + lane;
+    const bool active = cidx < g.n_fields * np;
+    const int f = active ? cidx / np : 0, q = active ? cidx - f * np : 0;
+    const int l = active ? g.col_l[q] : -1;
+    const int len = (n_r + T - 1) / T;
+    const size_t base = (size_t)f * n_r * np + q;
+    const int cl = l < 0 ? 0 : l;
+    const double *cf = g.coef + 4 * (size_t)cl;
+    const size_t cstep = 4 * (size_t)(L + 1);
+
+    for (int ch = row; ch < T; ch += W) {
+        // a chunk is taken by one wave: its shell range is wave-uniform
+        const int lo = __builtin_amdgcn_readfirstlane(min(n_r, ch * len));
+        const int hi = __builtin_amdgcn_readfirstlane(min(n_r, lo + len));
+        ChunkMap m{1.0, 0.0, 1.0, 0.0};
+        if (l >= 0) m = compose_chunk(g, base, cf, cstep, lo, hi);
+        sA[ch * kLanes + lane] = m.A;
+        sY[ch * kLanes + lane] = m.y;
+        sC[ch * kLanes + lane] = m.P;
+        sZ[ch * kLanes + lane] = m.zl;
+    }
+    __syncthreads();
+    if (!active) return;  // after the barrier: every thread must reach it
+    for (int ch = row; ch < T; ch += W) {
+        const int lo = __builtin_amdgcn_readfirstlane(min(n_r, ch * len));
+        const int hi = __builtin_amdgcn_readfirstlane(min(n_r, lo + len));
+        double Yin = 0.0, Zin = 0.0;
+        for (int c = 0; c < ch; ++c) Yin = sA[c * kLanes + lane] * Yin + sY[c * kLanes + lane];
+        for (int c = T - 1; c > ch; --c) Zin = sZ[c * kLanes + lane] + sC[c * kLanes + lane] * Zin;
+        if (l < 0) {
+            for (int n = lo; n < hi; ++n) {
+                g.M[base + (size_t)n * np] = 0.0;
+                g.Bred[base + (size_t)n * np] = 0.0;
+                if (g.Ms) {
+                    bf16 *o = g.Ms + split_offset_of(f, n, q, n_r, np, g.pp, g.ks2);
+                    o[0] = o[kBlk] = o[2 * kBlk] = (bf16)0.0f;
+                }
+            }
+            continue;
+        }
+        finish_chunk(g, base, cf, cstep, f, q, lo, hi, Yin, Zin);
     }
 }
 

@@ -80,8 +80,9 @@ def test_plan_rejects_bad_grids_on_host():
     assert h.value is None
     assert L.mpg_moments(None, 1, None, 0, None, None) == mpg.MPG_EINVAL
     assert L.mpg_potential(None, 1, None, 0, None, 0) == mpg.MPG_EINVAL
-    assert L.mpg_set_tuning(None, 1, 16, 1) == mpg.MPG_EINVAL
-    assert L.mpg_autotune(None, 1, None, 0, None, None, None) == mpg.MPG_EINVAL
+    assert L.mpg_set_tuning(None, 1, 16, 1, 1) == mpg.MPG_EINVAL
+    assert L.mpg_autotune(None, 1, None, 0, None, None, None, None) == mpg.MPG_EINVAL
+    assert L.mpg_batch_choices(0, None, mpg.MPG_F32, None, None, None, None) == mpg.MPG_EINVAL
 
 
 class _FakeTensor:

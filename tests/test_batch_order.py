@@ -25,9 +25,9 @@ int main() {
     if (std::scanf("%d %d", &n, &workers) != 2) return 1;
     std::vector<mpg::FieldShape> s(n);
     for (auto &x : s)
-        if (std::scanf("%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d", &x.split_units, &x.row_tiles1, &x.pairs_e,
-                       &x.pairs_o, &x.six_e, &x.six_o, &x.kang, &x.splitk_min, &x.splitk_max, &x.scan_blocks,
-                       &x.n_r, &x.row_tiles2, &x.ang_pairs, &x.k2_three, &x.k2_six) != 15) return 1;
+        if (std::scanf("%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d", &x.split_units, &x.rows1, &x.units_e,
+                       &x.units_o, &x.six_e, &x.six_o, &x.kang, &x.splitk_min, &x.splitk_max, &x.scan_blocks,
+                       &x.n_r, &x.chunks, &x.rows2, &x.cols2, &x.k2_three, &x.k2_six) != 16) return 1;
     for (const auto &it : mpg::fused_items(s, workers))
         std::printf("%d %d %d %d %d %.6f %d\n", it.f, it.st, it.a, it.b, it.c,
                     mpg::fused_cost(s[it.f], mpg::fused_splitk(s[it.f]), it.st, it.a, it.b), mpg::fused_splitk(s[it.f]));
@@ -40,9 +40,10 @@ def cdiv(a, b):
     return -(-a // b)
 
 
-def shape(g, lmax, splitk_max=32, tier=15):
+def shape(g, lmax, splitk_max=32, tier=15, chunks=16, g1=1, g2=1):
     """The fused kernel's work units of one Yin-Yang field (column layout:
-    even-m and odd-m blocks padded to 32; tiles of 128, K slabs of 32)."""
+    even-m and odd-m blocks padded to 32; tiles of 128, K slabs of 32;
+    blocks of 128 x 256 (g1, g2 = 1) or 256 x 128 (2))."""
     kang = cdiv(g.n_theta * g.n_phi, 128) * 128
     ne = sum(1 if m == 0 else 2 for l in range(lmax + 1) for m in range(0, l + 1, 2))
     no = (lmax + 1) ** 2 - ne
@@ -50,15 +51,18 @@ def shape(g, lmax, splitk_max=32, tier=15):
     to = (min(lmax, tier) + 1) ** 2 - te
     ne_p, no_p = cdiv(ne, 32) * 32, cdiv(no, 32) * 32
     six_e, six_o = min(cdiv(te, 32) * 32, ne_p), min(cdiv(to, 32) * 32, no_p)
-    pe, po = cdiv(cdiv(ne_p, 128), 2), cdiv(cdiv(no_p, 128), 2)
+    nb = 2 if g1 == 1 else 1  # column tiles per moment block
+    pe, po = cdiv(cdiv(ne_p, 128), nb), cdiv(cdiv(no_p, 128), nb)
 
     def three(nsl, six_sl):
         n3 = max(nsl - six_sl, 0)
         return n3 if n3 == nsl else n3 & ~1
     e3, o3 = three(ne_p // 32, six_e // 32), three(no_p // 32, six_o // 32)
     rt = cdiv(g.n_r, 128)
-    return [rt * cdiv(kang // 32, 4), rt, pe, po, min(cdiv(six_e, 256), pe), min(cdiv(six_o, 256), po), kang,
-            1, splitk_max, cdiv(ne_p + no_p, 64), g.n_r, rt, cdiv(kang // 128, 2), e3 + o3,
+    at = kang // 128
+    return [rt * cdiv(kang // 32, 4), rt if g1 == 1 else cdiv(rt, 2), pe, po, min(cdiv(six_e, 128 * nb), pe),
+            min(cdiv(six_o, 128 * nb), po), kang, 1, splitk_max, cdiv(ne_p + no_p, 64), g.n_r, min(chunks, g.n_r),
+            rt if g2 == 1 else cdiv(rt, 2), cdiv(at, 2) if g2 == 1 else at, e3 + o3,
             (ne_p // 32 - e3) + (no_p // 32 - o3)]
 
 
@@ -99,14 +103,11 @@ def replay(queue, n_fields, rng, spread):
     return free.max(), wait, busy, done
 
 
-def test_batch_queue_order_of_the_64_field_workload():
-    fields = W.config4_fields()
-    shapes = [shape(g, g.lmax) for g, _ in fields]
-    queue = schedule(shapes)
-    # every item exactly once
+def check_queue(shapes, queue):
+    """Every item exactly once, and every item after its producers."""
     expect = set()
     for f, s in enumerate(shapes):
-        su, rt1, pe, po, _, _, _, _, _, sb, _, rt2, ap, _, _ = s
+        su, rt1, pe, po, _, _, _, _, _, sb, _, _, rt2, ap, _, _ = s
         sk = next(q[6] for q in queue if q[0] == f)
         expect |= {(f, 0, u) for u in range(0, su, 8)}
         expect |= {(f, 1, c, m, z) for z in range(sk) for m in range(rt1) for c in range(pe + po)}
@@ -125,6 +126,13 @@ def test_batch_queue_order_of_the_64_field_workload():
         if st > 0:
             assert seen.get((f, st - 1), 0) == count[(f, st - 1)]
         seen[(f, st)] = seen.get((f, st), 0) + 1
+
+
+def test_batch_queue_order_of_the_64_field_workload():
+    fields = W.config4_fields()
+    shapes = [shape(g, g.lmax) for g, _ in fields]
+    queue = schedule(shapes)
+    check_queue(shapes, queue)
     # replays: exact and perturbed costs
     total = sum(q[5] for q in queue)
     rng = np.random.Generator(np.random.PCG64(7))
@@ -137,3 +145,20 @@ def test_batch_queue_order_of_the_64_field_workload():
         assert span <= 1.12 * lower
         assert np.median(done) <= 0.6 * span
     assert total > 0
+
+
+def test_batch_queue_with_each_fields_own_shapes():
+    """Fields whose plans chose other block shapes and scan chunks: the
+    queue still holds every item once, producers first, and replays keep
+    the blocks busy."""
+    fields = W.config4_fields()
+    rng = np.random.Generator(np.random.PCG64(11))
+    shapes = [shape(g, g.lmax, chunks=int(rng.choice([4, 8, 12, 16])), g1=int(rng.integers(1, 3)),
+                    g2=int(rng.integers(1, 3))) for g, _ in fields]
+    queue = schedule(shapes)
+    check_queue(shapes, queue)
+    span, wait, busy, done = replay(queue, len(fields), rng, 0.3)
+    print(f"mixed shapes: makespan / lower bound {span / (busy / WORKERS):.3f}, "
+          f"field done p50 {np.median(done) / span:.2f} of the makespan")
+    assert span <= 1.12 * busy / WORKERS
+    assert np.median(done) <= 0.6 * span

@@ -122,12 +122,13 @@ def test_autotune_keeps_parity(precision):
     rho = W.random_rho(g, 31)
     t = torch.tensor(rho, device="cuda")
     plan = mpg.Plan(g, precision=precision)
-    sk, ch, rows = plan.autotune(t)
-    assert sk >= 1 and ch in (4, 8, 12, 16) and rows in (1, 2)
+    sk, ch, g1, rows = plan.autotune(t)
+    assert sk >= 1 and ch in (4, 8, 12, 16) and g1 in (1, 2) and rows in (1, 2)
     M = O.radial(g, g.lmax, O.moments(g, g.lmax, U, rho))
     phi = O.expand(g, g.lmax, Q, M)
     out = plan.potential(t).cpu().numpy()
-    print(f"{precision}: autotuned splitk {sk}, scan chunks {ch}, expansion rows {rows}, err {rel_err(out, phi):.3e}")
+    print(f"{precision}: autotuned splitk {sk}, scan chunks {ch}, moment rows {g1}, expansion rows {rows}, "
+          f"err {rel_err(out, phi):.3e}")
     assert rel_err(out, phi) < TOL[precision]
 
 
@@ -169,6 +170,42 @@ def test_batch_matches_single_solves_over_replays(precision):
             e = rel_err(o.cpu().numpy(), ref.cpu().numpy())
             print(f"{precision} rep {rep} field {k}: batch vs single {e:.3e}")
             assert e < TOL[precision]
+
+
+# per field of fields(): scan chunks, moment and expansion block shapes
+CHOICES = [(4, 2, 1), (8, 1, 2), (12, 2, 2), (16, 1, 1), (3, 2, 1), (1, 1, 2)]
+
+
+@pytest.mark.parametrize("precision", ["split_bf16_tiered", "split_bf16", "fp64"])
+def test_batch_takes_each_plans_choices(precision):
+    """Each field of a batch runs with its own plan's scan chunks and block
+    shapes (set here, different for every field); batch_choices reports
+    them with the batch's K split, and a single solve with exactly those
+    choices gives the batched field bit for bit, over two replays."""
+    import torch
+    import paper_1903_08475_amd as mpg
+    gs = fields()
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    plans = [mpg.Plan(g, precision=precision) for g in gs]
+    for p, (ch, g1, g2) in zip(plans, CHOICES):
+        p.set_tuning(chunks=ch, gemm1_rows=g1, gemm2_rows=g2)
+    choices = mpg.batch_choices(plans, dt)
+    for g, (sk, ch, g1, g2), (ch0, g10, g20) in zip(gs, choices, CHOICES):
+        assert sk >= 1 and ch == min(ch0, g.n_r)
+        assert (g1, g2) == ((1, 1) if precision == "fp64" else (g10, g20))
+    singles = [mpg.Plan(g, precision=precision) for g in gs]
+    for s, c in zip(singles, choices):
+        s.set_tuning(*c)
+    print(f"{precision}: batch choices {choices}")
+    for rep in range(2):
+        rhos = [torch.tensor(W.random_rho(g, 7300 + 10 * rep + k), dtype=dt, device="cuda")
+                for k, g in enumerate(gs)]
+        outs = [torch.full_like(r, float("nan")) for r in rhos]
+        mpg.potential_batch(plans, rhos, outs)
+        for k, (s, r, o) in enumerate(zip(singles, rhos, outs)):
+            ref = s.potential(r)
+            diff = (o - ref).abs().max().item()
+            assert torch.equal(o, ref), (rep, k, diff)
 
 
 def test_batch_wait_give_up_path_exits(monkeypatch):

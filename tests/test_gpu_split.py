@@ -151,11 +151,43 @@ def test_expansion_block_shapes_agree(key, method):
     assert rel_err(tall, wide) <= 1e-12
 
 
+@pytest.mark.parametrize("key,method", [("c1", "global"), ("ragged", "global"), ("polar", "global"),
+                                        ("medium", "global"), ("tiny", "global"), ("ragged", "per_patch")])
+@pytest.mark.parametrize("precision", ["split_bf16_tiered", "split_bf16"])
+def test_moment_block_shapes_agree(key, method, precision):
+    """The moment contraction's two block shapes (128 x 256 and 256 x 128)
+    give the same moments and potential bit for bit (every output takes the
+    same products in the same order), with one K split and with three (or
+    two, as far as the plan's K allows)."""
+    torch, mpg = torch_mods()
+    g, w, U, Q = oracle_tables(key)
+    t = torch.tensor(density(key, g).astype(np.float32), device="cuda")
+    plan = mpg.Plan(g, precision=precision, method=method)
+    done_split = False
+    for splitk in (1, 3, 2):
+        try:
+            plan.set_tuning(splitk=splitk, gemm1_rows=1)
+        except mpg.MpgError:
+            continue  # more splits than the plan's work space holds (small K)
+        if splitk == 2 and done_split:
+            break
+        done_split = splitk > 1
+        B1, M1 = (x.cpu().numpy() for x in plan.moments(t))
+        wide = plan.potential(t).cpu().numpy()
+        plan.set_tuning(gemm1_rows=2)
+        B2, M2 = (x.cpu().numpy() for x in plan.moments(t))
+        tall = plan.potential(t).cpu().numpy()
+        print(f"{key} {method} {precision} split {splitk}: moment blocks 256x128 vs 128x256, "
+              f"max abs diff B {np.abs(B2 - B1).max():.3e}, Phi {np.abs(tall - wide).max():.3e}")
+        assert np.array_equal(B1, B2) and np.array_equal(M1, M2)
+        assert np.array_equal(wide, tall)
+
+
 def test_set_tuning_rejects_out_of_range_values():
     torch, mpg = torch_mods()
     g, w, U, Q = oracle_tables("tiny")
     plan = mpg.Plan(g, precision="split_bf16")
-    for kw in ({"gemm2_rows": 3}, {"chunks": 17}, {"splitk": 10 ** 6}):
+    for kw in ({"gemm1_rows": 3}, {"gemm2_rows": 3}, {"chunks": 17}, {"splitk": 10 ** 6}):
         with pytest.raises(mpg.MpgError):
             plan.set_tuning(**kw)
 
