@@ -156,7 +156,7 @@ __device__ __forceinline__ void fold_split_load(const SplitArgs &g, size_t t, Ch
     }
 }
 
-template <bool FOLD>
+template <bool FOLD, bool NT = false>
 __device__ __forceinline__ void fold_split_store(const SplitArgs &g, const ChunkIn &in) {
     if (!in.live) return;
     const size_t plane = (size_t)g.row_tiles * g.ks1 * 3 * kBlk;
@@ -175,9 +175,9 @@ __device__ __forceinline__ void fold_split_store(const SplitArgs &g, const Chunk
             l[q] = pack2(l0, l1);
         }
         bf16 *o = g.A + par * plane + in.dst;
-        *(u32x4 *)(o) = (u32x4){h[0], h[1], h[2], h[3]};
-        *(u32x4 *)(o + kBlk) = (u32x4){m[0], m[1], m[2], m[3]};
-        *(u32x4 *)(o + 2 * kBlk) = (u32x4){l[0], l[1], l[2], l[3]};
+        store<NT>((u32x4 *)(o), (u32x4){h[0], h[1], h[2], h[3]});
+        store<NT>((u32x4 *)(o + kBlk), (u32x4){m[0], m[1], m[2], m[3]});
+        store<NT>((u32x4 *)(o + 2 * kBlk), (u32x4){l[0], l[1], l[2], l[3]});
     }
 }
 
@@ -190,14 +190,14 @@ __device__ __forceinline__ void fold_split_chunk(const SplitArgs &g, size_t t) {
 
 // the 2048 chunks of one split unit by a block of kThreads threads: every
 // thread's loads first, then its stores
-template <typename T, bool FOLD>
+template <typename T, bool FOLD, bool NT = false>
 __device__ __forceinline__ void fold_split_unit(const SplitArgs &g, size_t u, int tid) {
     constexpr int kPer = 2048 / kThreads;
     ChunkIn in[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) fold_split_load<T, FOLD>(g, u * 2048 + k * kThreads + tid, in[k]);
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) fold_split_store<FOLD>(g, in[k]);
+    for (int k = 0; k < kPer; ++k) fold_split_store<FOLD, NT>(g, in[k]);
 }
 
 template <typename T, bool FOLD>
@@ -500,9 +500,10 @@ __device__ __forceinline__ void run_tiered(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1,
 // NA = 1 is 128 x 256 (column pair tn: two 128-column tiles, pairs of the
 // even-m block first, then of the odd-m block; row tile tm), NA = 2 is
 // 256 x 128 (column tile tn, tiles of the even-m block first; row tile pair
-// tm); K split tz.  Writes Bpart[tz][row][col] in FP64.  Each output takes
-// the same products in the same order in both shapes.
-template <bool FOLD, int NA>
+// tm); K split tz.  Writes Bpart[tz][row][col] in FP64 (non-temporally
+// with NT).  Each output takes the same products in the same order in both
+// shapes.
+template <bool FOLD, int NA, bool NT = false>
 __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, int tz, SlabT<NA, 3 - NA> &S0,
                                            SlabT<NA, 3 - NA> &S1) {
     constexpr int NB = 3 - NA;
@@ -569,7 +570,7 @@ __device__ __forceinline__ void gemm1_tile(const SplitArgs &g, int tn, int tm, i
             for (int r = 0; r < 16; ++r) {
                 int rr = m0 + wm + 32 * a + d_row(lane, r);
                 int cc = c0 + wn + 32 * b + (lane & 31);
-                if (rr < rows && cc < cend) out[(size_t)rr * np + cc] = acc64[a][b][r];
+                if (rr < rows && cc < cend) store<NT>(out + (size_t)rr * np + cc, acc64[a][b][r]);
             }
 }
 
@@ -774,24 +775,24 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const SplitArgs *__res
         if (w.st == 0) {
             // input split: units of 2048 chunks
             for (int u = w.a; u < w.a + w.b; ++u) {
-                if (g.fold) fold_split_unit<T, true>(g, u, tid);
-                else fold_split_unit<T, false>(g, u, tid);
+                if (g.fold) fold_split_unit<T, true, true>(g, u, tid);
+                else fold_split_unit<T, false, true>(g, u, tid);
             }
         } else if (w.st == 1) {
             if (g.g1_rows == 2) {
-                if (g.fold) gemm1_tile<true, 2>(g, w.a, w.b, w.c, t0, t1);
-                else gemm1_tile<false, 2>(g, w.a, w.b, w.c, t0, t1);
+                if (g.fold) gemm1_tile<true, 2, true>(g, w.a, w.b, w.c, t0, t1);
+                else gemm1_tile<false, 2, true>(g, w.a, w.b, w.c, t0, t1);
             } else {
-                if (g.fold) gemm1_tile<true, 1>(g, w.a, w.b, w.c, s0, s1);
-                else gemm1_tile<false, 1>(g, w.a, w.b, w.c, s0, s1);
+                if (g.fold) gemm1_tile<true, 1, true>(g, w.a, w.b, w.c, s0, s1);
+                else gemm1_tile<false, 1, true>(g, w.a, w.b, w.c, s0, s1);
             }
         } else if (w.st == 2) {
             // the field's own chunk count, eight thread rows
             constexpr int kMC = scan_detail::kMaxChunks * scan_detail::kLanes;
             static_assert(4 * kMC * sizeof(double) <= sizeof(Slab1), "scan carries fit in one slab buffer");
             double *lds = reinterpret_cast<double *>(&s0);
-            scan_detail::scan_block_core(sargs[w.f], w.a, tid & 63, tid >> 6, kThreads / 64, lds, lds + kMC,
-                                         lds + 2 * kMC, lds + 3 * kMC);
+            scan_detail::scan_block_core<true>(sargs[w.f], w.a, tid & 63, tid >> 6, kThreads / 64, lds, lds + kMC,
+                                               lds + 2 * kMC, lds + 3 * kMC);
         } else {
             if (g.g2_rows == 2) {
                 if (g.fold) gemm2_tile<T, true, false, 2, true>(g, w.a, w.b, t0, t1);

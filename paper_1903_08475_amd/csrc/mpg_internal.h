@@ -16,6 +16,15 @@ namespace mpg {
 
 typedef __bf16 bf16;
 
+// A store, non-temporal with NT (streamed past the caches: the fused batch
+// kernel's stage outputs, so that its per-item L2 write-backs find few
+// dirty lines).
+template <bool NT, typename V>
+__device__ __forceinline__ void store(V *p, V v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Thread-local error text behind mpg_last_error().
 void set_error(const std::string &msg);
 

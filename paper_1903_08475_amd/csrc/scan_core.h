@@ -44,6 +44,7 @@ struct ChunkMap {
     double A, y, P, zl;
 };
 
+template <bool NT>
 __device__ __forceinline__ ChunkMap compose_chunk(const ScanArgs &g, size_t base, const double *cf, size_t cstep,
                                                   int lo, int hi) {
     const double *__restrict__ Bpart = g.Bpart;
@@ -69,7 +70,7 @@ __device__ __forceinline__ ChunkMap compose_chunk(const ScanArgs &g, size_t base
         for (int u = 0; u < kGroup; ++u) {
             if (u >= cnt) break;
             const int n = n0 + u;
-            Bred[base + (size_t)n * np] = Bv[u];
+            store<NT>(Bred + base + (size_t)n * np, Bv[u]);
             m.y = c[u][0] * m.y + c[u][1] * Bv[u];
             m.A *= c[u][0];
             if (n > lo) {
@@ -91,6 +92,7 @@ __device__ __forceinline__ ChunkMap compose_chunk(const ScanArgs &g, size_t base
 // Second sweep over chunk [lo, hi) of one column, entered with the inner
 // sum of the shells below the chunk (Yin) and the outer sum of the shells
 // above it (Zin): writes M (and its split copy).
+template <bool NT>
 __device__ __forceinline__ void finish_chunk(const ScanArgs &g, size_t base, const double *cf, size_t cstep, int f,
                                              int q, int lo, int hi, double Yin, double Zin) {
     const int n_r = g.n_r, np = g.np;
@@ -138,7 +140,7 @@ __device__ __forceinline__ void finish_chunk(const ScanArgs &g, size_t base, con
             const int n = n1 - 1 - u;
             z = cc[u] * z + e[u] * Bv[u];
             double m = Mv[u] + z;
-            M[base + (size_t)n * np] = m;
+            store<NT>(M + base + (size_t)n * np, m);
             if (Ms) {
                 // three-piece bf16 copy for the split contraction
                 bf16 h = (bf16)(float)m;
@@ -146,9 +148,9 @@ __device__ __forceinline__ void finish_chunk(const ScanArgs &g, size_t base, con
                 bf16 md = (bf16)(float)r;
                 double r2 = r - (double)(float)md;
                 bf16 *o = Ms + split_offset_of(f, n, q, n_r, np, g.pp, g.ks2);
-                o[0] = h;
-                o[kBlk] = md;
-                o[2 * kBlk] = (bf16)(float)r2;
+                store<NT>(o, h);
+                store<NT>(o + kBlk, md);
+                store<NT>(o + 2 * kBlk, (bf16)(float)r2);
             }
         }
     }
@@ -163,6 +165,7 @@ __device__ __forceinline__ void finish_chunk(const ScanArgs &g, size_t base, con
 // sC, sZ: g.chunks x 64 doubles of LDS each.  Threads with lane >= the
 // column count, and chunks past the last shell, hold identity maps and
 // write nothing.
+template <bool NT = false>
 __device__ __forceinline__ void scan_block_core(const ScanArgs &g, int bx, int lane, int row, int W, double *sA,
                                                 double *sY, double *sC, double *sZ) {
     const int n_r = g.n_r, np = g.np, L = g.L, T = g.chunks;
@@ -181,7 +184,7 @@ __device__ __forceinline__ void scan_block_core(const ScanArgs &g, int bx, int l
         const int lo = __builtin_amdgcn_readfirstlane(min(n_r, ch * len));
         const int hi = __builtin_amdgcn_readfirstlane(min(n_r, lo + len));
         ChunkMap m{1.0, 0.0, 1.0, 0.0};
-        if (l >= 0) m = compose_chunk(g, base, cf, cstep, lo, hi);
+        if (l >= 0) m = compose_chunk<NT>(g, base, cf, cstep, lo, hi);
         sA[ch * kLanes + lane] = m.A;
         sY[ch * kLanes + lane] = m.y;
         sC[ch * kLanes + lane] = m.P;
@@ -197,16 +200,18 @@ __device__ __forceinline__ void scan_block_core(const ScanArgs &g, int bx, int l
         for (int c = T - 1; c > ch; --c) Zin = sZ[c * kLanes + lane] + sC[c * kLanes + lane] * Zin;
         if (l < 0) {
             for (int n = lo; n < hi; ++n) {
-                g.M[base + (size_t)n * np] = 0.0;
-                g.Bred[base + (size_t)n * np] = 0.0;
+                store<NT>(g.M + base + (size_t)n * np, 0.0);
+                store<NT>(g.Bred + base + (size_t)n * np, 0.0);
                 if (g.Ms) {
                     bf16 *o = g.Ms + split_offset_of(f, n, q, n_r, np, g.pp, g.ks2);
-                    o[0] = o[kBlk] = o[2 * kBlk] = (bf16)0.0f;
+                    store<NT>(o, (bf16)0.0f);
+                    store<NT>(o + kBlk, (bf16)0.0f);
+                    store<NT>(o + 2 * kBlk, (bf16)0.0f);
                 }
             }
             continue;
         }
-        finish_chunk(g, base, cf, cstep, f, q, lo, hi, Yin, Zin);
+        finish_chunk<NT>(g, base, cf, cstep, f, q, lo, hi, Yin, Zin);
     }
 }
 
