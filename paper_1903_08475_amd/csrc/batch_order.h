@@ -140,29 +140,37 @@ struct FieldShape {
 // A queue entry of the fused kernel: field f, stage st (0 input split,
 // 1 moments, 2 radial scans, 3 expansion) and the stage's block
 // coordinates: split (first unit, units), moments (column unit, row unit,
-// K split), scans (column block), expansion (row unit, angular unit).
+// K split), scans (column block), expansion (row unit, first angular unit,
+// angular units).
 struct FusedItem {
     int f, st, a, b, c;
 };
 
 constexpr int kFusedStages = 4;
-constexpr int kSplitUnitsPerItem = 8;
+// Item sizes: input-split units per item, and expansion blocks (angular
+// units of one row unit) per item.  Larger items pay the end of an item
+// (waiting for its stores, counting it) less often.
+constexpr int kSplitUnitsPerItem = 16;
+constexpr int kExpansionUnitsPerItem = 2;
 
-// Estimated item costs (microseconds on one CU of the target): measured
-// rates of the stage kernels on the benchmark workload.  sk: K splits.  A
-// scan item's eight thread rows take the chunks in turns.
+// Estimated item costs (microseconds on one CU of the target), from the
+// fused kernel's own item times on the batching workload: per split unit,
+// per K slab of a moment block (plus its start and end), per shell chunk
+// step of a scan (eight thread rows take the chunks in turns), and per K
+// slab of an expansion block plus its fixed cost (ring starts of its four
+// runs, its output stores).  sk: K splits.
 inline double fused_cost(const FieldShape &s, int sk, int st, int a, int b) {
     switch (st) {
-        case 0: return 14.0 * b;
+        case 0: return 11.0 * b;
         case 1: {
             const bool six = a < s.units_e ? a < s.six_e : a - s.units_e < s.six_o;
-            return ksplit_chunk(s.kang, sk, 32) / 32 * (six ? 2.4 : 1.6);
+            return 4.0 + ksplit_chunk(s.kang, sk, 32) / 32 * (six ? 2.75 : 1.85);
         }
         case 2: {
             const int ch = std::max(s.chunks, 1);
-            return 1.2 * ((ch + 7) / 8) * ((s.n_r + ch - 1) / ch) * (1.0 + sk / 3.0);
+            return 1.75 * ((ch + 7) / 8) * ((s.n_r + ch - 1) / ch) * (1.0 + sk / 3.0);
         }
-        default: return 1.66 * s.k2_three + 2.5 * s.k2_six;
+        default: return 18.0 + 1.66 * s.k2_three + 2.5 * s.k2_six;
     }
 }
 
@@ -188,7 +196,8 @@ inline std::vector<FusedItem> fused_items(const std::vector<FieldShape> &shapes,
         const FieldShape &s = shapes[f];
         const int sk = fused_splitk(s);
         auto add = [&](int st, int a, int b, int c) {
-            ord.push_back({f, st, (int)all.size(), fused_cost(s, sk, st, a, b)});
+            // an expansion item costs its blocks' cost each
+            ord.push_back({f, st, (int)all.size(), fused_cost(s, sk, st, a, b) * (st == 3 ? c : 1)});
             all.push_back({f, st, a, b, c});
         };
         for (int u = 0; u < s.split_units; u += kSplitUnitsPerItem)
@@ -197,8 +206,8 @@ inline std::vector<FusedItem> fused_items(const std::vector<FieldShape> &shapes,
             for (int m = 0; m < s.rows1; ++m)
                 for (int c = 0; c < s.units_e + s.units_o; ++c) add(1, c, m, z);
         for (int x = 0; x < s.scan_blocks; ++x) add(2, x, 0, 0);
-        for (int a = 0; a < s.cols2; ++a)
-            for (int m = 0; m < s.rows2; ++m) add(3, m, a, 0);
+        for (int a = 0; a < s.cols2; a += kExpansionUnitsPerItem)
+            for (int m = 0; m < s.rows2; ++m) add(3, m, a, std::min(kExpansionUnitsPerItem, s.cols2 - a));
     }
     for (int i = 0; i < (int)ord.size(); ++i) ord[i].idx = i;
     const std::vector<int> q = order_items(ord, (int)shapes.size(), kFusedStages, workers);

@@ -645,37 +645,68 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
         }
     }
 
+    // Output: row rr = f*n_r + i of (field, shell), column kk = gp*n_angp +
+    // jk of (patch, cell), at phi + f*fld + gp*pstride + i*n_ang + jk.  The
+    // row offsets of the block go to LDS once (one division per row; -1:
+    // past the last row), the column offsets of this thread's two columns
+    // are computed once, and a block inside the output on both axes stores
+    // without checks.
     const size_t pstride = (size_t)n_r * n_ang, fld = (size_t)g.n_patches * pstride;
     const int n_angp = g.n_angp;
+    __syncthreads();  // every wave is past its last read of the slab buffers
+    long long *row_off = reinterpret_cast<long long *>(&S0);
+    for (int j = threadIdx.x; j < NA * TB; j += kThreads) {
+        const int rr = m0 + j;
+        long long v = -1;
+        if (rr < rows) {
+            const int f = rr / n_r, i = rr - f * n_r;
+            v = (long long)f * (long long)fld + (long long)i * n_ang;
+        }
+        row_off[j] = v;
+    }
+    long long col_off[2];
+    bool col_ok[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+        const int kk = n0 + wn + 32 * b + (lane & 31);
+        const int gp = kk / n_angp, jk = kk - gp * n_angp;
+        col_ok[b] = kk < n_cols && jk < n_ang;
+        col_off[b] = (long long)gp * (long long)pstride + jk;
+    }
+    // the block's columns lie in one patch's cells and its rows in the output
+    const int c_last = n0 + NB * TB - 1;
+    const bool full = m0 + NA * TB <= rows && c_last < n_cols && n0 / n_angp == c_last / n_angp &&
+                      c_last - (c_last / n_angp) * n_angp < n_ang;
+    __syncthreads();
+    auto put = [&](int a, int b, int r) {
+        const long long ro = row_off[wm + 32 * a + d_row(lane, r)];
+        T *o = phi + ro + col_off[b];
+        double e = (double)acc_e[a][b][r];
+        if (!FOLD && pp) e = acc64[a][b][r];
+        if (FOLD) {
+            const double od = (double)acc_o[a][b][r];
+            store<NT>(o, (T)(e + od));
+            store<NT>(o + pstride, (T)(e - od));
+        } else {
+            store<NT>(o, (T)e);
+        }
+    };
+    if (full) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                int rr = m0 + wm + 32 * a + d_row(lane, r);
-                int kk = n0 + wn + 32 * b + (lane & 31);
-                const int gp = kk / n_angp, jk = kk - gp * n_angp;
-                if (rr >= rows || kk >= n_cols || jk >= n_ang) continue;
-                int f = rr / n_r, i = rr - f * n_r;
-                T *o = phi + f * fld + gp * pstride + (size_t)i * n_ang + jk;
-                double e = (double)acc_e[a][b][r];
-                if (!FOLD && pp) e = acc64[a][b][r];
-                if (FOLD) {
-                    double od = (double)acc_o[a][b][r];
-                    if (NT) {
-                        __builtin_nontemporal_store((T)(e + od), o);
-                        __builtin_nontemporal_store((T)(e - od), o + pstride);
-                    } else {
-                        o[0] = (T)(e + od);
-                        o[pstride] = (T)(e - od);
-                    }
-                } else if (NT) {
-                    __builtin_nontemporal_store((T)e, o);
-                } else {
-                    o[0] = (T)e;
-                }
-            }
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) put(a, b, r);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if (col_ok[b] && row_off[wm + 32 * a + d_row(lane, r)] >= 0) put(a, b, r);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -794,12 +825,16 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const SplitArgs *__res
             scan_detail::scan_block_core<true>(sargs[w.f], w.a, tid & 63, tid >> 6, kThreads / 64, lds, lds + kMC,
                                                lds + 2 * kMC, lds + 3 * kMC);
         } else {
-            if (g.g2_rows == 2) {
-                if (g.fold) gemm2_tile<T, true, false, 2, true>(g, w.a, w.b, t0, t1);
-                else gemm2_tile<T, false, false, 2, true>(g, w.a, w.b, t0, t1);
-            } else {
-                if (g.fold) gemm2_tile<T, true, false, 1, true>(g, w.a, w.b, s0, s1);
-                else gemm2_tile<T, false, false, 1, true>(g, w.a, w.b, s0, s1);
+            // w.c angular units of row unit w.a, from unit w.b
+            for (int k = 0; k < w.c; ++k) {
+                if (k) __syncthreads();  // every wave is done with the slab buffers
+                if (g.g2_rows == 2) {
+                    if (g.fold) gemm2_tile<T, true, false, 2, true>(g, w.a, w.b + k, t0, t1);
+                    else gemm2_tile<T, false, false, 2, true>(g, w.a, w.b + k, t0, t1);
+                } else {
+                    if (g.fold) gemm2_tile<T, true, false, 1, true>(g, w.a, w.b + k, s0, s1);
+                    else gemm2_tile<T, false, false, 1, true>(g, w.a, w.b + k, s0, s1);
+                }
             }
         }
         // this block's stores are complete; then (but after the expansion,

@@ -30,7 +30,8 @@ int main() {
                        &x.n_r, &x.chunks, &x.rows2, &x.cols2, &x.k2_three, &x.k2_six) != 16) return 1;
     for (const auto &it : mpg::fused_items(s, workers))
         std::printf("%d %d %d %d %d %.6f %d\n", it.f, it.st, it.a, it.b, it.c,
-                    mpg::fused_cost(s[it.f], mpg::fused_splitk(s[it.f]), it.st, it.a, it.b), mpg::fused_splitk(s[it.f]));
+                    mpg::fused_cost(s[it.f], mpg::fused_splitk(s[it.f]), it.st, it.a, it.b) * (it.st == 3 ? it.c : 1),
+                    mpg::fused_splitk(s[it.f]));
     return 0;
 }
 """
@@ -109,11 +110,11 @@ def check_queue(shapes, queue):
     for f, s in enumerate(shapes):
         su, rt1, pe, po, _, _, _, _, _, sb, _, _, rt2, ap, _, _ = s
         sk = next(q[6] for q in queue if q[0] == f)
-        expect |= {(f, 0, u) for u in range(0, su, 8)}
+        expect |= {(f, 0, u) for u in range(0, su, 16)}
         expect |= {(f, 1, c, m, z) for z in range(sk) for m in range(rt1) for c in range(pe + po)}
         expect |= {(f, 2, x) for x in range(sb)}
-        expect |= {(f, 3, m, a) for a in range(ap) for m in range(rt2)}
-    got = [(f, 0, a) if st == 0 else (f, 1, a, b, c) if st == 1 else (f, 2, a) if st == 2 else (f, 3, a, b)
+        expect |= {(f, 3, m, a, min(2, ap - a)) for a in range(0, ap, 2) for m in range(rt2)}
+    got = [(f, 0, a) if st == 0 else (f, 1, a, b, c) if st == 1 else (f, 2, a) if st == 2 else (f, 3, a, b, c)
            for f, st, a, b, c, _, _ in queue]
     assert len(got) == len(set(got)) == len(expect) and set(got) == expect
     # producers first
