@@ -254,6 +254,9 @@ int mpg_batch_choices(int n, const mpg_plan_t *plans, int dtype, int *splitk, in
  *    (gemm2_rows = 1, the default) or 256 x 128 (gemm2_rows = 2).  Its
  *    timing writes a temporary output of one call's size, allocated and
  *    freed here; if it cannot be allocated, the shape is left as it is.
+ * Candidates are timed in rounds that launch each of them once (three
+ * rounds after a warm-up round), and each keeps its fastest time, so that
+ * clock changes during the tuning weigh on all alike.
  * Of two block shapes the one with less chip work is kept when it is at
  * least 1% less: the time of one of its blocks (its time over its waves of
  * one block per CU) times its blocks, over the CUs; that is its time when

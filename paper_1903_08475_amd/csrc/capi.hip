@@ -566,50 +566,55 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
         return hip_fail(e, "mpg_autotune");
     }
     const bool split = p->split();
-    int best_g1 = p->gemm1_rows;
-    auto time_stage = [&](int sk, int ch, bool scan, float *ms) -> hipError_t {
-        Plan q = *p;
-        q.splitk = sk;
-        q.scan_chunks = ch;
-        q.gemm1_rows = best_g1;
-        float best = 1e30f;
-        for (int rep = 0; rep < 4; ++rep) {  // first run is a warm-up
-            hipError_t err;
-            if ((err = hipEventRecord(a, q.stream)) != hipSuccess) return err;
-            if (scan) err = radial_scan(q, n_fields, split);
-            else err = split ? gemm1_bf16(q, n_fields, rho, rho_dtype) : gemm1_f64(q, n_fields, rho, rho_dtype);
-            if (err != hipSuccess) return err;
-            if ((err = hipEventRecord(b, q.stream)) != hipSuccess) return err;
-            if ((err = hipEventSynchronize(b)) != hipSuccess) return err;
-            float t = 0.0f;
-            if ((err = hipEventElapsedTime(&t, a, b)) != hipSuccess) return err;
-            if (rep > 0 && t < best) best = t;
-        }
-        *ms = best;
-        return hipSuccess;
+    // Every timing takes kRounds rounds, each launching every candidate once
+    // (round 0 is a warm-up), and keeps each candidate's fastest: clock
+    // changes during the tuning then weigh on all candidates alike.
+    constexpr int kRounds = 4;
+    auto time_once = [&](const Plan &q, int what, void *phi, float *ms) -> hipError_t {
+        hipError_t err;
+        if ((err = hipEventRecord(a, q.stream)) != hipSuccess) return err;
+        if (what == 0) err = split ? gemm1_bf16(q, n_fields, rho, rho_dtype) : gemm1_f64(q, n_fields, rho, rho_dtype);
+        else if (what == 1) err = radial_scan(q, n_fields, split);
+        else err = gemm2_bf16(q, n_fields_in, phi, rho_dtype);
+        if (err != hipSuccess) return err;
+        if ((err = hipEventRecord(b, q.stream)) != hipSuccess) return err;
+        if ((err = hipEventSynchronize(b)) != hipSuccess) return err;
+        return hipEventElapsedTime(ms, a, b);
+    };
+    // index of the fastest candidate: the first, unless another is at least
+    // 1% faster than the best so far
+    auto first_within_1pct = [](const std::vector<float> &t) {
+        size_t k = 0;
+        for (size_t i = 1; i < t.size(); ++i)
+            if (t[i] < 0.99f * t[k]) k = i;
+        return k;
     };
     if (split && (e = split_input_bf16(*p, n_fields, rho, rho_dtype)) != hipSuccess) {
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
         return hip_fail(e, "mpg_autotune");
     }
-    // K splits: the heuristic choice, then powers of two up to the work
-    // space; each timed as the moment contraction plus the scan that reduces
-    // its partial sums, and kept only when it beats the best so far by 1%
+    int best_g1 = p->gemm1_rows;
+    // K splits: the heuristic choice, then 1, 2, 3, 4 and powers of two up to
+    // the work space; each timed as the moment contraction plus the scan
+    // that reduces its partial sums
     std::vector<int> cands;
     p->splitk_sel = 0;
     int heur = choose_splitk(*p, n_fields);
     cands.push_back(heur);
     for (int s = 1; s <= p->splitk; s = s < 4 ? s + 1 : 2 * s)  // 1, 2, 3, 4, 8, 16, ...
         if (s != heur) cands.push_back(s);
-    int best_s = heur;
-    float best_t = 1e30f;
-    for (int s : cands) {
-        float t, ts;
-        if ((e = time_stage(s, p->scan_chunks, false, &t)) != hipSuccess) break;
-        if ((e = time_stage(s, p->scan_chunks, true, &ts)) != hipSuccess) break;
-        if (t + ts < 0.99f * best_t) { best_t = t + ts; best_s = s; }
-    }
+    std::vector<float> tk(cands.size(), 1e30f);
+    for (int round = 0; round < kRounds && e == hipSuccess; ++round)
+        for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
+            Plan q = *p;
+            q.splitk = cands[i];
+            float t1 = 0.0f, t2 = 0.0f;
+            if ((e = time_once(q, 0, nullptr, &t1)) == hipSuccess && (e = time_once(q, 1, nullptr, &t2)) == hipSuccess &&
+                round > 0)
+                tk[i] = std::min(tk[i], t1 + t2);
+        }
+    const int best_s = cands[first_within_1pct(tk)];
     // rows of the contractions (GEMM1's per-patch rows included)
     const int rt1 = (n_fields * p->n_r + kSplitTile - 1) / kSplitTile;
     const int rt2 = (n_fields_in * p->n_r + kSplitTile - 1) / kSplitTile;
@@ -620,27 +625,42 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
         // block shape of the moment contraction: 128 x 256 (the default) or
         // 256 x 128, each timed without a K split
         float tg[3] = {0.0f, 1e30f, 1e30f};
-        const int g1_was = best_g1;
-        for (int r = 1; r <= 2 && e == hipSuccess; ++r) {
-            best_g1 = r;
-            e = time_stage(1, p->scan_chunks, false, &tg[r]);
-        }
+        for (int round = 0; round < kRounds && e == hipSuccess; ++round)
+            for (int r = 1; r <= 2 && e == hipSuccess; ++r) {
+                Plan q = *p;
+                q.splitk = 1;
+                q.gemm1_rows = r;
+                float t = 0.0f;
+                if ((e = time_once(q, 0, nullptr, &t)) == hipSuccess && round > 0) tg[r] = std::min(tg[r], t);
+            }
         const int ct_e = p->tiles_e(), ct_o = p->tiles_o();
         const long b1 = (long)((ct_e + 1) / 2 + (ct_o + 1) / 2) * rt1, b2 = (long)(ct_e + ct_o) * ((rt1 + 1) / 2);
-        best_g1 = e == hipSuccess ? pick_shape(tg[1], tg[2], b1, b2, cus) : g1_was;
+        if (e == hipSuccess) best_g1 = pick_shape(tg[1], tg[2], b1, b2, cus);
     }
     int best_c = p->scan_chunks;
     if (e == hipSuccess) {
-        // scan schedule: shell chunks per column (the scan reads best_s partial sums)
-        float tc = 1e30f;
-        if ((e = time_stage(best_s, 16, false, &tc)) == hipSuccess) {  // leave matching partials in place
-            tc = 1e30f;
-            for (int ch : {4, 8, 12, 16}) {
-                if (ch > p->n_r && ch != 4) continue;
-                float t;
-                if ((e = time_stage(best_s, ch, true, &t)) != hipSuccess) break;
-                if (t < tc) { tc = t; best_c = ch; }
+        // scan schedule: shell chunks per column, on the partial sums of the
+        // chosen K split (the scan leaves them in place)
+        Plan q = *p;
+        q.splitk = best_s;
+        q.gemm1_rows = best_g1;
+        float t0 = 0.0f;
+        e = time_once(q, 0, nullptr, &t0);
+        std::vector<int> chs;
+        for (int ch : {4, 8, 12, 16})
+            if (ch <= p->n_r || ch == 4) chs.push_back(ch);
+        std::vector<float> tc(chs.size(), 1e30f);
+        for (int round = 0; round < kRounds && e == hipSuccess; ++round)
+            for (size_t i = 0; i < chs.size() && e == hipSuccess; ++i) {
+                q.scan_chunks = chs[i];
+                float t = 0.0f;
+                if ((e = time_once(q, 1, nullptr, &t)) == hipSuccess && round > 0) tc[i] = std::min(tc[i], t);
             }
+        if (e == hipSuccess) {
+            size_t k = 0;
+            for (size_t i = 1; i < tc.size(); ++i)
+                if (tc[i] < tc[k]) k = i;
+            best_c = chs[k];
         }
     }
     int best_r = p->gemm2_rows;
@@ -663,18 +683,12 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
             e = gemm1_bf16(q, n_fields, rho, rho_dtype);
             if (e == hipSuccess) e = radial_scan(q, n_fields, true);
             float tr[3] = {0.0f, 1e30f, 1e30f};
-            for (int r = 1; r <= 2 && e == hipSuccess; ++r) {
-                q.gemm2_rows = r;
-                for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {  // first run is a warm-up
+            for (int round = 0; round < kRounds && e == hipSuccess; ++round)
+                for (int r = 1; r <= 2 && e == hipSuccess; ++r) {
+                    q.gemm2_rows = r;
                     float t = 0.0f;
-                    if ((e = hipEventRecord(a, q.stream)) != hipSuccess) break;
-                    if ((e = gemm2_bf16(q, n_fields_in, phi, rho_dtype)) != hipSuccess) break;
-                    if ((e = hipEventRecord(b, q.stream)) != hipSuccess) break;
-                    if ((e = hipEventSynchronize(b)) != hipSuccess) break;
-                    if ((e = hipEventElapsedTime(&t, a, b)) != hipSuccess) break;
-                    if (rep > 0 && t < tr[r]) tr[r] = t;
+                    if ((e = time_once(q, 2, phi, &t)) == hipSuccess && round > 0) tr[r] = std::min(tr[r], t);
                 }
-            }
             if (e == hipSuccess) {
                 const int at = p->n2() / kSplitTile;
                 best_r = pick_shape(tr[1], tr[2], (long)rt2 * ((at + 1) / 2), (long)((rt2 + 1) / 2) * at, cus);
