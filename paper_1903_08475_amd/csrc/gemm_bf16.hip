@@ -802,7 +802,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const SplitArgs *__res
         }
         __syncthreads();
         if (!__builtin_amdgcn_readfirstlane(go)) break;
-        const SplitArgs g = args[w.f];
+        const SplitArgs &g = args[w.f];
         if (w.st == 0) {
             // input split: units of 2048 chunks
             for (int u = w.a; u < w.a + w.b; ++u) {
