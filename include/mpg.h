@@ -266,7 +266,8 @@ int mpg_batch_choices(int n, const mpg_plan_t *plans, int dtype, int *splitk, in
  * equal too.
  * Blocks until done; overwrites the plan's work space.  splitk, chunks,
  * gemm1_rows and gemm2_rows (each may be NULL) receive the choices (the
- * shapes: 1 for the FP64 form).
+ * shapes: 1 for the FP64 form).  On an error the plan keeps its previous
+ * choices.
  * Errors: as mpg_moments. */
 int mpg_autotune(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
                  int *splitk, int *chunks, int *gemm1_rows, int *gemm2_rows);

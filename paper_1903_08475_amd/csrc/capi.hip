@@ -599,8 +599,9 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
     // the work space; each timed as the moment contraction plus the scan
     // that reduces its partial sums
     std::vector<int> cands;
-    p->splitk_sel = 0;
-    int heur = choose_splitk(*p, n_fields);
+    Plan unset = *p;  // the heuristic choice (the plan keeps its choices until the tuning succeeds)
+    unset.splitk_sel = 0;
+    const int heur = choose_splitk(unset, n_fields);
     cands.push_back(heur);
     for (int s = 1; s <= p->splitk; s = s < 4 ? s + 1 : 2 * s)  // 1, 2, 3, 4, 8, 16, ...
         if (s != heur) cands.push_back(s);
