@@ -38,9 +38,13 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the sources the split contractions are compiled from (their
+    file and every header of the library's sources)."""
     h = hashlib.sha256()
-    for name in ("gemm_bf16.hip", "gemm_f64.hip", "scan.hip"):
-        with open(os.path.join(ROOT, "paper_1903_08475_amd", "csrc", name), "rb") as f:
+    csrc = os.path.join(ROOT, "paper_1903_08475_amd", "csrc")
+    names = ["gemm_bf16.hip"] + sorted(n for n in os.listdir(csrc) if n.endswith(".h"))
+    for name in names:
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -194,7 +198,8 @@ def fp64_workload(dev, steps):
            "value": g.n_cells * g.n_lm / (ms * 1e-3), "unit": "terms/s", "stage_ms": per,
            "moments_fp64_mfma_frac": flops / (per["moments"] * 1e-3) / PEAK_FP64,
            "expansion_fp64_mfma_frac": flops / (per["expansion"] * 1e-3) / PEAK_FP64,
-           "autotuned": {"gemm1_splitk": tuned[0], "scan_chunks": tuned[1]}}
+           "autotuned": {"gemm1_splitk": tuned[0], "scan_chunks": tuned[1],
+                         "moment_tiles": "128x128" if tuned[2] == 1 else "64x64"}}
     log(f"[bench] FP64 workload: {ms:.3f} ms per solve")
     return out
 

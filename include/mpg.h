@@ -231,7 +231,7 @@ int mpg_batch_field_times(int n, const mpg_plan_t *plans, int dtype, double *ms)
  * of these plans in this dtype: per field f, splitk[f] the K split of its
  * moment contraction, chunks[f] its scan's shell chunks per column, and
  * gemm1_rows[f], gemm2_rows[f] the block shapes of its contractions (as in
- * mpg_set_tuning; 1 for the FP64 form).  Each pointer is a host array of n
+ * mpg_set_tuning; gemm2_rows 1 for the FP64 form).  Each pointer is a host array of n
  * entries, or NULL.  A single solve with these choices set
  * (mpg_set_tuning) gives the batched field's results bit for bit.
  * Errors: MPG_EINVAL (bad arguments). */
@@ -239,16 +239,17 @@ int mpg_batch_choices(int n, const mpg_plan_t *plans, int dtype, int *splitk, in
                       int *gemm1_rows, int *gemm2_rows);
 
 /* Autotune the plan for n_fields fields on the given device input, and keep
- * the choices for later calls (batched calls take all but the K split):
- *  - the K split of the moment contraction, timed together with the radial
- *    scan that reduces its partial sums, for every split the work space
- *    allows (the default choice first, then 1, 2, 3, 4 and the powers of
- *    two beyond; another split is kept only when it is at least 1% faster;
- *    the work space holds at least four splits when their partial sums fit
- *    in 2 GiB, and up to 32 while they fit in 512 MiB);
- *  - split forms: the moment contraction's block shape, 128 rows x 256
- *    columns (gemm1_rows = 1, the default) or 256 x 128 (gemm1_rows = 2),
- *    each timed without a K split;
+ * the choices for later calls:
+ *  - the moment contraction's block shape and K split, every pair timed
+ *    together with the radial scan that reduces the partial sums.  Shapes:
+ *    split forms 128 rows x 256 columns (gemm1_rows = 1, the default) or
+ *    256 x 128 (gemm1_rows = 2); FP64 tiles of 128 x 128 (1, the default)
+ *    or 64 x 64 (2).  K splits: the default choice first, then 1, 2, 3, 4
+ *    and the powers of two beyond, as far as the work space allows (at
+ *    least four splits when their partial sums fit in 2 GiB, up to 32
+ *    while they fit in 512 MiB).  Each shape keeps its default split
+ *    unless another is at least 1% faster, and single-plan calls keep the
+ *    default shape unless the other is at least 1% faster;
  *  - the radial scan's shell chunks per column: 4, 8, 12 or 16;
  *  - split forms: the expansion's block shape, 128 rows x 256 angular cells
  *    (gemm2_rows = 1, the default) or 256 x 128 (gemm2_rows = 2).  Its
@@ -256,18 +257,21 @@ int mpg_batch_choices(int n, const mpg_plan_t *plans, int dtype, int *splitk, in
  *    freed here; if it cannot be allocated, the shape is left as it is.
  * Candidates are timed in rounds that launch each of them once (three
  * rounds after a warm-up round), and each keeps its fastest time, so that
- * clock changes during the tuning weigh on all alike.
- * Of two block shapes the one with less chip work is kept when it is at
- * least 1% less: the time of one of its blocks (its time over its waves of
- * one block per CU) times its blocks, over the CUs; that is its time when
- * its blocks fill whole waves, and otherwise leaves out the CUs a partial
- * wave leaves idle, which the other fields of a batch use.  Otherwise the
- * one with fewer blocks (padding included), and the default when those are
- * equal too.
+ * clock changes during the tuning weigh on all alike.  The expansion's two
+ * shapes, and for batched calls (mpg_potential_batch) the moment
+ * contraction's two shapes without a K split, are ranked by chip work: the
+ * time of one block (a shape's time over its waves of one block per CU)
+ * times its blocks, over the CUs; that is its time when its blocks fill
+ * whole waves, and otherwise leaves out the CUs a partial wave leaves
+ * idle, which the other fields of a batch use.  The one with at least 1%
+ * less chip work is kept; otherwise the one with fewer blocks (padding
+ * included), and the default when those are equal too.  Batched calls take
+ * the scan chunks, the expansion shape and that moment shape, and split K
+ * their own way.
  * Blocks until done; overwrites the plan's work space.  splitk, chunks,
- * gemm1_rows and gemm2_rows (each may be NULL) receive the choices (the
- * shapes: 1 for the FP64 form).  On an error the plan keeps its previous
- * choices.
+ * gemm1_rows and gemm2_rows (each may be NULL) receive the single-plan
+ * choices (gemm2_rows: 1 for the FP64 form).  On an error the plan keeps
+ * its previous choices.
  * Errors: as mpg_moments. */
 int mpg_autotune(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
                  int *splitk, int *chunks, int *gemm1_rows, int *gemm2_rows);
@@ -275,9 +279,12 @@ int mpg_autotune(mpg_plan_t plan, int n_fields, const void *rho, int rho_dtype,
 /* Set the choices mpg_autotune makes, e.g. ones it made earlier for the same
  * grid and lmax: the K split of the moment contraction (at most the plan's
  * work space allows), the radial scan's shell chunks per column (1..16),
- * and the split contractions' block shapes (gemm1_rows, gemm2_rows 1: 128
- * rows x 256 columns or angular cells, 2: 256 x 128).  A value <= 0 leaves
- * that choice as it is.  Results do not depend on the shapes; they may
+ * and the contractions' block shapes: gemm1_rows and gemm2_rows 1 (the
+ * default) or 2, in the split forms 128 rows x 256 columns or angular
+ * cells (1) or 256 x 128 (2), for the FP64 moment contraction tiles of
+ * 128 x 128 (1) or 64 x 64 (2) (the FP64 expansion has one shape).  A
+ * value <= 0 leaves that choice as it is; a moment shape set here holds
+ * for batched calls too.  Results do not depend on the shapes; they may
  * differ in rounding with the K split and the chunks.
  * Errors: MPG_EINVAL (NULL plan, a value out of range; nothing is changed). */
 int mpg_set_tuning(mpg_plan_t plan, int splitk, int chunks, int gemm1_rows, int gemm2_rows);

@@ -90,7 +90,9 @@ int cu_count() {
 
 // Work of one field (one field of the plan) in the fused kernel's units,
 // with the plan's block shapes and scan chunks.
-FieldShape field_shape(const Plan &p) {
+FieldShape field_shape(const Plan &plan) {
+    Plan p = plan;
+    p.gemm1_rows = p.gemm1_rows_batch;  // a batch's moment shape
     FieldShape sh;
     const int rt = (p.n_r + kSplitTile - 1) / kSplitTile;
     const int nb1 = p.gemm1_rows == 2 ? 1 : 2;  // column tiles per moment block
@@ -150,6 +152,7 @@ hipError_t build_fused(Batch &b, const std::vector<const Plan *> &plans, int dty
     for (int f = 0; f < n; ++f) {
         Plan q = *plans[f];
         q.splitk = fused_splitk(shapes[f]);
+        q.gemm1_rows = q.gemm1_rows_batch;
         b.sa.push_back(split_args(q, 1, nullptr, nullptr, dtype));
         b.sc.push_back(scan_args(q, 1, true));
     }
@@ -194,7 +197,7 @@ hipError_t build_staged(Batch &b, const std::vector<const Plan *> &plans, int dt
     b.dtype = dtype;
     b.precision = plans[0]->precision;
     const int n = (int)plans.size();
-    const int T1 = kF64Tile1, T2 = kF64Tile2;  // tile sides of the moment contraction (rows) and the expansion
+    const int T2 = kF64Tile2;  // tile side of the expansion
 
     // work items per stage, longest first
     std::vector<int> order(n);
@@ -204,6 +207,7 @@ hipError_t build_staged(Batch &b, const std::vector<const Plan *> &plans, int dt
     for (int f = 0; f < n; ++f) {
         q[f] = *plans[f];
         q[f].splitk = choose_splitk(q[f], 1);
+        q[f].gemm1_rows = q[f].gemm1_rows_batch;
         b.fa.push_back(f64_args(q[f], 1, nullptr, nullptr, dtype));
         b.sc.push_back(scan_args(q[f], 1, false));
     }
@@ -211,7 +215,8 @@ hipError_t build_staged(Batch &b, const std::vector<const Plan *> &plans, int dt
     std::vector<std::pair<long long, BatchItem>> c1;
     for (int f = 0; f < n; ++f) {
         const Plan &p = q[f];
-        const int rt = (p.n_r + T1 - 1) / T1, ct = b.fa[f].tiles_e + b.fa[f].tiles_o;
+        const int t1 = b.fa[f].t1;  // the plan's moment tile side
+        const int rt = (p.n_r + t1 - 1) / t1, ct = b.fa[f].tiles_e + b.fa[f].tiles_o;
         for (int z = 0; z < p.splitk; ++z)
             for (int m = 0; m < rt; ++m)
                 for (int c = 0; c < ct; ++c) c1.push_back({(long long)b.fa[f].kchunk, BatchItem{f, c, m, z}});
@@ -328,13 +333,13 @@ hipError_t potential_batch(const std::vector<const Plan *> &plans, const void *c
 BatchChoice batch_choice(const Plan &p) {
     BatchChoice c;
     c.chunks = scan_args(p, 1, true).chunks;
+    c.gemm1_rows = p.gemm1_rows_batch;
     if (p.split()) {
         c.splitk = fused_splitk(field_shape(p));
-        c.gemm1_rows = p.gemm1_rows;
         c.gemm2_rows = p.gemm2_rows;
     } else {
         c.splitk = choose_splitk(p, 1);
-        c.gemm1_rows = c.gemm2_rows = 1;
+        c.gemm2_rows = 1;
     }
     return c;
 }

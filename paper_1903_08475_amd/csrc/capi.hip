@@ -594,10 +594,11 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
         (void)hipEventDestroy(b);
         return hip_fail(e, "mpg_autotune");
     }
-    int best_g1 = p->gemm1_rows;
-    // K splits: the heuristic choice, then 1, 2, 3, 4 and powers of two up to
-    // the work space; each timed as the moment contraction plus the scan
-    // that reduces its partial sums
+    // Moment contraction: every (block shape, K split) pair, timed as the
+    // contraction plus the scan that reduces its partial sums.  Shapes:
+    // split forms 128 x 256 (1, the default) or 256 x 128 (2); FP64 tiles
+    // of 128 x 128 (1) or 64 x 64 (2).  K splits: the heuristic choice,
+    // then 1, 2, 3, 4 and powers of two up to the work space.
     std::vector<int> cands;
     Plan unset = *p;  // the heuristic choice (the plan keeps its choices until the tuning succeeds)
     unset.splitk_sel = 0;
@@ -605,38 +606,55 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
     cands.push_back(heur);
     for (int s = 1; s <= p->splitk; s = s < 4 ? s + 1 : 2 * s)  // 1, 2, 3, 4, 8, 16, ...
         if (s != heur) cands.push_back(s);
-    std::vector<float> tk(cands.size(), 1e30f);
+    size_t one = 0;  // index of K split 1
+    while (cands[one] != 1) ++one;
+    std::vector<float> tk[3], tg1[3];  // [shape][split]: contraction + scan; contraction alone
+    for (int r = 1; r <= 2; ++r) {
+        tk[r].assign(cands.size(), 1e30f);
+        tg1[r].assign(cands.size(), 1e30f);
+    }
     for (int round = 0; round < kRounds && e == hipSuccess; ++round)
-        for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
-            Plan q = *p;
-            q.splitk = cands[i];
-            float t1 = 0.0f, t2 = 0.0f;
-            if ((e = time_once(q, 0, nullptr, &t1)) == hipSuccess && (e = time_once(q, 1, nullptr, &t2)) == hipSuccess &&
-                round > 0)
-                tk[i] = std::min(tk[i], t1 + t2);
-        }
-    const int best_s = cands[first_within_1pct(tk)];
+        for (int r = 1; r <= 2 && e == hipSuccess; ++r)
+            for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
+                Plan q = *p;
+                q.splitk = cands[i];
+                q.gemm1_rows = r;
+                float t1 = 0.0f, t2 = 0.0f;
+                if ((e = time_once(q, 0, nullptr, &t1)) == hipSuccess &&
+                    (e = time_once(q, 1, nullptr, &t2)) == hipSuccess && round > 0) {
+                    tk[r][i] = std::min(tk[r][i], t1 + t2);
+                    tg1[r][i] = std::min(tg1[r][i], t1);
+                }
+            }
+    // per shape its K split (the heuristic unless another is 1% faster);
+    // single solves take the default shape unless the other is 1% faster
+    const size_t k1 = first_within_1pct(tk[1]), k2 = first_within_1pct(tk[2]);
+    const int best_g1 = tk[2][k2] < 0.99f * tk[1][k1] ? 2 : 1;
+    const int best_s = cands[best_g1 == 2 ? k2 : k1];
     // rows of the contractions (GEMM1's per-patch rows included)
     const int rt1 = (n_fields * p->n_r + kSplitTile - 1) / kSplitTile;
     const int rt2 = (n_fields_in * p->n_r + kSplitTile - 1) / kSplitTile;
     int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
     if (cus < 1) cus = 1;
-    if (e == hipSuccess && split) {
-        // block shape of the moment contraction: 128 x 256 (the default) or
-        // 256 x 128, each timed without a K split
-        float tg[3] = {0.0f, 1e30f, 1e30f};
-        for (int round = 0; round < kRounds && e == hipSuccess; ++round)
-            for (int r = 1; r <= 2 && e == hipSuccess; ++r) {
-                Plan q = *p;
-                q.splitk = 1;
-                q.gemm1_rows = r;
-                float t = 0.0f;
-                if ((e = time_once(q, 0, nullptr, &t)) == hipSuccess && round > 0) tg[r] = std::min(tg[r], t);
-            }
-        const int ct_e = p->tiles_e(), ct_o = p->tiles_o();
-        const long b1 = (long)((ct_e + 1) / 2 + (ct_o + 1) / 2) * rt1, b2 = (long)(ct_e + ct_o) * ((rt1 + 1) / 2);
-        if (e == hipSuccess) best_g1 = pick_shape(tg[1], tg[2], b1, b2, cus);
+    // batched solves: the shape with less chip work without a K split (a
+    // batch splits K its own way, and other fields fill the chip)
+    int batch_g1 = best_g1;
+    if (e == hipSuccess) {
+        long b1, b2;
+        if (split) {
+            const int ct_e = p->tiles_e(), ct_o = p->tiles_o();
+            b1 = (long)((ct_e + 1) / 2 + (ct_o + 1) / 2) * rt1;
+            b2 = (long)(ct_e + ct_o) * ((rt1 + 1) / 2);
+        } else {
+            auto tiles = [&](int t) {
+                const int ct = p->fold ? (p->ne_p + t - 1) / t + (p->no_p + t - 1) / t : (p->np + t - 1) / t;
+                return (long)ct * ((n_fields * p->n_r + t - 1) / t);
+            };
+            b1 = tiles(kF64Tile1);
+            b2 = tiles(64);
+        }
+        batch_g1 = pick_shape(tg1[1][one], tg1[2][one], b1, b2, cus);
     }
     int best_c = p->scan_chunks;
     if (e == hipSuccess) {
@@ -705,11 +723,12 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
     p->splitk_sel = best_s;
     p->scan_chunks = best_c;
     p->gemm1_rows = best_g1;
+    p->gemm1_rows_batch = batch_g1;
     p->gemm2_rows = best_r;
     ++p->tune_epoch;
     if (splitk) *splitk = best_s;
     if (chunks) *chunks = best_c;
-    if (gemm1_rows) *gemm1_rows = split ? best_g1 : 1;
+    if (gemm1_rows) *gemm1_rows = best_g1;
     if (gemm2_rows) *gemm2_rows = split ? best_r : 1;
     return MPG_OK;
 }
@@ -729,7 +748,7 @@ int mpg_set_tuning(mpg_plan_t p, int splitk, int chunks, int gemm1_rows, int gem
     if (gemm2_rows > 2) return fail(MPG_EINVAL, "mpg_set_tuning: gemm2_rows must be 1 or 2");
     if (splitk > 0) p->splitk_sel = splitk;
     if (chunks > 0) p->scan_chunks = chunks;
-    if (gemm1_rows > 0) p->gemm1_rows = gemm1_rows;
+    if (gemm1_rows > 0) p->gemm1_rows = p->gemm1_rows_batch = gemm1_rows;
     if (gemm2_rows > 0) p->gemm2_rows = gemm2_rows;
     ++p->tune_epoch;
     return MPG_OK;

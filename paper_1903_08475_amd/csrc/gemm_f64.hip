@@ -137,11 +137,12 @@ __device__ inline void mma_slab(const double (*As)[ldp<TS>()], const double (*Bs
 }
 
 
-// One output tile of GEMM1 (column tile tn: even-m tiles first, then
-// odd-m tiles; row tile tm; K split tz).
-template <typename T, bool FOLD>
-__device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int tz, Smem<T1> &sm) {
-    constexpr int BM = T1, BN = T1, WT = T1 / 32;
+// One output tile of GEMM1, TS x TS (128, or 64 for small problems; each
+// output takes the same products in the same order in both): column tile
+// tn (even-m tiles first, then odd-m tiles), row tile tm, K split tz.
+template <typename T, bool FOLD, int TS>
+__device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int tz, Smem<TS> &sm) {
+    constexpr int BM = TS, BN = TS, WT = TS / 32;
     const T *rho = (const T *)g.rho;
     const int rows = g.rows, n_r = g.n_r, n_ang = g.n_ang, n_angp = g.n_angp, np = g.np, ne_p = g.ne_p;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -153,7 +154,7 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
     const int kbeg = tz * g.kchunk;
     const int kend = min(g.kang, kbeg + g.kchunk);
 
-    const int lr = slab_row<T1>(t), lk = slab_k<T1>(t);
+    const int lr = slab_row<TS>(t), lk = slab_k<TS>(t);
     const int row = m0 + lr;
     const bool row_ok = row < rows;
     const int f = row_ok ? row / n_r : 0, i = row_ok ? row - f * n_r : 0;
@@ -168,9 +169,9 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
 #pragma unroll
         for (int b = 0; b < WT; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    Slab<T1> sa, sb;
+    Slab<TS> sa, sb;
     if (kbeg < kend) {
-        load_rho<T, FOLD, T1>(sa, r0, r1, kbeg + lk, n_ang, n_angp, pstride, row_ok, odd);
+        load_rho<T, FOLD, TS>(sa, r0, r1, kbeg + lk, n_ang, n_angp, pstride, row_ok, odd);
         load_rowk(sb, urow, kbeg + lk, true);
     }
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
@@ -179,10 +180,10 @@ __device__ __forceinline__ void gemm1_tile(const F64Args &g, int tn, int tm, int
         store_slab(sm.Bs, sb, lr, lk);
         __syncthreads();
         if (k0 + BK < kend) {
-            load_rho<T, FOLD, T1>(sa, r0, r1, k0 + BK + lk, n_ang, n_angp, pstride, row_ok, odd);
+            load_rho<T, FOLD, TS>(sa, r0, r1, k0 + BK + lk, n_ang, n_angp, pstride, row_ok, odd);
             load_rowk(sb, urow, k0 + BK + lk, true);
         }
-        mma_slab<T1>(sm.As, sm.Bs, wm, wn, lane, acc);
+        mma_slab<TS>(sm.As, sm.Bs, wm, wn, lane, acc);
     }
     __syncthreads();
     double *out = g.Bpart + (size_t)tz * rows * np;
@@ -279,10 +280,10 @@ __device__ __forceinline__ void gemm2_tile(const F64Args &g, int tm, int tn, Sme
 }
 
 // grid: x = column tile (E tiles then O tiles), y = row tile, z = K split
-template <typename T, bool FOLD>
+template <typename T, bool FOLD, int TS>
 __global__ __launch_bounds__(256) void k_gemm1(F64Args g) {
-    __shared__ Smem<T1> sm;
-    gemm1_tile<T, FOLD>(g, blockIdx.x, blockIdx.y, blockIdx.z, sm);
+    __shared__ Smem<TS> sm;
+    gemm1_tile<T, FOLD, TS>(g, blockIdx.x, blockIdx.y, blockIdx.z, sm);
 }
 
 // grid: x = row tile, y = angular tile
@@ -307,13 +308,20 @@ __global__ __launch_bounds__(256) void k_batch_gemm1(const F64Args *__restrict__
                                                      const BatchItem *__restrict__ items, int n_items, int *head) {
     __shared__ Smem<T1> sm;
     __shared__ int slot;
+    static_assert(sizeof(Smem<64>) <= sizeof(Smem<T1>), "both tile sides fit the shared buffers");
+    Smem<64> &sm64 = *reinterpret_cast<Smem<64> *>(&sm);
     for (;;) {
         const int it = next_item(head, &slot);
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const F64Args g = args[w.f];
-        if (g.fold) gemm1_tile<T, true>(g, w.a, w.b, w.c, sm);
-        else gemm1_tile<T, false>(g, w.a, w.b, w.c, sm);
+        if (g.t1 == 64) {
+            if (g.fold) gemm1_tile<T, true, 64>(g, w.a, w.b, w.c, sm64);
+            else gemm1_tile<T, false, 64>(g, w.a, w.b, w.c, sm64);
+        } else {
+            if (g.fold) gemm1_tile<T, true, T1>(g, w.a, w.b, w.c, sm);
+            else gemm1_tile<T, false, T1>(g, w.a, w.b, w.c, sm);
+        }
     }
 }
 
@@ -355,8 +363,11 @@ F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io
     g.kang = pp2 ? p.n2() : p.kang();
     g.nq = pp2 ? p.nq() : 1;
     g.kq = pp2 ? p.kq() : p.np;
-    g.tiles_e = p.fold ? (p.ne_p + T1 - 1) / T1 : (p.np + T1 - 1) / T1;
-    g.tiles_o = p.fold ? (p.no_p + T1 - 1) / T1 : 0;
+    // GEMM1 tiles: 128 x 128, or 64 x 64 (the plan's second moment shape)
+    const int t1 = p.gemm1_rows == 2 ? 64 : T1;
+    g.t1 = t1;
+    g.tiles_e = p.fold ? (p.ne_p + t1 - 1) / t1 : (p.np + t1 - 1) / t1;
+    g.tiles_o = p.fold ? (p.no_p + t1 - 1) / t1 : 0;
     g.kchunk = ksplit_chunk(p.kang(), p.splitk, BK);
     g.splitk = p.splitk;
     g.Ut = p.Ut;
@@ -366,16 +377,22 @@ F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io
     return g;
 }
 
+template <int TS>
+static void launch_gemm1(const Plan &p, const F64Args &g, dim3 grid, int rho_dtype) {
+    if (rho_dtype == MPG_F64) {
+        if (p.fold) hipLaunchKernelGGL((k_gemm1<double, true, TS>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm1<double, false, TS>), grid, dim3(256), 0, p.stream, g);
+    } else {
+        if (p.fold) hipLaunchKernelGGL((k_gemm1<float, true, TS>), grid, dim3(256), 0, p.stream, g);
+        else hipLaunchKernelGGL((k_gemm1<float, false, TS>), grid, dim3(256), 0, p.stream, g);
+    }
+}
+
 hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
     F64Args g = f64_args(p, n_fields, rho, nullptr, rho_dtype);
-    dim3 grid(g.tiles_e + g.tiles_o, (g.rows + T1 - 1) / T1, p.splitk);
-    if (rho_dtype == MPG_F64) {
-        if (p.fold) hipLaunchKernelGGL((k_gemm1<double, true>), grid, dim3(256), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm1<double, false>), grid, dim3(256), 0, p.stream, g);
-    } else {
-        if (p.fold) hipLaunchKernelGGL((k_gemm1<float, true>), grid, dim3(256), 0, p.stream, g);
-        else hipLaunchKernelGGL((k_gemm1<float, false>), grid, dim3(256), 0, p.stream, g);
-    }
+    dim3 grid(g.tiles_e + g.tiles_o, (g.rows + g.t1 - 1) / g.t1, p.splitk);
+    if (g.t1 == 64) launch_gemm1<64>(p, g, grid, rho_dtype);
+    else launch_gemm1<T1>(p, g, grid, rho_dtype);
     return hipGetLastError();
 }
 

@@ -123,7 +123,9 @@ struct Plan {
     int splitk = 1;            // K splits of the moment contraction (work space holds this many)
     int splitk_sel = 0;        // chosen by mpg_autotune (0: heuristic)
     int scan_chunks = 16;      // shell chunks per column in the radial scan
-    int gemm1_rows = 1;        // split moment blocks: 1 = 128 rows x 256 columns, 2 = 256 x 128
+    int gemm1_rows = 1;        // moment blocks, split forms: 1 = 128 rows x 256 columns, 2 = 256 x 128;
+                               // FP64: 1 = 128 x 128 tiles, 2 = 64 x 64
+    int gemm1_rows_batch = 1;  // the same choice for batched solves
     int gemm2_rows = 1;        // split expansion blocks: 1 = 128 rows x 256 cells, 2 = 256 x 128
     int tune_epoch = 0;        // raised whenever the choices above change (batched solves rebuild)
     double *Bpart = nullptr;   // [splitk][rows][np]
@@ -219,7 +221,8 @@ struct F64Args {
     int rows, n_r, n_ang, n_angp, np, ne_p, fold;
     int n_patches, kang;  // patches of a field; npat*n_angp (GEMM1 K, GEMM2 N)
     int nq, kq;           // GEMM2 K: moment sets (per-patch method) and their total length
-    int tiles_e, tiles_o;
+    int tiles_e, tiles_o;  // GEMM1 column tiles of the even / odd block
+    int t1;                // GEMM1 tile side (128, or 64: the plan's second moment shape)
     int kchunk, splitk;
     const double *Ut, *Qt, *M;
     double *Bpart;

@@ -192,7 +192,7 @@ def test_batch_takes_each_plans_choices(precision):
     choices = mpg.batch_choices(plans, dt)
     for g, (sk, ch, g1, g2), (ch0, g10, g20) in zip(gs, choices, CHOICES):
         assert sk >= 1 and ch == min(ch0, g.n_r)
-        assert (g1, g2) == ((1, 1) if precision == "fp64" else (g10, g20))
+        assert (g1, g2) == ((g10, 1) if precision == "fp64" else (g10, g20))
     singles = [mpg.Plan(g, precision=precision) for g in gs]
     for s, c in zip(singles, choices):
         s.set_tuning(*c)

@@ -68,6 +68,33 @@ def test_potential_matches_oracle(key):
     assert rel_err(out, phi) < TOL64, rel_err(out, phi)
 
 
+@pytest.mark.parametrize("key", ["c1", "ragged", "polar", "tiny", "medium"])
+@pytest.mark.parametrize("method", ["global", "per_patch"])
+def test_moment_tile_sides_agree(key, method):
+    """The FP64 moment contraction's two tile sides (128 and 64) give the
+    same moments and potential bit for bit (every output takes the same
+    products in the same order), with one K split and with two; the 64-tile
+    result also matches the oracle."""
+    torch, mpg = torch_mods()
+    g, w, U, Q = oracle_tables(key)
+    if method == "per_patch" and g.n_patches < 2:
+        pytest.skip("one patch: the per-patch method is the global one")
+    t = torch.tensor(_rho(g, 13), device="cuda")
+    plan = mpg.Plan(g, method=method)
+    for splitk in (1, 2):
+        plan.set_tuning(splitk=splitk, gemm1_rows=1)
+        B1, M1 = (x.cpu().numpy() for x in plan.moments(t))
+        p1 = plan.potential(t).cpu().numpy()
+        plan.set_tuning(gemm1_rows=2)
+        B2, M2 = (x.cpu().numpy() for x in plan.moments(t))
+        p2 = plan.potential(t).cpu().numpy()
+        print(f"{key} {method} split {splitk}: 64 vs 128 tiles, max abs diff B {np.abs(B2 - B1).max():.3e}")
+        assert np.array_equal(B1, B2) and np.array_equal(M1, M2) and np.array_equal(p1, p2)
+    if method == "global":
+        B = O.moments(g, g.lmax, U, t.cpu().numpy())
+        assert rel_err(B2[0], B) < TOL64
+
+
 def test_batched_fields_match_single_solves():
     torch, mpg = torch_mods()
     g, w, U, Q = oracle_tables("ragged")
