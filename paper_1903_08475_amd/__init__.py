@@ -221,7 +221,9 @@ class Plan:
         shape on this input and keep the fastest; returns (splitk, chunks,
         gemm1_rows, gemm2_rows).  With cache (a JSON file path), choices
         stored there for the same key are applied without timing, and new
-        ones are added to it."""
+        ones are added to it; choices applied from the cache set the moment
+        shape of batched solves too (a tuning run keeps one of its own for
+        them, see mpg_autotune)."""
         import json
         n = self._fields(rho)
         key = self.tuning_key(n, str(rho.dtype).replace("torch.", ""))

@@ -583,7 +583,7 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
     };
     // index of the fastest candidate: the first, unless another is at least
     // 1% faster than the best so far
-    auto first_within_1pct = [](const std::vector<float> &t) {
+    auto keep_within_1pct = [](const std::vector<float> &t) {
         size_t k = 0;
         for (size_t i = 1; i < t.size(); ++i)
             if (t[i] < 0.99f * t[k]) k = i;
@@ -628,7 +628,7 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
             }
     // per shape its K split (the heuristic unless another is 1% faster);
     // single solves take the default shape unless the other is 1% faster
-    const size_t k1 = first_within_1pct(tk[1]), k2 = first_within_1pct(tk[2]);
+    const size_t k1 = keep_within_1pct(tk[1]), k2 = keep_within_1pct(tk[2]);
     const int best_g1 = tk[2][k2] < 0.99f * tk[1][k1] ? 2 : 1;
     const int best_s = cands[best_g1 == 2 ? k2 : k1];
     // rows of the contractions (GEMM1's per-patch rows included)
