@@ -357,6 +357,14 @@ __device__ __forceinline__ void pipe_barrier() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// The first slab of the run that follows (block k0 of the tiles, six: with
+// its l pieces), when a run issues its copy into S0 from its last steps so
+// that the next run starts with it in flight (on: there is such a run).
+struct NextRun {
+    int k0;
+    bool six, on;
+};
+
 // Multiplies nsl consecutive K slabs (slab t is block k0 + t*dk of the
 // tiles), all with six products (SIX) or all with three, into acc through
 // the two buffers S0, S1.  Step t: read the second step's fragments of slab
@@ -368,13 +376,17 @@ __device__ __forceinline__ void pipe_barrier() {
 // buffers must be free on entry (no wave reading them, no copy in flight),
 // and are free again on return.  Without MMA only the copies, reads and
 // barriers (waves whose tile lies past the end of the block).
+// With pre, slab 0's copy into S0 was issued by the run before.  With
+// nx.on (nsl even, so that step nsl - 2 reads S0), step nsl - 2 copies the
+// next run's first slab into S0 once every wave is past its barrier.
 template <int NA, int NB, bool SIX, bool FLUSH, bool MMA = true>
 __device__ __forceinline__ void run_pipe(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
                                          int dk, int nsl, int wm, int wn, int lane, v16f (&acc)[2][2],
-                                         double (&acc64)[2][2][16]) {
+                                         double (&acc64)[2][2][16], bool pre = false,
+                                         NextRun nx = NextRun{0, false, false}) {
     if (nsl <= 0) return;
     Frags<SIX> F0, F1;
-    load_slab(S0, L, k0, SIX);
+    if (!pre) load_slab(S0, L, k0, SIX);
     pipe_barrier();
     if (nsl > 1) load_slab(S1, L, k0 + dk, SIX);
     read_frags<NA, NB, SIX>(F0, S0, 0, wm, wn, lane);
@@ -385,6 +397,7 @@ __device__ __forceinline__ void run_pipe(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, c
         if (MMA) mma_frags<SIX>(F0, acc);                                    \
         pipe_barrier();                                                      \
         if (t + 2 < nsl) load_slab(CUR, L, k0 + (t + 2) * dk, SIX);          \
+        else if (nx.on && t + 2 == nsl) load_slab(CUR, L, nx.k0, nx.six);    \
         if (t + 1 < nsl) read_frags<NA, NB, SIX>(F0, NXT, 0, wm, wn, lane);  \
         if (MMA) mma_frags<SIX>(F1, acc);                                    \
     }
@@ -414,10 +427,11 @@ __device__ __forceinline__ void run_pipe(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, c
 template <int NA, int NB, bool FLUSH, bool SIX, bool MMA>
 __device__ __forceinline__ void ring_phase(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
                                            int dk, int t0, int t1, int last, int n3_load, int wm, int wn, int lane,
-                                           v16f (&acc)[2][2], double (&acc64)[2][2][16]) {
+                                           v16f (&acc)[2][2], double (&acc64)[2][2][16], NextRun nx, int fin) {
 #define RING_STEP(CUR, NXT, O)                                       \
     ring_barrier<0>();                                               \
-    load_slab(NXT, L, k0 + min(t + O + 1, last) * dk, t + O + 1 >= n3_load); \
+    if (nx.on && t + O + 1 == fin) load_slab(NXT, L, nx.k0, nx.six); \
+    else load_slab(NXT, L, k0 + min(t + O + 1, last) * dk, t + O + 1 >= n3_load); \
     if (MMA && t + O < t1) mma_slab<NA, NB, SIX>(CUR, wm, wn, lane, acc);
     for (int s = t0; s < t1; s += kFlushSlabs) {
 #pragma unroll
@@ -456,42 +470,62 @@ __device__ __forceinline__ void ring_phase(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1,
 // Every wave must call it with the same k0, dk, nsl and n3_load; n3 may
 // differ between waves when it is 0 or nsl (each wave then runs nsl steps,
 // rounded up to even, and as many barriers).  On return all copies have
-// landed, and the buffers may be refilled after a barrier.
+// landed, and the buffers may be refilled after a barrier.  With pre, slab
+// 0's copy into S0 was issued by the run before; with nx.on, the last step
+// (whose copy goes to S0, the step count being even) copies the next run's
+// first slab instead of this run's last again, and it is left in flight.
 template <int NA, int NB, bool FLUSH, bool MMA = true>
 __device__ __forceinline__ void run_ring(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
                                          int dk, int nsl, int n3, int n3_load, int wm, int wn, int lane,
-                                         v16f (&acc)[2][2], double (&acc64)[2][2][16]) {
+                                         v16f (&acc)[2][2], double (&acc64)[2][2][16], bool pre = false,
+                                         NextRun nx = NextRun{0, false, false}) {
     if (nsl <= 0) return;
-    const int last = nsl - 1;
-    load_slab(S0, L, k0, n3_load == 0);
-    ring_phase<NA, NB, FLUSH, false, MMA>(S0, S1, L, k0, dk, 0, n3, last, n3_load, wm, wn, lane, acc, acc64);
-    ring_phase<NA, NB, FLUSH, true, MMA>(S0, S1, L, k0, dk, n3, nsl, last, n3_load, wm, wn, lane, acc, acc64);
-    // the trailing copy lands before anyone may reuse or free the LDS
-    asm volatile("" ::: "memory");
-    MPG_WAIT_VM(0);
-    asm volatile("" ::: "memory");
+    const int last = nsl - 1, fin = (nsl + 1) & ~1;  // steps run: nsl rounded up to even
+    if (!pre) load_slab(S0, L, k0, n3_load == 0);
+    ring_phase<NA, NB, FLUSH, false, MMA>(S0, S1, L, k0, dk, 0, n3, last, n3_load, wm, wn, lane, acc, acc64, nx, fin);
+    ring_phase<NA, NB, FLUSH, true, MMA>(S0, S1, L, k0, dk, n3, nsl, last, n3_load, wm, wn, lane, acc, acc64, nx, fin);
+    if (!nx.on) {
+        // the trailing copy lands before anyone may reuse or free the LDS
+        asm volatile("" ::: "memory");
+        MPG_WAIT_VM(0);
+        asm volatile("" ::: "memory");
+    }
 }
 
 // nsl slabs whose first n3 take three products (pipelined ring) and the
 // rest six (the plain ring, which keeps one step's fragments in registers:
 // the expansion's two accumulator sets leave no room for two six-product
-// fragment sets); the second run starts with its own first copy
-// (PIPE false: the plain ring for both, for kernels with no registers to
-// spare for a second fragment set)
+// fragment sets).  The runs are chained: each issues the next one's first
+// copy from its last steps (pre: this call's first copy was issued so;
+// nx: the run after this call, whose first copy the call issues if it can,
+// and then returns true).  PIPE false: the plain ring for both, unchained,
+// for kernels with no registers to spare for a second fragment set.
 template <int NA, int NB, bool PIPE = true>
-__device__ __forceinline__ void run_tiered(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
+__device__ __forceinline__ bool run_tiered(SlabT<NA, NB> &S0, SlabT<NA, NB> &S1, const LoaderT<NA, NB> &L, int k0,
                                            int dk, int nsl, int n3, int wm, int wn, int lane, v16f (&acc)[2][2],
-                                           double (&acc64)[2][2][16]) {
+                                           double (&acc64)[2][2][16], bool pre = false,
+                                           NextRun nx = NextRun{0, false, false}) {
     if constexpr (!PIPE) {
         run_ring<NA, NB, false>(S0, S1, L, k0, dk, nsl, n3, n3, wm, wn, lane, acc, acc64);
         __syncthreads();
-        return;
+        return false;
     }
-    run_pipe<NA, NB, false, false>(S0, S1, L, k0, dk, n3, wm, wn, lane, acc, acc64);
-    if (nsl > n3) {
-        run_ring<NA, NB, false>(S0, S1, L, k0 + n3 * dk, dk, nsl - n3, 0, 0, wm, wn, lane, acc, acc64);
-        __syncthreads();  // no wave still reads the buffers the next run refills
+    if (nsl <= 0) return false;
+    if (n3 > 0 && nsl > n3) {
+        // n3 is even here: the three-product run's step n3 - 2 reads S0
+        run_pipe<NA, NB, false, false>(S0, S1, L, k0, dk, n3, wm, wn, lane, acc, acc64, pre,
+                                       NextRun{k0 + n3 * dk, true, true});
+        run_ring<NA, NB, false>(S0, S1, L, k0 + n3 * dk, dk, nsl - n3, 0, 0, wm, wn, lane, acc, acc64, true, nx);
+    } else if (n3 > 0) {
+        const bool chain = nx.on && (n3 & 1) == 0;
+        run_pipe<NA, NB, false, false>(S0, S1, L, k0, dk, n3, wm, wn, lane, acc, acc64, pre,
+                                       NextRun{nx.k0, nx.six, chain});
+        return chain;
+    } else {
+        run_ring<NA, NB, false>(S0, S1, L, k0, dk, nsl, 0, 0, wm, wn, lane, acc, acc64, pre, nx);
     }
+    if (!nx.on) __syncthreads();  // no wave still reads the buffers the next run refills
+    return nx.on;
 }
 
 
@@ -618,8 +652,11 @@ __device__ __forceinline__ void gemm2_tile(const SplitArgs &g, int tm, int tn, S
     if (FOLD) {
         const int ne = ne_p / TK, no = (np - ne_p) / TK;
         const int e3 = three_slabs(ne, g.six_e / TK), o3 = three_slabs(no, g.six_o / TK);
-        run_tiered<NA, NB>(S0, S1, L, ne - 1, -1, ne, e3, wm, wn, lane, acc_e, acc64);
-        run_tiered<NA, NB>(S0, S1, L, ne + no - 1, -1, no, o3, wm, wn, lane, acc_o, acc64);
+        // the even block's last run issues the odd block's first copy (its
+        // top slab, with l pieces when the odd block starts with six products)
+        const bool pre = run_tiered<NA, NB>(S0, S1, L, ne - 1, -1, ne, e3, wm, wn, lane, acc_e, acc64, false,
+                                            NextRun{ne + no - 1, o3 == 0, no > 0});
+        run_tiered<NA, NB>(S0, S1, L, ne + no - 1, -1, no, o3, wm, wn, lane, acc_o, acc64, pre);
     } else if (!pp) {
         const int ns = g.ks2, n3 = three_slabs(ns, g.six_e / TK);
         run_tiered<NA, NB>(S0, S1, L, ns - 1, -1, ns, n3, wm, wn, lane, acc_e, acc64);
