@@ -140,6 +140,9 @@ int mpg_plan(const mpg_grid *grid, int lmax, int precision, int max_fields,
                                    every patch in its own frame, radial sums
                                    per patch, and an expansion that adds the
                                    potentials of every patch's source        */
+#define MPG_METHOD_SEPARABLE 2  /* the paper's method with each angular
+                                   contraction factored over the patch's
+                                   (theta, phi) cell grid: see below         */
 
 /* As mpg_plan, with the method chosen.  The per-patch method gives the same
  * potential up to rounding (the degree-l part of each patch's expansion
@@ -148,8 +151,32 @@ int mpg_plan(const mpg_grid *grid, int lmax, int precision, int max_fields,
  * It uses one table U for every patch (so per-patch weights must agree),
  * mpg_moments returns B and M per patch ([n_fields][n_patches][n_r][n_lm],
  * each in the patch's own frame), and mpg_potential_batch rejects it
- * (MPG_EUNSUPPORTED).  Errors: as mpg_plan, MPG_EINVAL for an unknown
- * method. */
+ * (MPG_EUNSUPPORTED).
+ *
+ * MPG_METHOD_SEPARABLE computes the same B, M and Phi as the paper's
+ * method (Eqs. B_CS, M_C, gravpotmult) in fewer operations.  In each
+ * patch's own frame the weights of its cell (j, k) factor over theta and phi
+ * (the single-grid sums of Eqs. a_ci^lm/a_si^lm): the local moments are a
+ * phi transform of every (field, patch, shell, theta row) row followed by a
+ * theta contraction per order u, A^(lu) = sum_j s_lu T_j^(lu) sum_k w_jk
+ * rho_jk {C_k^u, S_k^u}; the N factors of Eqs. U_C/U_S rotate them into
+ * the common frame degree by degree and the patches' sums are added.  The
+ * expansion rotates M into each patch's frame and runs the two transforms
+ * backwards (the same factors write the harmonics of Eqs. Q_C/Q_S in local
+ * ones).  On a phi grid symmetric about 0 with an even cell count the phi
+ * transforms fold cell k with its mirror cell n_phi - 1 - k.  Operations
+ * per shell and patch: about n_theta n_phi (2 lmax + 1) (halved by the
+ * mirror fold) against n_theta n_phi (lmax + 1)^2 for the dense
+ * contraction (under the parity fold, per patch pair).  FP64 only
+ * (precision MPG_FP64, else MPG_EUNSUPPORTED); any patches and Euler
+ * angles.  mpg_potential_static, mpg_potential_batch, mpg_autotune and
+ * mpg_set_tuning reject such plans (MPG_EUNSUPPORTED); mpg_moments,
+ * mpg_potential, mpg_tables and stage timing take them (stages: phi
+ * transform of the moments, theta contraction and rotation, radial scans,
+ * expansion).  The plan holds two extra FP64 work arrays:
+ * (lmax + 1 and lmax, each rounded up to 16) x max_fields x n_patches x
+ * n_r x n_theta values, and max_fields x n_patches x n_r x (lmax + 1)^2.
+ * Errors: as mpg_plan, MPG_EINVAL for an unknown method. */
 int mpg_plan_method(const mpg_grid *grid, int lmax, int precision, int max_fields,
                     int method, void *stream, mpg_plan_t *out);
 

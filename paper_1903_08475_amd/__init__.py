@@ -22,8 +22,11 @@ MPG_F64, MPG_F32 = 0, 1
 
 PRECISIONS = {"fp64": MPG_FP64, "split_bf16": MPG_SPLIT_BF16, "split_bf16_tiered": MPG_SPLIT_BF16_TIERED}
 # "global": the paper's method; "per_patch": the comparison method (moments
-# of every patch in its own frame, potentials of the patches added)
-METHODS = {"global": 0, "per_patch": 1}
+# of every patch in its own frame, potentials of the patches added);
+# "separable": the paper's method with each angular contraction factored
+# into a phi transform and a theta contraction per order m (FP64; one patch
+# or the Yin/Yang fold, patch 0 in the common frame)
+METHODS = {"global": 0, "per_patch": 1, "separable": 2}
 # where Phi is evaluated in each cell (on the shell's outer radius)
 EVAL_POINTS = {"vertex": 0, "centre": 1}
 

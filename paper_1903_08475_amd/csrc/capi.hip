@@ -76,8 +76,10 @@ void free_plan(mpg_plan_s *p) {
     if (!p) return;
     forget_plan(p);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    void *bufs[] = {p->col_src, p->col_l, p->Ut,   p->Qt, p->coef, p->w,
-                    p->Us,      p->Qs,    p->Bpart, p->Bred, p->M,  p->Ms, p->A_split};
+    void *bufs[] = {p->col_src, p->col_l,  p->Ut,     p->Qt,     p->coef,   p->w,      p->Us,
+                    p->Qs,      p->Bpart,  p->Bred,   p->M,      p->Ms,     p->A_split, p->sep_m,
+                    p->sep_col, p->sep_f1, p->sep_t1, p->sep_t2, p->sep_f2, p->sep_F,
+                    p->sep_A,   p->sep_kxy, p->sep_xoff, p->sep_perm, p->sep_x1, p->sep_x2};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     clear_events(p);
@@ -142,7 +144,7 @@ int mpg_plan(const mpg_grid *g, int lmax, int precision, int max_fields, void *s
 int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, int method, void *stream,
                     mpg_plan_t *out) {
     if (!out) return fail(MPG_EINVAL, "mpg_plan: out is NULL");
-    if (method != MPG_METHOD_GLOBAL && method != MPG_METHOD_PER_PATCH)
+    if (method != MPG_METHOD_GLOBAL && method != MPG_METHOD_PER_PATCH && method != MPG_METHOD_SEPARABLE)
         return fail(MPG_EINVAL, "mpg_plan: unknown method");
     *out = nullptr;
     if (!g) return fail(MPG_EINVAL, "mpg_plan: grid is NULL");
@@ -244,6 +246,13 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
             }
     }
     p->npat = (p->fold || p->per_patch) ? 1 : g->n_patches;
+    if (method == MPG_METHOD_SEPARABLE) {
+        if (precision != MPG_FP64) {
+            free_plan(p);
+            return fail(MPG_EUNSUPPORTED, "mpg_plan: the separable method runs in FP64 only");
+        }
+        p->sep = true;
+    }
 
     // column layout
     if (p->fold) {
@@ -263,6 +272,18 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
     p->np = p->ne_p + p->no_p;
     p->np_alloc = p->np + kColSlack;
     p->n_angp = roundup(p->n_ang, kAngPad);
+    if (p->sep) {
+        // phi columns: C of every order, S of every order above 0; the
+        // mirror fold on a phi grid symmetric about 0 with an even cell count
+        const int n = p->n_phi;
+        p->sep_ce = roundup(lmax + 1, 16);
+        p->sep_co = roundup(lmax, 16);
+        p->sep_lp = roundup(lmax + 1, 16);
+        p->sep_mir = n % 2 == 0 && fabs(p->phi0 + 0.5 * n * p->dphi) <= 1e-12;
+        p->sep_kh = p->sep_mir ? n / 2 : n;
+        p->sep_khp = roundup(p->sep_kh, 16);
+        p->sep_kx = !p->sep_mir ? n : p->eval_centre ? n / 2 : n / 2 + 1;
+    }
 
     // work space
     {
@@ -318,6 +339,17 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
             return rc;
         }
     }
+    if (p->sep) {
+        // zeroed once so that no padding row ever holds a non-finite value
+        const size_t n = (size_t)p->sep_nc() * p->sep_rows(), na = (size_t)p->sep_vrows() * p->n_lm;
+        if ((e = hipMalloc(&p->sep_F, sizeof(double) * n)) != hipSuccess ||
+            (e = hipMemset(p->sep_F, 0, sizeof(double) * n)) != hipSuccess ||
+            (e = hipMalloc(&p->sep_A, sizeof(double) * na)) != hipSuccess) {
+            int rc = hip_fail(e, "mpg_plan: separable work space");
+            free_plan(p);
+            return rc;
+        }
+    }
     if ((e = build_tables(*p, g->euler, g->r_edges, g->overlap_w, g->w_per_patch)) != hipSuccess) {
         int rc = hip_fail(e, "mpg_plan: table build");
         free_plan(p);
@@ -346,7 +378,7 @@ static int run_moments(const Plan *p, int n_fields_in, const void *rho, int rho_
                        bool all_six = false) {
     hipError_t e;
     const int n_fields = p->vfields(n_fields_in);
-    int sk = choose_splitk(*p, n_fields);
+    int sk = p->sep ? 1 : choose_splitk(*p, n_fields);
     Plan q = *p;
     q.splitk = sk;
     if (all_six) {
@@ -354,6 +386,22 @@ static int run_moments(const Plan *p, int n_fields_in, const void *rho, int rho_
         q.six_o = q.no_p;
     }
     hipEvent_t ev;
+    if (p->sep) {
+        // phi transform; theta contraction and rotation (into partial plane 0); radial scans
+        ev = stage_begin(q, 0);
+        e = sep_phi_moments(q, n_fields, rho, rho_dtype);
+        stage_end(q, ev);
+        if (e != hipSuccess) return hip_fail(e, "phi transform");
+        ev = stage_begin(q, 1);
+        e = sep_theta_moments(q, n_fields);
+        stage_end(q, ev);
+        if (e != hipSuccess) return hip_fail(e, "theta contraction and rotation");
+        ev = stage_begin(q, 2);
+        e = radial_scan(q, n_fields, false);
+        stage_end(q, ev);
+        if (e != hipSuccess) return hip_fail(e, "radial scan");
+        return MPG_OK;
+    }
     if (p->split()) {
         ev = stage_begin(q, 0);
         e = split_input_bf16(q, n_fields, rho, rho_dtype);
@@ -390,7 +438,12 @@ static int solve(const Plan *p, int n_fields, const void *rho, int rho_dtype, vo
     bool split = p->split();
     if ((rc = run_moments(p, n_fields, rho, rho_dtype, split))) return rc;
     hipEvent_t ev = stage_begin(*p, 3);
-    hipError_t e = split ? gemm2_bf16(*p, n_fields, phi, phi_dtype) : gemm2_f64(*p, n_fields, phi, phi_dtype);
+    hipError_t e;
+    if (p->sep) {
+        e = sep_expansion(*p, n_fields, phi, phi_dtype);
+    } else {
+        e = split ? gemm2_bf16(*p, n_fields, phi, phi_dtype) : gemm2_f64(*p, n_fields, phi, phi_dtype);
+    }
     stage_end(*p, ev);
     if (e != hipSuccess) return hip_fail(e, "expansion");
     return MPG_OK;
@@ -468,6 +521,7 @@ extern "C" {
 int mpg_potential_static(mpg_plan_t p, int n_fields, const void *rho, int rho_dtype, void *phi, int phi_dtype) {
     int rc = check_call(p, n_fields, rho, rho_dtype, "mpg_potential_static");
     if (rc) return rc;
+    if (p->sep) return fail(MPG_EUNSUPPORTED, "mpg_potential_static: separable-method plans need their work array");
     if (!phi) return fail(MPG_EINVAL, "mpg_potential_static: phi is NULL");
     if (phi_dtype != MPG_F64 && phi_dtype != MPG_F32)
         return fail(MPG_EINVAL, "mpg_potential_static: bad phi dtype");
@@ -512,6 +566,8 @@ int mpg_potential_batch(int n, const mpg_plan_t *plans, const void *const *rho, 
             return fail(MPG_EINVAL, "mpg_potential_batch: plans differ in precision");
         if (plans[f]->per_patch)
             return fail(MPG_EUNSUPPORTED, "mpg_potential_batch: per-patch-method plans are solved one by one");
+        if (plans[f]->sep)
+            return fail(MPG_EUNSUPPORTED, "mpg_potential_batch: separable-method plans are solved one by one");
         for (int g = 0; g < f; ++g)
             if (plans[g] == plans[f])
                 return fail(MPG_EINVAL, "mpg_potential_batch: a plan appears twice (they own their work space)");
@@ -557,6 +613,7 @@ int mpg_autotune(mpg_plan_t p, int n_fields_in, const void *rho, int rho_dtype, 
                  int *gemm1_rows, int *gemm2_rows) {
     int rc = check_call(p, n_fields_in, rho, rho_dtype, "mpg_autotune");
     if (rc) return rc;
+    if (p->sep) return fail(MPG_EUNSUPPORTED, "mpg_autotune: the separable method has no choices to tune");
     const int n_fields = p->vfields(n_fields_in);
     hipEvent_t a, b;
     hipError_t e;
@@ -742,6 +799,7 @@ int mpg_tables(mpg_plan_t p, double *U, double *Q, double *w) {
 
 int mpg_set_tuning(mpg_plan_t p, int splitk, int chunks, int gemm1_rows, int gemm2_rows) {
     if (!p) return fail(MPG_EINVAL, "mpg_set_tuning: plan is NULL");
+    if (p->sep) return fail(MPG_EUNSUPPORTED, "mpg_set_tuning: the separable method has no choices to tune");
     if (splitk > p->splitk) return fail(MPG_EINVAL, "mpg_set_tuning: K split exceeds the plan's work space");
     if (chunks > 16) return fail(MPG_EINVAL, "mpg_set_tuning: more than 16 shell chunks");
     if (gemm1_rows > 2) return fail(MPG_EINVAL, "mpg_set_tuning: gemm1_rows must be 1 or 2");

@@ -109,6 +109,37 @@ struct Plan {
     // single-patch fields that GEMM1 and the scans see for n_fields fields
     int vfields(int n_fields) const { return per_patch ? n_fields * n_patches : n_fields; }
 
+    // separable method: in each patch's own frame the cell weights factor
+    // over (theta, phi), so each contraction runs as a phi transform of
+    // every (field, patch, shell, theta row) row, a theta contraction per
+    // order u, and a rotation to or from the common frame per degree.  Phi
+    // columns c: C of u = 0..lmax (padded to 16), then S of u = 1..lmax
+    // (padded to 16).  On a phi grid symmetric about 0 with an even cell
+    // count (sep_mir) cells k and n_phi-1-k are taken together: the C
+    // columns see their sum, the S columns their difference.
+    bool sep = false, sep_mir = false;
+    int sep_ce = 0, sep_co = 0;  // C / S phi columns (multiples of 16)
+    int sep_lp = 0;              // degree slots per phi column (lmax + 1 rounded up to 16)
+    int sep_kh = 0, sep_khp = 0; // cells of a row the moments' transform walks (n_phi/2 mirrored), padded to 16
+    int sep_kx = 0;              // evaluation points of a row the expansion's transform computes
+    int *sep_m = nullptr;        // [nc] order u of a phi column, -1 = pad
+    int *sep_col = nullptr;      // [nc][sep_lp] real index of degree u + slot, -1 = none
+    int2 *sep_kxy = nullptr;     // [sep_kx] cell of an evaluation point and its mirror cell (-1: none)
+    long long *sep_xoff = nullptr;  // [lmax + 2] offsets of the degrees' rotations
+    int *sep_perm = nullptr;     // [n_lm] column of a real index
+    double *sep_f1 = nullptr;    // [sep_khp][nc] moments' phi factors (C_k^u, S_k^u)
+    double *sep_t1 = nullptr;    // [nc][sep_lp][n_theta] moments' theta factors (s_lu T_j^{lu})
+    double *sep_t2 = nullptr;    // [nc][sep_lp][n_theta] expansion's theta factors (-G s_lu P_l^u)
+    double *sep_f2 = nullptr;    // [nc][sep_kx] expansion's phi factors
+    double *sep_x1 = nullptr;    // rotations local -> common frame (moments)
+    double *sep_x2 = nullptr;    // rotations common frame -> local (expansion)
+    double *sep_A = nullptr;     // [sep_vrows()][n_lm] local moments / local expansion coefficients
+    double *sep_F = nullptr;     // [nc][sep_rows()] phi transforms (moments, then expansion)
+    int sep_nc() const { return sep_ce + sep_co; }
+    // (field, patch, shell) rows, and (field, patch, shell, theta row) rows padded to 128
+    int sep_vrows() const { return max_fields * n_patches * n_r; }
+    size_t sep_rows() const { return ((size_t)sep_vrows() * n_theta + 127) / 128 * 128; }
+
     int *col_src = nullptr;    // [np_alloc] real index of a permuted column, -1 = pad
     int *col_l = nullptr;      // [np_alloc] degree, -1 = pad
     double *Ut = nullptr;      // [np_alloc][kang]  U of the npat patch blocks, K(angular)-contiguous
@@ -257,6 +288,12 @@ hipError_t export_tables(const Plan &p, double *U, double *Q, double *w);
 // FP64 path (gemm_f64.hip)
 hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype);
+// separable method: the moments (phi transform, theta contraction, rotation
+// into Bpart plane 0) and the expansion (rotation, theta contraction, phi
+// transform)
+hipError_t sep_phi_moments(const Plan &p, int n_fields, const void *rho, int rho_dtype);
+hipError_t sep_theta_moments(const Plan &p, int n_fields);
+hipError_t sep_expansion(const Plan &p, int n_fields, void *phi, int phi_dtype);
 // expansion = true: the arguments of GEMM2 (they differ from GEMM1's only
 // for the per-patch method, whose GEMM1 sees single-patch fields)
 F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype, bool expansion = false);

@@ -463,6 +463,121 @@ __global__ void k_export(const double *Ut, const double *Qt, int np, int n_angp,
     }
 }
 
+// ---- factors of the separable method ------------------------------------
+// In each patch's own frame its cell weights factor over (theta, phi) (Eqs.
+// a_ci^lm, a_si^lm): the local moments are A^(lu) = sum_jk w_jk rho_jk
+// s_lu T_j^{lu} {C_k^u, S_k^u}, and the rotation sums of Eqs. U_C/U_S take
+// them to the common frame degree by degree.  A phi column c has
+// code[c] = 2 u + (0 for C, 1 for S), -1 on padding: the C columns of
+// u = 0..lmax first, then the S columns of u = 1..lmax.
+
+// f1[k][c] = C_k^u or S_k^u for the first kh cells (zero past them)
+__global__ void k_sep_f1(int L, int kh, int khp, int nc, const int *code, const double *CS, double *f1) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= khp * nc) return;
+    int k = t / nc, c = t - k * nc, cd = code[c];
+    f1[t] = (cd < 0 || k >= kh) ? 0.0 : CS[((size_t)k * (L + 1) + (cd >> 1)) * 2 + (cd & 1)];
+}
+
+// f2[c][b] = cos or sin of u phi at the evaluation point of the cell kx[b]
+__global__ void k_sep_f2(int kxn, int nc, double phi0, double dphi, double ev, const int *code, const int2 *kx,
+                         double *f2) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc * kxn) return;
+    int c = t / kxn, b = t - c * kxn, cd = code[c];
+    double v = 0.0;
+    if (cd >= 0) {
+        double s, co;
+        sincos((cd >> 1) * (phi0 + (kx[b].x + ev) * dphi), &s, &co);
+        v = (cd & 1) ? s : co;
+    }
+    f2[t] = v;
+}
+
+// t1[c][l - u][j] = s_lu T_j^{lu}, zero past lmax and on padding
+__global__ void k_sep_t1(int L, int n_theta, int nc, int lp, const int *code, const double *Tt, double *t1) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)nc * lp * n_theta) return;
+    int j = (int)(t % n_theta), r = (int)(t / n_theta), slot = r % lp, c = r / lp, cd = code[c];
+    double v = 0.0;
+    if (cd >= 0) {
+        int u = cd >> 1, l = u + slot;
+        if (l <= L) v = Tt[(size_t)j * off_tri(L + 1) + off_tri(l) + u];
+    }
+    t1[t] = v;
+}
+
+// t2[c][l - u][j] = -G s_lu P_l^u(cos theta) at the evaluation colatitude of
+// row j (normalised associated Legendre recurrences, Condon-Shortley phase,
+// as for Eqs. Q_C/Q_S); one thread per (column, row)
+__global__ void k_sep_t2(int L, int n_theta, int nc, int lp, double theta0, double dtheta, double ev, double G,
+                         const int *code, double *t2) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc * n_theta) return;
+    int c = t / n_theta, j = t - c * n_theta, cd = code[c];
+    double *o = t2 + (size_t)c * lp * n_theta + j;
+    for (int slot = 0; slot < lp; ++slot) o[(size_t)slot * n_theta] = 0.0;
+    if (cd < 0) return;
+    const int m = cd >> 1;
+    double sth, cth;
+    sincos(theta0 + (j + ev) * dtheta, &sth, &cth);
+    double pmm = 1.0;
+    for (int u = 1; u <= m; ++u) pmm *= -sqrt((2.0 * u - 1.0) / (2.0 * u)) * sth;
+    double p2 = 0.0, p1 = pmm;
+    for (int l = m; l <= L; ++l) {
+        double pl;
+        if (l == m) pl = pmm;
+        else if (l == m + 1) pl = cth * sqrt(2.0 * m + 1.0) * pmm;
+        else pl = (cth * (2.0 * l - 1.0) * p1 - sqrt((double)(l - 1) * (l - 1) - (double)m * m) * p2) /
+                  sqrt((double)l * l - (double)m * m);
+        if (l > m) {
+            p2 = p1;
+            p1 = pl;
+        }
+        o[(size_t)(l - m) * n_theta] = -G * pl;
+    }
+}
+
+// Rotation of degree l for patch g, from the patch's N factors (Eqs.
+// N_CC..N_SC): with i, o positions inside the degree's 2l + 1 real-index
+// entries (pos(m, C) = 2m - 1 or 0 for m = 0, pos(m, S) = 2m),
+//   X[(m, C)][(u, C)] = N_CC, X[(m, C)][(u, S)] = N_CS,
+//   X[(m, S)][(u, S)] = N_SS, X[(m, S)][(u, C)] = -N_SC.
+// Moments (Eqs. U_C/U_S): B[(m, .)] = f_m sum_g sum_(u, .) X A^g[(u, .)] with
+// f_m = 2/delta_m for C and 2 for S, stored x1[l][g (2l+1) + pos(u)][pos(m)].
+// Expansion: the common-frame moments M give the patch's local ones
+// L^g[(u, .)] = sum_(m, .) M[(m, .)] X[(m, .)][(u, .)] (the same factors
+// write the common-frame harmonics in local ones), x2[l][g][pos(m)][pos(u)].
+__device__ inline void pos_decode(int p, int &m, int &s) {
+    m = (p + 1) >> 1;
+    s = p > 0 && (p & 1) == 0;
+}
+
+__global__ void k_sep_x(int L, int n_patches, int g, const double *N4, const long long *xoff, double *x1,
+                        double *x2) {
+    // t runs over (l, pos(m), pos(u)) of all degrees: find l
+    const long long tt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long acc = 0;
+    int l;
+    for (l = 0; l <= L; ++l) {
+        const long long n2 = (long long)(2 * l + 1) * (2 * l + 1);
+        if (tt < acc + n2) break;
+        acc += n2;
+    }
+    if (l > L) return;
+    const int n = 2 * l + 1, r = (int)(tt - acc), pm = r / n, pu = r - pm * n;
+    int m, sm, u, su;
+    pos_decode(pm, m, sm);
+    pos_decode(pu, u, su);
+    const double *N = N4 + 4 * (size_t)(off_sq(l) + m * (l + 1) + u);
+    double x;
+    if (!sm) x = su ? N[1] : N[0];
+    else x = su ? N[2] : -N[3];
+    const double f = (!sm && m == 0) ? 1.0 : 2.0;
+    x1[xoff[l] + ((size_t)g * n + pu) * n + pm] = f * x;
+    x2[xoff[l] + ((size_t)g * n + pm) * n + pu] = x;
+}
+
 inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -497,7 +612,8 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
             }
     }
     hipError_t err = hipSuccess;
-    int *d_perm = nullptr;
+    int *d_perm = nullptr, *d_code = nullptr;
+    int2 *d_kx = nullptr;
     double *d_re = nullptr, *dh = nullptr, *db = nullptr, *N4 = nullptr, *Tt = nullptr, *CS = nullptr;
     const size_t kang = (size_t)p.kang();
     const size_t nU = (size_t)p.np_alloc * kang, nQ = (size_t)p.n2() * p.kq();
@@ -553,6 +669,70 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
     hipLaunchKernelGGL(k_cs, dim3(blocks((size_t)p.n_phi * (L + 1), 128)), dim3(128), 0, s, L, p.n_phi, p.phi0,
                        p.dphi, CS);
     STEP(hipGetLastError());
+
+    if (p.sep) {
+        // phi columns: C of u = 0..L (padded to 16), then S of u = 1..L
+        const int nc = p.sep_nc(), lp = p.sep_lp, P = p.n_patches, n = p.n_phi;
+        std::vector<int> code(nc, -1), ucol(nc, -1), scol((size_t)nc * lp, -1);
+        for (int u = 0; u <= L; ++u)
+            for (int cs = 0; cs < (u == 0 ? 1 : 2); ++cs) {
+                const int c = cs ? p.sep_ce + u - 1 : u;
+                code[c] = 2 * u + cs;
+                ucol[c] = u;
+                for (int l = u; l <= L; ++l)
+                    scol[(size_t)c * lp + (l - u)] = cs ? l * l + 2 * u : (u == 0 ? l * l : l * l + 2 * u - 1);
+            }
+        // expansion points: cell kx[b].x, and its mirror image kx[b].y (-1: none)
+        std::vector<int2> kx(p.sep_kx);
+        for (int b = 0; b < p.sep_kx; ++b) {
+            if (!p.sep_mir) kx[b] = make_int2(b, -1);
+            else if (p.eval_centre) kx[b] = make_int2(b, n - 1 - b);
+            else if (b < n / 2 - 1) kx[b] = make_int2(b, n - 2 - b);
+            else kx[b] = make_int2(b == n / 2 - 1 ? b : n - 1, -1);
+        }
+        std::vector<long long> xoff(L + 2, 0);
+        for (int l = 0; l <= L; ++l) xoff[l + 1] = xoff[l] + (long long)P * (2 * l + 1) * (2 * l + 1);
+        const double ev = p.eval_centre ? 0.5 : 1.0;
+        STEP(hipMalloc(&d_code, sizeof(int) * nc));
+        STEP(hipMalloc(&d_kx, sizeof(int2) * p.sep_kx));
+        STEP(hipMalloc(&p.sep_m, sizeof(int) * nc));
+        STEP(hipMalloc(&p.sep_col, sizeof(int) * nc * lp));
+        STEP(hipMalloc(&p.sep_kxy, sizeof(int2) * p.sep_kx));
+        STEP(hipMalloc(&p.sep_xoff, sizeof(long long) * (L + 2)));
+        STEP(hipMalloc(&p.sep_perm, sizeof(int) * p.n_lm));
+        STEP(hipMalloc(&p.sep_f1, sizeof(double) * p.sep_khp * nc));
+        STEP(hipMalloc(&p.sep_f2, sizeof(double) * nc * p.sep_kx));
+        STEP(hipMalloc(&p.sep_t1, sizeof(double) * nc * lp * p.n_theta));
+        STEP(hipMalloc(&p.sep_t2, sizeof(double) * nc * lp * p.n_theta));
+        STEP(hipMalloc(&p.sep_x1, sizeof(double) * xoff[L + 1]));
+        STEP(hipMalloc(&p.sep_x2, sizeof(double) * xoff[L + 1]));
+        STEP(hipMemcpyAsync(d_code, code.data(), sizeof(int) * nc, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(d_kx, kx.data(), sizeof(int2) * p.sep_kx, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(p.sep_kxy, kx.data(), sizeof(int2) * p.sep_kx, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(p.sep_m, ucol.data(), sizeof(int) * nc, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(p.sep_col, scol.data(), sizeof(int) * nc * lp, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(p.sep_xoff, xoff.data(), sizeof(long long) * (L + 2), hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(p.sep_perm, perm_of.data(), sizeof(int) * p.n_lm, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_sep_f1, dim3(blocks((size_t)p.sep_khp * nc, 128)), dim3(128), 0, s, L, p.sep_kh,
+                           p.sep_khp, nc, d_code, CS, p.sep_f1);
+        hipLaunchKernelGGL(k_sep_f2, dim3(blocks((size_t)nc * p.sep_kx, 128)), dim3(128), 0, s, p.sep_kx, nc,
+                           p.phi0, p.dphi, ev, d_code, d_kx, p.sep_f2);
+        hipLaunchKernelGGL(k_sep_t1, dim3(blocks((size_t)nc * lp * p.n_theta, 128)), dim3(128), 0, s, L,
+                           p.n_theta, nc, lp, d_code, Tt, p.sep_t1);
+        hipLaunchKernelGGL(k_sep_t2, dim3(blocks((size_t)nc * p.n_theta, 64)), dim3(64), 0, s, L, p.n_theta, nc,
+                           lp, p.theta0, p.dtheta, ev, p.G, d_code, p.sep_t2);
+        STEP(hipGetLastError());
+        // every patch's N factors from its own Euler angles
+        for (int g = 0; g < P; ++g) {
+            const double *e = euler + 3 * g;
+            hipLaunchKernelGGL(k_dbeta, dim3(blocks(2 * off_sq(L + 1), 128)), dim3(128), 0, s, L, dh, e[1],
+                               M_PI - e[1], db);
+            hipLaunchKernelGGL(k_ncoef, dim3(blocks(off_sq(L + 1), 128)), dim3(128), 0, s, L, db, e[0], e[2], N4);
+            hipLaunchKernelGGL(k_sep_x, dim3(blocks((size_t)(xoff[L + 1] / P), 128)), dim3(128), 0, s, L, P, g, N4,
+                               p.sep_xoff, p.sep_x1, p.sep_x2);
+            STEP(hipGetLastError());
+        }
+    }
 
     // U and Q of every patch block (under the fold, patch 0 only: patch 1
     // is derived from it); d at beta and pi - beta and the N factors come
@@ -618,6 +798,8 @@ done:
     (void)hipStreamSynchronize(s);
     (void)hipFree(d_perm);
     (void)hipFree(d_re);
+    (void)hipFree(d_code);
+    (void)hipFree(d_kx);
     (void)hipFree(dh);
     (void)hipFree(db);
     (void)hipFree(N4);
