@@ -37,12 +37,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the sources the split contractions are compiled from (their
-    file and every header of the library's sources)."""
+def kernel_source_hash(source="gemm_bf16.hip"):
+    """Hash of the sources a path's contractions are compiled from (their
+    file and every header of the library's sources): gemm_bf16.hip for the
+    split contractions, sep_f64.hip for the separable method's."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1903_08475_amd", "csrc")
-    names = ["gemm_bf16.hip"] + sorted(n for n in os.listdir(csrc) if n.endswith(".h"))
+    names = [source] + sorted(n for n in os.listdir(csrc) if n.endswith(".h"))
     for name in names:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
@@ -61,7 +62,8 @@ def traffic_record(stage, precision):
         return None
     key = f"{precision}:{stage}"
     r = rec.get(key)
-    if not r or r.get("source_hash") != kernel_source_hash():
+    source = "sep_f64.hip" if precision == "separable" else "gemm_bf16.hip"
+    if not r or r.get("source_hash") != kernel_source_hash(source):
         return None
     return r.get("bytes_per_launch")
 
@@ -204,6 +206,63 @@ def fp64_workload(dev, steps):
     return out
 
 
+def separable_flops(grid, n_fields):
+    """Algorithmic FP64 flops of one launch of each phi transform of the
+    separable method: 2 per product, rows (field, patch, shell, theta row)
+    x phi columns (2 lmax + 1) x cells walked by the moments' (half of a
+    row's under the mirror fold) or points computed by the expansion's (one
+    per mirror pair, plus the unpaired ones)."""
+    rows = n_fields * grid.n_patches * grid.n_r * grid.n_theta
+    n = grid.n_phi
+    mir = n % 2 == 0 and abs(grid.phi0 + 0.5 * n * grid.dphi) <= 1e-12
+    cells = n // 2 if mir else n
+    centre = getattr(grid, "eval_point", "vertex") == "centre"
+    points = (n // 2 if centre else n // 2 + 1) if mir else n
+    cols = 2 * grid.lmax + 1
+    return {"phi_moments": 2.0 * rows * cells * cols, "phi_expansion": 2.0 * rows * points * cols}
+
+
+SEP_STAGES = {"input_split": "phi_moments", "moments": "theta_and_rotations", "radial_scan": "radial_scan",
+              "expansion": "phi_expansion"}
+SEP_KERNELS = {"phi_moments": "k_sep_phi1 (moments' phi transform, FP64 MFMA)",
+               "phi_expansion": "k_sep_phi2 (expansion's phi transform, FP64 MFMA)"}
+
+
+def separable_workload(grid, rho, steps, warmup, ref=None):
+    """The separable method (FP64) on the large workload: ms per solve,
+    per-stage times (the theta contractions and rotations launch twice per
+    solve), the roofline of its dominant kernel (the costlier phi
+    transform) and its difference from a reference potential when given."""
+    import torch
+    import paper_1903_08475_amd as mpg
+    n = rho.shape[0]
+    plan = mpg.Plan(grid, precision="fp64", max_fields=n, method="separable")
+    phi = torch.empty_like(rho)
+    ms, _, st, pct = time_path(plan, rho, phi, steps, warmup)
+    per = {SEP_STAGES[k]: v[0] / max(1, v[1]) for k, v in st.items()}
+    per_solve = {SEP_STAGES[k]: v[0] / steps for k, v in st.items()}
+    flops = separable_flops(grid, n)
+    dom = max(("phi_moments", "phi_expansion"), key=lambda k: per[k])
+    achieved = flops[dom] / (per[dom] * 1e-3)
+    out = {"precision": "fp64", "ms_per_step": ms, "ms_per_step_percentiles": pct,
+           "value": grid.n_cells * grid.n_lm * n / (ms * 1e-3), "unit": "terms/s",
+           "stage_ms_per_solve": per_solve,
+           "phi_fp64_mfma_frac": {k: flops[k] / (per[k] * 1e-3) / PEAK_FP64 for k in flops},
+           "roofline": {"bound": "mfma", "kernel": SEP_KERNELS[dom], "achieved": achieved / 1e12,
+                        "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+                        "traffic": traffic_record(dom, "separable"), "avg_launch_ms": per[dom],
+                        "algorithmic_flops_per_launch": flops[dom]}}
+    if ref is not None:
+        out64 = torch.empty_like(ref)
+        plan.potential(rho, out=out64)
+        torch.cuda.synchronize()
+        out["vs_dense_fp64_max_rel_err"] = float((out64 - ref).abs().max() / ref.abs().max())
+        del out64
+    log(f"[bench] separable method: {ms:.3f} ms/step; per solve {per_solve}")
+    del plan, phi
+    return out
+
+
 def precision_workload(dev):
     """The precision workload (Yin-Yang pi/32, 32 shells, lmax 40; ellipsoid +
     a point-like Gaussian mass): max-norm relative error of Phi against the
@@ -333,7 +392,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the FP64 workload and the precision workload")
-    ap.add_argument("--only", choices=["fp64", "precision", "batch"], default=None,
+    ap.add_argument("--no-separable", action="store_true", help="skip the separable method")
+    ap.add_argument("--only", choices=["fp64", "precision", "batch", "separable"], default=None,
                     help="run only this workload (no headline line; e.g. to profile its kernels) and print its "
                          "JSON")
     args = ap.parse_args()
@@ -347,6 +407,10 @@ def main():
         torch.cuda.set_device(dev)
         if args.only == "fp64":
             res = fp64_workload(dev, 10)
+        elif args.only == "separable":
+            import workloads as W
+            grid = W.config5()
+            res = separable_workload(grid, make_inputs(grid, args.snapshots, dev), args.steps, args.warmup)
         elif args.only == "precision":
             res = precision_workload(dev)
         else:
@@ -450,6 +514,7 @@ def main():
         "stage_ms": {k: per[k] for k in per},
     }
 
+    sep = None
     phi_other = None
     if not args.no_other_split:
         log(f"[bench] {other} on the same workload")
@@ -489,7 +554,11 @@ def main():
         if phi_other is not None:
             out["other_split_form"]["vs_fp64_max_rel_err"] = float(
                 (phi_other.to(torch.float64) - ref).abs().max() / ref.abs().max())
-        del plan64, ref
+        del plan64
+        if not args.no_separable:
+            log("[bench] separable method on the same workload")
+            sep = separable_workload(grid, rho, args.steps, args.warmup, ref)
+        del ref
 
     if not args.no_compare:
         # the comparison method of the paper: every patch's moments in its own
@@ -527,6 +596,28 @@ def main():
         precs = ("split_bf16_tiered", "split_bf16", "fp64") if args.batch_all else ("split_bf16_tiered", "fp64")
         out["batch"] = batch_workload(dev, args.batch_reps, autotune=not args.no_autotune, precisions=precs)
 
+    if args.no_fp64 and not args.no_separable:
+        log("[bench] separable method on the same workload")
+        sep = separable_workload(grid, rho, args.steps, args.warmup)
+    if sep is not None:
+        # the headline: the fastest path that meets the FP64 bar (the same
+        # moments and potential, 1e-12 against the oracle); the dense
+        # split-BF16 path's line moves under its own key
+        dense = {k: out.pop(k) for k in ("value", "ms_per_step", "ms_per_step_percentiles", "roofline")}
+        dense.update(dtype="bf16", precision=out["config"]["precision"], autotuned=out["config"].pop("autotuned"))
+        for k in ("split_vs_fp64_max_rel_err", "speedup_vs_fp64"):
+            if k in out:
+                dense[k] = out.pop(k)
+        out["dense_split_bf16"] = dense
+        out.update(value=sep["value"], ms_per_step=sep["ms_per_step"],
+                   ms_per_step_percentiles=sep["ms_per_step_percentiles"], dtype="f64", roofline=sep.pop("roofline"))
+        out["config"]["precision"] = ("separable method in FP64: per-patch phi transforms (mirror cells folded), "
+                                      "theta contractions per order and rotations per degree on FP64 MFMA; "
+                                      "FP64 tables and scans")
+        out["separable_method"] = sep
+        if "fp64_path" in out:
+            out["speedup_vs_dense_fp64"] = out["fp64_path"]["ms_per_step"] / sep["ms_per_step"]
+            out["speedup_vs_dense_split_bf16"] = dense["ms_per_step"] / sep["ms_per_step"]
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -172,8 +172,8 @@ int mpg_plan(const mpg_grid *grid, int lmax, int precision, int max_fields,
  * angles.  mpg_potential_static, mpg_potential_batch, mpg_autotune and
  * mpg_set_tuning reject such plans (MPG_EUNSUPPORTED); mpg_moments,
  * mpg_potential, mpg_tables and stage timing take them (stages: phi
- * transform of the moments, theta contraction and rotation, radial scans,
- * expansion).  The plan holds two extra FP64 work arrays:
+ * transform of the moments; theta contractions and rotations of moments
+ * and expansion; radial scans; phi transform of the expansion).  The plan holds two extra FP64 work arrays:
  * (lmax + 1 and lmax, each rounded up to 16) x max_fields x n_patches x
  * n_r x n_theta values, and max_fields x n_patches x n_r x (lmax + 1)^2.
  * Errors: as mpg_plan, MPG_EINVAL for an unknown method. */
@@ -329,7 +329,10 @@ int mpg_plan_info(mpg_plan_t plan, int *n_lm, long long *field_elems);
 /* Per-stage device timing, for measurement.  With enable != 0 every later
  * compute call of the plan records HIP events on the plan's stream around
  * its stages: 0 = input split (split-BF16 only: rho_Yin +- rho_Yang as bf16
- * pieces), 1 = moment contraction, 2 = radial scan, 3 = expansion.
+ * pieces), 1 = moment contraction, 2 = radial scan, 3 = expansion (the
+ * separable method: 0 = phi transform of the moments, 1 = theta
+ * contractions and rotations of both steps, 3 = phi transform of the
+ * expansion; each solve counts two launches of stage 1).
  * mpg_stage_times waits for the stream and returns the summed milliseconds
  * and launch counts per stage since the last reset (reset != 0 clears them
  * after reading); ms and launches (4 entries each) may be NULL.

@@ -78,7 +78,7 @@ void free_plan(mpg_plan_s *p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *bufs[] = {p->col_src, p->col_l,  p->Ut,     p->Qt,     p->coef,   p->w,      p->Us,
                     p->Qs,      p->Bpart,  p->Bred,   p->M,      p->Ms,     p->A_split, p->sep_m,
-                    p->sep_col, p->sep_f1, p->sep_t1, p->sep_t2, p->sep_f2, p->sep_F,
+                    p->sep_coff, p->sep_cslot, p->sep_f1, p->sep_t1, p->sep_t2, p->sep_f2, p->sep_F,
                     p->sep_A,   p->sep_kxy, p->sep_xoff, p->sep_perm, p->sep_x1, p->sep_x2};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -247,9 +247,17 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
     }
     p->npat = (p->fold || p->per_patch) ? 1 : g->n_patches;
     if (method == MPG_METHOD_SEPARABLE) {
-        if (precision != MPG_FP64) {
+        // grid limits of its launches: theta rows and 128-row blocks of
+        // (field, patch, shell) rows on a grid axis, a weight row in LDS
+        const long long vblocks = ((long long)max_fields * g->n_patches * g->n_r + 127) / 128;
+        const char *why = precision != MPG_FP64 ? "the separable method runs in FP64 only"
+                          : (g->n_theta > 65535 || vblocks > 65535 || g->n_phi > 8192)
+                              ? "the separable method takes at most 65535 theta rows, 8192 phi cells and 65535 "
+                                "blocks of 128 (field, patch, shell) rows"
+                              : nullptr;
+        if (why) {
             free_plan(p);
-            return fail(MPG_EUNSUPPORTED, "mpg_plan: the separable method runs in FP64 only");
+            return fail(MPG_EUNSUPPORTED, std::string("mpg_plan: ") + why);
         }
         p->sep = true;
     }
@@ -341,10 +349,11 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
     }
     if (p->sep) {
         // zeroed once so that no padding row ever holds a non-finite value
-        const size_t n = (size_t)p->sep_nc() * p->sep_rows(), na = (size_t)p->sep_vrows() * p->n_lm;
+        const size_t n = (size_t)p->sep_nc() * p->n_theta * p->sep_ldv(), na = (size_t)p->n_lm * p->sep_ldv();
         if ((e = hipMalloc(&p->sep_F, sizeof(double) * n)) != hipSuccess ||
             (e = hipMemset(p->sep_F, 0, sizeof(double) * n)) != hipSuccess ||
-            (e = hipMalloc(&p->sep_A, sizeof(double) * na)) != hipSuccess) {
+            (e = hipMalloc(&p->sep_A, sizeof(double) * na)) != hipSuccess ||
+            (e = hipMemset(p->sep_A, 0, sizeof(double) * na)) != hipSuccess) {
             int rc = hip_fail(e, "mpg_plan: separable work space");
             free_plan(p);
             return rc;
@@ -437,11 +446,18 @@ static int solve(const Plan *p, int n_fields, const void *rho, int rho_dtype, vo
     int rc;
     bool split = p->split();
     if ((rc = run_moments(p, n_fields, rho, rho_dtype, split))) return rc;
-    hipEvent_t ev = stage_begin(*p, 3);
+    hipEvent_t ev;
     hipError_t e;
     if (p->sep) {
-        e = sep_expansion(*p, n_fields, phi, phi_dtype);
+        // rotation and theta contraction (timed with the moments' ones), phi transform
+        ev = stage_begin(*p, 1);
+        e = sep_theta_expansion(*p, n_fields);
+        stage_end(*p, ev);
+        if (e != hipSuccess) return hip_fail(e, "expansion");
+        ev = stage_begin(*p, 3);
+        e = sep_phi_expansion(*p, n_fields, phi, phi_dtype);
     } else {
+        ev = stage_begin(*p, 3);
         e = split ? gemm2_bf16(*p, n_fields, phi, phi_dtype) : gemm2_f64(*p, n_fields, phi, phi_dtype);
     }
     stage_end(*p, ev);

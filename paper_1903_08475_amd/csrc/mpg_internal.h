@@ -123,7 +123,8 @@ struct Plan {
     int sep_kh = 0, sep_khp = 0; // cells of a row the moments' transform walks (n_phi/2 mirrored), padded to 16
     int sep_kx = 0;              // evaluation points of a row the expansion's transform computes
     int *sep_m = nullptr;        // [nc] order u of a phi column, -1 = pad
-    int *sep_col = nullptr;      // [nc][sep_lp] real index of degree u + slot, -1 = none
+    int *sep_coff = nullptr;     // [nc] first slot of a phi column (slots of degrees u..lmax)
+    int *sep_cslot = nullptr;    // [n_lm] slot of a real index
     int2 *sep_kxy = nullptr;     // [sep_kx] cell of an evaluation point and its mirror cell (-1: none)
     long long *sep_xoff = nullptr;  // [lmax + 2] offsets of the degrees' rotations
     int *sep_perm = nullptr;     // [n_lm] column of a real index
@@ -133,12 +134,12 @@ struct Plan {
     double *sep_f2 = nullptr;    // [nc][sep_kx] expansion's phi factors
     double *sep_x1 = nullptr;    // rotations local -> common frame (moments)
     double *sep_x2 = nullptr;    // rotations common frame -> local (expansion)
-    double *sep_A = nullptr;     // [sep_vrows()][n_lm] local moments / local expansion coefficients
-    double *sep_F = nullptr;     // [nc][sep_rows()] phi transforms (moments, then expansion)
+    double *sep_A = nullptr;     // [n_lm][sep_ldv()] local moments / local expansion coefficients (by slot)
+    double *sep_F = nullptr;     // [nc][n_theta][sep_ldv()] phi transforms (moments, then expansion)
     int sep_nc() const { return sep_ce + sep_co; }
-    // (field, patch, shell) rows, and (field, patch, shell, theta row) rows padded to 128
+    // (field, patch, shell) rows v, and their count padded to 128
     int sep_vrows() const { return max_fields * n_patches * n_r; }
-    size_t sep_rows() const { return ((size_t)sep_vrows() * n_theta + 127) / 128 * 128; }
+    int sep_ldv() const { return (sep_vrows() + 127) / 128 * 128; }
 
     int *col_src = nullptr;    // [np_alloc] real index of a permuted column, -1 = pad
     int *col_l = nullptr;      // [np_alloc] degree, -1 = pad
@@ -288,12 +289,13 @@ hipError_t export_tables(const Plan &p, double *U, double *Q, double *w);
 // FP64 path (gemm_f64.hip)
 hipError_t gemm1_f64(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t gemm2_f64(const Plan &p, int n_fields, void *phi, int phi_dtype);
-// separable method: the moments (phi transform, theta contraction, rotation
-// into Bpart plane 0) and the expansion (rotation, theta contraction, phi
-// transform)
+// separable method: the moments (phi transform; theta contraction and
+// rotation into Bpart plane 0) and the expansion (rotation and theta
+// contraction; phi transform)
 hipError_t sep_phi_moments(const Plan &p, int n_fields, const void *rho, int rho_dtype);
 hipError_t sep_theta_moments(const Plan &p, int n_fields);
-hipError_t sep_expansion(const Plan &p, int n_fields, void *phi, int phi_dtype);
+hipError_t sep_theta_expansion(const Plan &p, int n_fields);
+hipError_t sep_phi_expansion(const Plan &p, int n_fields, void *phi, int phi_dtype);
 // expansion = true: the arguments of GEMM2 (they differ from GEMM1's only
 // for the per-patch method, whose GEMM1 sees single-patch fields)
 F64Args f64_args(const Plan &p, int n_fields, const void *rho, void *phi, int io_dtype, bool expansion = false);

@@ -10,27 +10,28 @@
 // patch's local ones, so the expansion runs the steps backwards:
 //   L^(lu) = sum_m M^(lm) X^(l)[(m, .)][(u, .)],
 //   Phi_jk = sum_lu -G s_lu P_l^u(cos theta_j) {cos, sin}(u phi_k) L^(lu).
-// Rows r = (field, patch, shell, theta row j) of the density are
-// contiguous runs of n_phi cells.  Five kernels:
-//   phi1   F[c][r]      = sum_k w_jk rho_r,k f_k^(c)          (phi transform)
-//   theta1 A[v][lu]     = sum_j t1_j^(lu) F[c(u)][v, j]         (per order u)
-//   rot1   B[row][lm]   = sum_(patch, u) x1^(l) A               (per degree l)
-//   rot2   L[v][lu]     = sum_m M[row][lm] x2^(l)               (per degree, patch)
-//   theta2 G[c][v, j]   = sum_l t2_j^(lu) L[v][lu]
-//   phi2   Phi_r,k      = sum_c G[c][r] f2_k^(c)
-// (v = (field, patch, shell)).  On a phi grid symmetric about 0 with an even
-// cell count the transforms fold the mirror cells k and n_phi-1-k: C_k^u is
-// even and S_k^u odd in phi, so the C columns take the weighted sum of the
-// two cells and the S columns their difference over half the cells, and the
-// expansion writes E + O and E - O to a point and its mirror image from the
-// cosine (E) and sine (O) sums.
+// Rows (v, j), v = (field, patch, shell), j the theta row, of the density
+// are contiguous runs of n_phi cells.  Five kernels:
+//   phi1   F[c][j][v]      = sum_k w_jk rho_(v,j),k f1_k^(c)     (phi transform)
+//   theta1 A[slot][v]      = sum_j t1_j^(lu) F[c(u)][j][v]       (per order u)
+//   rot1   B[row][lm]      = sum_(patch, u) x1^(l) A             (per degree l)
+//   rot2   L[slot][v]      = sum_m M[row][lm] x2^(l)             (per degree, patch)
+//   theta2 G[c][j][v]      = sum_l t2_j^(lu) L[slot][v]
+//   phi2   Phi_(v,j),k     = sum_c G[c][j][v] f2_k^(c)
+// (slot: one per (l, u, C or S), grouped by phi column).  On a phi grid
+// symmetric about 0 with an even cell count the transforms fold the mirror
+// cells k and n_phi-1-k: C_k^u is even and S_k^u odd in phi, so the C
+// columns take the weighted sum of the two cells and the S columns their
+// difference over half the cells, and the expansion writes E + O and E - O
+// to a point and its mirror image from the cosine (E) and sine (O) sums.
 //
 // All are v_mfma_f64_16x16x4f64 contractions with 256 threads (four waves)
-// per block and 16-deep K slabs staged through LDS.  The phi transforms
-// carry almost all the work: phi1 reads the density once (converted,
-// weighted and folded on the way into LDS) and keeps every phi column of its
-// 128 rows in registers; phi2 keeps the cosine and sine sums of a 128 x 64
-// tile of rows and evaluation points.
+// per block and 16-deep K slabs staged through LDS, laid out so that every
+// global access runs along v.  The phi transforms carry almost all the
+// work: phi1 reads the density once (converted, weighted and folded on the
+// way into LDS) and keeps every phi column of its 128 rows in registers;
+// phi2 keeps the cosine and sine sums of a 128 x 64 tile of rows and
+// evaluation points.
 #include "mpg_internal.h"
 
 namespace mpg {
@@ -40,9 +41,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int SK = 16;       // K slab depth
-constexpr int RB = 128;      // rows per block of the phi transforms
-constexpr int PA = RB + 16;  // LDS row pitch of a 128-row operand (doubles)
-constexpr int TR = 64;       // rows per block of the theta contractions and rotations
+constexpr int TR = 64;       // rows per block of the rotations
+constexpr int VB = 128;      // rows v per block of the transforms and theta contractions
+constexpr int PA = VB + 16;  // LDS row pitch of a 128-wide operand (doubles)
+constexpr int JB = 4;        // theta rows per block of the expansion's phi transform
+constexpr int JR1 = 1;       // and of the moments' (whose registers hold no more state)
 constexpr int kMaxTiles = 9; // 16-wide tiles of a degree's 2 lmax + 1 <= 129 entries
 
 __device__ inline v4d mfma(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
@@ -56,21 +59,27 @@ __host__ __device__ constexpr int pitch(int n) { return (n / 16) % 2 ? n : n + 1
 // B[l/16][l%16]; result register q of lane l is D[l/16 + 4q][l%16].
 
 // ---------------------------------------------------------------------------
-// Phi transform of the moments.  Block: 128 rows x all NT column tiles of 16
-// (the first NE the C columns), K = the kh cells (mirrored: the first half)
-// in slabs of 16.  Thread t stages 8 consecutive cells of row t/2 (from
-// (t%2)*8), and with MIR their 8 mirror cells, with their weights; and NT
-// entries of the factor slab.  The next slab is loaded into registers while
-// the current one is multiplied.
+// The transforms keep their columns apart: F and G are [c][j][v] (v =
+// (field, patch, shell), ldv of them per (c, j)), the local moments and
+// coefficients [slot][v] with slot = coff[c] + l - u (every (l, u, C/S) once).
+
+// Phi transform of the moments.  Block: 128 rows v of one (field, patch)
+// group at JR consecutive theta rows j, one after the other; output
+// F[c][j][v] = sum_k w_jk rho_(v,j),k f1[k][c] for all NT column tiles of 16
+// (the first NE = (NT + 1)/2 the C columns), as the product f1^T (columns as rows) times
+// the folded density slab (rows v as columns), so that a store writes 16
+// consecutive v.  K = the kh cells in slabs of 16.  The weight row of the
+// current j sits in LDS.  Thread t stages 8 consecutive cells of row t/2
+// (from (t%2)*8), with MIR also their 8 mirror cells, and NT entries of the
+// factor slab; the next slab (the next theta row's first after a row's
+// last) is loaded into registers while the current one is multiplied.
 template <typename T>
 struct PhiStage {
     T a[8], b[8];
-    double wa[8], wb[8];
 };
 
 template <typename T, bool MIR>
-__device__ inline void load_phi(PhiStage<T> &st, const T *row, const double *wr, int k, int n_phi, int kh,
-                                bool row_ok) {
+__device__ inline void load_phi(PhiStage<T> &st, const T *row, int k, int n_phi, int kh, bool row_ok) {
     if (sizeof(T) == 4 && (n_phi & 3) == 0 && k + 8 <= kh) {
         // 16-byte aligned: rows start at multiples of 4 cells, k and the
         // mirror run n_phi-8-k too
@@ -89,8 +98,6 @@ __device__ inline void load_phi(PhiStage<T> &st, const T *row, const double *wr,
         for (int q = 0; q < 8; ++q) {
             st.a[q] = (T)xa[q];
             st.b[q] = (T)ya[q];
-            st.wa[q] = row_ok ? wr[k + q] : 0.0;
-            st.wb[q] = (MIR && row_ok) ? wr[n_phi - 1 - k - q] : 0.0;
         }
         return;
     }
@@ -99,171 +106,192 @@ __device__ inline void load_phi(PhiStage<T> &st, const T *row, const double *wr,
         const bool ok = row_ok && k + q < kh;
         st.a[q] = ok ? row[k + q] : (T)0;
         st.b[q] = (ok && MIR) ? row[n_phi - 1 - k - q] : (T)0;
-        st.wa[q] = ok ? wr[k + q] : 0.0;
-        st.wb[q] = (ok && MIR) ? wr[n_phi - 1 - k - q] : 0.0;
     }
 }
 
-template <typename T, bool MIR, int NT>
-__global__ __launch_bounds__(256) void k_sep_phi1(const T *__restrict__ rho, const double *__restrict__ w,
-                                                  size_t w_patch, const double *__restrict__ f1,
-                                                  double *__restrict__ F, size_t ldF, size_t n_rows,
-                                                  int rows_per_patch, int n_patches, int n_theta, int n_phi, int kh,
-                                                  int ne) {
-    constexpr int NC = NT * 16, PB = pitch(NC);
+template <typename T, bool MIR, int NT, int JR>
+__global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, const double *__restrict__ w,
+                                                     size_t w_patch, const double *__restrict__ f1,
+                                                     double *__restrict__ F, int ldv, int n_r, int n_patches,
+                                                     int n_theta, int n_phi, int kh, int nst) {
+    // C column tiles: lmax + 1 and lmax columns round up to NE and NT - NE tiles
+    constexpr int NC = NT * 16, PB = pitch(NC), NE = (NT + 1) / 2;
+    extern __shared__ double sW[];  // the weight row w_j. of the block's patch
     __shared__ double Ae[SK][PA];
     __shared__ double Ao[MIR ? SK : 1][MIR ? PA : 1];
     __shared__ double Bs[SK][PB];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const size_t r0 = (size_t)blockIdx.x * RB;
+    const int fg = blockIdx.x / nst, st0 = (blockIdx.x - fg * nst) * VB;
+    const int j0 = blockIdx.y * JR, jn = min(JR, n_theta - j0);
+    const int nv = min(VB, n_r - st0);
+    const size_t v0 = (size_t)fg * n_r + st0;
+    const double *wp = w + (size_t)(fg % n_patches) * w_patch;
 
-    // this thread's staging row and cells
+    // this thread's staging row (v0 + sr, j) and cells
     const int sr = tid >> 1, sk = (tid & 1) * 8;
-    const size_t r = r0 + sr;
-    const bool row_ok = r < n_rows;
-    const size_t rr = row_ok ? r : 0;
-    const T *prow = rho + rr * n_phi;
-    const double *wr = w + (rr / rows_per_patch % n_patches) * w_patch + (rr % n_theta) * n_phi;
+    const bool row_ok = sr < nv;
+    const T *prow0 = rho + ((v0 + (row_ok ? sr : 0)) * n_theta + j0) * n_phi;
 
-    v4d acc[2][NT];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[i][t] = v4d{0.0, 0.0, 0.0, 0.0};
-
+    v4d acc[NT][2];
     const int nsl = (kh + SK - 1) / SK;
-    PhiStage<T> st;
+    PhiStage<T> stg;
     double bv[NT];
-    auto load = [&](int s) {
-        load_phi<T, MIR>(st, prow, wr, s * SK + sk, n_phi, kh, row_ok);
+    // slab s of theta row j0 + jj into registers
+    auto load = [&](int jj, int s) {
+        load_phi<T, MIR>(stg, prow0 + (size_t)jj * n_phi, s * SK + sk, n_phi, kh, row_ok);
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const int e = tid + 256 * q;
             bv[q] = f1[(size_t)(s * SK + e / NC) * NC + e % NC];
         }
     };
-    load(0);
-    const int wm = wave * 32;
-    for (int s = 0; s < nsl; ++s) {
-        // stage slab s
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const double a = st.wa[q] * (double)st.a[q], b = st.wb[q] * (double)st.b[q];
-            Ae[sk + q][sr] = a + b;
-            if (MIR) Ao[sk + q][sr] = a - b;
-        }
-#pragma unroll
-        for (int q = 0; q < NT; ++q) {
-            const int e = tid + 256 * q;
-            Bs[e / NC][e % NC] = bv[q];
-        }
-        __syncthreads();
-        if (s + 1 < nsl) load(s + 1);
-#pragma unroll
-        for (int kk = 0; kk < SK / 4; ++kk) {
-            const int kr = kk * 4 + (lane >> 4);
-            double ae[2], ao[2], b[NT];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                ae[i] = Ae[kr][wm + i * 16 + (lane & 15)];
-                ao[i] = MIR ? Ao[kr][wm + i * 16 + (lane & 15)] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < NT; ++t) b[t] = Bs[kr][t * 16 + (lane & 15)];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int t = 0; t < NT; ++t) acc[i][t] = mfma((MIR && t >= ne) ? ao[i] : ae[i], b[t], acc[i][t]);
-        }
-        __syncthreads();
-    }
-
-    // F[c][r]: register q of lane l is row l/16 + 4q of the 16-row tile
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
+    load(0, 0);
+    const int wv = wave * 32;
+    for (int jj = 0; jj < jn; ++jj) {
+        const int j = j0 + jj;
+        // the weight row of theta row j (the previous row's slabs are done)
+        for (int k = tid; k < n_phi; k += 256) sW[k] = wp[(size_t)j * n_phi + k];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const size_t row = r0 + wm + i * 16 + (lane >> 4) + 4 * q;
-                if (row < n_rows) F[(size_t)(t * 16 + (lane & 15)) * ldF + row] = acc[i][t][q];
+            for (int i = 0; i < 2; ++i) acc[t][i] = v4d{0.0, 0.0, 0.0, 0.0};
+        __syncthreads();
+        for (int s = 0; s < nsl; ++s) {
+            // stage slab s (weights of cells past kh multiply zeros)
+            const int k = s * SK + sk;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool in = k + q < kh;
+                const double a = (in ? sW[k + q] : 0.0) * (double)stg.a[q];
+                const double b = (MIR && in) ? sW[n_phi - 1 - k - q] * (double)stg.b[q] : 0.0;
+                Ae[sk + q][sr] = a + b;
+                if (MIR) Ao[sk + q][sr] = a - b;
             }
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                const int e = tid + 256 * q;
+                Bs[e / NC][e % NC] = bv[q];
+            }
+            __syncthreads();
+            // the next slab, of this theta row or the first of the next
+            {
+                const bool last = s + 1 == nsl;
+                if (!last || jj + 1 < jn) load(last ? jj + 1 : jj, last ? 0 : s + 1);
+            }
+#pragma unroll
+            for (int kk = 0; kk < SK / 4; ++kk) {
+                const int kr = kk * 4 + (lane >> 4);
+                double ae[2], ao[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    ae[i] = Ae[kr][wv + i * 16 + (lane & 15)];
+                    ao[i] = MIR ? Ao[kr][wv + i * 16 + (lane & 15)] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const double b = Bs[kr][t * 16 + (lane & 15)];
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) acc[t][i] = mfma(b, (MIR && t >= NE) ? ao[i] : ae[i], acc[t][i]);
+                }
+            }
+            __syncthreads();
+        }
+        // register q of lane l: column c = 16t + l/16 + 4q, row v = wv + 16i + l%16
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = t * 16 + (lane >> 4) + 4 * q, vv = wv + i * 16 + (lane & 15);
+                    if (vv < nv) F[((size_t)c * n_theta + j) * ldv + v0 + vv] = acc[t][i][q];
+                }
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Theta contraction of the moments: block (64 rows v, phi column c):
-// A[v][col(c, s)] = sum_j F[c][v * n_theta + j] t1[c][s][j] for the degree
-// slots s < lmax + 1 - u (at most five tiles of 16), K = n_theta in slabs of
-// 16.  Wave w takes rows 16w..16w+15.
-__global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F, size_t ldF,
+// Theta contraction of the moments: block (128 rows v from v0 = 128 x, phi
+// column c = y): A[coff[c] + s][v] = sum_j t1[c][s][j] F[c][j][v] for the
+// degree slots s < lmax + 1 - u (at most five tiles of 16), K = n_theta in
+// slabs of 16; slots as rows, v as columns (stores of 16 consecutive v).
+// Wave w takes v 32w..32w+31.  v past the last row lie in the zeroed
+// padding of the work arrays and are not stored.
+__global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F, int ldv,
                                                     const double *__restrict__ t1, const int *__restrict__ sep_u,
-                                                    const int *__restrict__ sep_col, double *__restrict__ A, int rows,
-                                                    int n_theta, int lp, int L, int lda) {
-    constexpr int NTM = 5, PB = pitch(NTM * 16);
-    __shared__ double As[SK][pitch(TR)];
-    __shared__ double Bs[SK][PB];
+                                                    const int *__restrict__ coff, double *__restrict__ A, int vrows,
+                                                    int n_theta, int lp, int L) {
+    constexpr int NTM = 5;
+    __shared__ double As[SK][pitch(NTM * 16)];
+    __shared__ double Bs[SK][PA];
     const int c = blockIdx.y, u = sep_u[c];
     if (u < 0) return;  // padding column (the whole block)
     const int nl = L + 1 - u, ntl = (nl + 15) / 16;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int row0 = blockIdx.x * TR;
-    const double *Fc = F + (size_t)c * ldF;
+    const int v0 = blockIdx.x * VB, wv = wave * 32;
     const double *tc = t1 + (size_t)c * lp * n_theta;
+    const double *Fc = F + (size_t)c * n_theta * ldv + v0;
 
-    v4d acc[NTM];
+    v4d acc[NTM][2];
 #pragma unroll
-    for (int t = 0; t < NTM; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-    // staging: A 64 rows x 16 (thread: row tid/4, 4 consecutive j);
-    // B 16 x 80 (thread: slots tid/16 + 16q, j tid%16)
-    const int ar = tid >> 2, aj = (tid & 3) * 4;
-    const bool arow_ok = row0 + ar < rows;
-    const double *fa = Fc + (size_t)(arow_ok ? row0 + ar : 0) * n_theta;
+    for (int t = 0; t < NTM; ++t)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) acc[t][i] = v4d{0.0, 0.0, 0.0, 0.0};
+    // staging: t1 16 j x 80 slots (entry e = tid + 256q: slot e/16, j e%16);
+    // F 16 j x 128 v (thread: j tid/16, v 8(tid%16)..)
+    const int bj = tid >> 4, bv = (tid & 15) * 8;
     for (int j0 = 0; j0 < n_theta; j0 += SK) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int j = j0 + aj + q;
-            As[aj + q][ar] = (arow_ok && j < n_theta) ? fa[j] : 0.0;
-        }
-#pragma unroll
         for (int q = 0; q < NTM; ++q) {
-            const int sl = (tid >> 4) + 16 * q, j = j0 + (tid & 15);
-            Bs[tid & 15][sl] = (sl < lp && j < n_theta) ? tc[(size_t)sl * n_theta + j] : 0.0;
+            const int e = tid + 256 * q, sl = e >> 4, jj = e & 15, j = j0 + jj;
+            As[jj][sl] = (sl < nl && j < n_theta) ? tc[(size_t)sl * n_theta + j] : 0.0;
         }
+        const bool jok = j0 + bj < n_theta;
+        const double *fr = Fc + (size_t)(jok ? j0 + bj : 0) * ldv + bv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Bs[bj][bv + q] = jok ? fr[q] : 0.0;
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < SK / 4; ++kk) {
             const int kr = kk * 4 + (lane >> 4);
-            const double a = As[kr][wave * 16 + (lane & 15)];
+            double b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) b[i] = Bs[kr][wv + i * 16 + (lane & 15)];
 #pragma unroll
             for (int t = 0; t < NTM; ++t)
-                if (t < ntl) acc[t] = mfma(a, Bs[kr][t * 16 + (lane & 15)], acc[t]);
+                if (t < ntl) {
+                    const double a = As[kr][t * 16 + (lane & 15)];
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) acc[t][i] = mfma(a, b[i], acc[t][i]);
+                }
         }
         __syncthreads();
     }
-    const int *cols = sep_col + (size_t)c * lp;
+    double *Ac = A + (size_t)coff[c] * ldv + v0;
 #pragma unroll
     for (int t = 0; t < NTM; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = row0 + wave * 16 + (lane >> 4) + 4 * q, sl = t * 16 + (lane & 15);
-            if (t < ntl && row < rows && sl < nl) A[(size_t)row * lda + cols[sl]] = acc[t][q];
-        }
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int sl = t * 16 + (lane >> 4) + 4 * q, vv = wv + i * 16 + (lane & 15);
+                if (t < ntl && sl < nl && v0 + vv < vrows) Ac[(size_t)sl * ldv + vv] = acc[t][i][q];
+            }
 }
 
 // ---------------------------------------------------------------------------
 // Rotations of degree l (blockIdx.y), 64 rows of (field, shell) per block.
 //   EXP = false (moments): B[row][perm[l^2 + o]] = sum over kk = (patch g,
-//     position i) of A[(f, g, shell)][l^2 + i] x1[l][kk][o];  K = P (2l+1)
+//     position i) of A[cslot[l^2 + i]][(f, g, shell)] x1[l][kk][o];  K = P (2l+1)
 //   EXP = true (expansion, patch g = blockIdx.z):
-//     L[(f, g, shell)][l^2 + o] = sum_i M[row][perm[l^2 + i]] x2[l][g][i][o];  K = 2l+1
+//     L[cslot[l^2 + o]][(f, g, shell)] = sum_i M[row][perm[l^2 + i]] x2[l][g][i][o];  K = 2l+1
 // N = 2l + 1 in up to nine tiles of 16; wave w takes rows 16w..16w+15.
 template <bool EXP>
 __global__ __launch_bounds__(256) void k_sep_rot(const double *__restrict__ src, const double *__restrict__ x,
                                                  const long long *__restrict__ xoff, const int *__restrict__ perm,
-                                                 double *__restrict__ dst, int rows, int n_r, int P, int n_lm,
-                                                 int np) {
+                                                 const int *__restrict__ cslot, double *__restrict__ dst, int rows,
+                                                 int n_r, int P, int ldv, int np) {
     constexpr int NB = kMaxTiles * 16;
     __shared__ double As[SK][pitch(TR)];
     __shared__ double Bs[SK][pitch(NB)];
@@ -277,9 +305,9 @@ __global__ __launch_bounds__(256) void k_sep_rot(const double *__restrict__ src,
     v4d acc[kMaxTiles];
 #pragma unroll
     for (int t = 0; t < kMaxTiles; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-    // staging: A 64 rows x 16 (thread: row tid/4, 4 consecutive kk); B 16 x
-    // 144 (thread: entries tid + 256q)
-    const int ar = tid >> 2, ak = (tid & 3) * 4;
+    // staging: A 64 rows x 16 (thread: row tid%64, 4 consecutive kk from
+    // 4 (tid/64)); B 16 x 144 (entries tid + 256q)
+    const int ar = tid & 63, ak = (tid >> 6) * 4;
     const int arow = row0 + ar;
     const bool arow_ok = arow < rows;
     const int af = arow_ok ? arow / n_r : 0, ash = arow_ok ? arow - af * n_r : 0;
@@ -293,7 +321,7 @@ __global__ __launch_bounds__(256) void k_sep_rot(const double *__restrict__ src,
                     v = src[(size_t)arow * np + perm[l2 + kk]];
                 } else {
                     const int gi = kk / n, i = kk - gi * n;
-                    v = src[((size_t)(af * P + gi) * n_r + ash) * n_lm + l2 + i];
+                    v = src[(size_t)cslot[l2 + i] * ldv + (size_t)(af * P + gi) * n_r + ash];
                 }
             }
             As[ak + q][ar] = v;
@@ -322,7 +350,7 @@ __global__ __launch_bounds__(256) void k_sep_rot(const double *__restrict__ src,
             if (t >= nto || row >= rows || o >= n) continue;
             if (EXP) {
                 const int f = row / n_r, sh = row - f * n_r;
-                dst[((size_t)(f * P + g) * n_r + sh) * n_lm + l2 + o] = acc[t][q];
+                dst[(size_t)cslot[l2 + o] * ldv + (size_t)(f * P + g) * n_r + sh] = acc[t][q];
             } else {
                 dst[(size_t)row * np + perm[l2 + o]] = acc[t][q];
             }
@@ -330,169 +358,178 @@ __global__ __launch_bounds__(256) void k_sep_rot(const double *__restrict__ src,
 }
 
 // ---------------------------------------------------------------------------
-// Theta contraction of the expansion: block (64 rows v, 64 theta rows, phi
-// column c): G[c][v * n_theta + j] = sum_s L[v][col(c, s)] t2[c][s][j], K =
-// the degree slots in slabs of 16.  Wave w takes rows 32(w%2).. and theta
-// rows 32(w/2)..
+// Theta contraction of the expansion: block (128 v from 128 x, phi column
+// c = y, 128 theta rows from 128 z): G[c][j][v] = sum_s t2[c][s][j]
+// L[coff[c] + s][v], K = the degree slots in slabs of 16; theta rows as
+// rows, v as columns.  Wave w takes theta rows 64(w%2).. and v 64(w/2)..
 __global__ __launch_bounds__(256) void k_sep_theta2(const double *__restrict__ Lc, const double *__restrict__ t2,
-                                                    const int *__restrict__ sep_u, const int *__restrict__ sep_col,
-                                                    double *__restrict__ G, size_t ldF, int rows, int n_theta, int lp,
-                                                    int L, int lda) {
-    __shared__ double As[SK][pitch(TR)];
-    __shared__ double Bs[SK][pitch(TR)];
-    const int c = blockIdx.z, u = sep_u[c];
+                                                    const int *__restrict__ sep_u, const int *__restrict__ coff,
+                                                    double *__restrict__ G, int ldv, int vrows, int n_theta, int lp,
+                                                    int L) {
+    __shared__ double As[SK][PA];
+    __shared__ double Bs[SK][PA];
+    const int c = blockIdx.y, u = sep_u[c];
     if (u < 0) return;
     const int nl = L + 1 - u;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int row0 = blockIdx.x * TR, j0 = blockIdx.y * TR;
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-    const int *cols = sep_col + (size_t)c * lp;
+    const int v0 = blockIdx.x * VB, j0 = blockIdx.z * VB;
+    const int wj = (wave & 1) * 64, wv = (wave >> 1) * 64;
     const double *tc = t2 + (size_t)c * lp * n_theta;
+    const double *lc = Lc + (size_t)coff[c] * ldv + v0;
 
-    v4d acc[2][2];
+    v4d acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[i][t] = v4d{0.0, 0.0, 0.0, 0.0};
-    // staging: A 64 rows x 16 slots (thread: row tid/4, slots 4(tid%4)..);
-    // B 16 slots x 64 theta rows (thread: slot tid/16, rows 4(tid%16)..)
-    const int ar = tid >> 2, as = (tid & 3) * 4, bs = tid >> 4, bj = (tid & 15) * 4;
-    const bool arow_ok = row0 + ar < rows;
-    const double *la = Lc + (size_t)(arow_ok ? row0 + ar : 0) * lda;
+        for (int t = 0; t < 4; ++t) acc[i][t] = v4d{0.0, 0.0, 0.0, 0.0};
+    // staging (thread: slot tid/16, 8 consecutive j or v from 8(tid%16))
+    const int ss = tid >> 4, sx = (tid & 15) * 8;
     for (int s0 = 0; s0 < nl; s0 += SK) {
+        const bool sok = s0 + ss < nl;
+        const double *tr = tc + (size_t)(sok ? s0 + ss : 0) * n_theta;
+        const double *lr = lc + (size_t)(sok ? s0 + ss : 0) * ldv + sx;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int sl = s0 + as + q;
-            As[as + q][ar] = (arow_ok && sl < nl) ? la[cols[sl]] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int sl = s0 + bs, j = j0 + bj + q;
-            Bs[bs][bj + q] = (sl < nl && j < n_theta) ? tc[(size_t)sl * n_theta + j] : 0.0;
+        for (int q = 0; q < 8; ++q) {
+            const int j = j0 + sx + q;
+            As[ss][sx + q] = (sok && j < n_theta) ? tr[j] : 0.0;
+            Bs[ss][sx + q] = sok ? lr[q] : 0.0;
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < SK / 4; ++kk) {
             const int kr = kk * 4 + (lane >> 4);
-            double a[2], b[2];
+            double a[4], b[4];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+            for (int i = 0; i < 4; ++i) a[i] = As[kr][wj + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) b[t] = Bs[kr][wn + t * 16 + (lane & 15)];
+            for (int t = 0; t < 4; ++t) b[t] = Bs[kr][wv + t * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int t = 0; t < 2; ++t) acc[i][t] = mfma(a[i], b[t], acc[i][t]);
+                for (int t = 0; t < 4; ++t) acc[i][t] = mfma(a[i], b[t], acc[i][t]);
         }
         __syncthreads();
     }
-    double *Gc = G + (size_t)c * ldF;
+    double *Gc = G + (size_t)c * n_theta * ldv + v0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row = row0 + wm + i * 16 + (lane >> 4) + 4 * q, j = j0 + wn + t * 16 + (lane & 15);
-                if (row < rows && j < n_theta) Gc[(size_t)row * n_theta + j] = acc[i][t][q];
+                const int j = j0 + wj + i * 16 + (lane >> 4) + 4 * q, vv = wv + t * 16 + (lane & 15);
+                if (j < n_theta && v0 + vv < vrows) Gc[(size_t)j * ldv + vv] = acc[i][t][q];
             }
 }
 
 // ---------------------------------------------------------------------------
-// Phi transform of the expansion: block (128 rows, 64 evaluation points b):
+// Phi transform of the expansion: block (64 evaluation points b from 64 x,
+// 128 rows v from 128 y, JB theta rows from JB z, one after the other; the
+// point tiles of the same rows run next to each other and share G in L2):
 // E = the sum over the C columns, O over the S columns (with MIR; else all
-// columns go to E); Phi[r][kxy[b].x] = E + O and, with a mirror cell,
-// Phi[r][kxy[b].y] = E - O.  K = the phi columns in slabs of 16.  Wave w
-// takes rows 32w.. and all 64 points.  Thread t stages 8 rows of phi column
-// t/16 (from (t%16)*8) and 4 points of factor row t/16.
+// columns go to E); Phi[(v, j)][kxy[b].x] = E + O and, with a mirror cell,
+// Phi[(v, j)][kxy[b].y] = E - O.  K = the phi columns in slabs of 16.  Wave
+// w takes v 32w.. and the block's point tiles (fewer than four in the
+// last).  Thread t stages 8 v of phi column t/16 (from 8(t%16)) and 4
+// points of factor row t/16.
 template <typename T, bool MIR>
-__global__ __launch_bounds__(256) void k_sep_phi2(const double *__restrict__ G, size_t ldF,
-                                                  const double *__restrict__ f2, const int2 *__restrict__ kxy,
-                                                  T *__restrict__ phi, size_t n_rows, int n_phi, int kx, int ce,
-                                                  int co) {
+__global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ G, int ldv,
+                                                     const double *__restrict__ f2, const int2 *__restrict__ kxy,
+                                                     T *__restrict__ phi, int vrows, int n_theta, int n_phi, int kx,
+                                                     int ce, int co) {
     __shared__ double As[SK][PA];
     __shared__ double Bs[SK][pitch(64)];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const size_t r0 = (size_t)blockIdx.x * RB;
-    const int b0 = blockIdx.y * 64, wm = wave * 32;
-    const int sc = tid >> 4, sr = (tid & 15) * 8, sb = (tid & 15) * 4;
+    const int b0 = blockIdx.x * 64, v0 = blockIdx.y * VB, wv = wave * 32;
+    const int j0 = blockIdx.z * JB, jn = min(JB, n_theta - j0);
+    const int ntc = min(4, (kx - b0 + 15) / 16);  // point tiles of this block
+    const int sc = tid >> 4, sv = (tid & 15) * 8, sb = (tid & 15) * 4;
 
     v4d E[2][4], O[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) E[i][t] = O[i][t] = v4d{0.0, 0.0, 0.0, 0.0};
-
     const int nsl = (ce + co) / SK, nse = ce / SK;
     double av[8], bv[4];
-    auto load = [&](int s) {
-        // G rows past n_rows lie inside the padded work array and feed only
-        // output rows that are not stored
-        const double *g = G + (size_t)(s * SK + sc) * ldF + r0 + sr;
+    // slab s of theta row j0 + jj into registers (v past the last row lie
+    // in the zeroed padding of G and feed only rows that are not stored)
+    auto load = [&](int jj, int s) {
+        const double *g = G + ((size_t)(s * SK + sc) * n_theta + j0 + jj) * ldv + v0 + sv;
 #pragma unroll
         for (int q = 0; q < 8; ++q) av[q] = g[q];
         const double *f = f2 + (size_t)(s * SK + sc) * kx;
 #pragma unroll
         for (int q = 0; q < 4; ++q) bv[q] = b0 + sb + q < kx ? f[b0 + sb + q] : 0.0;
     };
-    // slabs [s0, s1) into acc; the first slab's operands are in registers
-    auto run = [&](v4d(&acc)[2][4], int s0, int s1) {
+    // slabs [s0, s1) of theta row j0 + jj into acc; the first slab's
+    // operands are in registers, and the last prefetches the next row's first
+    auto run = [&](v4d(&acc)[2][4], int jj, int s0, int s1) {
         for (int s = s0; s < s1; ++s) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) As[sc][sr + q] = av[q];
+            for (int q = 0; q < 8; ++q) As[sc][sv + q] = av[q];
 #pragma unroll
             for (int q = 0; q < 4; ++q) Bs[sc][sb + q] = bv[q];
             __syncthreads();
-            if (s + 1 < nsl) load(s + 1);
+            {
+                const bool last = s + 1 == nsl;
+                if (!last || jj + 1 < jn) load(last ? jj + 1 : jj, last ? 0 : s + 1);
+            }
 #pragma unroll
             for (int kk = 0; kk < SK / 4; ++kk) {
                 const int kr = kk * 4 + (lane >> 4);
                 double a[2], b[4];
 #pragma unroll
-                for (int i = 0; i < 2; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+                for (int i = 0; i < 2; ++i) a[i] = As[kr][wv + i * 16 + (lane & 15)];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) b[t] = Bs[kr][t * 16 + (lane & 15)];
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int t = 0; t < 4; ++t)
+                    if (t < ntc) {
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) acc[i][t] = mfma(a[i], b[t], acc[i][t]);
+                        for (int i = 0; i < 2; ++i) acc[i][t] = mfma(a[i], b[t], acc[i][t]);
+                    }
             }
             __syncthreads();
         }
     };
-    load(0);
-    run(E, 0, MIR ? nse : nsl);
-    if (MIR) run(O, nse, nsl);
-
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int b = b0 + t * 16 + (lane & 15);
-        if (b >= kx) continue;
-        const int2 kk = kxy[b];
+    load(0, 0);
+    for (int jj = 0; jj < jn; ++jj) {
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const size_t row = r0 + wm + i * 16 + (lane >> 4) + 4 * q;
-                if (row >= n_rows) continue;
-                T *o = phi + row * n_phi;
-                const double e = E[i][t][q], d = O[i][t][q];
-                o[kk.x] = (T)(e + d);
-                if (MIR && kk.y >= 0) o[kk.y] = (T)(e - d);
-            }
+            for (int t = 0; t < 4; ++t) E[i][t] = O[i][t] = v4d{0.0, 0.0, 0.0, 0.0};
+        run(E, jj, 0, MIR ? nse : nsl);
+        if (MIR) run(O, jj, nse, nsl);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int b = b0 + t * 16 + (lane & 15);
+            if (t >= ntc || b >= kx) continue;
+            const int2 kk = kxy[b];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int v = v0 + wv + i * 16 + (lane >> 4) + 4 * q;
+                    if (v >= vrows) continue;
+                    T *o = phi + ((size_t)v * n_theta + j0 + jj) * n_phi;
+                    const double e = E[i][t][q], d = O[i][t][q];
+                    o[kk.x] = (T)(e + d);
+                    if (MIR && kk.y >= 0) o[kk.y] = (T)(e - d);
+                }
+        }
     }
 }
 
 template <typename T, bool MIR>
-hipError_t launch_phi1(const Plan &p, dim3 grid, const T *rho, size_t n_rows) {
-    const int nt = p.sep_nc() / 16, ne = p.sep_ce / 16, rpp = p.n_r * p.n_theta;
+hipError_t launch_phi1(const Plan &p, int n_fields, const T *rho) {
+    const int nt = p.sep_nc() / 16, nst = (p.n_r + VB - 1) / VB;
+    if (p.sep_ce / 16 != (nt + 1) / 2) return hipErrorInvalidValue;
     const size_t w_patch = p.npat == 1 ? 0 : (size_t)p.n_ang;
+    const dim3 grid(n_fields * p.n_patches * nst, (p.n_theta + JR1 - 1) / JR1);
+    const size_t lds = sizeof(double) * p.n_phi;
 #define MPG_PHI1(N)                                                                                                 \
     case N:                                                                                                         \
-        hipLaunchKernelGGL((k_sep_phi1<T, MIR, N>), grid, dim3(256), 0, p.stream, rho, p.w, w_patch, p.sep_f1,      \
-                           p.sep_F, p.sep_rows(), n_rows, rpp, p.n_patches, p.n_theta, p.n_phi, p.sep_kh, ne);       \
+        hipLaunchKernelGGL((k_sep_phi1<T, MIR, N, JR1>), grid, dim3(256), lds, p.stream, rho, p.w, w_patch, p.sep_f1,    \
+                           p.sep_F, p.sep_ldv(), p.n_r, p.n_patches, p.n_theta, p.n_phi, p.sep_kh, nst);         \
         break;
     switch (nt) {
         MPG_PHI1(1)
@@ -512,52 +549,55 @@ hipError_t launch_phi1(const Plan &p, dim3 grid, const T *rho, size_t n_rows) {
 }
 
 template <typename T, bool MIR>
-void launch_phi2(const Plan &p, dim3 grid, T *phi, size_t n_rows) {
-    hipLaunchKernelGGL((k_sep_phi2<T, MIR>), grid, dim3(256), 0, p.stream, p.sep_F, p.sep_rows(), p.sep_f2,
-                       p.sep_kxy, phi, n_rows, p.n_phi, p.sep_kx, p.sep_ce, p.sep_co);
+void launch_phi2(const Plan &p, int vrows, T *phi) {
+    const dim3 grid((p.sep_kx + 63) / 64, (vrows + VB - 1) / VB, (p.n_theta + JB - 1) / JB);
+    hipLaunchKernelGGL((k_sep_phi2<T, MIR>), grid, dim3(256), 0, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2,
+                       p.sep_kxy, phi, vrows, p.n_theta, p.n_phi, p.sep_kx, p.sep_ce, p.sep_co);
 }
 
 }  // namespace
 
 hipError_t sep_phi_moments(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
-    const size_t n_rows = (size_t)n_fields * p.n_patches * p.n_r * p.n_theta;
-    if (n_rows > p.sep_rows()) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((n_rows + RB - 1) / RB));
+    if (n_fields > p.max_fields) return hipErrorInvalidValue;
     if (rho_dtype == MPG_F64)
-        return p.sep_mir ? launch_phi1<double, true>(p, grid, (const double *)rho, n_rows)
-                         : launch_phi1<double, false>(p, grid, (const double *)rho, n_rows);
-    return p.sep_mir ? launch_phi1<float, true>(p, grid, (const float *)rho, n_rows)
-                     : launch_phi1<float, false>(p, grid, (const float *)rho, n_rows);
+        return p.sep_mir ? launch_phi1<double, true>(p, n_fields, (const double *)rho)
+                         : launch_phi1<double, false>(p, n_fields, (const double *)rho);
+    return p.sep_mir ? launch_phi1<float, true>(p, n_fields, (const float *)rho)
+                     : launch_phi1<float, false>(p, n_fields, (const float *)rho);
 }
 
 hipError_t sep_theta_moments(const Plan &p, int n_fields) {
     const int vrows = n_fields * p.n_patches * p.n_r, rows = n_fields * p.n_r;
     if (p.sep_lp > 80 || p.lmax > 64) return hipErrorInvalidValue;  // five slot tiles, nine degree tiles
-    hipLaunchKernelGGL(k_sep_theta1, dim3((vrows + TR - 1) / TR, p.sep_nc()), dim3(256), 0, p.stream, p.sep_F,
-                       p.sep_rows(), p.sep_t1, p.sep_m, p.sep_col, p.sep_A, vrows, p.n_theta, p.sep_lp, p.lmax,
-                       p.n_lm);
+    hipLaunchKernelGGL(k_sep_theta1, dim3((vrows + VB - 1) / VB, p.sep_nc()), dim3(256), 0, p.stream, p.sep_F,
+                       p.sep_ldv(), p.sep_t1, p.sep_m, p.sep_coff, p.sep_A, vrows, p.n_theta, p.sep_lp, p.lmax);
     hipLaunchKernelGGL(k_sep_rot<false>, dim3((rows + TR - 1) / TR, p.lmax + 1), dim3(256), 0, p.stream, p.sep_A,
-                       p.sep_x1, p.sep_xoff, p.sep_perm, p.Bpart, rows, p.n_r, p.n_patches, p.n_lm, p.np);
+                       p.sep_x1, p.sep_xoff, p.sep_perm, p.sep_cslot, p.Bpart, rows, p.n_r, p.n_patches,
+                       p.sep_ldv(), p.np);
     return hipGetLastError();
 }
 
-hipError_t sep_expansion(const Plan &p, int n_fields, void *phi, int phi_dtype) {
+hipError_t sep_theta_expansion(const Plan &p, int n_fields) {
     const int vrows = n_fields * p.n_patches * p.n_r, rows = n_fields * p.n_r;
-    const size_t n_rows = (size_t)vrows * p.n_theta;
-    if (n_rows > p.sep_rows() || p.lmax > 64) return hipErrorInvalidValue;
+    if (n_fields > p.max_fields || p.lmax > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sep_rot<true>, dim3((rows + TR - 1) / TR, p.lmax + 1, p.n_patches), dim3(256), 0,
-                       p.stream, p.M, p.sep_x2, p.sep_xoff, p.sep_perm, p.sep_A, rows, p.n_r, p.n_patches, p.n_lm,
-                       p.np);
-    hipLaunchKernelGGL(k_sep_theta2, dim3((vrows + TR - 1) / TR, (p.n_theta + TR - 1) / TR, p.sep_nc()), dim3(256),
-                       0, p.stream, p.sep_A, p.sep_t2, p.sep_m, p.sep_col, p.sep_F, p.sep_rows(), vrows, p.n_theta,
-                       p.sep_lp, p.lmax, p.n_lm);
-    dim3 grid((unsigned)((n_rows + RB - 1) / RB), (p.sep_kx + 63) / 64);
+                       p.stream, p.M, p.sep_x2, p.sep_xoff, p.sep_perm, p.sep_cslot, p.sep_A, rows, p.n_r,
+                       p.n_patches, p.sep_ldv(), p.np);
+    hipLaunchKernelGGL(k_sep_theta2, dim3((vrows + VB - 1) / VB, p.sep_nc(), (p.n_theta + VB - 1) / VB), dim3(256),
+                       0, p.stream, p.sep_A, p.sep_t2, p.sep_m, p.sep_coff, p.sep_F, p.sep_ldv(), vrows, p.n_theta,
+                       p.sep_lp, p.lmax);
+    return hipGetLastError();
+}
+
+hipError_t sep_phi_expansion(const Plan &p, int n_fields, void *phi, int phi_dtype) {
+    const int vrows = n_fields * p.n_patches * p.n_r;
+    if (n_fields > p.max_fields) return hipErrorInvalidValue;
     if (phi_dtype == MPG_F64) {
-        if (p.sep_mir) launch_phi2<double, true>(p, grid, (double *)phi, n_rows);
-        else launch_phi2<double, false>(p, grid, (double *)phi, n_rows);
+        if (p.sep_mir) launch_phi2<double, true>(p, vrows, (double *)phi);
+        else launch_phi2<double, false>(p, vrows, (double *)phi);
     } else {
-        if (p.sep_mir) launch_phi2<float, true>(p, grid, (float *)phi, n_rows);
-        else launch_phi2<float, false>(p, grid, (float *)phi, n_rows);
+        if (p.sep_mir) launch_phi2<float, true>(p, vrows, (float *)phi);
+        else launch_phi2<float, false>(p, vrows, (float *)phi);
     }
     return hipGetLastError();
 }

@@ -673,15 +673,20 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
     if (p.sep) {
         // phi columns: C of u = 0..L (padded to 16), then S of u = 1..L
         const int nc = p.sep_nc(), lp = p.sep_lp, P = p.n_patches, n = p.n_phi;
-        std::vector<int> code(nc, -1), ucol(nc, -1), scol((size_t)nc * lp, -1);
+        std::vector<int> code(nc, -1), ucol(nc, -1), coff(nc, 0), cslot(p.n_lm, -1);
         for (int u = 0; u <= L; ++u)
             for (int cs = 0; cs < (u == 0 ? 1 : 2); ++cs) {
                 const int c = cs ? p.sep_ce + u - 1 : u;
                 code[c] = 2 * u + cs;
                 ucol[c] = u;
-                for (int l = u; l <= L; ++l)
-                    scol[(size_t)c * lp + (l - u)] = cs ? l * l + 2 * u : (u == 0 ? l * l : l * l + 2 * u - 1);
             }
+        // slots: the degrees u..L of every column, column after column
+        for (int c = 0, o = 0; c < nc; ++c) {
+            if (code[c] < 0) continue;
+            const int u = code[c] >> 1, cs = code[c] & 1;
+            coff[c] = o;
+            for (int l = u; l <= L; ++l) cslot[cs ? l * l + 2 * u : (u == 0 ? l * l : l * l + 2 * u - 1)] = o++;
+        }
         // expansion points: cell kx[b].x, and its mirror image kx[b].y (-1: none)
         std::vector<int2> kx(p.sep_kx);
         for (int b = 0; b < p.sep_kx; ++b) {
@@ -696,7 +701,8 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
         STEP(hipMalloc(&d_code, sizeof(int) * nc));
         STEP(hipMalloc(&d_kx, sizeof(int2) * p.sep_kx));
         STEP(hipMalloc(&p.sep_m, sizeof(int) * nc));
-        STEP(hipMalloc(&p.sep_col, sizeof(int) * nc * lp));
+        STEP(hipMalloc(&p.sep_coff, sizeof(int) * nc));
+        STEP(hipMalloc(&p.sep_cslot, sizeof(int) * p.n_lm));
         STEP(hipMalloc(&p.sep_kxy, sizeof(int2) * p.sep_kx));
         STEP(hipMalloc(&p.sep_xoff, sizeof(long long) * (L + 2)));
         STEP(hipMalloc(&p.sep_perm, sizeof(int) * p.n_lm));
@@ -710,7 +716,8 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
         STEP(hipMemcpyAsync(d_kx, kx.data(), sizeof(int2) * p.sep_kx, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(p.sep_kxy, kx.data(), sizeof(int2) * p.sep_kx, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(p.sep_m, ucol.data(), sizeof(int) * nc, hipMemcpyHostToDevice, s));
-        STEP(hipMemcpyAsync(p.sep_col, scol.data(), sizeof(int) * nc * lp, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(p.sep_coff, coff.data(), sizeof(int) * nc, hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(p.sep_cslot, cslot.data(), sizeof(int) * p.n_lm, hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(p.sep_xoff, xoff.data(), sizeof(long long) * (L + 2), hipMemcpyHostToDevice, s));
         STEP(hipMemcpyAsync(p.sep_perm, perm_of.data(), sizeof(int) * p.n_lm, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_sep_f1, dim3(blocks((size_t)p.sep_khp * nc, 128)), dim3(128), 0, s, L, p.sep_kh,

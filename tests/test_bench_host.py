@@ -59,5 +59,21 @@ def test_traffic_is_used_only_for_the_current_kernel_sources(tmp_path, monkeypat
     rec[key]["source_hash"] = "0" * 16
     (fake / "traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "1" * 16)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda source="gemm_bf16.hip": "1" * 16)
     assert bench.traffic_record("moments", "split_bf16_tiered") is None
+    # a record stamped with the current hash of its own kernel file is used
+    rec[key]["source_hash"] = "1" * 16
+    (fake / "traffic.json").write_text(json.dumps(rec))
+    assert bench.traffic_record("moments", "split_bf16_tiered") == rec[key]["bytes_per_launch"]
+
+
+def test_separable_flops_count():
+    """Products of the separable phi transforms on the large workload: rows
+    x (2 lmax + 1) columns x 192 mirror pairs (moments) or 193 points
+    (expansion: 191 mirror pairs, phi = 0 and the last vertex)."""
+    import workloads as W
+    g = W.config5()
+    f = bench.separable_flops(g, 8)
+    rows = 8 * 2 * 1200 * 128
+    assert f["phi_moments"] == 2.0 * rows * 192 * 97
+    assert f["phi_expansion"] == 2.0 * rows * 193 * 97
