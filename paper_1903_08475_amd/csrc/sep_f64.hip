@@ -239,19 +239,32 @@ __global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F
 #pragma unroll
         for (int i = 0; i < 2; ++i) acc[t][i] = v4d{0.0, 0.0, 0.0, 0.0};
     // staging: t1 16 j x 80 slots (entry e = tid + 256q: slot e/16, j e%16);
-    // F 16 j x 128 v (thread: j tid/16, v 8(tid%16)..)
-    const int bj = tid >> 4, bv = (tid & 15) * 8;
-    for (int j0 = 0; j0 < n_theta; j0 += SK) {
+    // F 16 j x 128 v (thread: j tid/16, v tid%16 + 16q); the next slab is
+    // loaded into registers while the current one is multiplied
+    const int bj = tid >> 4, bv = tid & 15;
+    double ra[NTM], rb[8];
+    auto load = [&](int j0) {
 #pragma unroll
         for (int q = 0; q < NTM; ++q) {
-            const int e = tid + 256 * q, sl = e >> 4, jj = e & 15, j = j0 + jj;
-            As[jj][sl] = (sl < nl && j < n_theta) ? tc[(size_t)sl * n_theta + j] : 0.0;
+            const int e = tid + 256 * q, sl = e >> 4, j = j0 + (e & 15);
+            ra[q] = (sl < nl && j < n_theta) ? tc[(size_t)sl * n_theta + j] : 0.0;
         }
         const bool jok = j0 + bj < n_theta;
         const double *fr = Fc + (size_t)(jok ? j0 + bj : 0) * ldv + bv;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) Bs[bj][bv + q] = jok ? fr[q] : 0.0;
+        for (int q = 0; q < 8; ++q) rb[q] = jok ? fr[16 * q] : 0.0;
+    };
+    load(0);
+    for (int j0 = 0; j0 < n_theta; j0 += SK) {
+#pragma unroll
+        for (int q = 0; q < NTM; ++q) {
+            const int e = tid + 256 * q;
+            As[e & 15][e >> 4] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Bs[bj][bv + 16 * q] = rb[q];
         __syncthreads();
+        if (j0 + SK < n_theta) load(j0 + SK);
 #pragma unroll
         for (int kk = 0; kk < SK / 4; ++kk) {
             const int kr = kk * 4 + (lane >> 4);
@@ -306,12 +319,14 @@ __global__ __launch_bounds__(256) void k_sep_rot(const double *__restrict__ src,
 #pragma unroll
     for (int t = 0; t < kMaxTiles; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
     // staging: A 64 rows x 16 (thread: row tid%64, 4 consecutive kk from
-    // 4 (tid/64)); B 16 x 144 (entries tid + 256q)
+    // 4 (tid/64)); B 16 x 144 (entries tid + 256q); the next slab is loaded
+    // into registers while the current one is multiplied
     const int ar = tid & 63, ak = (tid >> 6) * 4;
     const int arow = row0 + ar;
     const bool arow_ok = arow < rows;
     const int af = arow_ok ? arow / n_r : 0, ash = arow_ok ? arow - af * n_r : 0;
-    for (int k0 = 0; k0 < K; k0 += SK) {
+    double ra[4], rb[kMaxTiles];
+    auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int kk = k0 + ak + q;
@@ -324,14 +339,25 @@ __global__ __launch_bounds__(256) void k_sep_rot(const double *__restrict__ src,
                     v = src[(size_t)cslot[l2 + i] * ldv + (size_t)(af * P + gi) * n_r + ash];
                 }
             }
-            As[ak + q][ar] = v;
+            ra[q] = v;
         }
 #pragma unroll
         for (int q = 0; q < kMaxTiles; ++q) {
             const int e = tid + 256 * q, kr = e / NB, o = e - kr * NB, kk = k0 + kr;
-            Bs[kr][o] = (kk < K && o < n) ? xl[(size_t)kk * n + o] : 0.0;
+            rb[q] = (kk < K && o < n) ? xl[(size_t)kk * n + o] : 0.0;
+        }
+    };
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += SK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) As[ak + q][ar] = ra[q];
+#pragma unroll
+        for (int q = 0; q < kMaxTiles; ++q) {
+            const int e = tid + 256 * q, kr = e / NB;
+            Bs[kr][e - kr * NB] = rb[q];
         }
         __syncthreads();
+        if (k0 + SK < K) load(k0 + SK);
 #pragma unroll
         for (int kk = 0; kk < SK / 4; ++kk) {
             const int kr = kk * 4 + (lane >> 4);
@@ -383,19 +409,29 @@ __global__ __launch_bounds__(256) void k_sep_theta2(const double *__restrict__ L
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[i][t] = v4d{0.0, 0.0, 0.0, 0.0};
-    // staging (thread: slot tid/16, 8 consecutive j or v from 8(tid%16))
-    const int ss = tid >> 4, sx = (tid & 15) * 8;
-    for (int s0 = 0; s0 < nl; s0 += SK) {
+    // staging (thread: slot tid/16, theta rows or v tid%16 + 16q); the next
+    // slab is loaded into registers while the current one is multiplied
+    const int ss = tid >> 4, sx = tid & 15;
+    double ra[8], rb[8];
+    auto load = [&](int s0) {
         const bool sok = s0 + ss < nl;
-        const double *tr = tc + (size_t)(sok ? s0 + ss : 0) * n_theta;
+        const double *tr = tc + (size_t)(sok ? s0 + ss : 0) * n_theta + j0 + sx;
         const double *lr = lc + (size_t)(sok ? s0 + ss : 0) * ldv + sx;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int j = j0 + sx + q;
-            As[ss][sx + q] = (sok && j < n_theta) ? tr[j] : 0.0;
-            Bs[ss][sx + q] = sok ? lr[q] : 0.0;
+            ra[q] = (sok && j0 + sx + 16 * q < n_theta) ? tr[16 * q] : 0.0;
+            rb[q] = sok ? lr[16 * q] : 0.0;
+        }
+    };
+    load(0);
+    for (int s0 = 0; s0 < nl; s0 += SK) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            As[ss][sx + 16 * q] = ra[q];
+            Bs[ss][sx + 16 * q] = rb[q];
         }
         __syncthreads();
+        if (s0 + SK < nl) load(s0 + SK);
 #pragma unroll
         for (int kk = 0; kk < SK / 4; ++kk) {
             const int kr = kk * 4 + (lane >> 4);
@@ -424,28 +460,33 @@ __global__ __launch_bounds__(256) void k_sep_theta2(const double *__restrict__ L
 }
 
 // ---------------------------------------------------------------------------
-// Phi transform of the expansion: block (64 evaluation points b from 64 x,
-// 128 rows v from 128 y, JB theta rows from JB z, one after the other; the
-// point tiles of the same rows run next to each other and share G in L2):
+// Phi transform of the expansion: block (64 evaluation points b, 128 rows v,
+// JB theta rows one after the other; the point tiles of the same rows run
+// on one XCD and share G in its L2):
 // E = the sum over the C columns, O over the S columns (with MIR; else all
 // columns go to E); Phi[(v, j)][kxy[b].x] = E + O and, with a mirror cell,
 // Phi[(v, j)][kxy[b].y] = E - O.  K = the phi columns in slabs of 16.  Wave
 // w takes v 32w.. and the block's point tiles (fewer than four in the
-// last).  Thread t stages 8 v of phi column t/16 (from 8(t%16)) and 4
-// points of factor row t/16.
+// last).  Thread t stages v t%16 + 16q (q < 8) of phi column t/16 and
+// points t%16 + 16q (q < 4) of its factor row.
 template <typename T, bool MIR>
 __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ G, int ldv,
                                                      const double *__restrict__ f2, const int2 *__restrict__ kxy,
                                                      T *__restrict__ phi, int vrows, int n_theta, int n_phi, int kx,
-                                                     int ce, int co) {
+                                                     int ce, int co, int nbt, int nvt, int ngroups) {
     __shared__ double As[SK][PA];
     __shared__ double Bs[SK][pitch(64)];
+    // blocks go to the eight XCDs in turn (block id mod 8): the nbt point
+    // tiles of one group of rows take ids 8 apart, so they run on one XCD
+    // and read their group's G through one L2
+    const int id = blockIdx.x, k8 = id >> 3, bt = k8 % nbt, grp = (k8 / nbt) * 8 + (id & 7);
+    if (grp >= ngroups) return;  // the whole block, before any barrier
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int b0 = blockIdx.x * 64, v0 = blockIdx.y * VB, wv = wave * 32;
-    const int j0 = blockIdx.z * JB, jn = min(JB, n_theta - j0);
+    const int b0 = bt * 64, v0 = (grp % nvt) * VB, wv = wave * 32;
+    const int j0 = (grp / nvt) * JB, jn = min(JB, n_theta - j0);
     const int ntc = min(4, (kx - b0 + 15) / 16);  // point tiles of this block
-    const int sc = tid >> 4, sv = (tid & 15) * 8, sb = (tid & 15) * 4;
+    const int sc = tid >> 4, sx = tid & 15;
 
     v4d E[2][4], O[2][4];
     const int nsl = (ce + co) / SK, nse = ce / SK;
@@ -453,21 +494,21 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ 
     // slab s of theta row j0 + jj into registers (v past the last row lie
     // in the zeroed padding of G and feed only rows that are not stored)
     auto load = [&](int jj, int s) {
-        const double *g = G + ((size_t)(s * SK + sc) * n_theta + j0 + jj) * ldv + v0 + sv;
+        const double *g = G + ((size_t)(s * SK + sc) * n_theta + j0 + jj) * ldv + v0 + sx;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) av[q] = g[q];
-        const double *f = f2 + (size_t)(s * SK + sc) * kx;
+        for (int q = 0; q < 8; ++q) av[q] = g[16 * q];
+        const double *f = f2 + (size_t)(s * SK + sc) * kx + b0 + sx;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bv[q] = b0 + sb + q < kx ? f[b0 + sb + q] : 0.0;
+        for (int q = 0; q < 4; ++q) bv[q] = b0 + sx + 16 * q < kx ? f[16 * q] : 0.0;
     };
     // slabs [s0, s1) of theta row j0 + jj into acc; the first slab's
     // operands are in registers, and the last prefetches the next row's first
     auto run = [&](v4d(&acc)[2][4], int jj, int s0, int s1) {
         for (int s = s0; s < s1; ++s) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) As[sc][sv + q] = av[q];
+            for (int q = 0; q < 8; ++q) As[sc][sx + 16 * q] = av[q];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Bs[sc][sb + q] = bv[q];
+            for (int q = 0; q < 4; ++q) Bs[sc][sx + 16 * q] = bv[q];
             __syncthreads();
             {
                 const bool last = s + 1 == nsl;
@@ -550,9 +591,11 @@ hipError_t launch_phi1(const Plan &p, int n_fields, const T *rho) {
 
 template <typename T, bool MIR>
 void launch_phi2(const Plan &p, int vrows, T *phi) {
-    const dim3 grid((p.sep_kx + 63) / 64, (vrows + VB - 1) / VB, (p.n_theta + JB - 1) / JB);
+    // groups of rows = (128 v, JB theta rows); nbt point tiles per group
+    const int nbt = (p.sep_kx + 63) / 64, nvt = (vrows + VB - 1) / VB, ng = nvt * ((p.n_theta + JB - 1) / JB);
+    const dim3 grid((unsigned)((ng + 7) / 8 * 8 * nbt));
     hipLaunchKernelGGL((k_sep_phi2<T, MIR>), grid, dim3(256), 0, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2,
-                       p.sep_kxy, phi, vrows, p.n_theta, p.n_phi, p.sep_kx, p.sep_ce, p.sep_co);
+                       p.sep_kxy, phi, vrows, p.n_theta, p.n_phi, p.sep_kx, p.sep_ce, p.sep_co, nbt, nvt, ng);
 }
 
 }  // namespace
