@@ -281,11 +281,12 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
     p->np_alloc = p->np + kColSlack;
     p->n_angp = roundup(p->n_ang, kAngPad);
     if (p->sep) {
-        // phi columns: C of every order, S of every order above 0; the
-        // mirror fold on a phi grid symmetric about 0 with an even cell count
+        // phi columns: the order-0 column, then C and S of the orders 1..lmax
+        // in tiles of 16 (at least one each); the mirror fold on a phi grid
+        // symmetric about 0 with an even cell count
         const int n = p->n_phi;
-        p->sep_ce = roundup(lmax + 1, 16);
-        p->sep_co = roundup(lmax, 16);
+        p->sep_ce = std::max(16, roundup(lmax, 16));
+        p->sep_co = p->sep_ce;
         p->sep_lp = roundup(lmax + 1, 16);
         p->sep_mir = n % 2 == 0 && fabs(p->phi0 + 0.5 * n * p->dphi) <= 1e-12;
         p->sep_kh = p->sep_mir ? n / 2 : n;

@@ -113,12 +113,13 @@ struct Plan {
     // over (theta, phi), so each contraction runs as a phi transform of
     // every (field, patch, shell, theta row) row, a theta contraction per
     // order u, and a rotation to or from the common frame per degree.  Phi
-    // columns c: C of u = 0..lmax (padded to 16), then S of u = 1..lmax
-    // (padded to 16).  On a phi grid symmetric about 0 with an even cell
+    // columns c: 0 is the order-0 column (constant factors: summed outside
+    // the MFMA tiles), then C of u = 1..lmax and S of u = 1..lmax, each
+    // padded to 16.  On a phi grid symmetric about 0 with an even cell
     // count (sep_mir) cells k and n_phi-1-k are taken together: the C
     // columns see their sum, the S columns their difference.
     bool sep = false, sep_mir = false;
-    int sep_ce = 0, sep_co = 0;  // C / S phi columns (multiples of 16)
+    int sep_ce = 0, sep_co = 0;  // C / S phi columns of orders >= 1 (multiples of 16)
     int sep_lp = 0;              // degree slots per phi column (lmax + 1 rounded up to 16)
     int sep_kh = 0, sep_khp = 0; // cells of a row the moments' transform walks (n_phi/2 mirrored), padded to 16
     int sep_kx = 0;              // evaluation points of a row the expansion's transform computes
@@ -136,7 +137,7 @@ struct Plan {
     double *sep_x2 = nullptr;    // rotations common frame -> local (expansion)
     double *sep_A = nullptr;     // [n_lm][sep_ldv()] local moments / local expansion coefficients (by slot)
     double *sep_F = nullptr;     // [nc][n_theta][sep_ldv()] phi transforms (moments, then expansion)
-    int sep_nc() const { return sep_ce + sep_co; }
+    int sep_nc() const { return 1 + sep_ce + sep_co; }
     // (field, patch, shell) rows v, and their count padded to 128
     int sep_vrows() const { return max_fields * n_patches * n_r; }
     int sep_ldv() const { return (sep_vrows() + 127) / 128 * 128; }

@@ -65,12 +65,13 @@ __host__ __device__ constexpr int pitch(int n) { return (n / 16) % 2 ? n : n + 1
 
 // Phi transform of the moments.  Block: 128 rows v of one (field, patch)
 // group at JR consecutive theta rows j, one after the other; output
-// F[c][j][v] = sum_k w_jk rho_(v,j),k f1[k][c] for all NT column tiles of 16
-// (the first NE = (NT + 1)/2 the C columns), as the product f1^T (columns as rows) times
+// F[c][j][v] = sum_k w_jk rho_(v,j),k f1[k][c] for the order-0 column (a
+// row sum) and all NT column tiles of 16 after it (the first NE = NT/2 the
+// C columns), as the product f1^T (columns as rows) times
 // the folded density slab (rows v as columns), so that a store writes 16
 // consecutive v.  K = the kh cells in slabs of 16.  The weight row of the
 // current j sits in LDS.  Thread t stages 8 consecutive cells of row t/2
-// (from (t%2)*8), with MIR also their 8 mirror cells, and NT entries of the
+// (from 8 (t%2)), with MIR also their 8 mirror cells, and NT entries of the
 // factor slab; the next slab (the next theta row's first after a row's
 // last) is loaded into registers while the current one is multiplied.
 template <typename T>
@@ -114,8 +115,10 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, 
                                                      size_t w_patch, const double *__restrict__ f1,
                                                      double *__restrict__ F, int ldv, int n_r, int n_patches,
                                                      int n_theta, int n_phi, int kh, int nst) {
-    // C column tiles: lmax + 1 and lmax columns round up to NE and NT - NE tiles
-    constexpr int NC = NT * 16, PB = pitch(NC), NE = (NT + 1) / 2;
+    // column tiles: C then S of the orders 1..lmax, NE = NT/2 of each; the
+    // order-0 column (factor C_k^0 = dphi for every cell) is a weighted row
+    // sum, formed while staging
+    constexpr int NC = NT * 16, PB = pitch(NC), NE = NT / 2;
     extern __shared__ double sW[];  // the weight row w_j. of the block's patch
     __shared__ double Ae[SK][PA];
     __shared__ double Ao[MIR ? SK : 1][MIR ? PA : 1];
@@ -143,13 +146,15 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, 
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const int e = tid + 256 * q;
-            bv[q] = f1[(size_t)(s * SK + e / NC) * NC + e % NC];
+            bv[q] = f1[(size_t)(s * SK + e / NC) * (NC + 1) + 1 + e % NC];
         }
     };
     load(0, 0);
     const int wv = wave * 32;
+    const double c0 = f1[0];  // C_k^0, the same for every cell
     for (int jj = 0; jj < jn; ++jj) {
         const int j = j0 + jj;
+        double sum0 = 0.0;  // this thread's cells of the order-0 sum
         // the weight row of theta row j (the previous row's slabs are done)
         for (int k = tid; k < n_phi; k += 256) sW[k] = wp[(size_t)j * n_phi + k];
 #pragma unroll
@@ -167,6 +172,7 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, 
                 const double b = (MIR && in) ? sW[n_phi - 1 - k - q] * (double)stg.b[q] : 0.0;
                 Ae[sk + q][sr] = a + b;
                 if (MIR) Ao[sk + q][sr] = a - b;
+                sum0 += a + b;
             }
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
@@ -197,14 +203,17 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, 
             }
             __syncthreads();
         }
-        // register q of lane l: column c = 16t + l/16 + 4q, row v = wv + 16i + l%16
+        // the order-0 column: the row's two staging threads are lanes 2i, 2i+1
+        sum0 += __shfl_xor(sum0, 1);
+        if (sk == 0 && row_ok) F[(size_t)j * ldv + v0 + sr] = c0 * sum0;
+        // register q of lane l: column c = 1 + 16t + l/16 + 4q, row v = wv + 16i + l%16
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int c = t * 16 + (lane >> 4) + 4 * q, vv = wv + i * 16 + (lane & 15);
+                    const int c = 1 + t * 16 + (lane >> 4) + 4 * q, vv = wv + i * 16 + (lane & 15);
                     if (vv < nv) F[((size_t)c * n_theta + j) * ldv + v0 + vv] = acc[t][i][q];
                 }
     }
@@ -222,7 +231,9 @@ __global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F
                                                     const int *__restrict__ coff, double *__restrict__ A, int vrows,
                                                     int n_theta, int lp, int L) {
     constexpr int NTM = 5;
-    __shared__ double As[SK][pitch(NTM * 16)];
+    // t1 slab slot-major ([slot][j], odd pitch: its staging writes and the
+    // fragment reads of 16 slots x 4 j both spread over the banks)
+    __shared__ double As[NTM * 16][SK + 1];
     __shared__ double Bs[SK][PA];
     const int c = blockIdx.y, u = sep_u[c];
     if (u < 0) return;  // padding column (the whole block)
@@ -259,7 +270,7 @@ __global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F
 #pragma unroll
         for (int q = 0; q < NTM; ++q) {
             const int e = tid + 256 * q;
-            As[e & 15][e >> 4] = ra[q];
+            As[e >> 4][e & 15] = ra[q];
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) Bs[bj][bv + 16 * q] = rb[q];
@@ -274,7 +285,7 @@ __global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F
 #pragma unroll
             for (int t = 0; t < NTM; ++t)
                 if (t < ntl) {
-                    const double a = As[kr][t * 16 + (lane & 15)];
+                    const double a = As[t * 16 + (lane & 15)][kr];
 #pragma unroll
                     for (int i = 0; i < 2; ++i) acc[t][i] = mfma(a, b[i], acc[t][i]);
                 }
@@ -462,13 +473,13 @@ __global__ __launch_bounds__(256) void k_sep_theta2(const double *__restrict__ L
 // ---------------------------------------------------------------------------
 // Phi transform of the expansion: block (64 evaluation points b, 128 rows v,
 // JB theta rows one after the other; the point tiles of the same rows run
-// on one XCD and share G in its L2):
-// E = the sum over the C columns, O over the S columns (with MIR; else all
-// columns go to E); Phi[(v, j)][kxy[b].x] = E + O and, with a mirror cell,
-// Phi[(v, j)][kxy[b].y] = E - O.  K = the phi columns in slabs of 16.  Wave
-// w takes v 32w.. and the block's point tiles (fewer than four in the
-// last).  Thread t stages v t%16 + 16q (q < 8) of phi column t/16 and
-// points t%16 + 16q (q < 4) of its factor row.
+// on one XCD and share G in its L2): E = the sum over the order-0 and C
+// columns, O over the S columns (with MIR; else all columns go to E);
+// Phi[(v, j)][kxy[b].x] = E + O and, with a mirror cell, Phi[(v, j)][kxy[b].y]
+// = E - O.  K = the phi columns in slabs of 16.  Wave w takes v 32w.. and
+// the block's point tiles (fewer than four in the last).  Thread t stages v
+// t%16 + 16q (q < 8) of phi column t/16 and points t%16 + 16q (q < 4) of
+// its factor row.
 template <typename T, bool MIR>
 __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ G, int ldv,
                                                      const double *__restrict__ f2, const int2 *__restrict__ kxy,
@@ -489,17 +500,23 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ 
     const int sc = tid >> 4, sx = tid & 15;
 
     v4d E[2][4], O[2][4];
-    const int nsl = (ce + co) / SK, nse = ce / SK;
+    // E slabs: the order-0 and C columns [0, 1 + ce), zero past them in the
+    // last; O slabs: the S columns [1 + ce, nc).  Without MIR every column
+    // goes to E.
+    const int nc = 1 + ce + co;
+    const int nse = MIR ? (1 + ce + SK - 1) / SK : (nc + SK - 1) / SK, nsl = MIR ? nse + co / SK : nse;
     double av[8], bv[4];
     // slab s of theta row j0 + jj into registers (v past the last row lie
     // in the zeroed padding of G and feed only rows that are not stored)
     auto load = [&](int jj, int s) {
-        const double *g = G + ((size_t)(s * SK + sc) * n_theta + j0 + jj) * ldv + v0 + sx;
+        const int c = s < nse ? s * SK + sc : 1 + ce + (s - nse) * SK + sc;
+        const bool ok = c < (s < nse ? (MIR ? 1 + ce : nc) : nc);
+        const double *g = G + ((size_t)(ok ? c : 0) * n_theta + j0 + jj) * ldv + v0 + sx;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) av[q] = g[16 * q];
-        const double *f = f2 + (size_t)(s * SK + sc) * kx + b0 + sx;
+        for (int q = 0; q < 8; ++q) av[q] = ok ? g[16 * q] : 0.0;
+        const double *f = f2 + (size_t)(ok ? c : 0) * kx + b0 + sx;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bv[q] = b0 + sx + 16 * q < kx ? f[16 * q] : 0.0;
+        for (int q = 0; q < 4; ++q) bv[q] = (ok && b0 + sx + 16 * q < kx) ? f[16 * q] : 0.0;
     };
     // slabs [s0, s1) of theta row j0 + jj into acc; the first slab's
     // operands are in registers, and the last prefetches the next row's first
@@ -562,8 +579,8 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ 
 
 template <typename T, bool MIR>
 hipError_t launch_phi1(const Plan &p, int n_fields, const T *rho) {
-    const int nt = p.sep_nc() / 16, nst = (p.n_r + VB - 1) / VB;
-    if (p.sep_ce / 16 != (nt + 1) / 2) return hipErrorInvalidValue;
+    const int nt = (p.sep_nc() - 1) / 16, nst = (p.n_r + VB - 1) / VB;
+    if (p.sep_ce != p.sep_co || p.sep_ce / 16 != nt / 2) return hipErrorInvalidValue;
     const size_t w_patch = p.npat == 1 ? 0 : (size_t)p.n_ang;
     const dim3 grid(n_fields * p.n_patches * nst, (p.n_theta + JR1 - 1) / JR1);
     const size_t lds = sizeof(double) * p.n_phi;
@@ -573,15 +590,10 @@ hipError_t launch_phi1(const Plan &p, int n_fields, const T *rho) {
                            p.sep_F, p.sep_ldv(), p.n_r, p.n_patches, p.n_theta, p.n_phi, p.sep_kh, nst);         \
         break;
     switch (nt) {
-        MPG_PHI1(1)
         MPG_PHI1(2)
-        MPG_PHI1(3)
         MPG_PHI1(4)
-        MPG_PHI1(5)
         MPG_PHI1(6)
-        MPG_PHI1(7)
         MPG_PHI1(8)
-        MPG_PHI1(9)
     default:
         return hipErrorInvalidValue;
     }

@@ -468,8 +468,8 @@ __global__ void k_export(const double *Ut, const double *Qt, int np, int n_angp,
 // a_ci^lm, a_si^lm): the local moments are A^(lu) = sum_jk w_jk rho_jk
 // s_lu T_j^{lu} {C_k^u, S_k^u}, and the rotation sums of Eqs. U_C/U_S take
 // them to the common frame degree by degree.  A phi column c has
-// code[c] = 2 u + (0 for C, 1 for S), -1 on padding: the C columns of
-// u = 0..lmax first, then the S columns of u = 1..lmax.
+// code[c] = 2 u + (0 for C, 1 for S), -1 on padding: the order-0 column,
+// the C columns of u = 1..lmax, then the S columns of u = 1..lmax.
 
 // f1[k][c] = C_k^u or S_k^u for the first kh cells (zero past them)
 __global__ void k_sep_f1(int L, int kh, int khp, int nc, const int *code, const double *CS, double *f1) {
@@ -671,12 +671,12 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
     STEP(hipGetLastError());
 
     if (p.sep) {
-        // phi columns: C of u = 0..L (padded to 16), then S of u = 1..L
+        // phi columns: order 0, then C of u = 1..L (padded to 16), then S
         const int nc = p.sep_nc(), lp = p.sep_lp, P = p.n_patches, n = p.n_phi;
         std::vector<int> code(nc, -1), ucol(nc, -1), coff(nc, 0), cslot(p.n_lm, -1);
         for (int u = 0; u <= L; ++u)
             for (int cs = 0; cs < (u == 0 ? 1 : 2); ++cs) {
-                const int c = cs ? p.sep_ce + u - 1 : u;
+                const int c = cs ? 1 + p.sep_ce + u - 1 : u;
                 code[c] = 2 * u + cs;
                 ucol[c] = u;
             }
