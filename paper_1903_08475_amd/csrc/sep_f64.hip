@@ -473,20 +473,31 @@ __global__ __launch_bounds__(256) void k_sep_theta2(const double *__restrict__ L
 // ---------------------------------------------------------------------------
 // Phi transform of the expansion: block (64 evaluation points b, 128 rows v,
 // JB theta rows one after the other; the point tiles of the same rows run
-// on one XCD and share G in its L2): E = the sum over the order-0 and C
-// columns, O over the S columns (with MIR; else all columns go to E);
+// on one XCD and share G in its L2): E = the sum over the C columns plus
+// the order-0 column's value (staged in LDS; its factor is cos 0 = 1), O
+// the sum over the S columns (with MIR; else all columns go to E);
 // Phi[(v, j)][kxy[b].x] = E + O and, with a mirror cell, Phi[(v, j)][kxy[b].y]
 // = E - O.  K = the phi columns in slabs of 16.  Wave w takes v 32w.. and
-// the block's point tiles (fewer than four in the last).  Thread t stages v
-// t%16 + 16q (q < 8) of phi column t/16 and points t%16 + 16q (q < 4) of
-// its factor row.
+// the block's point tiles (fewer than four in the last), and writes its
+// outputs 16 rows at a time through LDS so that each store instruction
+// covers one row's 64 consecutive points.  Thread t stages v t%16 + 16q
+// (q < 8) of phi column t/16 and points t%16 + 16q (q < 4) of its factor
+// row.
 template <typename T, bool MIR>
 __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ G, int ldv,
                                                      const double *__restrict__ f2, const int2 *__restrict__ kxy,
                                                      T *__restrict__ phi, int vrows, int n_theta, int n_phi, int kx,
                                                      int ce, int co, int nbt, int nvt, int ngroups) {
-    __shared__ double As[SK][PA];
-    __shared__ double Bs[SK][pitch(64)];
+    // the slab staging, or (after a theta row's last slab) each wave's 16
+    // x 128 tile of outputs on its way to global memory
+    constexpr int PO = 144;  // output tile pitch (elements of T): 16 rows x 16 points spread over the banks
+    constexpr int STG = SK * PA + SK * pitch(64), OUT = 4 * 16 * PO * (int)sizeof(T) / 8;
+    __shared__ double lds[STG > OUT ? STG : OUT];
+    double(*As)[PA] = reinterpret_cast<double(*)[PA]>(lds);
+    double(*Bs)[pitch(64)] = reinterpret_cast<double(*)[pitch(64)]>(lds + SK * PA);
+    // the order-0 column at the current theta row (MIR), by row parity: a
+    // row's epilogue reads it while faster waves may already stage the next
+    __shared__ double sG0[2][VB];
     // blocks go to the eight XCDs in turn (block id mod 8): the nbt point
     // tiles of one group of rows take ids 8 apart, so they run on one XCD
     // and read their group's G through one L2
@@ -498,19 +509,22 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ 
     const int j0 = (grp / nvt) * JB, jn = min(JB, n_theta - j0);
     const int ntc = min(4, (kx - b0 + 15) / 16);  // point tiles of this block
     const int sc = tid >> 4, sx = tid & 15;
+    const int2 kk = b0 + lane < kx ? kxy[b0 + lane] : make_int2(0, -1);  // this lane's output point
 
     v4d E[2][4], O[2][4];
-    // E slabs: the order-0 and C columns [0, 1 + ce), zero past them in the
-    // last; O slabs: the S columns [1 + ce, nc).  Without MIR every column
-    // goes to E.
+    // With MIR: E slabs the C columns [1, 1 + ce), O slabs the S columns
+    // [1 + ce, nc), and the order-0 column (factor cos 0 = 1 at every
+    // point) added to E from LDS.  Without MIR all columns [0, nc) go to
+    // E, zero past them in the last slab.
     const int nc = 1 + ce + co;
-    const int nse = MIR ? (1 + ce + SK - 1) / SK : (nc + SK - 1) / SK, nsl = MIR ? nse + co / SK : nse;
-    double av[8], bv[4];
+    const int nse = MIR ? ce / SK : (nc + SK - 1) / SK, nsl = MIR ? nse + co / SK : nse;
+    double av[8], bv[4], g0r = 0.0;
     // slab s of theta row j0 + jj into registers (v past the last row lie
     // in the zeroed padding of G and feed only rows that are not stored)
     auto load = [&](int jj, int s) {
-        const int c = s < nse ? s * SK + sc : 1 + ce + (s - nse) * SK + sc;
-        const bool ok = c < (s < nse ? (MIR ? 1 + ce : nc) : nc);
+        if (MIR && s == 0 && tid < VB) g0r = G[(size_t)(j0 + jj) * ldv + v0 + tid];  // padded rows are zero
+        const int c = (MIR ? 1 : 0) + s * SK + sc;
+        const bool ok = c < nc;
         const double *g = G + ((size_t)(ok ? c : 0) * n_theta + j0 + jj) * ldv + v0 + sx;
 #pragma unroll
         for (int q = 0; q < 8; ++q) av[q] = ok ? g[16 * q] : 0.0;
@@ -522,6 +536,7 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ 
     // operands are in registers, and the last prefetches the next row's first
     auto run = [&](v4d(&acc)[2][4], int jj, int s0, int s1) {
         for (int s = s0; s < s1; ++s) {
+            if (MIR && s == 0 && tid < VB) sG0[jj & 1][tid] = g0r;
 #pragma unroll
             for (int q = 0; q < 8; ++q) As[sc][sx + 16 * q] = av[q];
 #pragma unroll
@@ -557,22 +572,36 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ 
             for (int t = 0; t < 4; ++t) E[i][t] = O[i][t] = v4d{0.0, 0.0, 0.0, 0.0};
         run(E, jj, 0, MIR ? nse : nsl);
         if (MIR) run(O, jj, nse, nsl);
+        // outputs through LDS: each lane puts its values at (row, point) of
+        // the wave's tile, then a store instruction writes one row's 64
+        // points (and their mirror points), consecutive in memory
+        T(*ot)[PO] = reinterpret_cast<T(*)[PO]>(lds) + wave * 16;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int b = b0 + t * 16 + (lane & 15);
-            if (t >= ntc || b >= kx) continue;
-            const int2 kk = kxy[b];
+        for (int i = 0; i < 2; ++i) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int t = 0; t < 4; ++t) {
+                const int bl = t * 16 + (lane & 15);
+                const double f0 = MIR ? f2[min(b0 + bl, kx - 1)] : 0.0;  // the order-0 factor
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int v = v0 + wv + i * 16 + (lane >> 4) + 4 * q;
-                    if (v >= vrows) continue;
-                    T *o = phi + ((size_t)v * n_theta + j0 + jj) * n_phi;
-                    const double e = E[i][t][q], d = O[i][t][q];
-                    o[kk.x] = (T)(e + d);
-                    if (MIR && kk.y >= 0) o[kk.y] = (T)(e - d);
+                    const int r = (lane >> 4) + 4 * q;
+                    const double e = E[i][t][q] + (MIR ? f0 * sG0[jj & 1][wv + i * 16 + r] : 0.0), d = O[i][t][q];
+                    ot[r][bl] = (T)(e + d);
+                    if (MIR) ot[r][64 + bl] = (T)(e - d);
                 }
+            }
+            __syncthreads();
+            if (b0 + lane < kx) {
+#pragma unroll 4
+                for (int r = 0; r < 16; ++r) {
+                    const int v = v0 + wv + i * 16 + r;
+                    if (v >= vrows) break;
+                    T *o = phi + ((size_t)v * n_theta + j0 + jj) * n_phi;
+                    o[kk.x] = ot[r][lane];
+                    if (MIR && kk.y >= 0) o[kk.y] = ot[r][64 + lane];
+                }
+            }
+            __syncthreads();  // the tile area is the next round's, then the next row's staging
         }
     }
 }
