@@ -72,8 +72,8 @@ __host__ __device__ constexpr int pitch(int n) { return (n / 16) % 2 ? n : n + 1
 // consecutive v.  K = the kh cells in slabs of 16.  The weight row of the
 // current j sits in LDS.  Thread t stages 8 consecutive cells of row t/2
 // (from 8 (t%2)), with MIR also their 8 mirror cells, and NT entries of the
-// factor slab; the next slab (the next theta row's first after a row's
-// last) is loaded into registers while the current one is multiplied.
+// factor slab, into one of two register sets: each slab is loaded two slabs
+// ahead of its use (one with eight column tiles, whose registers are full).
 template <typename T>
 struct PhiStage {
     T a[8], b[8];
@@ -138,18 +138,32 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, 
 
     v4d acc[NT][2];
     const int nsl = (kh + SK - 1) / SK;
-    PhiStage<T> stg;
-    double bv[NT];
-    // slab s of theta row j0 + jj into registers
-    auto load = [&](int jj, int s) {
-        load_phi<T, MIR>(stg, prow0 + (size_t)jj * n_phi, s * SK + sk, n_phi, kh, row_ok);
+    // NR register sets: slab s is loaded NR slabs ahead of its use (two for
+    // up to six column tiles; the eight-tile variants have no room)
+    constexpr int NR = NT <= 6 ? 2 : 1;
+    PhiStage<T> stg[NR];
+    double bv[NR][NT];
+    // slab s of theta row j0 + jj into register set r
+    auto load = [&](int r, int jj, int s) {
+        load_phi<T, MIR>(stg[r], prow0 + (size_t)jj * n_phi, s * SK + sk, n_phi, kh, row_ok);
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const int e = tid + 256 * q;
-            bv[q] = f1[(size_t)(s * SK + e / NC) * (NC + 1) + 1 + e % NC];
+            bv[r][q] = f1[(size_t)(s * SK + e / NC) * (NC + 1) + 1 + e % NC];
         }
     };
-    load(0, 0);
+    // after slab s of row jj is staged from set r: the slab NR ahead (in the
+    // next row past this row's last) into set r
+    auto load_ahead = [&](int r, int jj, int s) {
+        const int t = s + NR;
+        if (t < nsl) load(r, jj, t);
+        else if (jj + 1 < jn && t - nsl < nsl) load(r, jj + 1, t - nsl);
+    };
+    load(0, 0, 0);
+    if (NR == 2) {
+        if (nsl > 1) load(NR - 1, 0, 1);
+        else if (jn > 1) load(NR - 1, 1, 0);
+    }
     const int wv = wave * 32;
     const double c0 = f1[0];  // C_k^0, the same for every cell
     for (int jj = 0; jj < jn; ++jj) {
@@ -162,14 +176,15 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, 
 #pragma unroll
             for (int i = 0; i < 2; ++i) acc[t][i] = v4d{0.0, 0.0, 0.0, 0.0};
         __syncthreads();
-        for (int s = 0; s < nsl; ++s) {
+        // slab s of this row uses register set (jj * nsl + s) % NR
+        auto step = [&](const int r, int s) {
             // stage slab s (weights of cells past kh multiply zeros)
             const int k = s * SK + sk;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const bool in = k + q < kh;
-                const double a = (in ? sW[k + q] : 0.0) * (double)stg.a[q];
-                const double b = (MIR && in) ? sW[n_phi - 1 - k - q] * (double)stg.b[q] : 0.0;
+                const double a = (in ? sW[k + q] : 0.0) * (double)stg[r].a[q];
+                const double b = (MIR && in) ? sW[n_phi - 1 - k - q] * (double)stg[r].b[q] : 0.0;
                 Ae[sk + q][sr] = a + b;
                 if (MIR) Ao[sk + q][sr] = a - b;
                 sum0 += a + b;
@@ -177,14 +192,10 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, 
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
                 const int e = tid + 256 * q;
-                Bs[e / NC][e % NC] = bv[q];
+                Bs[e / NC][e % NC] = bv[r][q];
             }
             __syncthreads();
-            // the next slab, of this theta row or the first of the next
-            {
-                const bool last = s + 1 == nsl;
-                if (!last || jj + 1 < jn) load(last ? jj + 1 : jj, last ? 0 : s + 1);
-            }
+            load_ahead(r, jj, s);
 #pragma unroll
             for (int kk = 0; kk < SK / 4; ++kk) {
                 const int kr = kk * 4 + (lane >> 4);
@@ -202,6 +213,25 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, 
                 }
             }
             __syncthreads();
+        };
+        if (NR == 1) {
+            for (int s = 0; s < nsl; ++s) step(0, s);
+        } else {
+            const int r0 = (jj * nsl) & 1;
+            int s = 0;
+            for (; s + 1 < nsl; s += 2) {
+                if (r0 == 0) {
+                    step(0, s);
+                    step(NR - 1, s + 1);
+                } else {
+                    step(NR - 1, s);
+                    step(0, s + 1);
+                }
+            }
+            if (s < nsl) {
+                if (r0 == 0) step(0, s);
+                else step(NR - 1, s);
+            }
         }
         // the order-0 column: the row's two staging threads are lanes 2i, 2i+1
         sum0 += __shfl_xor(sum0, 1);
@@ -305,7 +335,7 @@ __global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F
 }
 
 // ---------------------------------------------------------------------------
-// Rotations of degree l (blockIdx.y), 64 rows of (field, shell) per block.
+// Rotations of degree l (lmax - blockIdx.y), 64 rows of (field, shell) per block.
 //   EXP = false (moments): B[row][perm[l^2 + o]] = sum over kk = (patch g,
 //     position i) of A[cslot[l^2 + i]][(f, g, shell)] x1[l][kk][o];  K = P (2l+1)
 //   EXP = true (expansion, patch g = blockIdx.z):
@@ -319,7 +349,8 @@ __global__ __launch_bounds__(256) void k_sep_rot(const double *__restrict__ src,
     constexpr int NB = kMaxTiles * 16;
     __shared__ double As[SK][pitch(TR)];
     __shared__ double Bs[SK][pitch(NB)];
-    const int l = blockIdx.y, n = 2 * l + 1, nto = (n + 15) / 16, g = EXP ? blockIdx.z : 0;
+    // the costliest degrees first (a block's work grows as (2l + 1)^2)
+    const int l = gridDim.y - 1 - blockIdx.y, n = 2 * l + 1, nto = (n + 15) / 16, g = EXP ? blockIdx.z : 0;
     const int K = EXP ? n : P * n, l2 = l * l;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
