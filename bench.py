@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid cells·(l,m) terms/s per solve, split-BF16 vs FP64 at ≤1e-6 rel err"
 PEAK_BF16 = 2.5e15     # dense bf16 MFMA, FLOP/s
 PEAK_FP64 = 78.6e12    # FP64 MFMA, FLOP/s
+PEAK_HBM = 8.0e12      # HBM3E, bytes/s
 HBM_PEAK = 8.0e12      # B/s
 
 
@@ -222,21 +223,35 @@ def separable_flops(grid, n_fields):
     return {"phi_moments": 2.0 * rows * cells * cols, "phi_expansion": 2.0 * rows * points * cols}
 
 
+def separable_bytes(grid, n_fields):
+    """Algorithmic HBM bytes of one launch of each phi transform: the FP32
+    field once (4 bytes per cell) and the FP64 phi transforms once (2 lmax
+    + 1 columns per row)."""
+    rows = n_fields * grid.n_patches * grid.n_r * grid.n_theta
+    field = 4.0 * rows * grid.n_phi
+    transforms = 8.0 * rows * (2 * grid.lmax + 1)
+    return {"phi_moments": field + transforms, "phi_expansion": field + transforms}
+
+
 SEP_STAGES = {"input_split": "phi_moments", "moments": "theta_and_rotations", "radial_scan": "radial_scan",
               "expansion": "phi_expansion"}
 SEP_KERNELS = {"phi_moments": "k_sep_phi1 (moments' phi transform, FP64 MFMA)",
                "phi_expansion": "k_sep_phi2 (expansion's phi transform, FP64 MFMA)"}
+SEP_KERNELS_SPLIT = {"phi_moments": "k_sep_phi1s (moments' phi transform, split-BF16 MFMA)",
+                     "phi_expansion": "k_sep_phi2s (expansion's phi transform, split-BF16 MFMA)"}
 
 
-def separable_workload(grid, rho, steps, warmup, ref=None):
-    """The separable method (FP64) on the large workload: ms per solve,
-    per-stage times (the theta contractions and rotations launch twice per
-    solve), the roofline of its dominant kernel (the costlier phi
-    transform) and its difference from a reference potential when given."""
+def separable_workload(grid, rho, steps, warmup, ref=None, precision="fp64"):
+    """The separable method (FP64, or its split form: the phi transforms in
+    six bf16 piece products with FP32 accumulation) on the large workload:
+    ms per solve, per-stage times (the theta contractions and rotations
+    launch twice per solve), the roofline of its dominant kernel (the
+    costlier phi transform) and its difference from a reference potential
+    when given."""
     import torch
     import paper_1903_08475_amd as mpg
     n = rho.shape[0]
-    plan = mpg.Plan(grid, precision="fp64", max_fields=n, method="separable")
+    plan = mpg.Plan(grid, precision=precision, max_fields=n, method="separable")
     phi = torch.empty_like(rho)
     ms, _, st, pct = time_path(plan, rho, phi, steps, warmup)
     per = {SEP_STAGES[k]: v[0] / max(1, v[1]) for k, v in st.items()}
@@ -244,14 +259,29 @@ def separable_workload(grid, rho, steps, warmup, ref=None):
     flops = separable_flops(grid, n)
     dom = max(("phi_moments", "phi_expansion"), key=lambda k: per[k])
     achieved = flops[dom] / (per[dom] * 1e-3)
-    out = {"precision": "fp64", "ms_per_step": ms, "ms_per_step_percentiles": pct,
+    out = {"precision": precision, "ms_per_step": ms, "ms_per_step_percentiles": pct,
            "value": grid.n_cells * grid.n_lm * n / (ms * 1e-3), "unit": "terms/s",
-           "stage_ms_per_solve": per_solve,
-           "phi_fp64_mfma_frac": {k: flops[k] / (per[k] * 1e-3) / PEAK_FP64 for k in flops},
-           "roofline": {"bound": "mfma", "kernel": SEP_KERNELS[dom], "achieved": achieved / 1e12,
-                        "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-                        "traffic": traffic_record(dom, "separable"), "avg_launch_ms": per[dom],
-                        "algorithmic_flops_per_launch": flops[dom]}}
+           "stage_ms_per_solve": per_solve}
+    key = "separable" if precision == "fp64" else "separable_split"
+    if precision == "fp64":
+        out["phi_fp64_mfma_frac"] = {k: flops[k] / (per[k] * 1e-3) / PEAK_FP64 for k in flops}
+        out["roofline"] = {"bound": "mfma", "kernel": SEP_KERNELS[dom], "achieved": achieved / 1e12,
+                           "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+                           "traffic": traffic_record(dom, key), "avg_launch_ms": per[dom],
+                           "algorithmic_flops_per_launch": flops[dom]}
+    else:
+        # six bf16 MFMA products per product leave the split transforms bound
+        # by HBM: algorithmic bytes are the FP32 field (read by the moments',
+        # written by the expansion's) and the FP64 phi transforms between them
+        byts = separable_bytes(grid, n)
+        ach = byts[dom] / (per[dom] * 1e-3)
+        out["phi_bf16_mfma_frac"] = {k: 6 * flops[k] / (per[k] * 1e-3) / PEAK_BF16 for k in flops}
+        out["phi_hbm_frac"] = {k: byts[k] / (per[k] * 1e-3) / PEAK_HBM for k in byts}
+        out["roofline"] = {"bound": "hbm", "kernel": SEP_KERNELS_SPLIT[dom], "achieved": ach / 1e9,
+                           "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
+                           "traffic": traffic_record(dom, key), "avg_launch_ms": per[dom],
+                           "algorithmic_bytes_per_launch": byts[dom],
+                           "algorithmic_flops_per_launch": flops[dom]}
     if ref is not None:
         out64 = torch.empty_like(ref)
         plan.potential(rho, out=out64)
@@ -393,6 +423,8 @@ def main():
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the FP64 workload and the precision workload")
     ap.add_argument("--no-separable", action="store_true", help="skip the separable method")
+    ap.add_argument("--sep-precision", default="fp64", choices=["fp64", "split_bf16"],
+                    help="precision of --only separable")
     ap.add_argument("--only", choices=["fp64", "precision", "batch", "separable"], default=None,
                     help="run only this workload (no headline line; e.g. to profile its kernels) and print its "
                          "JSON")
@@ -410,7 +442,8 @@ def main():
         elif args.only == "separable":
             import workloads as W
             grid = W.config5()
-            res = separable_workload(grid, make_inputs(grid, args.snapshots, dev), args.steps, args.warmup)
+            res = separable_workload(grid, make_inputs(grid, args.snapshots, dev), args.steps, args.warmup,
+                                     precision=args.sep_precision)
         elif args.only == "precision":
             res = precision_workload(dev)
         else:
@@ -514,7 +547,7 @@ def main():
         "stage_ms": {k: per[k] for k in per},
     }
 
-    sep = None
+    sep = sep_split = None
     phi_other = None
     if not args.no_other_split:
         log(f"[bench] {other} on the same workload")
@@ -556,8 +589,9 @@ def main():
                 (phi_other.to(torch.float64) - ref).abs().max() / ref.abs().max())
         del plan64
         if not args.no_separable:
-            log("[bench] separable method on the same workload")
+            log("[bench] separable method on the same workload (FP64 and split-BF16)")
             sep = separable_workload(grid, rho, args.steps, args.warmup, ref)
+            sep_split = separable_workload(grid, rho, args.steps, args.warmup, ref, precision="split_bf16")
         del ref
 
     if not args.no_compare:
@@ -597,27 +631,41 @@ def main():
         out["batch"] = batch_workload(dev, args.batch_reps, autotune=not args.no_autotune, precisions=precs)
 
     if args.no_fp64 and not args.no_separable:
-        log("[bench] separable method on the same workload")
+        log("[bench] separable method on the same workload (FP64 and split-BF16)")
         sep = separable_workload(grid, rho, args.steps, args.warmup)
+        sep_split = separable_workload(grid, rho, args.steps, args.warmup, precision="split_bf16")
     if sep is not None:
-        # the headline: the fastest path that meets the FP64 bar (the same
-        # moments and potential, 1e-12 against the oracle); the dense
-        # split-BF16 path's line moves under its own key
+        # the headline: the fastest separable form within the metric's bar
+        # (split-BF16 within 1e-6 of FP64; FP64 within 1e-12 of the oracle);
+        # the dense split-BF16 path's line moves under its own key
+        head = sep
+        split_ok = sep_split is not None and sep_split.get("vs_dense_fp64_max_rel_err", 0.0) <= 1e-6
+        if split_ok and sep_split["ms_per_step"] < sep["ms_per_step"]:
+            head = sep_split
         dense = {k: out.pop(k) for k in ("value", "ms_per_step", "ms_per_step_percentiles", "roofline")}
         dense.update(dtype="bf16", precision=out["config"]["precision"], autotuned=out["config"].pop("autotuned"))
         for k in ("split_vs_fp64_max_rel_err", "speedup_vs_fp64"):
             if k in out:
                 dense[k] = out.pop(k)
         out["dense_split_bf16"] = dense
-        out.update(value=sep["value"], ms_per_step=sep["ms_per_step"],
-                   ms_per_step_percentiles=sep["ms_per_step_percentiles"], dtype="f64", roofline=sep.pop("roofline"))
-        out["config"]["precision"] = ("separable method in FP64: per-patch phi transforms (mirror cells folded), "
-                                      "theta contractions per order and rotations per degree on FP64 MFMA; "
-                                      "FP64 tables and scans")
+        split_head = head is sep_split
+        out.update(value=head["value"], ms_per_step=head["ms_per_step"],
+                   ms_per_step_percentiles=head["ms_per_step_percentiles"], dtype="bf16" if split_head else "f64",
+                   roofline=head["roofline"])
+        out["config"]["precision"] = (
+            ("separable method, split-BF16: per-patch phi transforms (mirror cells folded) as six bf16 piece "
+             "products per product on MFMA with FP32 accumulation (at most 192 terms), theta contractions per "
+             "order and rotations per degree on FP64 MFMA; FP64 tables and scans") if split_head else
+            ("separable method in FP64: per-patch phi transforms (mirror cells folded), theta contractions per "
+             "order and rotations per degree on FP64 MFMA; FP64 tables and scans"))
+        if split_head:
+            out["split_vs_fp64_max_rel_err"] = sep_split["vs_dense_fp64_max_rel_err"]
         out["separable_method"] = sep
+        if sep_split is not None:
+            out["separable_split_bf16"] = sep_split
         if "fp64_path" in out:
-            out["speedup_vs_dense_fp64"] = out["fp64_path"]["ms_per_step"] / sep["ms_per_step"]
-            out["speedup_vs_dense_split_bf16"] = dense["ms_per_step"] / sep["ms_per_step"]
+            out["speedup_vs_dense_fp64"] = out["fp64_path"]["ms_per_step"] / head["ms_per_step"]
+            out["speedup_vs_dense_split_bf16"] = dense["ms_per_step"] / head["ms_per_step"]
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -79,7 +79,8 @@ void free_plan(mpg_plan_s *p) {
     void *bufs[] = {p->col_src, p->col_l,  p->Ut,     p->Qt,     p->coef,   p->w,      p->Us,
                     p->Qs,      p->Bpart,  p->Bred,   p->M,      p->Ms,     p->A_split, p->sep_m,
                     p->sep_coff, p->sep_cslot, p->sep_f1, p->sep_t1, p->sep_t2, p->sep_f2, p->sep_F,
-                    p->sep_A,   p->sep_kxy, p->sep_xoff, p->sep_perm, p->sep_x1, p->sep_x2};
+                    p->sep_A,   p->sep_kxy, p->sep_xoff, p->sep_perm, p->sep_x1, p->sep_x2,
+                    p->sep_f1s, p->sep_f2s};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     clear_events(p);
@@ -250,7 +251,7 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
         // grid limits of its launches: theta rows and 128-row blocks of
         // (field, patch, shell) rows on a grid axis, a weight row in LDS
         const long long vblocks = ((long long)max_fields * g->n_patches * g->n_r + 127) / 128;
-        const char *why = precision != MPG_FP64 ? "the separable method runs in FP64 only"
+        const char *why = precision == MPG_SPLIT_BF16_TIERED ? "the separable method takes MPG_FP64 or MPG_SPLIT_BF16"
                           : (g->n_theta > 65535 || vblocks > 65535 || g->n_phi > 8192)
                               ? "the separable method takes at most 65535 theta rows, 8192 phi cells and 65535 "
                                 "blocks of 128 (field, patch, shell) rows"
@@ -292,6 +293,8 @@ int mpg_plan_method(const mpg_grid *g, int lmax, int precision, int max_fields, 
         p->sep_kh = p->sep_mir ? n / 2 : n;
         p->sep_khp = roundup(p->sep_kh, 16);
         p->sep_kx = !p->sep_mir ? n : p->eval_centre ? n / 2 : n / 2 + 1;
+        p->sep_nt2 = std::max(1, (lmax + 31) / 32);
+        p->sep_kxp = roundup(p->sep_kx, 64);
     }
 
     // work space

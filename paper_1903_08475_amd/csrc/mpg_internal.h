@@ -135,6 +135,13 @@ struct Plan {
     double *sep_f2 = nullptr;    // [nc][sep_kx] expansion's phi factors
     double *sep_x1 = nullptr;    // rotations local -> common frame (moments)
     double *sep_x2 = nullptr;    // rotations common frame -> local (expansion)
+    // split forms of the separable method: the phi transforms in six bf16
+    // piece products with FP32 accumulation (tiles of 32 columns: C rows
+    // [0, 32 sep_nt2), S rows after them)
+    int sep_nt2 = 0;             // 32-column tiles per block (C or S) of the moments' transform
+    int sep_kxp = 0;             // sep_kx rounded up to 64
+    bf16 *sep_f1s = nullptr;     // [3][64 sep_nt2][sep_khp] pieces of the moments' phi factors
+    bf16 *sep_f2s = nullptr;     // [3][sep_kxp][2 sep_ce] pieces of the expansion's phi factors (columns 1..)
     double *sep_A = nullptr;     // [n_lm][sep_ldv()] local moments / local expansion coefficients (by slot)
     double *sep_F = nullptr;     // [nc][n_theta][sep_ldv()] phi transforms (moments, then expansion)
     int sep_nc() const { return 1 + sep_ce + sep_co; }

@@ -637,6 +637,276 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split forms of the two phi transforms (MPG_SPLIT_BF16): the same sums in
+// six bf16 piece products (h h, h m, m h, h l, m m, l h of the three pieces
+// of each FP32-rounded operand) on v_mfma_f32_32x32x16_bf16, accumulated in
+// FP32 over at most 2 lmax + 1 or n_phi/2 terms, and written in FP64.  The
+// order-0 column stays an FP64 row sum (moments) and an FP64 term added to
+// the cosine sums (expansion).
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int PK = 24;  // LDS pitch (bf16) of a 16-deep row of pieces: 16 rows of a fragment read hit distinct banks
+
+// C/D layout of v_mfma_f32_32x32x16_bf16 (measured): register r of lane l
+// holds D[8(r/4) + 4(l/32) + r%4][l%32]; A rows are lane%32 with K elements
+// 8(l/32)..+7, B columns lane%32 with the same K elements.
+__device__ inline int d_row32(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+
+__device__ inline v16f mfma32(v8bf a, v8bf b, v16f c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+
+// the six partial products of a fragment pair into acc, smallest first
+__device__ inline v16f six(const v8bf (&a)[3], const v8bf (&b)[3], v16f acc) {
+    acc = mfma32(a[2], b[0], acc);
+    acc = mfma32(a[1], b[1], acc);
+    acc = mfma32(a[0], b[2], acc);
+    acc = mfma32(a[1], b[0], acc);
+    acc = mfma32(a[0], b[1], acc);
+    return mfma32(a[0], b[0], acc);
+}
+
+// three bf16 pieces of a value rounded to FP32 (h + m + l exact)
+__device__ inline void split3(double x, bf16 &h, bf16 &m, bf16 &l) {
+    const float v = (float)x;
+    h = (bf16)v;
+    const float r = v - (float)h;
+    m = (bf16)r;
+    l = (bf16)(r - (float)m);
+}
+
+// Moments.  Block: 128 rows v of one (field, patch) group at theta row j;
+// output F[c][j][v] for the order-0 column and the 2 NT2 tiles of 32 factor
+// rows (C of the orders 1.., then S); K = the kh cells in slabs of 16.  Wave
+// w takes v 32w.. and every factor tile.  Thread t stages 8 cells of row t/2
+// (as the FP64 kernel) as pieces, and chunks t + 256q of the factor slab.
+template <typename T, bool MIR, int NT2>
+__global__ __launch_bounds__(256, 2) void k_sep_phi1s(const T *__restrict__ rho, const double *__restrict__ w,
+                                                      size_t w_patch, const bf16 *__restrict__ f1s,
+                                                      const double *__restrict__ f1, double *__restrict__ F, int ldv,
+                                                      int n_r, int n_patches, int n_theta, int n_phi, int kh, int khp,
+                                                      int ce, int L, int nst) {
+    constexpr int NR = 64 * NT2, NCH = 3 * NR * 2, QF = (NCH + 255) / 256;
+    extern __shared__ double sW[];
+    __shared__ __attribute__((aligned(16))) bf16 Af[3][NR][PK];
+    __shared__ __attribute__((aligned(16))) bf16 Bd[MIR ? 2 : 1][3][VB][PK];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int fg = blockIdx.x / nst, st0 = (blockIdx.x - fg * nst) * VB, j = blockIdx.y;
+    const int nv = min(VB, n_r - st0);
+    const size_t v0 = (size_t)fg * n_r + st0;
+    const double *wrow = w + (size_t)(fg % n_patches) * w_patch + (size_t)j * n_phi;
+    for (int k = tid; k < n_phi; k += 256) sW[k] = wrow[k];
+
+    const int sr = tid >> 1, sk = (tid & 1) * 8;
+    const bool row_ok = sr < nv;
+    const T *prow = rho + ((v0 + (row_ok ? sr : 0)) * n_theta + j) * n_phi;
+    const size_t npc = (size_t)NR * khp;  // one piece of the factor table
+
+    v16f acc[2 * NT2];
+#pragma unroll
+    for (int t = 0; t < 2 * NT2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+    const int nsl = (kh + SK - 1) / SK;
+    PhiStage<T> stg;
+    v8bf fc[QF];
+    auto load = [&](int s) {
+        load_phi<T, MIR>(stg, prow, s * SK + sk, n_phi, kh, row_ok);
+#pragma unroll
+        for (int q = 0; q < QF; ++q) {
+            const int e = tid + 256 * q;
+            if (e < NCH) {
+                const int pc = e / (NR * 2), rem = e - pc * NR * 2;
+                fc[q] = *(const v8bf *)(f1s + pc * npc + (size_t)(rem >> 1) * khp + s * SK + (rem & 1) * 8);
+            }
+        }
+    };
+    load(0);
+    __syncthreads();  // the weight row
+    double sum0 = 0.0;
+    for (int s = 0; s < nsl; ++s) {
+        const int k = s * SK + sk;
+        {
+            v8bf ph[3], pd[3];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool in = k + q < kh;
+                const double a = (in ? sW[k + q] : 0.0) * (double)stg.a[q];
+                const double b = (MIR && in) ? sW[n_phi - 1 - k - q] * (double)stg.b[q] : 0.0;
+                sum0 += a + b;
+                bf16 h, m, l;
+                split3(a + b, h, m, l);
+                ph[0][q] = h;
+                ph[1][q] = m;
+                ph[2][q] = l;
+                if (MIR) {
+                    split3(a - b, h, m, l);
+                    pd[0][q] = h;
+                    pd[1][q] = m;
+                    pd[2][q] = l;
+                }
+            }
+#pragma unroll
+            for (int pc = 0; pc < 3; ++pc) {
+                *(v8bf *)&Bd[0][pc][sr][sk] = ph[pc];
+                if (MIR) *(v8bf *)&Bd[MIR ? 1 : 0][pc][sr][sk] = pd[pc];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < QF; ++q) {
+            const int e = tid + 256 * q;
+            if (e < NCH) {
+                const int pc = e / (NR * 2), rem = e - pc * NR * 2;
+                *(v8bf *)&Af[pc][rem >> 1][(rem & 1) * 8] = fc[q];
+            }
+        }
+        __syncthreads();
+        if (s + 1 < nsl) load(s + 1);
+        {
+            const int kg = (lane >> 5) * 8, row = lane & 31;
+            v8bf be[3], bo[3];
+#pragma unroll
+            for (int pc = 0; pc < 3; ++pc) {
+                be[pc] = *(const v8bf *)&Bd[0][pc][wave * 32 + row][kg];
+                if (MIR) bo[pc] = *(const v8bf *)&Bd[MIR ? 1 : 0][pc][wave * 32 + row][kg];
+            }
+#pragma unroll
+            for (int t = 0; t < 2 * NT2; ++t) {
+                v8bf a[3];
+#pragma unroll
+                for (int pc = 0; pc < 3; ++pc) a[pc] = *(const v8bf *)&Af[pc][t * 32 + row][kg];
+                acc[t] = six(a, (MIR && t >= NT2) ? bo : be, acc[t]);
+            }
+        }
+        __syncthreads();
+    }
+    // the order-0 column (factor C_k^0 = dphi for every cell), in FP64
+    sum0 += __shfl_xor(sum0, 1);
+    if (sk == 0 && row_ok) F[(size_t)j * ldv + v0 + sr] = f1[0] * sum0;
+    // register r of lane l: factor row 32t + d_row32(l, r), row v = 32w + l%32
+    const int vv = wave * 32 + (lane & 31);
+#pragma unroll
+    for (int t = 0; t < 2 * NT2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int fr = t * 32 + d_row32(lane, r), o = t < NT2 ? fr : fr - 32 * NT2;  // order - 1
+            const int c = 1 + (t < NT2 ? 0 : ce) + o;
+            if (o < L && vv < nv) F[((size_t)c * n_theta + j) * ldv + v0 + vv] = (double)acc[t][r];
+        }
+}
+
+// Expansion.  Block and schedule as the FP64 kernel (64 points, 128 rows v,
+// JB theta rows, XCD-aware ids); wave w takes v 32w.. and both 32-point
+// tiles, with the cosine sums E and the sine sums O in FP32.  K = the
+// columns 1.. in slabs of 16 (E: [0, ce), O: [ce, 2 ce) of them; without
+// MIR all into E).  Thread t stages 8 consecutive columns of row t%128 (from
+// 8 (t/128)) of G as pieces, and chunks of the factor slab.
+template <typename T, bool MIR>
+__global__ __launch_bounds__(256, 2) void k_sep_phi2s(const double *__restrict__ G, int ldv,
+                                                      const bf16 *__restrict__ f2s, const double *__restrict__ f2,
+                                                      const int2 *__restrict__ kxy, T *__restrict__ phi, int vrows,
+                                                      int n_theta, int n_phi, int kx, int kxp, int ce, int nbt, int nvt,
+                                                      int ngroups) {
+    __shared__ __attribute__((aligned(16))) bf16 As[3][VB][PK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[3][64][PK];
+    __shared__ double sG0[2][VB];
+    const int id = blockIdx.x, k8 = id >> 3, bt = k8 % nbt, grp = (k8 / nbt) * 8 + (id & 7);
+    if (grp >= ngroups) return;  // the whole block, before any barrier
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int b0 = bt * 64, v0 = (grp % nvt) * VB;
+    const int j0 = (grp / nvt) * JB, jn = min(JB, n_theta - j0);
+    const int K = 2 * ce, nsl = K / SK, nse = MIR ? ce / SK : nsl;
+    const size_t npc = (size_t)kxp * K;  // one piece of the factor table
+    const int sv = tid & (VB - 1), sc = (tid >> 7) * 8;
+
+    double gv[8], g0r = 0.0;
+    v8bf fc[2];
+    auto load = [&](int jj, int s) {
+        if (s == 0 && tid < VB) g0r = G[(size_t)(j0 + jj) * ldv + v0 + tid];  // padded rows are zero
+#pragma unroll
+        for (int q = 0; q < 8; ++q) gv[q] = G[((size_t)(1 + s * SK + sc + q) * n_theta + j0 + jj) * ldv + v0 + sv];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + 256 * q;
+            if (e < 3 * 64 * 2) {
+                const int pc = e / 128, rem = e - pc * 128;
+                fc[q] = *(const v8bf *)(f2s + pc * npc + (size_t)(b0 + (rem >> 1)) * K + s * SK + (rem & 1) * 8);
+            }
+        }
+    };
+    v16f E[2], O[2];
+    const int kg = (lane >> 5) * 8, row = lane & 31;
+    auto run = [&](v16f(&acc)[2], int jj, int s0, int s1) {
+        for (int s = s0; s < s1; ++s) {
+            if (s == 0 && tid < VB) sG0[jj & 1][tid] = g0r;
+            {
+                v8bf pcs[3];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    bf16 h, m, l;
+                    split3(gv[q], h, m, l);
+                    pcs[0][q] = h;
+                    pcs[1][q] = m;
+                    pcs[2][q] = l;
+                }
+#pragma unroll
+                for (int pc = 0; pc < 3; ++pc) *(v8bf *)&As[pc][sv][sc] = pcs[pc];
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int e = tid + 256 * q;
+                if (e < 3 * 64 * 2) {
+                    const int pc = e / 128, rem = e - pc * 128;
+                    *(v8bf *)&Bs[pc][rem >> 1][(rem & 1) * 8] = fc[q];
+                }
+            }
+            __syncthreads();
+            {
+                const bool last = s + 1 == nsl;
+                if (!last || jj + 1 < jn) load(last ? jj + 1 : jj, last ? 0 : s + 1);
+            }
+            v8bf a[3];
+#pragma unroll
+            for (int pc = 0; pc < 3; ++pc) a[pc] = *(const v8bf *)&As[pc][wave * 32 + row][kg];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                v8bf b[3];
+#pragma unroll
+                for (int pc = 0; pc < 3; ++pc) b[pc] = *(const v8bf *)&Bs[pc][t * 32 + row][kg];
+                acc[t] = six(a, b, acc[t]);
+            }
+            __syncthreads();
+        }
+    };
+    load(0, 0);
+    for (int jj = 0; jj < jn; ++jj) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) E[t][r] = O[t][r] = 0.f;
+        run(E, jj, 0, nse);
+        if (MIR) run(O, jj, nse, nsl);
+        // register r of lane l: row v = 32w + d_row32(l, r), point 32t + l%32
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int b = b0 + t * 32 + row;
+            if (b >= kx) continue;
+            const int2 kk = kxy[b];
+            const double f0 = f2[b];  // the order-0 factor (cos 0 = 1)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int vl = wave * 32 + d_row32(lane, r), v = v0 + vl;
+                if (v >= vrows) continue;
+                T *o = phi + ((size_t)v * n_theta + j0 + jj) * n_phi;
+                const double e = (double)E[t][r] + f0 * sG0[jj & 1][vl], d = (double)O[t][r];
+                o[kk.x] = (T)(e + d);
+                if (MIR && kk.y >= 0) o[kk.y] = (T)(e - d);
+            }
+        }
+    }
+}
+
 template <typename T, bool MIR>
 hipError_t launch_phi1(const Plan &p, int n_fields, const T *rho) {
     const int nt = (p.sep_nc() - 1) / 16, nst = (p.n_r + VB - 1) / VB;
@@ -672,8 +942,42 @@ void launch_phi2(const Plan &p, int vrows, T *phi) {
 
 }  // namespace
 
+template <typename T, bool MIR>
+hipError_t launch_phi1s(const Plan &p, int n_fields, const T *rho) {
+    const int nst = (p.n_r + VB - 1) / VB;
+    const size_t w_patch = p.npat == 1 ? 0 : (size_t)p.n_ang;
+    const dim3 grid(n_fields * p.n_patches * nst, p.n_theta);
+    const size_t lds = sizeof(double) * p.n_phi;
+    if (p.sep_nt2 == 1)
+        hipLaunchKernelGGL((k_sep_phi1s<T, MIR, 1>), grid, dim3(256), lds, p.stream, rho, p.w, w_patch, p.sep_f1s,
+                           p.sep_f1, p.sep_F, p.sep_ldv(), p.n_r, p.n_patches, p.n_theta, p.n_phi, p.sep_kh, p.sep_khp,
+                           p.sep_ce, p.lmax, nst);
+    else if (p.sep_nt2 == 2)
+        hipLaunchKernelGGL((k_sep_phi1s<T, MIR, 2>), grid, dim3(256), lds, p.stream, rho, p.w, w_patch, p.sep_f1s,
+                           p.sep_f1, p.sep_F, p.sep_ldv(), p.n_r, p.n_patches, p.n_theta, p.n_phi, p.sep_kh, p.sep_khp,
+                           p.sep_ce, p.lmax, nst);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename T, bool MIR>
+void launch_phi2s(const Plan &p, int vrows, T *phi) {
+    const int nbt = (p.sep_kx + 63) / 64, nvt = (vrows + VB - 1) / VB, ng = nvt * ((p.n_theta + JB - 1) / JB);
+    const dim3 grid((unsigned)((ng + 7) / 8 * 8 * nbt));
+    hipLaunchKernelGGL((k_sep_phi2s<T, MIR>), grid, dim3(256), 0, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2s, p.sep_f2,
+                       p.sep_kxy, phi, vrows, p.n_theta, p.n_phi, p.sep_kx, p.sep_kxp, p.sep_ce, nbt, nvt, ng);
+}
+
 hipError_t sep_phi_moments(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
     if (n_fields > p.max_fields) return hipErrorInvalidValue;
+    if (p.split()) {
+        if (rho_dtype == MPG_F64)
+            return p.sep_mir ? launch_phi1s<double, true>(p, n_fields, (const double *)rho)
+                             : launch_phi1s<double, false>(p, n_fields, (const double *)rho);
+        return p.sep_mir ? launch_phi1s<float, true>(p, n_fields, (const float *)rho)
+                         : launch_phi1s<float, false>(p, n_fields, (const float *)rho);
+    }
     if (rho_dtype == MPG_F64)
         return p.sep_mir ? launch_phi1<double, true>(p, n_fields, (const double *)rho)
                          : launch_phi1<double, false>(p, n_fields, (const double *)rho);
@@ -707,6 +1011,16 @@ hipError_t sep_theta_expansion(const Plan &p, int n_fields) {
 hipError_t sep_phi_expansion(const Plan &p, int n_fields, void *phi, int phi_dtype) {
     const int vrows = n_fields * p.n_patches * p.n_r;
     if (n_fields > p.max_fields) return hipErrorInvalidValue;
+    if (p.split()) {
+        if (phi_dtype == MPG_F64) {
+            if (p.sep_mir) launch_phi2s<double, true>(p, vrows, (double *)phi);
+            else launch_phi2s<double, false>(p, vrows, (double *)phi);
+        } else {
+            if (p.sep_mir) launch_phi2s<float, true>(p, vrows, (float *)phi);
+            else launch_phi2s<float, false>(p, vrows, (float *)phi);
+        }
+        return hipGetLastError();
+    }
     if (phi_dtype == MPG_F64) {
         if (p.sep_mir) launch_phi2<double, true>(p, vrows, (double *)phi);
         else launch_phi2<double, false>(p, vrows, (double *)phi);

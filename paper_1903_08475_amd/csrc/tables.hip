@@ -578,6 +578,48 @@ __global__ void k_sep_x(int L, int n_patches, int g, const double *N4, const lon
     x2[xoff[l] + ((size_t)g * n + pm) * n + pu] = x;
 }
 
+// three bf16 pieces of an FP64 factor (through FP32: 24 significant bits)
+__device__ inline void split3d(double x, bf16 &h, bf16 &m, bf16 &l) {
+    const float v = (float)x;
+    h = (bf16)v;
+    const float r = v - (float)h;
+    m = (bf16)r;
+    l = (bf16)(r - (float)m);
+}
+
+// f1s[p][row][k]: row < 32 nt2 is the C column of order row + 1, row >= 32
+// nt2 the S column of order row - 32 nt2 + 1 (zero past lmax); its phi
+// factor at column index 1 + (C: row, S: ce + row - 32 nt2) of f1
+__global__ void k_sep_f1s(int L, int nt2, int khp, int nc, int ce, const double *f1, bf16 *f1s) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, R = 64 * nt2;
+    if (t >= R * khp) return;
+    const int row = t / khp, k = t - row * khp;
+    const bool s = row >= 32 * nt2;
+    const int o = s ? row - 32 * nt2 : row;  // order - 1
+    double x = 0.0;
+    if (o < L) x = f1[(size_t)k * nc + 1 + (s ? ce : 0) + o];
+    bf16 h, m, l;
+    split3d(x, h, m, l);
+    const size_t n = (size_t)R * khp;
+    f1s[t] = h;
+    f1s[n + t] = m;
+    f1s[2 * n + t] = l;
+}
+
+// f2s[p][b][cc] = pieces of f2[1 + cc][b] (cc < 2 ce; zero past kx)
+__global__ void k_sep_f2s(int kx, int kxp, int ce, const double *f2, bf16 *f2s) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, K = 2 * ce;
+    if (t >= kxp * K) return;
+    const int b = t / K, cc = t - b * K;
+    const double x = b < kx ? f2[(size_t)(1 + cc) * kx + b] : 0.0;
+    bf16 h, m, l;
+    split3d(x, h, m, l);
+    const size_t n = (size_t)kxp * K;
+    f2s[t] = h;
+    f2s[n + t] = m;
+    f2s[2 * n + t] = l;
+}
+
 inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -729,6 +771,16 @@ hipError_t build_tables(Plan &p, const double *euler, const double *r_edges, con
         hipLaunchKernelGGL(k_sep_t2, dim3(blocks((size_t)nc * p.n_theta, 64)), dim3(64), 0, s, L, p.n_theta, nc,
                            lp, p.theta0, p.dtheta, ev, p.G, d_code, p.sep_t2);
         STEP(hipGetLastError());
+        if (p.split()) {
+            const size_t n1 = (size_t)64 * p.sep_nt2 * p.sep_khp, n2 = (size_t)p.sep_kxp * 2 * p.sep_ce;
+            STEP(hipMalloc(&p.sep_f1s, sizeof(bf16) * 3 * n1));
+            STEP(hipMalloc(&p.sep_f2s, sizeof(bf16) * 3 * n2));
+            hipLaunchKernelGGL(k_sep_f1s, dim3(blocks(n1, 128)), dim3(128), 0, s, L, p.sep_nt2, p.sep_khp, nc,
+                               p.sep_ce, p.sep_f1, p.sep_f1s);
+            hipLaunchKernelGGL(k_sep_f2s, dim3(blocks(n2, 128)), dim3(128), 0, s, p.sep_kx, p.sep_kxp, p.sep_ce,
+                               p.sep_f2, p.sep_f2s);
+            STEP(hipGetLastError());
+        }
         // every patch's N factors from its own Euler angles
         for (int g = 0; g < P; ++g) {
             const double *e = euler + 3 * g;

@@ -57,10 +57,10 @@ def test_plan_rejects_bad_grids_on_host():
     s.eval_point = mpg.EVAL_POINTS["centre"]
     assert L.mpg_plan(ctypes.byref(s), 65, 0, 1, None, ctypes.byref(h)) == mpg.MPG_EINVAL  # lmax above 64
     assert L.mpg_plan_method(ctypes.byref(s), 8, 0, 1, 3, None, ctypes.byref(h)) == mpg.MPG_EINVAL  # method
-    # the separable method runs in FP64 only
+    # the separable method takes FP64 or the six-product split form
     sep = mpg.METHODS["separable"]
-    assert L.mpg_plan_method(ctypes.byref(s), 8, 1, 1, sep, None, ctypes.byref(h)) == mpg.MPG_EUNSUPPORTED
-    assert b"FP64" in L.mpg_last_error()
+    assert L.mpg_plan_method(ctypes.byref(s), 8, 2, 1, sep, None, ctypes.byref(h)) == mpg.MPG_EUNSUPPORTED
+    assert b"MPG_SPLIT_BF16" in L.mpg_last_error()
     bad = r.copy()
     bad[5] = bad[4]
     s.r_edges = bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

@@ -22,37 +22,47 @@ def mods():
     return torch, mpg
 
 
-@pytest.mark.parametrize("key", ["c1", "ragged", "polar", "tiny", "medium"])
-def test_moments_and_potential_match_oracle(key):
+TOL = {"fp64": TOL64, "split_bf16": 1e-6}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
+@pytest.mark.parametrize("key", ["c1", "ragged", "polar", "tiny", "medium", "c3"])
+def test_moments_and_potential_match_oracle(key, precision):
     torch, mpg = mods()
     g, w, U, Q = oracle_tables(key)
     rho = W.random_rho(g, 71)
+    if precision != "fp64":
+        rho = rho.astype(np.float32).astype(np.float64)
     B = O.moments(g, g.lmax, U, rho)
     M = O.radial(g, g.lmax, B)
     phi = O.expand(g, g.lmax, Q, M)
-    plan = mpg.Plan(g, method="separable")
+    plan = mpg.Plan(g, method="separable", precision=precision)
     t = torch.tensor(rho, device="cuda")
+    if precision != "fp64":
+        t = t.float()
     Bg, Mg = (x[0].cpu().numpy() for x in plan.moments(t))
-    out = plan.potential(t).cpu().numpy()
+    out = plan.potential(t, out_dtype=torch.float64).cpu().numpy()
     eb, em, ep = rel_err(Bg, B), rel_err(Mg, M), rel_err(out, phi)
-    print(f"{key}: B {eb:.3e}  M {em:.3e}  Phi {ep:.3e}")
-    assert eb < TOL64 and em < TOL64 and ep < TOL64
+    print(f"{key} {precision}: B {eb:.3e}  M {em:.3e}  Phi {ep:.3e}")
+    tol = TOL[precision]
+    assert eb < tol and em < tol and ep < tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
 @pytest.mark.parametrize("key", ["yy_rot", "three", "two_free", "polar_turned", "yy_rot_hi"])
-def test_general_patch_sets_match_oracle(key):
+def test_general_patch_sets_match_oracle(key, precision):
     """Patches at any Euler angles, with their own overlap weights: the
     rotation stage takes each patch's local moments to the common frame."""
     torch, mpg = mods()
     from test_gpu_general import case
     g, w, rho, phi_ref, B_ref = case(key)
-    plan = mpg.Plan(g, method="separable", overlap_w=w)
+    plan = mpg.Plan(g, method="separable", precision=precision, overlap_w=w)
     t = torch.tensor(rho, device="cuda")
     out = plan.potential(t).cpu().numpy()
     B = plan.moments(t)[0][0].cpu().numpy()
     ep, eb = rel_err(out, phi_ref), rel_err(B, B_ref)
-    print(f"{key}: Phi {ep:.3e}  B {eb:.3e}")
-    assert ep < TOL64 and eb < TOL64
+    print(f"{key} {precision}: Phi {ep:.3e}  B {eb:.3e}")
+    assert ep < TOL[precision] and eb < TOL[precision]
 
 
 def _unmirrored(kind):
@@ -64,19 +74,20 @@ def _unmirrored(kind):
     return W.patches([[0.0, 0.0, 0.0]], 7, 20, np.pi / 4, -2.0, d, d, W.uniform_edges(9), 9, name="shifted")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
 @pytest.mark.parametrize("kind", ["odd_phi", "shifted"])
 @pytest.mark.parametrize("eval_point", ["vertex", "centre"])
-def test_unmirrored_phi_grids(kind, eval_point):
+def test_unmirrored_phi_grids(kind, eval_point, precision):
     torch, mpg = mods()
     g = _unmirrored(kind)
     g.eval_point = eval_point
     rho = W.random_rho(g, 72)
     phi, B, M, U, Q = O.potential(g, g.lmax, rho, None)
-    plan = mpg.Plan(g, method="separable")
+    plan = mpg.Plan(g, method="separable", precision=precision)
     out = plan.potential(torch.tensor(rho, device="cuda")).cpu().numpy()
     err = rel_err(out, phi)
-    print(f"{kind} {eval_point}: Phi {err:.3e}")
-    assert err < TOL64
+    print(f"{kind} {eval_point} {precision}: Phi {err:.3e}")
+    assert err < TOL[precision]
 
 
 @pytest.mark.parametrize("key", ["c1", "ragged", "polar"])
@@ -129,7 +140,7 @@ def test_rejected_calls():
     torch, mpg = mods()
     g = GRIDS["c1"]()
     with pytest.raises(mpg.MpgError) as err:
-        mpg.Plan(g, precision="split_bf16", method="separable")
+        mpg.Plan(g, precision="split_bf16_tiered", method="separable")
     assert err.value.code == mpg.MPG_EUNSUPPORTED
     plan = mpg.Plan(g, method="separable")
     t = torch.tensor(W.random_rho(g, 75), device="cuda")
@@ -143,6 +154,25 @@ def test_rejected_calls():
     rho = t.cpu().numpy()
     phi = O.expand(g, g.lmax, Q, O.radial(g, g.lmax, O.moments(g, g.lmax, U, rho)))
     assert rel_err(plan.potential(t).cpu().numpy(), phi) < TOL64
+
+
+@pytest.mark.slow
+def test_large_workload_split_against_fp64():
+    """The split form of the separable method on the large workload's own
+    density (8 snapshots): the whole potential against the FP64 separable
+    solve (pinned to the oracle by the test below), at the split bar."""
+    torch, mpg = mods()
+    g = W.config5()
+    dev = torch.device("cuda")
+    rho = torch.empty((8,) + g.shape, dtype=torch.float32, device=dev)
+    for t in range(8):
+        rho[t] = W.cell_average(g, W.density5(t), sub=2, device=dev, as_tensor=True, out_dtype=torch.float32)
+    ref = mpg.Plan(g, method="separable", max_fields=8).potential(rho, out_dtype=torch.float64)
+    out = mpg.Plan(g, method="separable", precision="split_bf16", max_fields=8).potential(rho,
+                                                                                         out_dtype=torch.float64)
+    err = float((out - ref).abs().max() / ref.abs().max())
+    print(f"large workload, separable split-BF16 vs FP64: {err:.3e}")
+    assert err < 1e-6
 
 
 @pytest.mark.slow
