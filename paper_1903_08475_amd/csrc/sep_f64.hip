@@ -55,6 +55,17 @@ __device__ inline v4d mfma(double a, double b, v4d c) { return __builtin_amdgcn_
 // halves
 __host__ __device__ constexpr int pitch(int n) { return (n / 16) % 2 ? n : n + 16; }
 
+// The split form keeps the phi columns c >= 1 of its transforms in FP32 (its
+// phi transforms sum in FP32 and round their operands to FP32 first, so no
+// value changes): column c at [(c - 1) n_theta + j][v] of the FP32 view
+// that starts past column 0, which stays FP64 at F[j][v].
+__device__ inline float *tf_f32(double *F, int n_theta, int ldv) {
+    return reinterpret_cast<float *>(F + (size_t)n_theta * ldv);
+}
+__device__ inline const float *tf_f32(const double *F, int n_theta, int ldv) {
+    return reinterpret_cast<const float *>(F + (size_t)n_theta * ldv);
+}
+
 // Lane layout of v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; result register q of lane l is D[l/16 + 4q][l%16].
 
@@ -255,7 +266,9 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1(const T *__restrict__ rho, 
 // degree slots s < lmax + 1 - u (at most five tiles of 16), K = n_theta in
 // slabs of 16; slots as rows, v as columns (stores of 16 consecutive v).
 // Wave w takes v 32w..32w+31.  v past the last row lie in the zeroed
-// padding of the work arrays and are not stored.
+// padding of the work arrays and are not stored.  F32: the columns c >= 1
+// are FP32 (the split form's phi transforms, see tf_f32).
+template <bool F32>
 __global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F, int ldv,
                                                     const double *__restrict__ t1, const int *__restrict__ sep_u,
                                                     const int *__restrict__ coff, double *__restrict__ A, int vrows,
@@ -272,7 +285,9 @@ __global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int v0 = blockIdx.x * VB, wv = wave * 32;
     const double *tc = t1 + (size_t)c * lp * n_theta;
+    const bool flt = F32 && c > 0;
     const double *Fc = F + (size_t)c * n_theta * ldv + v0;
+    const float *Fs = tf_f32(F, n_theta, ldv) + (size_t)(c - 1) * n_theta * ldv + v0;
 
     v4d acc[NTM][2];
 #pragma unroll
@@ -291,9 +306,21 @@ __global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F
             ra[q] = (sl < nl && j < n_theta) ? tc[(size_t)sl * n_theta + j] : 0.0;
         }
         const bool jok = j0 + bj < n_theta;
-        const double *fr = Fc + (size_t)(jok ? j0 + bj : 0) * ldv + bv;
+        const size_t fo = (size_t)(jok ? j0 + bj : 0) * ldv + bv;
+        if (flt) {
+            // FP32: v 4 bv + 64 q + e (e < 4) of row j, 16-byte loads
 #pragma unroll
-        for (int q = 0; q < 8; ++q) rb[q] = jok ? fr[16 * q] : 0.0;
+            for (int q = 0; q < 2; ++q) {
+                const float4 f = jok ? *(const float4 *)(Fs + fo - bv + 4 * bv + 64 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+                rb[4 * q] = f.x;
+                rb[4 * q + 1] = f.y;
+                rb[4 * q + 2] = f.z;
+                rb[4 * q + 3] = f.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) rb[q] = jok ? Fc[fo + 16 * q] : 0.0;
+        }
     };
     load(0);
     for (int j0 = 0; j0 < n_theta; j0 += SK) {
@@ -302,8 +329,15 @@ __global__ __launch_bounds__(256) void k_sep_theta1(const double *__restrict__ F
             const int e = tid + 256 * q;
             As[e >> 4][e & 15] = ra[q];
         }
+        if (flt) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) Bs[bj][bv + 16 * q] = rb[q];
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Bs[bj][4 * bv + 64 * q + e] = rb[4 * q + e];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Bs[bj][bv + 16 * q] = rb[q];
+        }
         __syncthreads();
         if (j0 + SK < n_theta) load(j0 + SK);
 #pragma unroll
@@ -430,7 +464,9 @@ __global__ __launch_bounds__(256) void k_sep_rot(const double *__restrict__ src,
 // c = y, 128 theta rows from 128 z): G[c][j][v] = sum_s t2[c][s][j]
 // L[coff[c] + s][v], K = the degree slots in slabs of 16; theta rows as
 // rows, v as columns.  Wave w takes theta rows 64(w%2).. and v 64(w/2)..
-__global__ __launch_bounds__(256) void k_sep_theta2(const double *__restrict__ Lc, const double *__restrict__ t2,
+// F32: the columns c >= 1 are stored in FP32 (see tf_f32).
+template <bool F32>
+__global__ __launch_bounds__(256, 2) void k_sep_theta2(const double *__restrict__ Lc, const double *__restrict__ t2,
                                                     const int *__restrict__ sep_u, const int *__restrict__ coff,
                                                     double *__restrict__ G, int ldv, int vrows, int n_theta, int lp,
                                                     int L) {
@@ -490,6 +526,8 @@ __global__ __launch_bounds__(256) void k_sep_theta2(const double *__restrict__ L
         __syncthreads();
     }
     double *Gc = G + (size_t)c * n_theta * ldv + v0;
+    float *Gs = tf_f32(G, n_theta, ldv) + (size_t)(c - 1) * n_theta * ldv + v0;
+    const bool flt = F32 && c > 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -497,7 +535,10 @@ __global__ __launch_bounds__(256) void k_sep_theta2(const double *__restrict__ L
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = j0 + wj + i * 16 + (lane >> 4) + 4 * q, vv = wv + t * 16 + (lane & 15);
-                if (j < n_theta && v0 + vv < vrows) Gc[(size_t)j * ldv + vv] = acc[i][t][q];
+                if (j < n_theta && v0 + vv < vrows) {
+                    if (flt) Gs[(size_t)j * ldv + vv] = (float)acc[i][t][q];
+                    else Gc[(size_t)j * ldv + vv] = acc[i][t][q];
+                }
             }
 }
 
@@ -665,9 +706,8 @@ __device__ inline v16f six(const v8bf (&a)[3], const v8bf (&b)[3], v16f acc) {
     return mfma32(a[0], b[0], acc);
 }
 
-// three bf16 pieces of a value rounded to FP32 (h + m + l exact)
-__device__ inline void split3(double x, bf16 &h, bf16 &m, bf16 &l) {
-    const float v = (float)x;
+// three bf16 pieces of an FP32 value (h + m + l exact)
+__device__ inline void split3(float v, bf16 &h, bf16 &m, bf16 &l) {
     h = (bf16)v;
     const float r = v - (float)h;
     m = (bf16)r;
@@ -735,12 +775,12 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1s(const T *__restrict__ rho,
                 const double b = (MIR && in) ? sW[n_phi - 1 - k - q] * (double)stg.b[q] : 0.0;
                 sum0 += a + b;
                 bf16 h, m, l;
-                split3(a + b, h, m, l);
+                split3((float)(a + b), h, m, l);
                 ph[0][q] = h;
                 ph[1][q] = m;
                 ph[2][q] = l;
                 if (MIR) {
-                    split3(a - b, h, m, l);
+                    split3((float)(a - b), h, m, l);
                     pd[0][q] = h;
                     pd[1][q] = m;
                     pd[2][q] = l;
@@ -783,127 +823,133 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1s(const T *__restrict__ rho,
     // the order-0 column (factor C_k^0 = dphi for every cell), in FP64
     sum0 += __shfl_xor(sum0, 1);
     if (sk == 0 && row_ok) F[(size_t)j * ldv + v0 + sr] = f1[0] * sum0;
-    // register r of lane l: factor row 32t + d_row32(l, r), row v = 32w + l%32
+    // register r of lane l: factor row 32t + d_row32(l, r), row v = 32w + l%32;
+    // the FP32 sums go to the FP32 columns unchanged
     const int vv = wave * 32 + (lane & 31);
+    float *Fs = tf_f32(F, n_theta, ldv);
 #pragma unroll
     for (int t = 0; t < 2 * NT2; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int fr = t * 32 + d_row32(lane, r), o = t < NT2 ? fr : fr - 32 * NT2;  // order - 1
             const int c = 1 + (t < NT2 ? 0 : ce) + o;
-            if (o < L && vv < nv) F[((size_t)c * n_theta + j) * ldv + v0 + vv] = (double)acc[t][r];
+            if (o < L && vv < nv) Fs[((size_t)(c - 1) * n_theta + j) * ldv + v0 + vv] = acc[t][r];
         }
 }
 
-// Expansion.  Block and schedule as the FP64 kernel (64 points, 128 rows v,
-// JB theta rows, XCD-aware ids); wave w takes v 32w.. and both 32-point
-// tiles, with the cosine sums E and the sine sums O in FP32.  K = the
-// columns 1.. in slabs of 16 (E: [0, ce), O: [ce, 2 ce) of them; without
-// MIR all into E).  Thread t stages 8 consecutive columns of row t%128 (from
-// 8 (t/128)) of G as pieces, and chunks of the factor slab.
+// Expansion.  Block: 64 points, 128 rows v and JBS theta rows one after
+// the other, XCD-aware ids as the FP64 kernel; the block's factor tile (3
+// pieces x 64 points x K columns) is loaded into LDS once and serves every
+// theta row.  Wave w takes v 32w.. and both 32-point tiles, with the cosine
+// sums E and the sine sums O in FP32.  K = the columns 1.. in slabs of 16
+// (E: [0, ce), O: [ce, 2 ce) of them; without MIR all into E).  Each wave
+// builds its A fragments from its own loads (lane l: row l%32, columns
+// 8 (l/32).. of the slab, two 128-byte runs per load) two slabs ahead, so
+// the slab loop needs no barrier.  The order-0 column (FP64) is added in
+// the epilogue: lane l loads row l%32 and the others read it by shuffle.
+constexpr int JBS = 8;
+__host__ __device__ constexpr int phi2s_pitch(int K) { return K + 8; }  // 16 rows of a fragment read: distinct banks
 template <typename T, bool MIR>
 __global__ __launch_bounds__(256, 2) void k_sep_phi2s(const double *__restrict__ G, int ldv,
                                                       const bf16 *__restrict__ f2s, const double *__restrict__ f2,
                                                       const int2 *__restrict__ kxy, T *__restrict__ phi, int vrows,
                                                       int n_theta, int n_phi, int kx, int kxp, int ce, int nbt, int nvt,
                                                       int ngroups) {
-    __shared__ __attribute__((aligned(16))) bf16 As[3][VB][PK];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[3][64][PK];
-    __shared__ double sG0[2][VB];
+    extern __shared__ __attribute__((aligned(16))) bf16 Bf[];  // [3][64][phi2s_pitch(K)]
     const int id = blockIdx.x, k8 = id >> 3, bt = k8 % nbt, grp = (k8 / nbt) * 8 + (id & 7);
     if (grp >= ngroups) return;  // the whole block, before any barrier
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int b0 = bt * 64, v0 = (grp % nvt) * VB;
-    const int j0 = (grp / nvt) * JB, jn = min(JB, n_theta - j0);
-    const int K = 2 * ce, nsl = K / SK, nse = MIR ? ce / SK : nsl;
+    const int j0 = (grp / nvt) * JBS, jn = min(JBS, n_theta - j0);
+    const int K = 2 * ce, nsl = K / SK, nse = MIR ? ce / SK : nsl, PF = phi2s_pitch(K);
     const size_t npc = (size_t)kxp * K;  // one piece of the factor table
-    const int sv = tid & (VB - 1), sc = (tid >> 7) * 8;
+    const int kg = (lane >> 5) * 8, row = lane & 31;
+    const size_t cstr = (size_t)n_theta * ldv;  // one column of the FP32 transforms
+    // this lane's A row: v = v0 + 32w + row, columns 1 + s SK + kg + q
+    const float *ga = tf_f32(G, n_theta, ldv) + (size_t)kg * cstr + (size_t)j0 * ldv + v0 + wave * 32 + row;
+    const double *g0p = G + (size_t)j0 * ldv + v0 + wave * 32 + row;
 
-    double gv[8], g0r = 0.0;
-    v8bf fc[2];
-    auto load = [&](int jj, int s) {
-        if (s == 0 && tid < VB) g0r = G[(size_t)(j0 + jj) * ldv + v0 + tid];  // padded rows are zero
+    for (int e = tid; e < 3 * 64 * (K / 8); e += 256) {
+        const int pc = e / (64 * (K / 8)), rem = e - pc * 64 * (K / 8), pt = rem / (K / 8), kc = (rem % (K / 8)) * 8;
+        *(v8bf *)&Bf[(pc * 64 + pt) * PF + kc] = *(const v8bf *)(f2s + pc * npc + (size_t)(b0 + pt) * K + kc);
+    }
+    // this lane's two points (one per 32-point tile) and their order-0 factors
+    int2 kk[2];
+    double f0[2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) gv[q] = G[((size_t)(1 + s * SK + sc + q) * n_theta + j0 + jj) * ldv + v0 + sv];
+    for (int t = 0; t < 2; ++t) {
+        const int b = b0 + t * 32 + row;
+        kk[t] = b < kx ? kxy[b] : make_int2(-1, -1);
+        f0[t] = b < kx ? f2[b] : 0.0;
+    }
+    __syncthreads();  // the factor tile; no barrier follows
+
+    const int total = jn * nsl;
+    float gv[2][8];
+    auto load = [&](float(&g)[8], int i) {
+        if (i < total) {
+            const int jj = i / nsl, s = i - jj * nsl;
+            const float *p = ga + (size_t)(s * SK) * cstr + (size_t)jj * ldv;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int e = tid + 256 * q;
-            if (e < 3 * 64 * 2) {
-                const int pc = e / 128, rem = e - pc * 128;
-                fc[q] = *(const v8bf *)(f2s + pc * npc + (size_t)(b0 + (rem >> 1)) * K + s * SK + (rem & 1) * 8);
-            }
+            for (int q = 0; q < 8; ++q) g[q] = p[(size_t)q * cstr];
         }
     };
     v16f E[2], O[2];
-    const int kg = (lane >> 5) * 8, row = lane & 31;
-    auto run = [&](v16f(&acc)[2], int jj, int s0, int s1) {
-        for (int s = s0; s < s1; ++s) {
-            if (s == 0 && tid < VB) sG0[jj & 1][tid] = g0r;
-            {
-                v8bf pcs[3];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    bf16 h, m, l;
-                    split3(gv[q], h, m, l);
-                    pcs[0][q] = h;
-                    pcs[1][q] = m;
-                    pcs[2][q] = l;
-                }
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int pc = 0; pc < 3; ++pc) *(v8bf *)&As[pc][sv][sc] = pcs[pc];
-            }
+        for (int r = 0; r < 16; ++r) E[t][r] = O[t][r] = 0.f;
+    double g0 = 0.0;
+    auto body = [&](float(&g)[8], int i) {
+        const int jj = i / nsl, s = i - jj * nsl;
+        if (s == 0) g0 = g0p[(size_t)jj * ldv];  // padded rows are zero
+        v8bf a[3];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int e = tid + 256 * q;
-                if (e < 3 * 64 * 2) {
-                    const int pc = e / 128, rem = e - pc * 128;
-                    *(v8bf *)&Bs[pc][rem >> 1][(rem & 1) * 8] = fc[q];
-                }
-            }
-            __syncthreads();
-            {
-                const bool last = s + 1 == nsl;
-                if (!last || jj + 1 < jn) load(last ? jj + 1 : jj, last ? 0 : s + 1);
-            }
-            v8bf a[3];
+        for (int q = 0; q < 8; ++q) {
+            bf16 h, m, l;
+            split3(g[q], h, m, l);
+            a[0][q] = h;
+            a[1][q] = m;
+            a[2][q] = l;
+        }
+        load(g, i + 2);
 #pragma unroll
-            for (int pc = 0; pc < 3; ++pc) a[pc] = *(const v8bf *)&As[pc][wave * 32 + row][kg];
+        for (int t = 0; t < 2; ++t) {
+            v8bf b[3];
+#pragma unroll
+            for (int pc = 0; pc < 3; ++pc) b[pc] = *(const v8bf *)&Bf[(pc * 64 + t * 32 + row) * PF + s * SK + kg];
+            if (!MIR || s < nse) E[t] = six(a, b, E[t]);
+            else O[t] = six(a, b, O[t]);
+        }
+        if (s + 1 < nsl) return;
+        // the theta row's outputs: register r of lane l holds row v = 32w +
+        // d_row32(l, r) at point 32t + l%32
+        T *o0 = phi + ((size_t)(v0 + wave * 32) * n_theta + j0 + jj) * n_phi;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int vl = d_row32(lane, r);
+            const double g0v = __shfl(g0, vl);
+            if (v0 + wave * 32 + vl >= vrows) continue;
+            T *o = o0 + (size_t)vl * n_theta * n_phi;
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                v8bf b[3];
-#pragma unroll
-                for (int pc = 0; pc < 3; ++pc) b[pc] = *(const v8bf *)&Bs[pc][t * 32 + row][kg];
-                acc[t] = six(a, b, acc[t]);
+                if (kk[t].x < 0) continue;
+                const double e = (double)E[t][r] + f0[t] * g0v, d = (double)O[t][r];
+                o[kk[t].x] = (T)(e + d);
+                if (MIR && kk[t].y >= 0) o[kk[t].y] = (T)(e - d);
             }
-            __syncthreads();
         }
-    };
-    load(0, 0);
-    for (int jj = 0; jj < jn; ++jj) {
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int r = 0; r < 16; ++r) E[t][r] = O[t][r] = 0.f;
-        run(E, jj, 0, nse);
-        if (MIR) run(O, jj, nse, nsl);
-        // register r of lane l: row v = 32w + d_row32(l, r), point 32t + l%32
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int b = b0 + t * 32 + row;
-            if (b >= kx) continue;
-            const int2 kk = kxy[b];
-            const double f0 = f2[b];  // the order-0 factor (cos 0 = 1)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int vl = wave * 32 + d_row32(lane, r), v = v0 + vl;
-                if (v >= vrows) continue;
-                T *o = phi + ((size_t)v * n_theta + j0 + jj) * n_phi;
-                const double e = (double)E[t][r] + f0 * sG0[jj & 1][vl], d = (double)O[t][r];
-                o[kk.x] = (T)(e + d);
-                if (MIR && kk.y >= 0) o[kk.y] = (T)(e - d);
-            }
-        }
+    };
+    load(gv[0], 0);
+    load(gv[1], 1);
+    for (int i = 0; i < total; i += 2) {
+        body(gv[0], i);
+        if (i + 1 < total) body(gv[1], i + 1);
     }
 }
 
@@ -963,9 +1009,10 @@ hipError_t launch_phi1s(const Plan &p, int n_fields, const T *rho) {
 
 template <typename T, bool MIR>
 void launch_phi2s(const Plan &p, int vrows, T *phi) {
-    const int nbt = (p.sep_kx + 63) / 64, nvt = (vrows + VB - 1) / VB, ng = nvt * ((p.n_theta + JB - 1) / JB);
+    const int nbt = (p.sep_kx + 63) / 64, nvt = (vrows + VB - 1) / VB, ng = nvt * ((p.n_theta + JBS - 1) / JBS);
     const dim3 grid((unsigned)((ng + 7) / 8 * 8 * nbt));
-    hipLaunchKernelGGL((k_sep_phi2s<T, MIR>), grid, dim3(256), 0, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2s, p.sep_f2,
+    const size_t lds = sizeof(bf16) * 3 * 64 * phi2s_pitch(2 * p.sep_ce);
+    hipLaunchKernelGGL((k_sep_phi2s<T, MIR>), grid, dim3(256), lds, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2s, p.sep_f2,
                        p.sep_kxy, phi, vrows, p.n_theta, p.n_phi, p.sep_kx, p.sep_kxp, p.sep_ce, nbt, nvt, ng);
 }
 
@@ -988,8 +1035,14 @@ hipError_t sep_phi_moments(const Plan &p, int n_fields, const void *rho, int rho
 hipError_t sep_theta_moments(const Plan &p, int n_fields) {
     const int vrows = n_fields * p.n_patches * p.n_r, rows = n_fields * p.n_r;
     if (p.sep_lp > 80 || p.lmax > 64) return hipErrorInvalidValue;  // five slot tiles, nine degree tiles
-    hipLaunchKernelGGL(k_sep_theta1, dim3((vrows + VB - 1) / VB, p.sep_nc()), dim3(256), 0, p.stream, p.sep_F,
-                       p.sep_ldv(), p.sep_t1, p.sep_m, p.sep_coff, p.sep_A, vrows, p.n_theta, p.sep_lp, p.lmax);
+    if (p.split())
+        hipLaunchKernelGGL(k_sep_theta1<true>, dim3((vrows + VB - 1) / VB, p.sep_nc()), dim3(256), 0, p.stream,
+                           p.sep_F, p.sep_ldv(), p.sep_t1, p.sep_m, p.sep_coff, p.sep_A, vrows, p.n_theta, p.sep_lp,
+                           p.lmax);
+    else
+        hipLaunchKernelGGL(k_sep_theta1<false>, dim3((vrows + VB - 1) / VB, p.sep_nc()), dim3(256), 0, p.stream,
+                           p.sep_F, p.sep_ldv(), p.sep_t1, p.sep_m, p.sep_coff, p.sep_A, vrows, p.n_theta, p.sep_lp,
+                           p.lmax);
     hipLaunchKernelGGL(k_sep_rot<false>, dim3((rows + TR - 1) / TR, p.lmax + 1), dim3(256), 0, p.stream, p.sep_A,
                        p.sep_x1, p.sep_xoff, p.sep_perm, p.sep_cslot, p.Bpart, rows, p.n_r, p.n_patches,
                        p.sep_ldv(), p.np);
@@ -1002,9 +1055,13 @@ hipError_t sep_theta_expansion(const Plan &p, int n_fields) {
     hipLaunchKernelGGL(k_sep_rot<true>, dim3((rows + TR - 1) / TR, p.lmax + 1, p.n_patches), dim3(256), 0,
                        p.stream, p.M, p.sep_x2, p.sep_xoff, p.sep_perm, p.sep_cslot, p.sep_A, rows, p.n_r,
                        p.n_patches, p.sep_ldv(), p.np);
-    hipLaunchKernelGGL(k_sep_theta2, dim3((vrows + VB - 1) / VB, p.sep_nc(), (p.n_theta + VB - 1) / VB), dim3(256),
-                       0, p.stream, p.sep_A, p.sep_t2, p.sep_m, p.sep_coff, p.sep_F, p.sep_ldv(), vrows, p.n_theta,
-                       p.sep_lp, p.lmax);
+    const dim3 g2((vrows + VB - 1) / VB, p.sep_nc(), (p.n_theta + VB - 1) / VB);
+    if (p.split())
+        hipLaunchKernelGGL(k_sep_theta2<true>, g2, dim3(256), 0, p.stream, p.sep_A, p.sep_t2, p.sep_m, p.sep_coff,
+                           p.sep_F, p.sep_ldv(), vrows, p.n_theta, p.sep_lp, p.lmax);
+    else
+        hipLaunchKernelGGL(k_sep_theta2<false>, g2, dim3(256), 0, p.stream, p.sep_A, p.sep_t2, p.sep_m, p.sep_coff,
+                           p.sep_F, p.sep_ldv(), vrows, p.n_theta, p.sep_lp, p.lmax);
     return hipGetLastError();
 }
 
