@@ -167,8 +167,12 @@ int mpg_plan(const mpg_grid *grid, int lmax, int precision, int max_fields,
  * transforms fold cell k with its mirror cell n_phi - 1 - k.  Operations
  * per shell and patch: about n_theta n_phi (2 lmax + 1) (halved by the
  * mirror fold) against n_theta n_phi (lmax + 1)^2 for the dense
- * contraction (under the parity fold, per patch pair).  FP64 only
- * (precision MPG_FP64, else MPG_EUNSUPPORTED); any patches and Euler
+ * contraction (under the parity fold, per patch pair).  Precision
+ * MPG_FP64, or MPG_SPLIT_BF16: the two phi transforms then run as six bf16
+ * piece products with FP32 accumulation (at most 2 (n_phi / 2) terms
+ * each) into FP64 work arrays, with the order-0 column, theta
+ * contractions, rotations and scans in FP64 (about 1e-8 relative to FP64);
+ * MPG_SPLIT_BF16_TIERED gives MPG_EUNSUPPORTED.  Any patches and Euler
  * angles.  mpg_potential_static, mpg_potential_batch, mpg_autotune and
  * mpg_set_tuning reject such plans (MPG_EUNSUPPORTED); mpg_moments,
  * mpg_potential, mpg_tables and stage timing take them (stages: phi

@@ -846,23 +846,31 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1s(const T *__restrict__ rho,
 // builds its A fragments from its own loads (lane l: row l%32, columns
 // 8 (l/32).. of the slab, two 128-byte runs per load) two slabs ahead, so
 // the slab loop needs no barrier.  The order-0 column (FP64) is added in
-// the epilogue: lane l loads row l%32 and the others read it by shuffle.
+// the epilogue: lane l loads row l%32, and the row of output register r
+// (the same for each half-wave) is read from its lane by v_readlane.
 constexpr int JBS = 8;
-__host__ __device__ constexpr int phi2s_pitch(int K) { return K + 8; }  // 16 rows of a fragment read: distinct banks
+// factor tile row pitch in 16-byte chunks (K + 8 values): the 16 rows of a
+// fragment read start on distinct bank groups
+__host__ __device__ constexpr int phi2s_pitch8(int K) { return K / 8 + 1; }
+constexpr int KMAX2 = 128;  // 2 ce for lmax <= 64
 template <typename T, bool MIR>
-__global__ __launch_bounds__(256, 2) void k_sep_phi2s(const double *__restrict__ G, int ldv,
+__global__ __launch_bounds__(256, 3) void k_sep_phi2s(const double *__restrict__ G, int ldv,
                                                       const bf16 *__restrict__ f2s, const double *__restrict__ f2,
                                                       const int2 *__restrict__ kxy, T *__restrict__ phi, int vrows,
                                                       int n_theta, int n_phi, int kx, int kxp, int ce, int nbt, int nvt,
                                                       int ngroups) {
-    extern __shared__ __attribute__((aligned(16))) bf16 Bf[];  // [3][64][phi2s_pitch(K)]
+    // [3][64][phi2s_pitch8(K)] chunks of 8 values (typed so that every
+    // access is a 16-byte one)
+    __shared__ v8bf Bf[3 * 64 * phi2s_pitch8(KMAX2)];
+    __shared__ int2 sK[64];    // the block's points (kxy), x = -1 past the last
+    __shared__ double sF0[64];  // and their order-0 factors
     const int id = blockIdx.x, k8 = id >> 3, bt = k8 % nbt, grp = (k8 / nbt) * 8 + (id & 7);
     if (grp >= ngroups) return;  // the whole block, before any barrier
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int b0 = bt * 64, v0 = (grp % nvt) * VB;
     const int j0 = (grp / nvt) * JBS, jn = min(JBS, n_theta - j0);
-    const int K = 2 * ce, nsl = K / SK, nse = MIR ? ce / SK : nsl, PF = phi2s_pitch(K);
+    const int K = 2 * ce, nsl = K / SK, nse = MIR ? ce / SK : nsl, PF = phi2s_pitch8(K);
     const size_t npc = (size_t)kxp * K;  // one piece of the factor table
     const int kg = (lane >> 5) * 8, row = lane & 31;
     const size_t cstr = (size_t)n_theta * ldv;  // one column of the FP32 transforms
@@ -872,18 +880,14 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2s(const double *__restrict__
 
     for (int e = tid; e < 3 * 64 * (K / 8); e += 256) {
         const int pc = e / (64 * (K / 8)), rem = e - pc * 64 * (K / 8), pt = rem / (K / 8), kc = (rem % (K / 8)) * 8;
-        *(v8bf *)&Bf[(pc * 64 + pt) * PF + kc] = *(const v8bf *)(f2s + pc * npc + (size_t)(b0 + pt) * K + kc);
+        Bf[(pc * 64 + pt) * PF + kc / 8] = *(const v8bf *)(f2s + pc * npc + (size_t)(b0 + pt) * K + kc);
     }
-    // this lane's two points (one per 32-point tile) and their order-0 factors
-    int2 kk[2];
-    double f0[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int b = b0 + t * 32 + row;
-        kk[t] = b < kx ? kxy[b] : make_int2(-1, -1);
-        f0[t] = b < kx ? f2[b] : 0.0;
+    if (tid < 64) {
+        const int b = b0 + tid;
+        sK[tid] = b < kx ? kxy[b] : make_int2(-1, -1);
+        sF0[tid] = b < kx ? f2[b] : 0.0;
     }
-    __syncthreads();  // the factor tile; no barrier follows
+    __syncthreads();  // the factor tile and point tables; no barrier follows
 
     const int total = jn * nsl;
     float gv[2][8];
@@ -918,7 +922,7 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2s(const double *__restrict__
         for (int t = 0; t < 2; ++t) {
             v8bf b[3];
 #pragma unroll
-            for (int pc = 0; pc < 3; ++pc) b[pc] = *(const v8bf *)&Bf[(pc * 64 + t * 32 + row) * PF + s * SK + kg];
+            for (int pc = 0; pc < 3; ++pc) b[pc] = Bf[(pc * 64 + t * 32 + row) * PF + (s * SK + kg) / 8];
             if (!MIR || s < nse) E[t] = six(a, b, E[t]);
             else O[t] = six(a, b, O[t]);
         }
@@ -926,18 +930,23 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2s(const double *__restrict__
         // the theta row's outputs: register r of lane l holds row v = 32w +
         // d_row32(l, r) at point 32t + l%32
         T *o0 = phi + ((size_t)(v0 + wave * 32) * n_theta + j0 + jj) * n_phi;
+        const int g0lo = __double2loint(g0), g0hi = __double2hiint(g0);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int vl = d_row32(lane, r);
-            const double g0v = __shfl(g0, vl);
+            const int vl = d_row32(lane, r), r0 = d_row32(0, r);  // vl = r0 or r0 + 4
+            const double ga0 = __hiloint2double(__builtin_amdgcn_readlane(g0hi, r0), __builtin_amdgcn_readlane(g0lo, r0));
+            const double ga1 = __hiloint2double(__builtin_amdgcn_readlane(g0hi, r0 + 4),
+                                                __builtin_amdgcn_readlane(g0lo, r0 + 4));
+            const double g0v = lane < 32 ? ga0 : ga1;
             if (v0 + wave * 32 + vl >= vrows) continue;
             T *o = o0 + (size_t)vl * n_theta * n_phi;
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                if (kk[t].x < 0) continue;
-                const double e = (double)E[t][r] + f0[t] * g0v, d = (double)O[t][r];
-                o[kk[t].x] = (T)(e + d);
-                if (MIR && kk[t].y >= 0) o[kk[t].y] = (T)(e - d);
+                const int2 kk = sK[t * 32 + row];  // LDS broadcast reads, kept out of registers
+                if (kk.x < 0) continue;
+                const double e = (double)E[t][r] + sF0[t * 32 + row] * g0v, d = (double)O[t][r];
+                o[kk.x] = (T)(e + d);
+                if (MIR && kk.y >= 0) o[kk.y] = (T)(e - d);
             }
         }
 #pragma unroll
@@ -1011,8 +1020,8 @@ template <typename T, bool MIR>
 void launch_phi2s(const Plan &p, int vrows, T *phi) {
     const int nbt = (p.sep_kx + 63) / 64, nvt = (vrows + VB - 1) / VB, ng = nvt * ((p.n_theta + JBS - 1) / JBS);
     const dim3 grid((unsigned)((ng + 7) / 8 * 8 * nbt));
-    const size_t lds = sizeof(bf16) * 3 * 64 * phi2s_pitch(2 * p.sep_ce);
-    hipLaunchKernelGGL((k_sep_phi2s<T, MIR>), grid, dim3(256), lds, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2s, p.sep_f2,
+    if (2 * p.sep_ce > KMAX2) return;  // lmax <= 64 (checked at plan creation)
+    hipLaunchKernelGGL((k_sep_phi2s<T, MIR>), grid, dim3(256), 0, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2s, p.sep_f2,
                        p.sep_kxy, phi, vrows, p.n_theta, p.n_phi, p.sep_kx, p.sep_kxp, p.sep_ce, nbt, nvt, ng);
 }
 

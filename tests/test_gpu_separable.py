@@ -1,9 +1,10 @@
 """The separable method (phi transform, theta contraction per order and a
-rotation per degree, in FP64) against the CPU oracle at the FP64 bar (1e-12
-max-norm relative), element by element: the small grids of the FP64 suite,
-rotated and general patch sets, grids whose phi cells do not mirror about 0,
-centre evaluation, float32 input and output, several fields, and the large
-workload at sampled vertices."""
+rotation per degree) against the CPU oracle, element by element: in FP64 at
+the FP64 bar (1e-12 max-norm relative), and with split-BF16 phi transforms
+at the split bar (1e-6), on the small grids of the FP64 suite, rotated and
+general patch sets, grids whose phi cells do not mirror about 0, centre
+evaluation, float32 input and output, several fields, and the large
+workload at sampled vertices (FP64) and whole against FP64 (split)."""
 import numpy as np
 import pytest
 
