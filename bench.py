@@ -63,7 +63,7 @@ def traffic_record(stage, precision):
         return None
     key = f"{precision}:{stage}"
     r = rec.get(key)
-    source = "sep_f64.hip" if precision == "separable" else "gemm_bf16.hip"
+    source = "sep_f64.hip" if precision.startswith("separable") else "gemm_bf16.hip"
     if not r or r.get("source_hash") != kernel_source_hash(source):
         return None
     return r.get("bytes_per_launch")
@@ -223,13 +223,14 @@ def separable_flops(grid, n_fields):
     return {"phi_moments": 2.0 * rows * cells * cols, "phi_expansion": 2.0 * rows * points * cols}
 
 
-def separable_bytes(grid, n_fields):
+def separable_bytes(grid, n_fields, split=False):
     """Algorithmic HBM bytes of one launch of each phi transform: the FP32
-    field once (4 bytes per cell) and the FP64 phi transforms once (2 lmax
-    + 1 columns per row)."""
+    field once (4 bytes per cell) and the phi transforms once (2 lmax + 1
+    columns per row; FP64, or in the split form FP32 past the order-0
+    column)."""
     rows = n_fields * grid.n_patches * grid.n_r * grid.n_theta
     field = 4.0 * rows * grid.n_phi
-    transforms = 8.0 * rows * (2 * grid.lmax + 1)
+    transforms = rows * (8.0 + (4.0 if split else 8.0) * 2 * grid.lmax)
     return {"phi_moments": field + transforms, "phi_expansion": field + transforms}
 
 
@@ -272,8 +273,8 @@ def separable_workload(grid, rho, steps, warmup, ref=None, precision="fp64"):
     else:
         # six bf16 MFMA products per product leave the split transforms bound
         # by HBM: algorithmic bytes are the FP32 field (read by the moments',
-        # written by the expansion's) and the FP64 phi transforms between them
-        byts = separable_bytes(grid, n)
+        # written by the expansion's) and the phi transforms between them
+        byts = separable_bytes(grid, n, split=True)
         ach = byts[dom] / (per[dom] * 1e-3)
         out["phi_bf16_mfma_frac"] = {k: 6 * flops[k] / (per[k] * 1e-3) / PEAK_BF16 for k in flops}
         out["phi_hbm_frac"] = {k: byts[k] / (per[k] * 1e-3) / PEAK_HBM for k in byts}
