@@ -682,9 +682,10 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi2(const double *__restrict__ 
 // Split forms of the two phi transforms (MPG_SPLIT_BF16): the same sums in
 // six bf16 piece products (h h, h m, m h, h l, m m, l h of the three pieces
 // of each FP32-rounded operand) on v_mfma_f32_32x32x16_bf16, accumulated in
-// FP32 over at most 2 lmax + 1 or n_phi/2 terms, and written in FP64.  The
-// order-0 column stays an FP64 row sum (moments) and an FP64 term added to
-// the cosine sums (expansion).
+// FP32 over at most n_phi/2 (moments) or 2 ce (expansion) terms.  The
+// moments' sums go unchanged to the FP32 columns (tf_f32), the expansion's
+// to the potential.  The order-0 column stays an FP64 row sum (moments) and
+// an FP64 term added to the cosine sums (expansion).
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int PK = 24;  // LDS pitch (bf16) of a 16-deep row of pieces: 16 rows of a fragment read hit distinct banks
