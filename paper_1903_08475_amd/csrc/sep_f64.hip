@@ -720,6 +720,8 @@ __device__ inline void split3(float v, bf16 &h, bf16 &m, bf16 &l) {
 // rows (C of the orders 1.., then S); K = the kh cells in slabs of 16.  Wave
 // w takes v 32w.. and every factor tile.  Thread t stages 8 cells of row t/2
 // (as the FP64 kernel) as pieces, and chunks t + 256q of the factor slab.
+// Block ids take the theta row fastest, so the blocks in flight read
+// neighbouring theta rows of the same density rows.
 template <typename T, bool MIR, int NT2>
 __global__ __launch_bounds__(256, 2) void k_sep_phi1s(const T *__restrict__ rho, const double *__restrict__ w,
                                                       size_t w_patch, const bf16 *__restrict__ f1s,
@@ -732,7 +734,8 @@ __global__ __launch_bounds__(256, 2) void k_sep_phi1s(const T *__restrict__ rho,
     __shared__ __attribute__((aligned(16))) bf16 Bd[MIR ? 2 : 1][3][VB][PK];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int fg = blockIdx.x / nst, st0 = (blockIdx.x - fg * nst) * VB, j = blockIdx.y;
+    const int j = blockIdx.x % n_theta, fs = blockIdx.x / n_theta;
+    const int fg = fs / nst, st0 = (fs - fg * nst) * VB;
     const int nv = min(VB, n_r - st0);
     const size_t v0 = (size_t)fg * n_r + st0;
     const double *wrow = w + (size_t)(fg % n_patches) * w_patch + (size_t)j * n_phi;
@@ -854,8 +857,8 @@ constexpr int JBS = 8;
 // fragment read start on distinct bank groups
 __host__ __device__ constexpr int phi2s_pitch8(int K) { return K / 8 + 1; }
 constexpr int KMAX2 = 128;  // 2 ce for lmax <= 64
-template <typename T, bool MIR>
-__global__ __launch_bounds__(256, 3) void k_sep_phi2s(const double *__restrict__ G, int ldv,
+template <typename T, bool MIR, bool O32>
+__global__ __launch_bounds__(256, O32 ? 3 : 2) void k_sep_phi2s(const double *__restrict__ G, int ldv,
                                                       const bf16 *__restrict__ f2s, const double *__restrict__ f2,
                                                       const int2 *__restrict__ kxy, T *__restrict__ phi, int vrows,
                                                       int n_theta, int n_phi, int kx, int kxp, int ce, int nbt, int nvt,
@@ -906,8 +909,9 @@ __global__ __launch_bounds__(256, 3) void k_sep_phi2s(const double *__restrict__
 #pragma unroll
         for (int r = 0; r < 16; ++r) E[t][r] = O[t][r] = 0.f;
     double g0 = 0.0;
-    auto body = [&](float(&g)[8], int i) {
-        const int jj = i / nsl, s = i - jj * nsl;
+    // slab s of theta row jj from register set g, which then loads the slab
+    // two ahead
+    auto body = [&](float(&g)[8], int jj, int s) {
         if (s == 0) g0 = g0p[(size_t)jj * ldv];  // padded rows are zero
         v8bf a[3];
 #pragma unroll
@@ -918,7 +922,7 @@ __global__ __launch_bounds__(256, 3) void k_sep_phi2s(const double *__restrict__
             a[1][q] = m;
             a[2][q] = l;
         }
-        load(g, i + 2);
+        load(g, jj * nsl + s + 2);
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             v8bf b[3];
@@ -927,10 +931,15 @@ __global__ __launch_bounds__(256, 3) void k_sep_phi2s(const double *__restrict__
             if (!MIR || s < nse) E[t] = six(a, b, E[t]);
             else O[t] = six(a, b, O[t]);
         }
-        if (s + 1 < nsl) return;
-        // the theta row's outputs: register r of lane l holds row v = 32w +
-        // d_row32(l, r) at point 32t + l%32
-        T *o0 = phi + ((size_t)(v0 + wave * 32) * n_theta + j0 + jj) * n_phi;
+    };
+    // the theta row's outputs: register r of lane l holds row v = 32w +
+    // d_row32(l, r) at point 32t + l%32.  Stores take byte offsets from the
+    // wave's first row, in 32 bits when its 32 rows span less than 4 GiB.
+    using Off = typename std::conditional<O32, unsigned, size_t>::type;
+    auto epilogue = [&](int jj) {
+        char *o0 = reinterpret_cast<char *>(phi + ((size_t)(v0 + wave * 32) * n_theta + j0 + jj) * n_phi);
+        const Off rb = (Off)((size_t)n_theta * n_phi * sizeof(T));
+        const int vlim = vrows - v0 - wave * 32;  // rows of this wave inside the call
         const int g0lo = __double2loint(g0), g0hi = __double2hiint(g0);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -939,15 +948,15 @@ __global__ __launch_bounds__(256, 3) void k_sep_phi2s(const double *__restrict__
             const double ga1 = __hiloint2double(__builtin_amdgcn_readlane(g0hi, r0 + 4),
                                                 __builtin_amdgcn_readlane(g0lo, r0 + 4));
             const double g0v = lane < 32 ? ga0 : ga1;
-            if (v0 + wave * 32 + vl >= vrows) continue;
-            T *o = o0 + (size_t)vl * n_theta * n_phi;
+            if (vl >= vlim) continue;
+            const Off ro = (Off)vl * rb;
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 const int2 kk = sK[t * 32 + row];  // LDS broadcast reads, kept out of registers
                 if (kk.x < 0) continue;
                 const double e = (double)E[t][r] + sF0[t * 32 + row] * g0v, d = (double)O[t][r];
-                o[kk.x] = (T)(e + d);
-                if (MIR && kk.y >= 0) o[kk.y] = (T)(e - d);
+                *reinterpret_cast<T *>(o0 + (ro + (Off)kk.x * (Off)sizeof(T))) = (T)(e + d);
+                if (MIR && kk.y >= 0) *reinterpret_cast<T *>(o0 + (ro + (Off)kk.y * (Off)sizeof(T))) = (T)(e - d);
             }
         }
 #pragma unroll
@@ -957,9 +966,12 @@ __global__ __launch_bounds__(256, 3) void k_sep_phi2s(const double *__restrict__
     };
     load(gv[0], 0);
     load(gv[1], 1);
-    for (int i = 0; i < total; i += 2) {
-        body(gv[0], i);
-        if (i + 1 < total) body(gv[1], i + 1);
+    for (int jj = 0; jj < jn; ++jj) {
+        for (int s = 0; s < nsl; s += 2) {  // nsl = ce / 8 is even
+            body(gv[0], jj, s);
+            body(gv[1], jj, s + 1);
+        }
+        epilogue(jj);
     }
 }
 
@@ -1002,7 +1014,9 @@ template <typename T, bool MIR>
 hipError_t launch_phi1s(const Plan &p, int n_fields, const T *rho) {
     const int nst = (p.n_r + VB - 1) / VB;
     const size_t w_patch = p.npat == 1 ? 0 : (size_t)p.n_ang;
-    const dim3 grid(n_fields * p.n_patches * nst, p.n_theta);
+    const size_t nb = (size_t)n_fields * p.n_patches * nst * p.n_theta;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;  // one grid axis
+    const dim3 grid((unsigned)nb);
     const size_t lds = sizeof(double) * p.n_phi;
     if (p.sep_nt2 == 1)
         hipLaunchKernelGGL((k_sep_phi1s<T, MIR, 1>), grid, dim3(256), lds, p.stream, rho, p.w, w_patch, p.sep_f1s,
@@ -1022,8 +1036,14 @@ void launch_phi2s(const Plan &p, int vrows, T *phi) {
     const int nbt = (p.sep_kx + 63) / 64, nvt = (vrows + VB - 1) / VB, ng = nvt * ((p.n_theta + JBS - 1) / JBS);
     const dim3 grid((unsigned)((ng + 7) / 8 * 8 * nbt));
     if (2 * p.sep_ce > KMAX2) return;  // lmax <= 64 (checked at plan creation)
-    hipLaunchKernelGGL((k_sep_phi2s<T, MIR>), grid, dim3(256), 0, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2s, p.sep_f2,
-                       p.sep_kxy, phi, vrows, p.n_theta, p.n_phi, p.sep_kx, p.sep_kxp, p.sep_ce, nbt, nvt, ng);
+    if ((size_t)32 * p.n_theta * p.n_phi * sizeof(T) <= 0xffffffffu)
+        hipLaunchKernelGGL((k_sep_phi2s<T, MIR, true>), grid, dim3(256), 0, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2s,
+                           p.sep_f2, p.sep_kxy, phi, vrows, p.n_theta, p.n_phi, p.sep_kx, p.sep_kxp, p.sep_ce, nbt, nvt,
+                           ng);
+    else
+        hipLaunchKernelGGL((k_sep_phi2s<T, MIR, false>), grid, dim3(256), 0, p.stream, p.sep_F, p.sep_ldv(), p.sep_f2s,
+                           p.sep_f2, p.sep_kxy, phi, vrows, p.n_theta, p.n_phi, p.sep_kx, p.sep_kxp, p.sep_ce, nbt, nvt,
+                           ng);
 }
 
 hipError_t sep_phi_moments(const Plan &p, int n_fields, const void *rho, int rho_dtype) {
