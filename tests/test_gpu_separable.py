@@ -157,6 +157,24 @@ def test_rejected_calls():
     assert rel_err(plan.potential(t).cpu().numpy(), phi) < TOL64
 
 
+def test_split_wide_patch_both_store_offsets():
+    """A polar patch of 4096 x 4096 cells: 32 rows of FP64 potential span
+    exactly 4 GiB, so the split expansion writes them with 64-bit offsets,
+    while FP32 output takes the 32-bit ones.  Both against the FP64
+    separable solve (pinned to the oracle above) at the split bar."""
+    torch, mpg = mods()
+    g = W.polar(4096, 4096, W.uniform_edges(2), 8, name="wide")
+    t = torch.tensor(W.random_rho(g, 76), device="cuda")
+    ref = mpg.Plan(g, method="separable").potential(t, out_dtype=torch.float64)
+    split = mpg.Plan(g, method="separable", precision="split_bf16")
+    tf = t.float()
+    for out_dtype in (torch.float64, torch.float32):
+        out = split.potential(tf, out_dtype=out_dtype).double()
+        err = float((out - ref).abs().max() / ref.abs().max())
+        print(f"wide patch, split vs FP64, {out_dtype}: {err:.3e}")
+        assert err < TOL["split_bf16"]
+
+
 @pytest.mark.slow
 def test_large_workload_split_against_fp64():
     """The split form of the separable method on the large workload's own
